@@ -1,0 +1,185 @@
+/*
+ * lf.h - C ABI of the MI355X sweeping-plane light-field renderer.
+ *
+ * The library turns an explicit radiance field (3D Gaussians or sparse voxels) into
+ * N_chunk shared, view-independent premultiplied RGBA sweeping planes seen from one
+ * reference camera, then swizzle-blends those planes front to back into many sheared
+ * light-field views in one pass ("Real-time 3D Visualization of Radiance Fields on
+ * Light Field Displays", Sec. 4 and Alg. 1).
+ *
+ * Conventions shared by every entry point
+ *  - Pointer spaces: lf_camera, lf_view arrays, lf_geometry_info and the out-parameters
+ *    of the *_workspace / *_stats / lf_geometry / lf_quilt_views calls are HOST memory.
+ *    Every array inside lf_field and lf_mpi, every image and every workspace is DEVICE
+ *    memory on the context's GPU.
+ *  - Ownership: the caller allocates and frees all inputs, outputs, gradients and
+ *    workspaces; the library frees nothing it did not allocate and owns only lf_ctx.
+ *  - Asynchrony: device work is enqueued on the given stream (a hipStream_t passed as
+ *    void*, NULL = the null stream) and returns without waiting, except the calls
+ *    documented as synchronising.
+ *  - Errors: every call returns an lf_status; arguments are validated on the host
+ *    before anything is enqueued, so an invalid call has no device side effect.
+ *    lf_last_error() returns a message for the last failing call on this thread.
+ *  - Camera frame: the base camera looks along +z, x to the right, y down; R, t map
+ *    world points p to base-camera coordinates R p + t.  Angles are full angles, radians.
+ *  - Thread safety: one context per thread (or per stream).
+ */
+#ifndef LF_H
+#define LF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LF_OK = 0,
+  LF_ERR_INVALID_ARG = 1,   /* a null pointer, a size or an enum out of range         */
+  LF_ERR_UNSUPPORTED = 2,   /* a valid request this build does not implement          */
+  LF_ERR_CAPACITY = 3,      /* a workspace too small; the needed size is reported      */
+  LF_ERR_OUT_OF_MEMORY = 4, /* a library-owned allocation failed                       */
+  LF_ERR_HIP = 5            /* a HIP runtime call failed (also deferred async errors)  */
+} lf_status;
+
+typedef enum { LF_F32 = 0, LF_F16 = 1, LF_BF16 = 2 } lf_dtype;
+typedef enum { LF_NEAREST = 0, LF_BILINEAR = 1 } lf_interp;
+typedef enum { LF_BIN_QUANTILE = 0, LF_BIN_INV_DEPTH = 1 } lf_binning;
+typedef enum { LF_GAUSSIANS = 0, LF_VOXELS = 1 } lf_field_kind;
+
+#define LF_MAX_VIEWS 256          /* views per lf_composite call                         */
+#define LF_MAX_CHUNKS 4096        /* sweeping planes per MPI                             */
+#define LF_MAX_RES 8192           /* per-view and per-plane resolution limit             */
+
+typedef struct lf_ctx lf_ctx;
+
+/* The quilt parameters H of Alg. 1: base camera, display window and plane settings
+ * (Sec. 4.2-4.3).  Host memory.                                                           */
+typedef struct {
+  float R[9];          /* world -> base camera rotation, row major                           */
+  float t[3];          /* world -> base camera translation                                   */
+  int32_t nx, ny;      /* per-view resolution N_x, N_y                                       */
+  float fov_x, fov_y;  /* base camera field of view theta_x, theta_y (0 < theta < pi)        */
+  float d_focal;       /* D_focal: base camera to focal-plane distance (> 0)                 */
+  float phi_x, phi_y;  /* display viewing angles (0 <= phi < pi)                             */
+  float d_shift;       /* D_shift: moves the reference camera back (Sec. 4.2), >= 0          */
+  float plane_scale;   /* P_s: plane resolution = round(P_s * N)                             */
+  float z_near;        /* primitives with reference depth <= z_near are culled (> 0)         */
+} lf_camera;
+
+/* One quilt view: lateral offset of Eq. 4 in base-camera units.  The principal-point
+ * shift of Eq. 5 is implied (principal rays meet the focal-plane centre).  Host memory. */
+typedef struct { float dx, dy; } lf_view;
+
+/* The radiance field P of Alg. 1.  Device memory, float32, C-contiguous.
+ *  LF_GAUSSIANS: means[n][3], log_scales[n][3], quats[n][4] (w, x, y, z; normalised
+ *                inside), opacity[n] (activated, in [0, 1]), rgb[n][3] (view-independent).
+ *  LF_VOXELS:    ijk[n][3] int32 cell indices, density[n][8] corner densities per world
+ *                unit (corner bit0 = +x, bit1 = +y, bit2 = +z), rgb[n][3]; the cell
+ *                (i, j, k) spans origin + voxel_size * [i, i+1] x [j, j+1] x [k, k+1].    */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  int64_t n;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity;
+  const float* rgb;
+  const int32_t* ijk;
+  const float* density;
+  float origin[3];
+  float voxel_size;
+} lf_field;
+
+/* Sweeping planes C, T of Sec. 4.2 as premultiplied RGBA (alpha = 1 - T_k).  Device.    */
+typedef struct {
+  int32_t dtype;          /* lf_dtype of rgba                                             */
+  int32_t n_chunk;        /* K                                                            */
+  int32_t height, width;  /* H_p = round(P_s N_y), W_p = round(P_s N_x)                   */
+  void* rgba;             /* [n_chunk][height][width][4]                                  */
+  float* depth;           /* [n_chunk] plane depths d_k (base-camera z)                   */
+  int32_t* chunk_of;      /* [n] chunk per primitive, -1 = culled (may be NULL)           */
+  int32_t* chunk_count;   /* [n_chunk] primitives per chunk (may be NULL)                 */
+} lf_mpi;
+
+/* Derived display geometry (Eqs. 1-2, 5, 8) - host values for inspection and tests.      */
+typedef struct {
+  double d_forward0;      /* Eq. 1                                                        */
+  double d_forward;       /* Eq. 1 minus D_shift: reference camera position on +z         */
+  double tan_half_theta_prime_x, tan_half_theta_prime_y;   /* Eq. 2                       */
+  double f_dilation;      /* Eq. 8, reference texels^2                                    */
+  double fpx, fpy, cpx, cpy;   /* reference intrinsics in plane texels                    */
+  double fx, fy, cx, cy;       /* base-view intrinsics in pixels                          */
+  int32_t plane_width, plane_height;
+  /* float32 constants of the decision programs (bit patterns the kernels use)            */
+  float d_forward32, guard_x32, guard_y32, ratio_x32, ratio_y32, fpx32, fpy32;
+  float cpx32, cpy32, cx32, cy32, inv_focal32;
+} lf_geometry_info;
+
+typedef struct {
+  int64_t n_visible;        /* primitives inside the reference frustum                    */
+  int64_t entries_needed;   /* (tile, chunk) list entries the last build needed           */
+  int64_t entry_capacity;   /* entries the workspace holds                                */
+  int32_t overflow;         /* 1 if entries_needed > entry_capacity (planes are invalid)  */
+} lf_build_info;
+
+/* Library version string.                                                               */
+const char* lf_version(void);
+
+/* Message of the last failing call on this thread ("" if none).                          */
+const char* lf_last_error(void);
+
+/* Create a context on HIP device `device`; fails with LF_ERR_HIP if it is absent.        */
+lf_status lf_create(lf_ctx** out, int device);
+void lf_destroy(lf_ctx* ctx);
+
+/* Derived geometry of a camera (Eqs. 1-2, 8; Sec. 4.2).  Host only, no GPU needed.       */
+lf_status lf_geometry(const lf_camera* cam, lf_geometry_info* out);
+
+/* View offsets of a vx-by-vy quilt, Eqs. 3-4 (row-major, s = 0 for a single row or
+ * column).  Host only.  `out` holds vx * vy entries.                                     */
+lf_status lf_quilt_views(const lf_camera* cam, int32_t vx, int32_t vy, lf_view* out);
+
+/* Bytes of workspace lf_build_mpi needs for `field` with room for `entry_capacity`
+ * (tile, chunk) list entries (entry_capacity <= 0 picks 32 entries per primitive).       */
+lf_status lf_build_mpi_workspace(const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                                 int64_t entry_capacity, size_t* bytes);
+
+/* Alg. 1 steps 1-5: cull and key, sort and chunk, rasterise every chunk into its plane.
+ * Sec. 4.4 (Gaussians) / Sec. 4.5 (voxels, followed by the in-place plane low-pass).
+ * binning: LF_BIN_QUANTILE (Sec. 4.4) or LF_BIN_INV_DEPTH with inv_depth_range = {z_lo,
+ * z_hi} (host, z_lo > D_forward).  `mpi` describes caller-allocated outputs whose
+ * n_chunk/width/height must match the camera; dtype may be F32, F16 or BF16.
+ * Enqueued on `stream` with no host synchronisation; if the workspace's entry capacity
+ * is exceeded the planes are invalid and lf_build_stats reports it.                    */
+lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                       int32_t binning, const float* inv_depth_range, lf_mpi* mpi,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* Counters of the last lf_build_mpi that used `workspace`.  SYNCHRONISES `stream`.
+ * Returns LF_ERR_CAPACITY (with *out filled) if that build overflowed.                   */
+lf_status lf_build_stats(lf_ctx* ctx, const void* workspace, size_t workspace_bytes,
+                         lf_build_info* out, void* stream);
+
+/* Swizzle blending (Sec. 4.3, Eqs. 6-7, Alg. 1 steps 6-11): for each view v, pixel (x, y)
+ * and plane k front to back, sample plane k at the texel coordinate of Eq. 6 (nearest or
+ * bilinear; outside the plane is transparent) and over-composite with float32
+ * transmittance.  out: device [n_views][ny][nx][4] of (Q_r, Q_g, Q_b, T) in out_dtype
+ * (F32 or F16).  views: host array of n_views (1..LF_MAX_VIEWS) offsets.                */
+lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
+                       int32_t n_views, int32_t interp, int32_t out_dtype, void* out, void* stream);
+
+/* The float32 texel-coordinate coefficients lf_composite uses (Eq. 6 in affine form):
+ * X = fl(fl(bx[k] * fl(x - c_x)) + Cx[k][v]) and Y likewise; the *_n offsets are the
+ * nearest-sampling ones (floor(X) is the texel).  Device outputs: bx, by [n_chunk];
+ * cx, cy, cxn, cyn [n_chunk][n_views].  Diagnostic entry point.                         */
+lf_status lf_plane_coeffs(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
+                          int32_t n_views, float* bx, float* by, float* cx, float* cy, float* cxn,
+                          float* cyn, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LF_H */

@@ -1,0 +1,223 @@
+"""ctypes binding of ``include/lf.h`` (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and raises
+:class:`LFError` when the call returns a status other than ``LF_OK``.  Device
+pointers are plain integers (e.g. ``tensor.data_ptr()``); streams are integers
+(``torch.cuda.current_stream().cuda_stream``) or 0 for the null stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblf.so")
+
+LF_OK, LF_ERR_INVALID_ARG, LF_ERR_UNSUPPORTED, LF_ERR_CAPACITY, LF_ERR_OUT_OF_MEMORY, LF_ERR_HIP = range(6)
+LF_F32, LF_F16, LF_BF16 = 0, 1, 2
+LF_NEAREST, LF_BILINEAR = 0, 1
+LF_BIN_QUANTILE, LF_BIN_INV_DEPTH = 0, 1
+LF_GAUSSIANS, LF_VOXELS = 0, 1
+LF_MAX_VIEWS, LF_MAX_CHUNKS, LF_MAX_RES = 256, 4096, 8192
+
+STATUS_NAMES = {0: "LF_OK", 1: "LF_ERR_INVALID_ARG", 2: "LF_ERR_UNSUPPORTED", 3: "LF_ERR_CAPACITY",
+                4: "LF_ERR_OUT_OF_MEMORY", 5: "LF_ERR_HIP"}
+
+# every symbol include/lf.h declares
+EXPORTS = [
+    "lf_version", "lf_last_error", "lf_create", "lf_destroy", "lf_geometry", "lf_quilt_views",
+    "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_plane_coeffs",
+]
+
+
+class LFError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class lf_camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("fov_x", C.c_float), ("fov_y", C.c_float), ("d_focal", C.c_float), ("phi_x", C.c_float),
+                ("phi_y", C.c_float), ("d_shift", C.c_float), ("plane_scale", C.c_float), ("z_near", C.c_float)]
+
+
+class lf_view(C.Structure):
+    _fields_ = [("dx", C.c_float), ("dy", C.c_float)]
+
+
+class lf_field(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64),
+                ("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("rgb", C.c_void_p), ("ijk", C.c_void_p), ("density", C.c_void_p),
+                ("origin", C.c_float * 3), ("voxel_size", C.c_float)]
+
+
+class lf_mpi(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("n_chunk", C.c_int32), ("height", C.c_int32), ("width", C.c_int32),
+                ("rgba", C.c_void_p), ("depth", C.c_void_p), ("chunk_of", C.c_void_p),
+                ("chunk_count", C.c_void_p)]
+
+
+class lf_geometry_info(C.Structure):
+    _fields_ = [("d_forward0", C.c_double), ("d_forward", C.c_double),
+                ("tan_half_theta_prime_x", C.c_double), ("tan_half_theta_prime_y", C.c_double),
+                ("f_dilation", C.c_double), ("fpx", C.c_double), ("fpy", C.c_double), ("cpx", C.c_double),
+                ("cpy", C.c_double), ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double),
+                ("cy", C.c_double), ("plane_width", C.c_int32), ("plane_height", C.c_int32),
+                ("d_forward32", C.c_float), ("guard_x32", C.c_float), ("guard_y32", C.c_float),
+                ("ratio_x32", C.c_float), ("ratio_y32", C.c_float), ("fpx32", C.c_float), ("fpy32", C.c_float),
+                ("cpx32", C.c_float), ("cpy32", C.c_float), ("cx32", C.c_float), ("cy32", C.c_float),
+                ("inv_focal32", C.c_float)]
+
+
+class lf_build_info(C.Structure):
+    _fields_ = [("n_visible", C.c_int64), ("entries_needed", C.c_int64), ("entry_capacity", C.c_int64),
+                ("overflow", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load ``liblf.so``; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2508_18540_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "lf_version": ([], C.c_char_p),
+        "lf_last_error": ([], C.c_char_p),
+        "lf_create": ([C.POINTER(P), C.c_int], C.c_int),
+        "lf_destroy": ([P], None),
+        "lf_geometry": ([C.POINTER(lf_camera), C.POINTER(lf_geometry_info)], C.c_int),
+        "lf_quilt_views": ([C.POINTER(lf_camera), C.c_int32, C.c_int32, C.POINTER(lf_view)], C.c_int),
+        "lf_build_mpi_workspace": ([C.POINTER(lf_field), C.POINTER(lf_camera), C.c_int32, C.c_int64,
+                                    C.POINTER(C.c_size_t)], C.c_int),
+        "lf_build_mpi": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.c_int32, C.c_int32,
+                          C.POINTER(C.c_float), C.POINTER(lf_mpi), P, C.c_size_t, P], C.c_int),
+        "lf_build_stats": ([P, P, C.c_size_t, C.POINTER(lf_build_info), P], C.c_int),
+        "lf_composite": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32, C.c_int32,
+                          C.c_int32, P, P], C.c_int),
+        "lf_plane_coeffs": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
+                             P, P, P, P, P, P, P], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        if not hasattr(lib, name):
+            continue
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != LF_OK:
+        raise LFError(status, where, load().lf_last_error().decode())
+
+
+# ------------------------------------------------------------------------------------------
+# struct builders
+# ------------------------------------------------------------------------------------------
+
+def make_camera(cam) -> lf_camera:
+    """An ``lf_camera`` from any object with the fields of ``scenegen.Camera``."""
+    c = lf_camera()
+    c.R[:] = [float(v) for v in cam.R]
+    c.t[:] = [float(v) for v in cam.t]
+    c.nx, c.ny = int(cam.nx), int(cam.ny)
+    for f in ("fov_x", "fov_y", "d_focal", "phi_x", "phi_y", "d_shift", "plane_scale", "z_near"):
+        setattr(c, f, float(getattr(cam, f)))
+    return c
+
+
+def make_views(dx, dy):
+    n = len(dx)
+    arr = (lf_view * n)()
+    for i in range(n):
+        arr[i].dx = float(dx[i])
+        arr[i].dy = float(dy[i])
+    return arr
+
+
+def make_mpi(dtype: int, n_chunk: int, height: int, width: int, rgba: int, depth: int,
+             chunk_of: int = 0, chunk_count: int = 0) -> lf_mpi:
+    m = lf_mpi()
+    m.dtype, m.n_chunk, m.height, m.width = dtype, n_chunk, height, width
+    m.rgba, m.depth = rgba or None, depth or None
+    m.chunk_of, m.chunk_count = chunk_of or None, chunk_count or None
+    return m
+
+
+# ------------------------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ------------------------------------------------------------------------------------------
+
+def lf_version() -> str:
+    return load().lf_version().decode()
+
+
+def lf_last_error() -> str:
+    return load().lf_last_error().decode()
+
+
+def lf_create(device: int = 0) -> int:
+    h = C.c_void_p()
+    _check(load().lf_create(C.byref(h), device), "lf_create")
+    return h.value
+
+
+def lf_destroy(ctx: int) -> None:
+    load().lf_destroy(ctx)
+
+
+def lf_geometry(cam: lf_camera) -> lf_geometry_info:
+    out = lf_geometry_info()
+    _check(load().lf_geometry(C.byref(cam), C.byref(out)), "lf_geometry")
+    return out
+
+
+def lf_quilt_views(cam: lf_camera, vx: int, vy: int):
+    out = (lf_view * (vx * vy))()
+    _check(load().lf_quilt_views(C.byref(cam), vx, vy, out), "lf_quilt_views")
+    return out
+
+
+def lf_build_mpi_workspace(field: lf_field, cam: lf_camera, n_chunk: int, entry_capacity: int = 0) -> int:
+    n = C.c_size_t()
+    _check(load().lf_build_mpi_workspace(C.byref(field), C.byref(cam), n_chunk, entry_capacity, C.byref(n)),
+           "lf_build_mpi_workspace")
+    return n.value
+
+
+def lf_build_mpi(ctx: int, field: lf_field, cam: lf_camera, n_chunk: int, binning: int, inv_depth_range,
+                 mpi: lf_mpi, workspace: int, workspace_bytes: int, stream: int = 0) -> None:
+    rng = None
+    if inv_depth_range is not None:
+        rng = (C.c_float * 2)(*[float(v) for v in inv_depth_range])
+    _check(load().lf_build_mpi(ctx, C.byref(field), C.byref(cam), n_chunk, binning, rng, C.byref(mpi),
+                               workspace, workspace_bytes, stream), "lf_build_mpi")
+
+
+def lf_build_stats(ctx: int, workspace: int, workspace_bytes: int, stream: int = 0, check: bool = True):
+    out = lf_build_info()
+    st = load().lf_build_stats(ctx, workspace, workspace_bytes, C.byref(out), stream)
+    if check:
+        _check(st, "lf_build_stats")
+    return out, st
+
+
+def lf_composite(ctx: int, mpi: lf_mpi, cam: lf_camera, views, interp: int, out_dtype: int, out: int,
+                 stream: int = 0) -> None:
+    _check(load().lf_composite(ctx, C.byref(mpi), C.byref(cam), views, len(views), interp, out_dtype, out, stream),
+           "lf_composite")
+
+
+def lf_plane_coeffs(ctx: int, mpi: lf_mpi, cam: lf_camera, views, bx: int, by: int, cx: int, cy: int,
+                    cxn: int, cyn: int, stream: int = 0) -> None:
+    _check(load().lf_plane_coeffs(ctx, C.byref(mpi), C.byref(cam), views, len(views), bx, by, cx, cy, cxn, cyn,
+                                  stream), "lf_plane_coeffs")

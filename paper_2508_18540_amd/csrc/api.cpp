@@ -1,0 +1,131 @@
+// C ABI entry points: argument validation on the host, then kernel launches.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "lf_internal.h"
+
+struct lf_ctx {
+  int device;
+};
+
+namespace lf {
+namespace {
+
+bool dtype_ok(int32_t d) { return d == LF_F32 || d == LF_F16 || d == LF_BF16; }
+
+lf_status check_mpi(const lf_mpi* mpi, const Geom& g) {
+  if (!mpi) return fail(LF_ERR_INVALID_ARG, "mpi is NULL");
+  if (!dtype_ok(mpi->dtype)) return fail(LF_ERR_INVALID_ARG, "mpi dtype %d is not F32/F16/BF16", mpi->dtype);
+  if (mpi->n_chunk < 1 || mpi->n_chunk > LF_MAX_CHUNKS)
+    return fail(LF_ERR_INVALID_ARG, "n_chunk %d outside [1, %d]", mpi->n_chunk, LF_MAX_CHUNKS);
+  if (mpi->width != g.wp || mpi->height != g.hp)
+    return fail(LF_ERR_INVALID_ARG, "mpi is %dx%d but the camera's planes are %dx%d", mpi->width, mpi->height,
+                g.wp, g.hp);
+  if (!mpi->rgba || !mpi->depth) return fail(LF_ERR_INVALID_ARG, "mpi rgba/depth is NULL");
+  return LF_OK;
+}
+
+lf_status check_views(const lf_view* views, int32_t n_views) {
+  if (!views) return fail(LF_ERR_INVALID_ARG, "views is NULL");
+  if (n_views < 1 || n_views > LF_MAX_VIEWS)
+    return fail(LF_ERR_INVALID_ARG, "n_views %d outside [1, %d]", n_views, LF_MAX_VIEWS);
+  for (int v = 0; v < n_views; ++v)
+    if (!std::isfinite(views[v].dx) || !std::isfinite(views[v].dy))
+      return fail(LF_ERR_INVALID_ARG, "view %d offset is not finite", v);
+  return LF_OK;
+}
+
+lf_status composite_args(const lf_mpi* mpi, const lf_camera* cam, const lf_view* views, int32_t n_views,
+                         CompositeArgs* a) {
+  Geom g;
+  lf_status s = derive_geometry(cam, &g);
+  if (s != LF_OK) return s;
+  if ((s = check_mpi(mpi, g)) != LF_OK) return s;
+  if ((s = check_views(views, n_views)) != LF_OK) return s;
+  std::memset(a, 0, sizeof(*a));
+  a->planes = mpi->rgba;
+  a->depth = mpi->depth;
+  a->K = mpi->n_chunk;
+  a->hp = g.hp;
+  a->wp = g.wp;
+  a->nx = g.nx;
+  a->ny = g.ny;
+  a->n_views = n_views;
+  a->plane_dtype = mpi->dtype;
+  a->c = g.c;
+  for (int v = 0; v < n_views; ++v) {
+    a->dx[v] = views[v].dx;
+    a->dy[v] = views[v].dy;
+  }
+  return LF_OK;
+}
+
+lf_status check_ctx(lf_ctx* ctx) {
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return LF_OK;
+}
+
+}  // namespace
+}  // namespace lf
+
+using namespace lf;
+
+extern "C" const char* lf_version(void) { return "lf-mi355x 0.1 (gfx950)"; }
+
+extern "C" lf_status lf_create(lf_ctx** out, int device) {
+  if (!out) return fail(LF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return fail(LF_ERR_HIP, "no HIP device available");
+  if (device < 0 || device >= n) return fail(LF_ERR_INVALID_ARG, "device %d outside [0, %d)", device, n);
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  lf_ctx* c = new (std::nothrow) lf_ctx;
+  if (!c) return fail(LF_ERR_OUT_OF_MEMORY, "context allocation failed");
+  c->device = device;
+  *out = c;
+  return LF_OK;
+}
+
+extern "C" void lf_destroy(lf_ctx* ctx) { delete ctx; }
+
+extern "C" lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
+                                  int32_t n_views, int32_t interp, int32_t out_dtype, void* out, void* stream) {
+  CompositeArgs* a = new (std::nothrow) CompositeArgs;
+  if (!a) return fail(LF_ERR_OUT_OF_MEMORY, "argument block allocation failed");
+  lf_status s = composite_args(mpi, cam, views, n_views, a);
+  if (s == LF_OK && interp != LF_NEAREST && interp != LF_BILINEAR)
+    s = fail(LF_ERR_INVALID_ARG, "interp %d is not NEAREST/BILINEAR", interp);
+  if (s == LF_OK && out_dtype != LF_F32 && out_dtype != LF_F16)
+    s = fail(LF_ERR_INVALID_ARG, "out_dtype %d is not F32/F16", out_dtype);
+  if (s == LF_OK && !out) s = fail(LF_ERR_INVALID_ARG, "out is NULL");
+  if (s == LF_OK) s = check_ctx(ctx);
+  if (s == LF_OK) {
+    a->interp = interp;
+    a->out_dtype = out_dtype;
+    a->out = out;
+    hipError_t e = composite_launch(*a, (hipStream_t)stream);
+    if (e != hipSuccess) s = hip_fail(e, "composite launch");
+  }
+  delete a;
+  return s;
+}
+
+extern "C" lf_status lf_plane_coeffs(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
+                                     int32_t n_views, float* bx, float* by, float* cx, float* cy, float* cxn,
+                                     float* cyn, void* stream) {
+  CompositeArgs* a = new (std::nothrow) CompositeArgs;
+  if (!a) return fail(LF_ERR_OUT_OF_MEMORY, "argument block allocation failed");
+  lf_status s = composite_args(mpi, cam, views, n_views, a);
+  if (s == LF_OK && !(bx && by && cx && cy && cxn && cyn)) s = fail(LF_ERR_INVALID_ARG, "an output is NULL");
+  if (s == LF_OK) s = check_ctx(ctx);
+  if (s == LF_OK) {
+    hipError_t e = plane_coeffs_launch(*a, bx, by, cx, cy, cxn, cyn, (hipStream_t)stream);
+    if (e != hipSuccess) s = hip_fail(e, "plane_coeffs launch");
+  }
+  delete a;
+  return s;
+}

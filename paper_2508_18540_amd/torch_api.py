@@ -1,0 +1,88 @@
+"""Torch-tensor front end of the C ABI: allocates outputs with torch, passes device pointers
+and the current stream.  No compute happens here."""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.LF_F32, torch.float16: L.LF_F16, torch.bfloat16: L.LF_BF16}
+_INTERP = {"nearest": L.LF_NEAREST, "bilinear": L.LF_BILINEAR}
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _need(t: torch.Tensor, name: str, dtypes=None, ndim=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+
+
+class Context:
+    """An ``lf_ctx`` bound to one device."""
+
+    def __init__(self, device: int | torch.device = 0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else device
+        self.handle = L.lf_create(self.device.index or 0)
+
+    def close(self):
+        if self.handle:
+            L.lf_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def views_of(dx, dy=None):
+    if dy is None:
+        dy = [0.0] * len(dx)
+    return L.make_views(list(map(float, dx)), list(map(float, dy)))
+
+
+def mpi_of(rgba: torch.Tensor, depth: torch.Tensor, chunk_of=None, chunk_count=None) -> L.lf_mpi:
+    _need(rgba, "rgba", tuple(_DT), 4)
+    _need(depth, "depth", (torch.float32,), 1)
+    K, H, W, C = rgba.shape
+    if C != 4 or depth.shape[0] != K:
+        raise ValueError("rgba must be [K,H,W,4] and depth [K]")
+    return L.make_mpi(_DT[rgba.dtype], K, H, W, rgba.data_ptr(), depth.data_ptr(),
+                      chunk_of.data_ptr() if chunk_of is not None else 0,
+                      chunk_count.data_ptr() if chunk_count is not None else 0)
+
+
+def composite(ctx: Context, rgba: torch.Tensor, depth: torch.Tensor, cam, views, interp: str = "nearest",
+              out_dtype=torch.float32, out: torch.Tensor | None = None) -> torch.Tensor:
+    """lf_composite: returns views [V, ny, nx, 4] of (Q_r, Q_g, Q_b, T)."""
+    m = mpi_of(rgba, depth)
+    c = L.make_camera(cam)
+    V = len(views)
+    if out is None:
+        out = torch.empty((V, cam.ny, cam.nx, 4), dtype=out_dtype, device=rgba.device)
+    _need(out, "out", (torch.float32, torch.float16), 4)
+    if tuple(out.shape) != (V, cam.ny, cam.nx, 4):
+        raise ValueError(f"out must be [{V}, {cam.ny}, {cam.nx}, 4]")
+    L.lf_composite(ctx.handle, m, c, views, _INTERP[interp], _DT[out.dtype], out.data_ptr(), _stream(rgba))
+    return out
+
+
+def plane_coeffs(ctx: Context, rgba: torch.Tensor, depth: torch.Tensor, cam, views):
+    """lf_plane_coeffs: returns (bx, by, cx, cy, cxn, cyn) float32 tensors."""
+    m = mpi_of(rgba, depth)
+    K, V = depth.shape[0], len(views)
+    dev = rgba.device
+    bx, by = (torch.empty(K, dtype=torch.float32, device=dev) for _ in range(2))
+    cs = [torch.empty((K, V), dtype=torch.float32, device=dev) for _ in range(4)]
+    L.lf_plane_coeffs(ctx.handle, m, L.make_camera(cam), views, bx.data_ptr(), by.data_ptr(),
+                      *[t.data_ptr() for t in cs], stream=_stream(rgba))
+    return (bx, by, *cs)

@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports every declared
+symbol, host geometry matches the oracle bit for bit after float32 rounding, and invalid
+arguments are rejected before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scenegen
+from oracle import decisions, geometry
+
+L = pytest.importorskip("paper_2508_18540_amd._lib")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("liblf.so is not built (run __graft_entry__.build())")
+    return L.load()
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "lf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lf_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 10
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(L.EXPORTS)
+    assert "gfx950" in L.lf_version()
+
+
+CAMS = {
+    "uniform10k": scenegen.config_camera("uniform10k")[0],
+    "cluster500k": scenegen.config_camera("cluster500k")[0],
+    "voxel256": scenegen.config_camera("voxel256")[0],
+    "shifted": scenegen.camera(300, 200, 60.0, 1.5, math.radians(25.0), math.radians(10.0), plane_scale=1.5,
+                               d_shift=0.2, z_near=0.1),
+    "rotated": scenegen.camera(128, 96, 45.0, 3.0, math.radians(35.0), R=[[0, 0, 1], [0, 1, 0], [-1, 0, 0]],
+                               t=[0.5, -0.25, 4.0]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CAMS))
+def test_host_geometry_bit_exact(lib, name):
+    cam = CAMS[name]
+    info = L.lf_geometry(L.make_camera(cam))
+    g = geometry.derive(cam)
+    c = decisions.constants(g, cam)
+    assert info.d_forward0 == pytest.approx(g.d_forward0, rel=1e-15, abs=1e-300)
+    assert info.tan_half_theta_prime_x == pytest.approx(g.tpx, rel=1e-15)
+    assert info.f_dilation == pytest.approx(g.f_dilation, rel=1e-15)
+    assert (info.plane_width, info.plane_height) == (g.wp, g.hp)
+    pairs = [("d_forward32", c.d_forward), ("guard_x32", c.guard_x), ("guard_y32", c.guard_y),
+             ("ratio_x32", c.ratio_x), ("ratio_y32", c.ratio_y), ("fpx32", c.fpx), ("fpy32", c.fpy),
+             ("cpx32", c.cpx), ("cpy32", c.cpy), ("cx32", c.cx), ("cy32", c.cy), ("inv_focal32", c.inv_focal)]
+    for field, ref in pairs:
+        got = np.float32(getattr(info, field))
+        assert got.view(np.uint32) == np.float32(ref).view(np.uint32), field
+
+
+@pytest.mark.parametrize("vx,vy", [(9, 1), (45, 1), (1, 1), (5, 3)])
+def test_quilt_views_match_eq3_eq4(lib, vx, vy):
+    cam = CAMS["shifted"]
+    v = L.lf_quilt_views(L.make_camera(cam), vx, vy)
+    dx, dy, _, _ = geometry.quilt_views(cam, vx, vy)
+    got = np.array([[e.dx, e.dy] for e in v], dtype=np.float32)
+    assert np.array_equal(got[:, 0].view(np.uint32), dx.astype(np.float32).view(np.uint32))
+    assert np.array_equal(got[:, 1].view(np.uint32), dy.astype(np.float32).view(np.uint32))
+
+
+def _valid_call(lib, **kw):
+    cam = L.make_camera(CAMS["uniform10k"])
+    for k, v in kw.pop("cam", {}).items():
+        setattr(cam, k, v)
+    mpi = L.make_mpi(kw.pop("dtype", L.LF_F32), kw.pop("n_chunk", 16), kw.pop("h", 128), kw.pop("w", 128),
+                     kw.pop("rgba", 0x1000), kw.pop("depth", 0x2000))
+    views = L.make_views([0.0, 0.01], [0.0, 0.0])
+    n_views = kw.pop("n_views", 2)
+    st = lib.lf_composite(kw.pop("ctx", None), ctypes.byref(mpi), ctypes.byref(cam), views, n_views,
+                          kw.pop("interp", 0), kw.pop("out_dtype", 0), kw.pop("out", 0x3000), None)
+    return st, L.lf_last_error()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(cam=dict(nx=0)), "resolution"),
+    (dict(cam=dict(fov_x=math.pi)), "field of view"),
+    (dict(cam=dict(d_focal=-1.0)), "d_focal"),
+    (dict(cam=dict(phi_x=-0.1)), "viewing angles"),
+    (dict(cam=dict(z_near=0.0)), "z_near"),
+    (dict(cam=dict(plane_scale=float("nan"))), "plane_scale"),
+    (dict(dtype=7), "dtype"),
+    (dict(n_chunk=0), "n_chunk"),
+    (dict(w=64), "planes are"),
+    (dict(rgba=0), "rgba"),
+    (dict(n_views=0), "n_views"),
+    (dict(n_views=300), "n_views"),
+    (dict(interp=5), "interp"),
+    (dict(out_dtype=2), "out_dtype"),
+    (dict(out=0), "out is NULL"),
+    (dict(), "ctx is NULL"),
+])
+def test_composite_rejects_invalid_arguments(lib, kw, needle):
+    st, msg = _valid_call(lib, **kw)
+    assert st == L.LF_ERR_INVALID_ARG
+    assert needle in msg
+
+
+def test_geometry_rejects_null(lib):
+    assert lib.lf_geometry(None, None) == L.LF_ERR_INVALID_ARG
+    assert lib.lf_quilt_views(ctypes.byref(L.make_camera(CAMS["uniform10k"])), 0, 1,
+                              (L.lf_view * 1)()) == L.LF_ERR_INVALID_ARG
