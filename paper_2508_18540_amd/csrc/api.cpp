@@ -5,10 +5,6 @@
 
 #include "lf_internal.h"
 
-struct lf_ctx {
-  int device;
-};
-
 namespace lf {
 namespace {
 

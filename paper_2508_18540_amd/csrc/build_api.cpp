@@ -1,17 +1,232 @@
-// MPI build entry points (Alg. 1 steps 1-5).
-#include "lf_internal.h"
+// MPI build entry points (Alg. 1 steps 1-5): validation, workspace layout, launches.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "build_internal.h"
+#include "sort_internal.h"
+
+namespace lf {
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+BuildLayout build_layout(int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t cap) {
+  BuildLayout L;
+  std::memset(&L, 0, sizeof(L));
+  L.n = n;
+  L.cap = cap;
+  L.K = K;
+  L.ntx = (wp + kTile - 1) / kTile;
+  L.nty = (hp + kTile - 1) / kTile;
+  L.n_tiles = L.ntx * L.nty;
+  L.n_buckets = (int64_t)L.n_tiles * K;
+  int bits = 1;
+  while ((1LL << bits) < L.n_tiles) ++bits;
+  L.tile_bits = bits;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  const size_t un = (size_t)(n > 0 ? n : 1);
+  L.o_hdr = take(sizeof(BuildHeader));
+  L.o_keys = take(un * 4);
+  L.o_vals = take(un * 4);
+  L.o_keys_alt = take(un * 4);
+  L.o_vals_alt = take(un * 4);
+  L.o_rec = take(un * sizeof(GRec));
+  L.o_ntiles_i = take(un * 4);
+  L.o_ntiles_r = take(un * 8);
+  L.o_chunk_r = take(un * 4);
+  L.o_offsets = take((un + 1) * 8);
+  L.o_scan64 = take(scan_tmp_elems((int64_t)un) * 8);
+  L.o_chunk_start = take((size_t)(K + 1) * 8);
+  L.o_edges = take((size_t)K * 4);
+  L.o_dtab = take((size_t)K * 4);
+  L.o_hist = take((size_t)(L.n_buckets + 1) * 4);
+  L.o_bucket = take((size_t)(L.n_buckets + 1) * 4);
+  L.o_scan32 = take(scan_tmp_elems(L.n_buckets) * 4);
+  L.o_radix = take(radix_tmp_u32(n > cap ? n : cap) * 4);
+  const size_t uc = (size_t)(cap > 0 ? cap : 1);
+  L.o_ekeys = take(uc * 4);
+  L.o_evals = take(uc * 4);
+  L.o_ekeys_alt = take(uc * 4);
+  L.o_evals_alt = take(uc * 4);
+  L.total = o;
+  return L;
+}
+
+namespace {
+
+constexpr int64_t kMaxPrimitives = (1LL << 31) - 1;
+constexpr int64_t kMaxEntries = (1LL << 31) - 1;
+
+int64_t default_capacity(int64_t n) {
+  const int64_t c = 32 * n;
+  return c < 65536 ? 65536 : (c > kMaxEntries ? kMaxEntries : c);
+}
+
+// The largest entry capacity a workspace of `bytes` holds (0 if none).
+int64_t capacity_of(int64_t n, int32_t K, int32_t wp, int32_t hp, size_t bytes) {
+  const size_t fixed = build_layout(n, K, wp, hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
+  if (bytes <= fixed) return 0;
+  int64_t cap = (int64_t)((bytes - fixed) / 16);
+  if (cap > kMaxEntries) cap = kMaxEntries;
+  while (cap > 0 && build_layout(n, K, wp, hp, cap).total > bytes) cap -= 64;
+  return cap > 0 ? cap : 0;
+}
+
+lf_status check_field(const lf_field* f) {
+  if (!f) return fail(LF_ERR_INVALID_ARG, "field is NULL");
+  if (f->n < 0 || f->n > kMaxPrimitives) return fail(LF_ERR_INVALID_ARG, "field size %lld outside [0, 2^31)", (long long)f->n);
+  if (f->kind == LF_GAUSSIANS) {
+    if (f->n > 0 && !(f->means && f->log_scales && f->quats && f->opacity && f->rgb))
+      return fail(LF_ERR_INVALID_ARG, "a Gaussian attribute pointer is NULL");
+    return LF_OK;
+  }
+  if (f->kind == LF_VOXELS) return fail(LF_ERR_UNSUPPORTED, "voxel fields are not supported by this build");
+  return fail(LF_ERR_INVALID_ARG, "field kind %d is not GAUSSIANS/VOXELS", f->kind);
+}
+
+lf_status check_common(const lf_field* field, const lf_camera* cam, int32_t n_chunk, Geom* g) {
+  lf_status s = check_field(field);
+  if (s != LF_OK) return s;
+  if ((s = derive_geometry(cam, g)) != LF_OK) return s;
+  if (n_chunk < 1 || n_chunk > LF_MAX_CHUNKS)
+    return fail(LF_ERR_INVALID_ARG, "n_chunk %d outside [1, %d]", n_chunk, LF_MAX_CHUNKS);
+  return LF_OK;
+}
+
+}  // namespace
+}  // namespace lf
 
 using namespace lf;
 
-extern "C" lf_status lf_build_mpi_workspace(const lf_field*, const lf_camera*, int32_t, int64_t, size_t*) {
-  return fail(LF_ERR_UNSUPPORTED, "lf_build_mpi_workspace is not available yet");
+extern "C" lf_status lf_build_mpi_workspace(const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                                            int64_t entry_capacity, size_t* bytes) {
+  if (!bytes) return fail(LF_ERR_INVALID_ARG, "bytes is NULL");
+  Geom g;
+  lf_status s = check_common(field, cam, n_chunk, &g);
+  if (s != LF_OK) return s;
+  if (entry_capacity > kMaxEntries) return fail(LF_ERR_INVALID_ARG, "entry_capacity exceeds 2^31 - 1");
+  const int64_t cap = entry_capacity > 0 ? entry_capacity : default_capacity(field->n);
+  const size_t fixed = build_layout(field->n, n_chunk, g.wp, g.hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
+  *bytes = fixed + (size_t)cap * 16 + 4096;
+  return LF_OK;
 }
 
-extern "C" lf_status lf_build_mpi(lf_ctx*, const lf_field*, const lf_camera*, int32_t, int32_t, const float*,
-                                  lf_mpi*, void*, size_t, void*) {
-  return fail(LF_ERR_UNSUPPORTED, "lf_build_mpi is not available yet");
+extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                                  int32_t binning, const float* inv_depth_range, lf_mpi* mpi, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+  Geom g;
+  lf_status s = check_common(field, cam, n_chunk, &g);
+  if (s != LF_OK) return s;
+  if (binning != LF_BIN_QUANTILE && binning != LF_BIN_INV_DEPTH)
+    return fail(LF_ERR_INVALID_ARG, "binning %d is not QUANTILE/INV_DEPTH", binning);
+  float zlo = 0.f, zhi = 0.f;
+  if (binning == LF_BIN_INV_DEPTH) {
+    if (!inv_depth_range) return fail(LF_ERR_INVALID_ARG, "inv_depth_range is NULL");
+    zlo = inv_depth_range[0];
+    zhi = inv_depth_range[1];
+    if (!(std::isfinite(zlo) && std::isfinite(zhi) && zlo < zhi && (double)zlo > g.d_forward))
+      return fail(LF_ERR_INVALID_ARG, "inverse-depth range must satisfy D_forward < z_lo < z_hi < inf");
+  }
+  if (!mpi) return fail(LF_ERR_INVALID_ARG, "mpi is NULL");
+  if (mpi->dtype != LF_F32 && mpi->dtype != LF_F16 && mpi->dtype != LF_BF16)
+    return fail(LF_ERR_INVALID_ARG, "mpi dtype %d is not F32/F16/BF16", mpi->dtype);
+  if (mpi->n_chunk != n_chunk) return fail(LF_ERR_INVALID_ARG, "mpi n_chunk %d != %d", mpi->n_chunk, n_chunk);
+  if (mpi->width != g.wp || mpi->height != g.hp)
+    return fail(LF_ERR_INVALID_ARG, "mpi is %dx%d but the camera's planes are %dx%d", mpi->width, mpi->height, g.wp,
+                g.hp);
+  if (!mpi->rgba || !mpi->depth) return fail(LF_ERR_INVALID_ARG, "mpi rgba/depth is NULL");
+  if (!workspace) return fail(LF_ERR_INVALID_ARG, "workspace is NULL");
+  const int64_t n = field->n;
+  const int64_t cap = capacity_of(n, n_chunk, g.wp, g.hp, workspace_bytes);
+  if (cap < 1) {
+    size_t need = 0;
+    lf_build_mpi_workspace(field, cam, n_chunk, 0, &need);
+    return fail(LF_ERR_CAPACITY, "workspace of %zu bytes is too small; %zu bytes needed", workspace_bytes, need);
+  }
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+
+  const BuildLayout L = build_layout(n, n_chunk, g.wp, g.hp, cap);
+  char* w = static_cast<char*>(workspace);
+  BuildArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.capacity = cap;
+  a.K = n_chunk;
+  a.ntx = L.ntx;
+  a.binning = binning;
+  a.plane_dtype = mpi->dtype;
+  a.d_focal32 = cam->d_focal;
+  a.c = g.c;
+  a.means = field->means;
+  a.log_scales = field->log_scales;
+  a.quats = field->quats;
+  a.opacity = field->opacity;
+  a.rgb = field->rgb;
+  a.planes = mpi->rgba;
+  a.depth = mpi->depth;
+  a.chunk_of = mpi->chunk_of;
+  a.chunk_count = mpi->chunk_count;
+  a.hdr = reinterpret_cast<BuildHeader*>(w + L.o_hdr);
+  a.keys = reinterpret_cast<uint32_t*>(w + L.o_keys);
+  a.vals = reinterpret_cast<uint32_t*>(w + L.o_vals);
+  a.keys_alt = reinterpret_cast<uint32_t*>(w + L.o_keys_alt);
+  a.vals_alt = reinterpret_cast<uint32_t*>(w + L.o_vals_alt);
+  a.rec = reinterpret_cast<GRec*>(w + L.o_rec);
+  a.ntiles_i = reinterpret_cast<uint32_t*>(w + L.o_ntiles_i);
+  a.ntiles_r = reinterpret_cast<uint64_t*>(w + L.o_ntiles_r);
+  a.chunk_r = reinterpret_cast<uint32_t*>(w + L.o_chunk_r);
+  a.offsets = reinterpret_cast<uint64_t*>(w + L.o_offsets);
+  a.scan_tmp64 = reinterpret_cast<uint64_t*>(w + L.o_scan64);
+  a.chunk_start = reinterpret_cast<int64_t*>(w + L.o_chunk_start);
+  a.edges = reinterpret_cast<float*>(w + L.o_edges);
+  a.dtab = reinterpret_cast<float*>(w + L.o_dtab);
+  a.hist = reinterpret_cast<uint32_t*>(w + L.o_hist);
+  a.bucket = reinterpret_cast<uint32_t*>(w + L.o_bucket);
+  a.scan_tmp32 = reinterpret_cast<uint32_t*>(w + L.o_scan32);
+  a.radix_tmp = reinterpret_cast<uint32_t*>(w + L.o_radix);
+  a.ekeys = reinterpret_cast<uint32_t*>(w + L.o_ekeys);
+  a.evals = reinterpret_cast<uint32_t*>(w + L.o_evals);
+  a.ekeys_alt = reinterpret_cast<uint32_t*>(w + L.o_ekeys_alt);
+  a.evals_alt = reinterpret_cast<uint32_t*>(w + L.o_evals_alt);
+
+  if (binning == LF_BIN_INV_DEPTH) {
+    // K planes uniform in 1/z over [z_lo, z_hi]: interior edges E_i and plane depths at i = k + 1/2
+    std::vector<float> edges((size_t)n_chunk, 0.0f), dtab((size_t)n_chunk);
+    const double il = 1.0 / (double)zlo, ih = 1.0 / (double)zhi;
+    for (int i = 1; i < n_chunk; ++i) edges[i - 1] = (float)(1.0 / (il + ((double)i / n_chunk) * (ih - il)));
+    for (int k = 0; k < n_chunk; ++k) dtab[k] = (float)(1.0 / (il + (((double)k + 0.5) / n_chunk) * (ih - il)));
+    if ((e = upload_table(a.edges, edges.data(), n_chunk, st)) != hipSuccess) return hip_fail(e, "table upload");
+    if ((e = upload_table(a.dtab, dtab.data(), n_chunk, st)) != hipSuccess) return hip_fail(e, "table upload");
+  }
+  if ((e = build_gaussians(a, L, st)) != hipSuccess) return hip_fail(e, "build launch");
+  return LF_OK;
 }
 
-extern "C" lf_status lf_build_stats(lf_ctx*, const void*, size_t, lf_build_info*, void*) {
-  return fail(LF_ERR_UNSUPPORTED, "lf_build_stats is not available yet");
+extern "C" lf_status lf_build_stats(lf_ctx* ctx, const void* workspace, size_t workspace_bytes, lf_build_info* out,
+                                    void* stream) {
+  if (!out) return fail(LF_ERR_INVALID_ARG, "out is NULL");
+  if (!workspace || workspace_bytes < sizeof(BuildHeader)) return fail(LF_ERR_INVALID_ARG, "workspace is NULL or too small");
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  BuildHeader h;
+  if ((e = hipMemcpyAsync(&h, workspace, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream)) != hipSuccess)
+    return hip_fail(e, "hipMemcpyAsync");
+  if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  out->n_visible = h.n_vis;
+  out->entries_needed = h.entries;
+  out->entry_capacity = h.capacity;
+  out->overflow = h.overflow;
+  if (h.overflow)
+    return fail(LF_ERR_CAPACITY, "the last build needed %lld entries but the workspace holds %lld",
+                (long long)h.entries, (long long)h.capacity);
+  return LF_OK;
 }

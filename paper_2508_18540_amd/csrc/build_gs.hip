@@ -1,0 +1,413 @@
+// MPI build for 3D Gaussians (G2LF, Sec. 4.4; Alg. 1 steps 1-5) for gfx950.
+//
+//  preprocess  per Gaussian: float32 depth key and reference-frustum cull (exact op order,
+//              shared with the oracle's float32 decision program), double-float projected
+//              mean, float32 EWA covariance with the Eq. 8 dilation, conic in log2 units,
+//              support box {o G >= 1/255} and its tile rectangle
+//  sort        stable radix sort of (key, index): the (depth, index) order of Alg. 1
+//  rank        chunk of every rank (quantile: floor(r K / N_vis); inverse depth: edge count)
+//  chunks      chunk starts, counts and plane depths d_k (lower-median key)
+//  emit        one (tile, Gaussian) entry per covered tile, written in rank order, plus a
+//              (tile, chunk) histogram
+//  tile sort   stable radix sort of the entries by tile: each tile's list stays in rank
+//              order, so every (tile, chunk) bucket is a contiguous, depth-ordered run
+//  splat       one work-group per (tile, chunk): front-to-back blending of the bucket into
+//              premultiplied RGBA (C, 1 - T) with alpha = min(0.99, o G), only where
+//              o G >= 1/255, no early termination
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "build_internal.h"
+#include "dfloat.h"
+#include "sort_internal.h"
+
+namespace lf {
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLog2AlphaMin = -7.994353436858858f;   // log2(1/255)
+constexpr float kAlphaMax = 0.99f;
+
+__device__ __forceinline__ uint32_t orderable(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float unorderable(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void preprocess_gs(BuildArgs a) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i0 < a.n;
+  const int64_t i = in ? i0 : a.n - 1;
+  const Consts& c = a.c;
+  const float mx = a.means[3 * i], my = a.means[3 * i + 1], mz = a.means[3 * i + 2];
+  // base-camera coordinates, float32, fixed order: ((r0 x + r1 y) + r2 z) + t
+  const float xc = ((c.R[0] * mx + c.R[1] * my) + c.R[2] * mz) + c.t[0];
+  const float yc = ((c.R[3] * mx + c.R[4] * my) + c.R[5] * mz) + c.t[1];
+  const float key = (((c.R[6] * mx + c.R[7] * my) + c.R[8] * mz) + c.t[2]) + 0.0f;
+  const float zr = key - c.d_fwd;
+  const bool vis = in && isfinite(key) && isfinite(xc) && isfinite(yc) && zr > c.z_near &&
+                   fabsf(xc) <= c.guard_x * zr && fabsf(yc) <= c.guard_y * zr;
+  const uint64_t wv = __ballot(vis);
+  if ((threadIdx.x & 63) == 0 && wv)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.hdr->n_vis), (unsigned long long)__popcll(wv));
+  if (!in) return;
+  a.keys[i] = vis ? orderable(key) : 0xffffffffu;
+  a.vals[i] = (uint32_t)i;
+  a.ntiles_i[i] = 0;
+  if (a.chunk_of) a.chunk_of[i] = -1;
+  if (!vis) return;
+
+  // projected mean in double-float: p = R m + t, z = p_z - D_forward, mu = f' p / z + c'
+  df px = two_prod(c.R[0], mx), py = two_prod(c.R[3], mx), pz = two_prod(c.R[6], mx);
+  px = df_add(df_add(px, two_prod(c.R[1], my)), two_prod(c.R[2], mz));
+  py = df_add(df_add(py, two_prod(c.R[4], my)), two_prod(c.R[5], mz));
+  pz = df_add(df_add(pz, two_prod(c.R[7], my)), two_prod(c.R[8], mz));
+  px = df_add_f(px, c.t[0]);
+  py = df_add_f(py, c.t[1]);
+  pz = df_add_f(pz, c.t[2]);
+  const df z = df_add(pz, df{-c.d_fwd, -c.d_fwd_lo});
+  const df mux = df_add_f(df_mul(df_div(px, z), df{c.fpx, c.fpx_lo}), c.cpx);
+  const df muy = df_add_f(df_mul(df_div(py, z), df{c.fpy, c.fpy_lo}), c.cpy);
+
+  // world covariance R(q) diag(e^{2l}) R(q)^T, camera rotation, EWA Jacobian (float32)
+  float qw = a.quats[4 * i], qx = a.quats[4 * i + 1], qy = a.quats[4 * i + 2], qz = a.quats[4 * i + 3];
+  const float qn = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+  const float Rg[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                       2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                       2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+  const float s0 = expf(a.log_scales[3 * i]), s1 = expf(a.log_scales[3 * i + 1]), s2 = expf(a.log_scales[3 * i + 2]);
+  // M = W Rg diag(s): columns are the scaled principal axes in camera space
+  float M[9];
+  for (int r = 0; r < 3; ++r) {
+    const float w0 = c.R[3 * r], w1 = c.R[3 * r + 1], w2 = c.R[3 * r + 2];
+    M[3 * r + 0] = (w0 * Rg[0] + w1 * Rg[3] + w2 * Rg[6]) * s0;
+    M[3 * r + 1] = (w0 * Rg[1] + w1 * Rg[4] + w2 * Rg[7]) * s1;
+    M[3 * r + 2] = (w0 * Rg[2] + w1 * Rg[5] + w2 * Rg[8]) * s2;
+  }
+  const float zf = z.hi;
+  const float iz = 1.0f / zf;
+  const float j00 = c.fpx * iz, j02 = -c.fpx * px.hi * iz * iz;
+  const float j11 = c.fpy * iz, j12 = -c.fpy * py.hi * iz * iz;
+  // rows of J M (2x3); Sigma' = (J M)(J M)^T + f' I
+  float u[3], v[3];
+  for (int k = 0; k < 3; ++k) {
+    u[k] = j00 * M[k] + j02 * M[6 + k];
+    v[k] = j11 * M[3 + k] + j12 * M[6 + k];
+  }
+  const float sa = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + c.f_dil;
+  const float sb = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+  const float sc = (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) + c.f_dil;
+  // determinant a c - b^2 with Kahan's compensated product difference, clamped at f'^2
+  const float bb = sb * sb;
+  const float det_raw = fmaf(sa, sc, -bb) + fmaf(-sb, sb, bb);
+  const float det = fmaxf(det_raw, fmaxf(c.f_dil * c.f_dil, 1e-10f));
+  const float idet = 1.0f / det;
+  const float o = a.opacity[i];
+
+  GRec r;
+  r.mx_hi = mux.hi;
+  r.my_hi = muy.hi;
+  r.mx_lo = mux.lo;
+  r.my_lo = muy.lo;
+  // log2 of o G(d) = l2o + ca dx^2 + cb dx dy + cc dy^2
+  r.ca = -0.5f * kLog2e * sc * idet;
+  r.cb = kLog2e * sb * idet;
+  r.cc = -0.5f * kLog2e * sa * idet;
+  r.l2o = log2f(o);
+  r.rgb[0] = a.rgb[3 * i];
+  r.rgb[1] = a.rgb[3 * i + 1];
+  r.rgb[2] = a.rgb[3 * i + 2];
+  r.pad = 0.0f;
+  r.x0 = r.y0 = 0;
+  r.x1 = r.y1 = -1;
+  // support box of {q <= 2 ln(255 o)}, widened by a 1e-3 relative margin
+  const float r2 = 2.0f * (5.541263545158426f + logf(o));
+  uint32_t nt = 0;
+  if (r2 >= 0.0f) {
+    const float hx = sqrtf(r2 * sa) * 1.001f + 1e-3f;
+    const float hy = sqrtf(r2 * sc) * 1.001f + 1e-3f;
+    const float fx0 = fmaxf(ceilf(mux.hi - hx), 0.0f), fx1 = fminf(floorf(mux.hi + hx), (float)(c.wp - 1));
+    const float fy0 = fmaxf(ceilf(muy.hi - hy), 0.0f), fy1 = fminf(floorf(muy.hi + hy), (float)(c.hp - 1));
+    if (fx0 <= fx1 && fy0 <= fy1) {
+      r.x0 = (int)fx0;
+      r.x1 = (int)fx1;
+      r.y0 = (int)fy0;
+      r.y1 = (int)fy1;
+      nt = (uint32_t)(((r.x1 >> kTileShift) - (r.x0 >> kTileShift) + 1) *
+                      ((r.y1 >> kTileShift) - (r.y0 >> kTileShift) + 1));
+    }
+  }
+  a.rec[i] = r;
+  a.ntiles_i[i] = nt;
+}
+
+// chunk of a visible key under inverse-depth binning: number of interior edges <= key
+__device__ __forceinline__ int edge_count(const float* edges, int ne, float key) {
+  int lo = 0, hi = ne;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (edges[mid] <= key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void rank_pass(BuildArgs a, const uint32_t* skeys, const uint32_t* svals) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n) return;
+  const int64_t nvis = a.hdr->n_vis;
+  if (r >= nvis) {
+    a.ntiles_r[r] = 0;
+    return;
+  }
+  const uint32_t idx = svals[r];
+  int chunk;
+  if (a.binning == LF_BIN_QUANTILE) chunk = (int)((r * (int64_t)a.K) / nvis);
+  else chunk = edge_count(a.edges, a.K - 1, unorderable(skeys[r]));
+  a.chunk_r[r] = (uint32_t)chunk;
+  if (a.chunk_of) a.chunk_of[idx] = chunk;
+  a.ntiles_r[r] = a.ntiles_i[idx];
+}
+
+// chunk_start[k] for k in [0, K]: first rank whose chunk is >= k
+__global__ void chunk_starts(BuildArgs a, const uint32_t* skeys) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > a.K) return;
+  const int64_t nvis = a.hdr->n_vis;
+  int64_t s;
+  if (k == 0) s = 0;
+  else if (k == a.K) s = nvis;
+  else if (a.binning == LF_BIN_QUANTILE) s = ((int64_t)k * nvis + a.K - 1) / a.K;
+  else {
+    const float e = a.edges[k - 1];
+    int64_t lo = 0, hi = nvis;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (unorderable(skeys[mid]) < e) lo = mid + 1;
+      else hi = mid;
+    }
+    s = lo;
+  }
+  a.chunk_start[k] = s;
+}
+
+__global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.K) return;
+  const int64_t s = a.chunk_start[k], cnt = a.chunk_start[k + 1] - s;
+  if (a.chunk_count) a.chunk_count[k] = (int32_t)cnt;
+  float d;
+  if (a.binning == LF_BIN_INV_DEPTH) {
+    d = a.dtab[k];
+  } else if (cnt > 0) {
+    d = unorderable(skeys[s + (cnt - 1) / 2]);               // lower median of the chunk
+  } else if (s > 0) {
+    // empty chunk: the depth of the previous non-empty chunk, the one holding rank s - 1
+    const int64_t nvis = a.hdr->n_vis;
+    const int kp = (int)(((s - 1) * a.K) / nvis);
+    const int64_t sp = a.chunk_start[kp], cp = a.chunk_start[kp + 1] - sp;
+    d = unorderable(skeys[sp + (cp - 1) / 2]);
+  } else {
+    d = a.d_focal32;
+  }
+  a.depth[k] = d;
+}
+
+__global__ __launch_bounds__(256) void emit_entries(BuildArgs a, const uint32_t* svals) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n || r >= a.hdr->n_vis) return;
+  const uint64_t base = a.offsets[r];
+  const uint64_t nt = a.ntiles_r[r];
+  if (nt == 0) return;
+  if (base + nt > (uint64_t)a.capacity) {
+    atomicOr(&a.hdr->overflow, 1);
+    return;
+  }
+  const uint32_t idx = svals[r];
+  const GRec& g = a.rec[idx];
+  const int chunk = (int)a.chunk_r[r];
+  const int tx0 = g.x0 >> kTileShift, tx1 = g.x1 >> kTileShift;
+  const int ty0 = g.y0 >> kTileShift, ty1 = g.y1 >> kTileShift;
+  uint64_t o = base;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const uint32_t tile = (uint32_t)(ty * a.ntx + tx);
+      a.ekeys[o] = tile;
+      a.evals[o] = idx;
+      atomicAdd(&a.hist[(int64_t)tile * a.K + chunk], 1u);
+      ++o;
+    }
+}
+
+__global__ void finalize(BuildArgs a) {
+  a.hdr->entries = (int64_t)a.offsets[a.n];
+  a.hdr->capacity = a.capacity;
+}
+
+// ---------------------------------------------------------------------------------------
+// Splat: one work-group per (tile, chunk).  Wave w of the 256 threads owns the 8x8 texel
+// block at ((w & 1) * 8, (w >> 1) * 8) of the 16x16 tile and skips Gaussians whose support
+// box misses that block.
+// ---------------------------------------------------------------------------------------
+struct LRec {
+  float mrx, mry, ca, cb, cc, l2o, r, g, b;
+  int x0, x1, y0, y1;
+};
+
+template <typename T>
+__device__ __forceinline__ void store_rgba(T* p, size_t i, float r, float g, float b, float al);
+
+template <>
+__device__ __forceinline__ void store_rgba<float>(float* p, size_t i, float r, float g, float b, float al) {
+  reinterpret_cast<float4*>(p)[i] = make_float4(r, g, b, al);
+}
+
+template <>
+__device__ __forceinline__ void store_rgba<__half>(__half* p, size_t i, float r, float g, float b, float al) {
+  const __half2 lo = __floats2half2_rn(r, g), hi = __floats2half2_rn(b, al);
+  uint2 u;
+  u.x = *reinterpret_cast<const uint32_t*>(&lo);
+  u.y = *reinterpret_cast<const uint32_t*>(&hi);
+  reinterpret_cast<uint2*>(p)[i] = u;
+}
+
+__device__ __forceinline__ uint32_t bf16_rn(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+template <>
+__device__ __forceinline__ void store_rgba<__hip_bfloat16>(__hip_bfloat16* p, size_t i, float r, float g, float b,
+                                                           float al) {
+  uint2 u;
+  u.x = bf16_rn(r) | (bf16_rn(g) << 16);
+  u.y = bf16_rn(b) | (bf16_rn(al) << 16);
+  reinterpret_cast<uint2*>(p)[i] = u;
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void splat_gs(BuildArgs a) {
+  __shared__ LRec recs[256];
+  const int tile = blockIdx.x, k = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
+  const int bx = ox + ((wave & 1) << 3), by = oy + ((wave >> 1) << 3);
+  const int px = bx + (lane & 7), py = by + (lane >> 3);
+  const float lx = (float)(px - ox), ly = (float)(py - oy);
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+  const bool ok = a.hdr->overflow == 0;
+  const int64_t bidx = (int64_t)tile * a.K + k;
+  const uint32_t b0 = ok ? a.bucket[bidx] : 0u, b1 = ok ? a.bucket[bidx + 1] : 0u;
+  for (uint32_t base = b0; base < b1; base += 256) {
+    const uint32_t n = min(256u, b1 - base);
+    if (tid < (int)n) {
+      uint32_t idx = a.evals[base + tid];
+      if (idx >= (uint32_t)a.n) idx = 0;
+      const GRec& g = a.rec[idx];
+      LRec l;
+      l.mrx = (g.mx_hi - (float)ox) + g.mx_lo;
+      l.mry = (g.my_hi - (float)oy) + g.my_lo;
+      l.ca = g.ca;
+      l.cb = g.cb;
+      l.cc = g.cc;
+      l.l2o = g.l2o;
+      l.r = g.rgb[0];
+      l.g = g.rgb[1];
+      l.b = g.rgb[2];
+      l.x0 = g.x0;
+      l.x1 = g.x1;
+      l.y0 = g.y0;
+      l.y1 = g.y1;
+      recs[tid] = l;
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < n; ++j) {
+      const LRec& l = recs[j];
+      if (l.x1 < bx || l.x0 > bx + 7 || l.y1 < by || l.y0 > by + 7) continue;   // uniform per wave
+      const float dx = lx - l.mrx, dy = ly - l.mry;
+      const float e = fmaf(l.ca * dx, dx, fmaf(l.cc * dy, dy, fmaf(l.cb * dx, dy, l.l2o)));
+      if (e >= kLog2AlphaMin) {
+        const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
+        const float w = alpha * T;
+        C0 = fmaf(w, l.r, C0);
+        C1 = fmaf(w, l.g, C1);
+        C2 = fmaf(w, l.b, C2);
+        T = T - w;
+      }
+    }
+    __syncthreads();
+  }
+  if (px < a.c.wp && py < a.c.hp)
+    store_rgba(static_cast<PT*>(a.planes), ((size_t)k * a.c.hp + py) * a.c.wp + px, C0, C1, C2, 1.0f - T);
+}
+
+__global__ void write_table(float* dst, TableChunk t) {
+  const int i = threadIdx.x;
+  if (i < t.count) dst[t.offset + i] = t.v[i];
+}
+
+}  // namespace
+
+hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s) {
+  for (int off = 0; off < n; off += kTableChunk) {
+    TableChunk t;
+    t.offset = off;
+    t.count = n - off < kTableChunk ? n - off : kTableChunk;
+    for (int i = 0; i < t.count; ++i) t.v[i] = host[off + i];
+    hipLaunchKernelGGL(write_table, dim3(1), dim3(kTableChunk), 0, s, dst, t);
+  }
+  return hipGetLastError();
+}
+
+hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s) {
+  hipError_t e;
+  const unsigned gN = (unsigned)((a.n + 255) / 256);
+  // zero the header and the (tile, chunk) histogram
+  if ((e = fill(reinterpret_cast<uint32_t*>(a.hdr), sizeof(BuildHeader) / 4, 0u, s)) != hipSuccess) return e;
+  if ((e = fill(a.hist, L.n_buckets + 1, 0u, s)) != hipSuccess) return e;
+  if (a.n == 0) {
+    // nothing to rasterise: transparent planes at D_focal (or the inverse-depth table)
+    const size_t words = (size_t)a.K * a.c.hp * a.c.wp * (a.plane_dtype == LF_F32 ? 4 : 2);
+    if ((e = fill(reinterpret_cast<uint32_t*>(a.planes), (int64_t)words, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, a.keys);
+    hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, a.keys);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(preprocess_gs, dim3(gN), dim3(256), 0, s, a);
+  // (key, index) order
+  int alt = 0;
+  if ((e = radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.n, nullptr, 32, a.radix_tmp, &alt, s)) !=
+      hipSuccess)
+    return e;
+  const uint32_t* skeys = alt ? a.keys_alt : a.keys;
+  const uint32_t* svals = alt ? a.vals_alt : a.vals;
+  hipLaunchKernelGGL(rank_pass, dim3(gN), dim3(256), 0, s, a, skeys, svals);
+  hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, skeys);
+  hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, skeys);
+  if ((e = exclusive_scan<uint64_t>(a.ntiles_r, a.offsets, a.n, a.scan_tmp64, s)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(emit_entries, dim3(gN), dim3(256), 0, s, a, svals);
+  hipLaunchKernelGGL(finalize, dim3(1), dim3(1), 0, s, a);
+  // stable sort of the entries by tile (entries beyond the capacity are never read)
+  int ealt = 0;
+  if ((e = radix_sort_pairs(a.ekeys, a.evals, a.ekeys_alt, a.evals_alt, a.capacity,
+                            reinterpret_cast<const int64_t*>(&a.hdr->entries), L.tile_bits, a.radix_tmp, &ealt,
+                            s)) != hipSuccess)
+    return e;
+  if (ealt) a.evals = a.evals_alt;
+  if ((e = exclusive_scan<uint32_t>(a.hist, a.bucket, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
+  const dim3 grid(L.n_tiles, a.K);
+  switch (a.plane_dtype) {
+    case LF_F16: hipLaunchKernelGGL((splat_gs<__half>), grid, dim3(256), 0, s, a); break;
+    case LF_BF16: hipLaunchKernelGGL((splat_gs<__hip_bfloat16>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((splat_gs<float>), grid, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lf

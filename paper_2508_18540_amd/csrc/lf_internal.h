@@ -7,6 +7,11 @@
 
 #include "lf.h"
 
+// Library context: the device it was created on.
+struct lf_ctx {
+  int device;
+};
+
 namespace lf {
 
 // Float32 constants of the decision programs and of the projection.  The host derives

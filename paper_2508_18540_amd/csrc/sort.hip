@@ -1,0 +1,241 @@
+// Device-wide primitives of the MPI build: exclusive scans, a stable LSD radix sort of
+// (u32 key, u32 value) pairs, and a fill kernel.  Every launch has a host-fixed grid; data
+// dependent lengths are read from device memory, so nothing here waits on the host.
+#include "sort_internal.h"
+
+namespace lf {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kScanThreads * kScanItems;   // elements per scan block
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* sh, T* total) {
+  // Hillis-Steele inclusive scan over kScanThreads values in LDS.
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    T add = tid >= off ? sh[tid - off] : T(0);
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  const T incl = sh[tid];
+  *total = sh[kScanThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_reduce(const T* in, int64_t n, T* block_sums) {
+  __shared__ T sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  T s = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t e = base + (int64_t)i * kScanThreads + threadIdx.x;
+    if (e < n) s += in[e];
+  }
+  T total;
+  block_exclusive_scan<T>(s, sh, &total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// One block scans the block sums (nb <= kScanChunk) in place; writes the grand total too.
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_top(T* block_sums, int nb, T* total_out) {
+  __shared__ T sh[kScanThreads];
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int b0 = threadIdx.x * per;
+  T s = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) s += block_sums[b0 + i];
+  T total;
+  T run = block_exclusive_scan<T>(s, sh, &total);
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) {
+      const T v = block_sums[b0 + i];
+      block_sums[b0 + i] = run;
+      run += v;
+    }
+  if (threadIdx.x == 0 && total_out) *total_out = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_down(const T* in, T* out, int64_t n, const T* block_sums) {
+  __shared__ T sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  T v[kScanItems];
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? in[base + i] : T(0);
+    s += v[i];
+  }
+  T total;
+  T run = block_exclusive_scan<T>(s, sh, &total) + block_sums[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+}
+
+template <typename T>
+__global__ void scan_write_total(T* out, int64_t n, const T* total) { out[n] = *total; }
+
+// ---------------------------------------------------------------------------------------
+// Radix sort.  P blocks; block b sorts the elements [b*span, min(n, (b+1)*span)) where
+// span = ceil(n / (P*256)) * 256 and n is read from device memory.
+// ---------------------------------------------------------------------------------------
+constexpr int kRadixThreads = 256;
+constexpr int kWaves = kRadixThreads / 64;
+
+__device__ __forceinline__ int64_t sort_len(const int64_t* n_dev, int64_t n_host, int64_t cap) {
+  int64_t n = n_dev ? *n_dev : n_host;
+  return n < cap ? n : cap;
+}
+
+__device__ __forceinline__ int64_t block_span(int64_t n) {
+  const int64_t per = (n + (int64_t)gridDim.x * kRadixThreads - 1) / ((int64_t)gridDim.x * kRadixThreads);
+  return per * kRadixThreads;
+}
+
+__global__ __launch_bounds__(kRadixThreads) void radix_upsweep(const uint32_t* keys, const int64_t* n_dev,
+                                                               int64_t n_host, int64_t cap, int shift,
+                                                               uint32_t* counts) {
+  __shared__ uint32_t hist[256];
+  const int64_t n = sort_len(n_dev, n_host, cap);
+  const int64_t span = block_span(n);
+  const int64_t b0 = (int64_t)blockIdx.x * span;
+  const int64_t b1 = min(n, b0 + span);
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t e = b0 + threadIdx.x; e < b1; e += kRadixThreads) atomicAdd(&hist[(keys[e] >> shift) & 255u], 1u);
+  __syncthreads();
+  counts[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRadixThreads) void radix_downsweep(const uint32_t* keys_in, const uint32_t* vals_in,
+                                                                 uint32_t* keys_out, uint32_t* vals_out,
+                                                                 const int64_t* n_dev, int64_t n_host, int64_t cap,
+                                                                 int shift, const uint32_t* offsets) {
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t wcount[kWaves][256];
+  const int64_t n = sort_len(n_dev, n_host, cap);
+  const int64_t span = block_span(n);
+  const int64_t b0 = (int64_t)blockIdx.x * span;
+  const int64_t b1 = min(n, b0 + span);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  running[tid] = offsets[(int64_t)tid * gridDim.x + blockIdx.x];
+  for (int w = 0; w < kWaves; ++w) wcount[w][tid] = 0;
+  __syncthreads();
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int64_t r0 = b0; r0 < b1; r0 += kRadixThreads) {
+    const int64_t e = r0 + tid;
+    const bool valid = e < b1;
+    uint32_t key = 0, val = 0, d = 0;
+    if (valid) {
+      key = keys_in[e];
+      val = vals_in[e];
+      d = (key >> shift) & 255u;
+    }
+    // lanes of this wave holding the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = __popcll(peers & lt);
+    if (valid && rank == 0) wcount[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = running[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcount[w][d];
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      add += wcount[w][tid];
+      wcount[w][tid] = 0;
+    }
+    running[tid] += add;
+    __syncthreads();
+  }
+}
+
+__global__ void fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1; }
+
+template <typename T>
+hipError_t exclusive_scan(const T* in, T* out, int64_t n, T* tmp, hipStream_t s) {
+  // out[0..n) = exclusive prefix sums, out[n] = total.  tmp holds scan_tmp_elems(n) values.
+  const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
+  if (nb == 0) {
+    hipLaunchKernelGGL(fill_u32, dim3(1), dim3(1), 0, s, reinterpret_cast<uint32_t*>(out), (int64_t)(sizeof(T) / 4), 0u);
+    return hipGetLastError();
+  }
+  if (nb > kScanChunk) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((scan_reduce<T>), dim3(nb), dim3(kScanThreads), 0, s, in, n, tmp);
+  hipLaunchKernelGGL((scan_top<T>), dim3(1), dim3(kScanThreads), 0, s, tmp, nb, tmp + nb);
+  hipLaunchKernelGGL((scan_down<T>), dim3(nb), dim3(kScanThreads), 0, s, in, out, n, tmp);
+  hipLaunchKernelGGL((scan_write_total<T>), dim3(1), dim3(1), 0, s, out, n, tmp + nb);
+  return hipGetLastError();
+}
+
+template hipError_t exclusive_scan<uint32_t>(const uint32_t*, uint32_t*, int64_t, uint32_t*, hipStream_t);
+template hipError_t exclusive_scan<uint64_t>(const uint64_t*, uint64_t*, int64_t, uint64_t*, hipStream_t);
+
+int radix_blocks(int64_t cap) {
+  const int64_t b = (cap + 4095) / 4096;
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+size_t radix_tmp_u32(int64_t cap) {
+  const int64_t nc = 256LL * radix_blocks(cap);
+  return (size_t)(2 * nc + scan_tmp_elems(nc) + 1);
+}
+
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t cap,
+                            const int64_t* n_dev, int bits, uint32_t* tmp, int* result_in_alt, hipStream_t s) {
+  const int P = radix_blocks(cap);
+  const int64_t nc = 256LL * P;
+  uint32_t* counts = tmp;
+  uint32_t* offs = tmp + nc;
+  uint32_t* stmp = tmp + 2 * nc;
+  uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+  int passes = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(radix_upsweep, dim3(P), dim3(kRadixThreads), 0, s, ki, n_dev, cap, cap, shift, counts);
+    hipError_t e = exclusive_scan<uint32_t>(counts, offs, nc, stmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_downsweep, dim3(P), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, n_dev, cap, cap, shift,
+                       offs);
+    uint32_t* t = ki; ki = ko; ko = t;
+    t = vi; vi = vo; vo = t;
+    ++passes;
+  }
+  *result_in_alt = passes & 1;
+  return hipGetLastError();
+}
+
+hipError_t fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace lf

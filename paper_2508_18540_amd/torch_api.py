@@ -86,3 +86,84 @@ def plane_coeffs(ctx: Context, rgba: torch.Tensor, depth: torch.Tensor, cam, vie
     L.lf_plane_coeffs(ctx.handle, m, L.make_camera(cam), views, bx.data_ptr(), by.data_ptr(),
                       *[t.data_ptr() for t in cs], stream=_stream(rgba))
     return (bx, by, *cs)
+
+
+_BIN = {"quantile": L.LF_BIN_QUANTILE, "inv_depth": L.LF_BIN_INV_DEPTH}
+GAUSSIAN_KEYS = ("means", "log_scales", "quats", "opacity", "rgb")
+
+
+def field_of(scene: dict) -> L.lf_field:
+    """An lf_field over CUDA float32 tensors: Gaussians (means, log_scales, quats, opacity, rgb)."""
+    f = L.lf_field()
+    if "means" in scene:
+        f.kind = L.LF_GAUSSIANS
+        for k in GAUSSIAN_KEYS:
+            _need(scene[k], k, (torch.float32,))
+        f.n = scene["means"].shape[0]
+        f.means, f.log_scales, f.quats, f.opacity, f.rgb = (scene[k].data_ptr() for k in GAUSSIAN_KEYS)
+    else:
+        f.kind = L.LF_VOXELS
+        _need(scene["ijk"], "ijk", (torch.int32,))
+        _need(scene["density"], "density", (torch.float32,))
+        _need(scene["rgb"], "rgb", (torch.float32,))
+        f.n = scene["ijk"].shape[0]
+        f.ijk, f.density, f.rgb = scene["ijk"].data_ptr(), scene["density"].data_ptr(), scene["rgb"].data_ptr()
+        f.origin[:] = [float(v) for v in scene["origin"]]
+        f.voxel_size = float(scene["voxel_size"])
+    return f
+
+
+def to_device(scene: dict, device="cuda") -> dict:
+    """Copy a scenegen scene (numpy) to CUDA tensors; scalars are kept as they are."""
+    out = {}
+    for k, v in scene.items():
+        out[k] = torch.from_numpy(v).to(device) if hasattr(v, "dtype") and getattr(v, "ndim", 0) > 0 else v
+    return out
+
+
+class Workspace:
+    """A device workspace for lf_build_mpi (a uint8 torch tensor)."""
+
+    def __init__(self, nbytes: int, device):
+        self.tensor = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self):
+        return self.tensor.data_ptr()
+
+    @property
+    def nbytes(self):
+        return self.tensor.numel()
+
+
+def workspace_for(scene: dict, cam, n_chunk: int, entry_capacity: int = 0, device="cuda") -> Workspace:
+    n = L.lf_build_mpi_workspace(field_of(scene), L.make_camera(cam), n_chunk, entry_capacity)
+    return Workspace(n, device)
+
+
+def build_mpi(ctx: Context, scene: dict, cam, n_chunk: int, binning: str = "quantile", inv_depth_range=None,
+              dtype=torch.float32, workspace: Workspace | None = None, out: dict | None = None) -> dict:
+    """lf_build_mpi: returns dict(rgba [K,H,W,4], depth [K], chunk_of [N], chunk_count [K], workspace)."""
+    f = field_of(scene)
+    c = L.make_camera(cam)
+    info = L.lf_geometry(c)
+    dev = ctx.device
+    if workspace is None:
+        workspace = workspace_for(scene, cam, n_chunk, device=dev)
+    if out is None:
+        out = dict(rgba=torch.empty((n_chunk, info.plane_height, info.plane_width, 4), dtype=dtype, device=dev),
+                   depth=torch.empty(n_chunk, dtype=torch.float32, device=dev),
+                   chunk_of=torch.empty(max(f.n, 1), dtype=torch.int32, device=dev),
+                   chunk_count=torch.empty(n_chunk, dtype=torch.int32, device=dev))
+    m = mpi_of(out["rgba"], out["depth"], out.get("chunk_of"), out.get("chunk_count"))
+    L.lf_build_mpi(ctx.handle, f, c, n_chunk, _BIN[binning], inv_depth_range, m, workspace.ptr, workspace.nbytes,
+                   torch.cuda.current_stream(dev).cuda_stream)
+    out["workspace"] = workspace
+    return out
+
+
+def build_stats(ctx: Context, workspace: Workspace, check: bool = True):
+    """lf_build_stats (synchronises the current stream)."""
+    info, status = L.lf_build_stats(ctx.handle, workspace.ptr, workspace.nbytes,
+                                    torch.cuda.current_stream(ctx.device).cuda_stream, check=check)
+    return info, status

@@ -1,0 +1,210 @@
+"""GPU parity of the Gaussian MPI build (lf_build_mpi; Sec. 4.4, Alg. 1 steps 1-5) and of
+the whole frame (build + composite) against the FP64 oracle.
+
+Chunk indices, chunk counts and plane depths must match bit for bit.  Plane texels and
+composited pixels must match to 1e-4 except where the oracle flags the 1/255 inclusion
+threshold as ambiguous (both outcomes correct); those must stay within the jump one
+threshold Gaussian can cause."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from oracle import composite, geometry, partition, project, render, splat
+from paper_2508_18540_amd import _lib as L
+from paper_2508_18540_amd import torch_api as T
+from tests.gpu_util import announce, ctx, host, psnr
+
+pytestmark = pytest.mark.gpu
+
+TDT = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+
+
+def _gpu_build(scene, cam, K, binning="quantile", rng=None, dtype=torch.float32, cap=0):
+    ds = T.to_device(scene)
+    ws = T.workspace_for(ds, cam, K, entry_capacity=cap)
+    out = T.build_mpi(ctx(), ds, cam, K, binning, rng, dtype=dtype, workspace=ws)
+    info, st = T.build_stats(ctx(), ws, check=False)
+    return out, info, st
+
+
+def _check_partition(out, part, n):
+    torch.cuda.synchronize()
+    co = out["chunk_of"].cpu().numpy()[:n]
+    assert np.array_equal(co, part.chunk_of)
+    assert np.array_equal(out["chunk_count"].cpu().numpy(), part.chunk_count)
+    assert np.array_equal(out["depth"].cpu().numpy().view(np.uint32), part.depth.view(np.uint32))
+
+
+def _rotated_camera():
+    from oracle.project import quat_to_rot
+    R = quat_to_rot(np.array([[0.97, 0.1, -0.2, 0.05]]))[0]
+    return scenegen.camera(160, 120, 50.0, 3.0, math.radians(25.0), R=R, t=(0.1, -0.05, 0.2))
+
+
+PART_CASES = [
+    ("uniform10k_invdepth", lambda: (scenegen.uniform_scene(10_000, 0), scenegen.config_camera("uniform10k")[0], 16,
+                                     "inv_depth", (2.0, 6.0))),
+    ("cluster50k_q64", lambda: (scenegen.cluster_scene(50_000, seed=3), scenegen.camera(256, 256, 50.0, 2.0, math.radians(40)),
+                                64, "quantile", None)),
+    ("fewer_than_chunks", lambda: (scenegen.small_scene(5, 1), scenegen.camera(64, 64, 50.0, 2.0, math.radians(20)), 16,
+                                   "quantile", None)),
+    ("rotated_camera", lambda: (scenegen.small_scene(3000, 2, xy=2.0, z=(-1.0, 6.0)), _rotated_camera(), 24, "quantile",
+                                None)),
+]
+
+
+@pytest.mark.parametrize("case", PART_CASES, ids=[c[0] for c in PART_CASES])
+def test_partition_bit_exact(case):
+    name, make = case
+    scene, cam, K, binning, rng = make()
+    if name == "rotated_camera":
+        m = scene["means"]
+        m[10:20, 2] = m[20:30, 2]            # duplicate keys (ties by index)
+        m[30] = [np.nan, 0.0, 3.0]
+        m[31] = [0.0, 0.0, np.inf]
+    announce("partition", name)
+    out, info, st = _gpu_build(scene, cam, K, binning, rng)
+    assert st == L.LF_OK
+    g = geometry.derive(cam)
+    part = partition.partition(scene["means"], cam, g, K, binning, rng)
+    assert info.n_visible == part.order.size
+    _check_partition(out, part, scene["means"].shape[0])
+
+
+def _masked_compare(got, ref, amb, tol, jump):
+    err = np.abs(got - ref).max(axis=-1)
+    bad = (err > tol) & ~amb
+    assert not bad.any(), f"{bad.sum()} unmasked texels above {tol}: max {err[~amb].max()}"
+    if amb.any():
+        assert err[amb].max() <= jump, err[amb].max()
+    return float(err[~amb].max()), float(amb.mean())
+
+
+@pytest.mark.parametrize("pdt", ["f32", "f16", "bf16"])
+def test_planes_uniform10k(pdt):
+    """All 16 planes of the 10k-Gaussian inverse-depth workload at 128^2."""
+    announce("planes uniform10k", pdt)
+    scene, cam, cfg = scenegen.config("uniform10k")
+    out, info, st = _gpu_build(scene, cam, 16, "inv_depth", (2.0, 6.0), dtype=TDT[pdt])
+    assert st == L.LF_OK
+    mpi = render.build_mpi_gaussians(scene, cam, 16, "inv_depth", (2.0, 6.0))
+    _check_partition(out, mpi.part, 10_000)
+    got = host(out["rgba"])
+    if pdt == "f32":
+        e, frac = _masked_compare(got, mpi.planes, mpi.ambiguous, 1e-4, 0.02)
+        print("unmasked max-abs", e, "ambiguous texel fraction", frac)
+    else:
+        tol = 2e-3 if pdt == "f16" else 4e-3      # one rounding of a value <= 1: 2^-11 / 2^-9
+        e, frac = _masked_compare(got, mpi.planes, mpi.ambiguous, tol, 0.02)
+        print(pdt, "unmasked max-abs", e)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+def test_frame_uniform10k(interp):
+    """Build + composite of the 9-view light field (plain method, FP32)."""
+    announce("frame uniform10k", interp)
+    scene, cam, cfg = scenegen.config("uniform10k")
+    out, info, st = _gpu_build(scene, cam, 16, "inv_depth", (2.0, 6.0))
+    dx, dy, _, _ = geometry.quilt_views(cam, 9, 1)
+    dx, dy = dx.astype(np.float32), dy.astype(np.float32)
+    views = T.composite(ctx(), out["rgba"], out["depth"], cam, T.views_of(dx, dy), interp)
+    mpi = render.build_mpi_gaussians(scene, cam, 16, "inv_depth", (2.0, 6.0))
+    ref, amb = composite.composite(mpi.planes, mpi.depth, cam, mpi.geom, dx, dy, interp, mpi.ambiguous)
+    e, frac = _masked_compare(host(views), ref, amb, 1e-4, 0.03)
+    print("frame unmasked max-abs", e, "ambiguous pixel fraction", frac)
+    assert frac < 0.01
+
+
+def test_zero_baseline_identity_on_gpu():
+    """phi = 0: every composited view equals the oracle's conventional render (any N_chunk)."""
+    announce("zero baseline")
+    cam = scenegen.camera(96, 96, 50.0, 2.0, 0.0)
+    scene = scenegen.small_scene(400, 9)
+    for K in (1, 4):
+        out, info, st = _gpu_build(scene, cam, K)
+        v = T.composite(ctx(), out["rgba"], out["depth"], cam, T.views_of([0.0, 0.0]), "nearest")
+        mpi = render.build_mpi_gaussians(scene, cam, K)
+        ref, amb = render.render_view(scene, cam, 0.0, 0.0, visible=mpi.part.visible)
+        ref = np.concatenate([ref[..., :3], 1.0 - ref[..., 3:]], axis=-1)
+        got = host(v)
+        for j in range(2):
+            _masked_compare(got[j], ref, amb, 1e-4, 0.03)
+
+
+class _OracleTexels:
+    """Oracle plane texels on demand for a big scene (chunk projections cached)."""
+
+    def __init__(self, scene, cam, K, binning="quantile", rng=None):
+        self.g = geometry.derive(cam)
+        self.part = partition.partition(scene["means"], cam, self.g, K, binning, rng)
+        self.scene, self.cam, self.cache = scene, cam, {}
+
+    def proj(self, k):
+        if k not in self.cache:
+            self.cache[k] = render.chunk_projection(self.scene, self.cam, self.g, self.part, k)
+        return self.cache[k]
+
+    def __call__(self, k, iy, ix):
+        return splat.blend_texels(self.proj(k), ix, iy)
+
+
+@pytest.mark.parametrize("pdt", ["f32", "f16"])
+def test_cluster500k_full_size(pdt):
+    """The headline workload: 500k clustered Gaussians, 512^2, 64 quantile planes, 45 views.
+    Partition bit-exact on all Gaussians; texels and pixels checked on seeded samples."""
+    announce("cluster500k full size", pdt)
+    scene, cam, cfg = scenegen.config("cluster500k")
+    out, info, st = _gpu_build(scene, cam, 64, dtype=TDT[pdt])
+    assert st == L.LF_OK, L.lf_last_error()
+    orc = _OracleTexels(scene, cam, 64)
+    _check_partition(out, orc.part, 500_000)
+    print("visible", info.n_visible, "entries", info.entries_needed, "capacity", info.entry_capacity)
+    rng = np.random.default_rng(0)
+    tol = 1e-4 if pdt == "f32" else 2e-3
+    for k in rng.choice(64, 8, replace=False):
+        iy = rng.integers(0, 512, 400)
+        ix = rng.integers(0, 512, 400)
+        ref, amb = orc(int(k), iy, ix)
+        plane = host(out["rgba"][int(k)])
+        _masked_compare(plane[iy, ix], ref, amb, tol, 0.02)
+    dx, dy, _, _ = geometry.quilt_views(cam, 45, 1)
+    dx, dy = dx.astype(np.float32), dy.astype(np.float32)
+    views = T.composite(ctx(), out["rgba"], out["depth"], cam, T.views_of(dx, dy), "nearest")
+    pix = np.stack([rng.integers(0, 45, 300), rng.integers(0, 512, 300), rng.integers(0, 512, 300)], 1)
+    ref, amb = composite.composite_at(orc, out["depth"].cpu().numpy(), cam, orc.g, dx, dy, "nearest", pix)
+    sel = torch.from_numpy(pix).cuda()
+    got = host(views[sel[:, 0], sel[:, 1], sel[:, 2]])
+    _masked_compare(got, ref, amb, tol if pdt == "f32" else 2e-3, 0.03)
+
+
+def test_capacity_overflow_is_reported():
+    announce("capacity overflow")
+    scene = scenegen.small_scene(2000, 4)
+    cam = scenegen.camera(256, 256, 50.0, 2.0, math.radians(30))
+    out, info, st = _gpu_build(scene, cam, 8, cap=1000)
+    assert st == L.LF_ERR_CAPACITY and info.overflow == 1 and info.entries_needed > 1000
+    need = info.entries_needed
+    out, info, st = _gpu_build(scene, cam, 8, cap=need)
+    assert st == L.LF_OK and info.entries_needed == need
+
+
+def test_build_deterministic():
+    scene = scenegen.cluster_scene(100_000, seed=8)
+    cam = scenegen.camera(384, 384, 50.0, 2.0, math.radians(40))
+    a, _, _ = _gpu_build(scene, cam, 32)
+    b, _, _ = _gpu_build(scene, cam, 32)
+    torch.cuda.synchronize()
+    assert torch.equal(a["rgba"], b["rgba"]) and torch.equal(a["depth"], b["depth"])
+
+
+def test_empty_field():
+    scene = {k: v[:0] for k, v in scenegen.small_scene(4, 0).items()}
+    cam = scenegen.camera(32, 32, 50.0, 2.0, math.radians(20))
+    out, info, st = _gpu_build(scene, cam, 4)
+    assert st == L.LF_OK and info.n_visible == 0
+    torch.cuda.synchronize()
+    assert float(out["rgba"].abs().max()) == 0.0
+    assert np.all(out["depth"].cpu().numpy() == np.float32(cam.d_focal))
