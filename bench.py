@@ -1,0 +1,209 @@
+#!/usr/bin/env python
+"""Light-field frame benchmark on one MI355X.
+
+A step renders one light field of the clustered-Gaussian workload: 500,000 Gaussians,
+512 x 512 views, N_chunk = 64 quantile planes, 45 horizontally sheared views over +-20 deg
+(D_focal = 2, base fov 50 deg), nearest sampling.  The step is the whole forward hot path:
+lf_build_mpi (cull, key, depth sort, chunking, tile binning, splat into planes) followed
+by lf_composite (swizzle blending of all 45 views).  Inputs are seeded synthetic scenes
+(scenegen) resident in HBM before timing starts.
+
+The JSON line reports views/s of the FP32-plane form as ``value`` and the FP16-plane form
+beside it, the roofline of the dominant kernel and of the composite, per-phase kernel
+times measured with HIP events on the launch stream, and the FP64 CPU oracle's rate on
+a bounded sample of the same frame.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: float32 lane-ops/s (no packed math)
+FP32_PEAK_TFLOPS = 2 * VALU_LANE_OPS / 1e12   # one FMA = 2 flops per lane-op -> 78.6
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--interp", default="nearest", choices=["nearest", "bilinear"])
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-planes", type=int, default=4, help="planes the CPU oracle rasterises")
+    p.add_argument("--cpu-views", type=int, default=2, help="views the CPU oracle composites")
+    p.add_argument("--forms", default="f32,f16", help="plane storage forms to time (first one is `value`)")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain device copy of known size (for HBM counter scaling)")
+    return p.parse_args()
+
+
+def cpu_baseline(scene, cam, views_dx, views_dy, n_chunk, n_planes, n_views, interp):
+    """Time the FP64 oracle on a bounded sample and scale it to one full frame."""
+    import numpy as np
+
+    from oracle import composite, geometry, partition, project, splat
+
+    g = geometry.derive(cam)
+    t0 = time.perf_counter()
+    part = partition.partition(scene["means"], cam, g, n_chunk, "quantile")
+    t_part = time.perf_counter() - t0
+    ks = np.linspace(0, n_chunk - 1, n_planes).round().astype(int)
+    planes = np.zeros((n_planes, g.hp, g.wp, 4))
+    t0 = time.perf_counter()
+    for j, k in enumerate(ks):
+        idx = part.order[part.chunk_start[k]:part.chunk_start[k + 1]]
+        pr = project.project_reference(scene, idx, cam, g)
+        planes[j], _ = splat.render_plane(pr, g.hp, g.wp)
+    t_planes = time.perf_counter() - t0
+    vsel = list(np.linspace(0, len(views_dx) - 1, n_views).round().astype(int))
+    t0 = time.perf_counter()
+    composite.composite(planes, part.depth[ks], cam, g, views_dx, views_dy, interp, views=vsel)
+    t_comp = time.perf_counter() - t0
+    frame_s = t_part + t_planes * n_chunk / n_planes + t_comp * (n_chunk / n_planes) * (len(views_dx) / n_views)
+    return dict(value=len(views_dx) / frame_s, unit="views/s", cores=1, kind="oracle",
+                sample=(f"partition of all {scene['means'].shape[0]} Gaussians ({t_part:.2f} s), "
+                        f"{n_planes} of {n_chunk} planes rasterised ({t_planes:.2f} s), {n_views} of "
+                        f"{len(views_dx)} views composited over them ({t_comp:.2f} s); scaled to one frame "
+                        f"= {frame_s:.1f} s"),
+                measured_s=round(t_part + t_planes + t_comp, 2))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design note, "
+                                   "not an implemented path", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2508_18540_amd import _lib as L
+    from paper_2508_18540_amd import torch_api as T
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    scene, cam, cfg = scenegen.config("cluster500k")
+    K, V = cfg["n_chunk"], cfg["vx"] * cfg["vy"]
+    ctx = T.Context(0)
+    camc = L.make_camera(cam)
+    vlist = L.lf_quilt_views(camc, cfg["vx"], cfg["vy"])
+    dx = np.array([v.dx for v in vlist], dtype=np.float32)
+    dy = np.array([v.dy for v in vlist], dtype=np.float32)
+    geo = L.lf_geometry(camc)
+    ds = T.to_device(scene, dev)
+    torch.cuda.synchronize()
+
+    # size the workspace from one probe build (re-allocated once if the default is short)
+    ws = T.workspace_for(ds, cam, K, device=dev)
+    T.build_mpi(ctx, ds, cam, K, dtype=torch.float32, workspace=ws)
+    info, st = T.build_stats(ctx, ws, check=False)
+    if st == L.LF_ERR_CAPACITY:
+        ws = T.workspace_for(ds, cam, K, entry_capacity=int(info.entries_needed * 1.25), device=dev)
+
+    def one_form(form):
+        pdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[form]
+        out = T.build_mpi(ctx, ds, cam, K, dtype=pdt, workspace=ws)
+        img = torch.empty((V, cam.ny, cam.nx, 4), dtype=torch.float32, device=dev)
+
+        def step():
+            T.build_mpi(ctx, ds, cam, K, dtype=pdt, workspace=ws, out=out)
+            T.composite(ctx, out["rgba"], out["depth"], cam, vlist, args.interp, out=img)
+
+        for _ in range(args.warmup):
+            step()
+        info, st = T.build_stats(ctx, ws, check=True)
+        L.lf_profile_read(ctx.handle, reset=True)
+        L.lf_profile_enable(ctx.handle, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.lf_profile_enable(ctx.handle, False)
+        prof = L.lf_profile_read(ctx.handle, reset=True)
+        info, st = T.build_stats(ctx, ws, check=True)
+        ms = (t1 - t0) * 1e3 / args.steps
+        phases = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}
+        pb = {"f32": 16, "f16": 8, "bf16": 8}[form]
+        comp_bytes = K * geo.plane_height * geo.plane_width * pb + V * cam.ny * cam.nx * 16
+        comp_ms = phases["composite"]
+        comp_roof = dict(bound="hbm", achieved=round(comp_bytes / (comp_ms * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS,
+                         unit="GB/s", frac=round(comp_bytes / (comp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         traffic=None, kernel="composite_rows", bytes_per_launch=comp_bytes,
+                         avg_ms=round(comp_ms, 4))
+        # splat: algorithmic work = (entry, texel) evaluations of the tile lists; one evaluation is
+        # about 8 FMA-equivalent lane-ops on the included texels (quadratic form, exp2, blend)
+        splat_ms = phases["splat"]
+        evals = info.entries_needed * 256
+        splat_roof = dict(bound="alu", achieved=round(evals * 16 / (splat_ms * 1e-3) / 1e12, 3),
+                          peak=round(FP32_PEAK_TFLOPS, 1), unit="TFLOP/s",
+                          frac=round(evals * 16 / (splat_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+                          traffic=None, kernel="splat_gs", flops_per_launch=evals * 16, avg_ms=round(splat_ms, 4))
+        return dict(form=form, ms_per_step=ms, views_per_s=V / (ms * 1e-3), phases_ms=phases,
+                    composite_roofline=comp_roof, splat_roofline=splat_roof, entries=int(info.entries_needed),
+                    n_visible=int(info.n_visible))
+
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    res = {f: one_form(f) for f in forms}
+    main_r = res[forms[0]]
+    ph = main_r["phases_ms"]
+    dominant = max(("splat", "composite"), key=lambda k: ph.get(k, 0.0))
+    roof = main_r["splat_roofline"] if dominant == "splat" else main_r["composite_roofline"]
+
+    if args.copy_calibration:
+        a = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": "light-field views/sec at 512^2, N_chunk=64 (FP32 vs FP16 planes); % HBM peak",
+        "value": round(main_r["views_per_s"], 1),
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded 64-cluster Gaussian mixture)",
+        "config": {"workload": "cluster500k: 500k Gaussians, 512x512 views, N_chunk=64 quantile planes, "
+                               "45x1 views over +-20 deg, D_focal=2, fov 50 deg, nearest sampling",
+                   "planes": forms[0], "interp": args.interp, "n_gaussians": 500_000, "n_chunk": K,
+                   "views": V, "resolution": [cam.nx, cam.ny]},
+        "roofline": roof,
+        "composite_roofline": main_r["composite_roofline"],
+        "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+        "entries": main_r["entries"],
+        "n_visible": main_r["n_visible"],
+    }
+    for f in forms[1:]:
+        r = res[f]
+        line[f"{f}_planes"] = {"value": round(r["views_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                               "speedup_vs_" + forms[0]: round(main_r["ms_per_step"] / r["ms_per_step"], 3),
+                               "composite_speedup_vs_" + forms[0]:
+                                   round(ph["composite"] / r["phases_ms"]["composite"], 3),
+                               "composite_roofline": r["composite_roofline"],
+                               "phases_ms": {k: round(v, 4) for k, v in r["phases_ms"].items()}}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(scene, cam, dx, dy, K, args.cpu_planes, args.cpu_views, args.interp)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,6 +179,23 @@ lf_status lf_plane_coeffs(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, 
                           int32_t n_views, float* bx, float* by, float* cx, float* cy, float* cxn,
                           float* cyn, void* stream);
 
+/* Per-phase device timing, a tracing aid.  While enabled, each entry point brackets its
+ * kernel phases with HIP events recorded on the launch stream; lf_profile_read sums the
+ * elapsed times.  Phases: PREPROCESS (cull, key, projection), SORT (depth sort), BIN
+ * (chunking, tile lists), SPLAT (plane rasterisation), FILTER (voxel plane low-pass),
+ * COMPOSITE (swizzle blending), and the two backward passes.                            */
+typedef enum {
+  LF_PHASE_PREPROCESS = 0, LF_PHASE_SORT = 1, LF_PHASE_BIN = 2, LF_PHASE_SPLAT = 3,
+  LF_PHASE_FILTER = 4, LF_PHASE_COMPOSITE = 5, LF_PHASE_COMPOSITE_BWD = 6, LF_PHASE_BUILD_BWD = 7,
+  LF_NUM_PHASES = 8
+} lf_phase;
+
+lf_status lf_profile_enable(lf_ctx* ctx, int32_t enable);
+
+/* Milliseconds summed per phase and the number of bracketed launches since the last reset
+ * (host arrays of LF_NUM_PHASES).  SYNCHRONISES the device.                             */
+lf_status lf_profile_read(lf_ctx* ctx, double* ms, int64_t* count, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

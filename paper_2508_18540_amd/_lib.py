@@ -27,7 +27,9 @@ STATUS_NAMES = {0: "LF_OK", 1: "LF_ERR_INVALID_ARG", 2: "LF_ERR_UNSUPPORTED", 3:
 EXPORTS = [
     "lf_version", "lf_last_error", "lf_create", "lf_destroy", "lf_geometry", "lf_quilt_views",
     "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_plane_coeffs",
+    "lf_profile_enable", "lf_profile_read",
 ]
+PHASES = ["preprocess", "sort", "bin", "splat", "filter", "composite", "composite_bwd", "build_bwd"]
 
 
 class LFError(RuntimeError):
@@ -104,6 +106,8 @@ def load():
                           C.c_int32, P, P], C.c_int),
         "lf_plane_coeffs": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
                              P, P, P, P, P, P, P], C.c_int),
+        "lf_profile_enable": ([P, C.c_int32], C.c_int),
+        "lf_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32], C.c_int),
     }
     for name, (args, res) in sig.items():
         if not hasattr(lib, name):
@@ -221,3 +225,15 @@ def lf_plane_coeffs(ctx: int, mpi: lf_mpi, cam: lf_camera, views, bx: int, by: i
                     cxn: int, cyn: int, stream: int = 0) -> None:
     _check(load().lf_plane_coeffs(ctx, C.byref(mpi), C.byref(cam), views, len(views), bx, by, cx, cy, cxn, cyn,
                                   stream), "lf_plane_coeffs")
+
+
+def lf_profile_enable(ctx: int, enable: bool) -> None:
+    _check(load().lf_profile_enable(ctx, 1 if enable else 0), "lf_profile_enable")
+
+
+def lf_profile_read(ctx: int, reset: bool = True) -> dict:
+    """{phase: (total_ms, count)} since the last reset (synchronises the device)."""
+    ms = (C.c_double * len(PHASES))()
+    cnt = (C.c_int64 * len(PHASES))()
+    _check(load().lf_profile_read(ctx, ms, cnt, 1 if reset else 0), "lf_profile_read")
+    return {p: (ms[i], cnt[i]) for i, p in enumerate(PHASES)}

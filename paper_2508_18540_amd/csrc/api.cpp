@@ -86,7 +86,89 @@ extern "C" lf_status lf_create(lf_ctx** out, int device) {
   return LF_OK;
 }
 
-extern "C" void lf_destroy(lf_ctx* ctx) { delete ctx; }
+extern "C" void lf_destroy(lf_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  ctx->prof.release();
+  if (ctx->table) hipFree(ctx->table);
+  delete ctx;
+}
+
+namespace lf {
+
+hipEvent_t Profiler::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Profiler::begin(int phase, hipStream_t s) {
+  Rec r{phase, take(), take()};
+  if (r.a) hipEventRecord(r.a, s);
+  recs.push_back(r);
+}
+
+void Profiler::end(hipStream_t s) {
+  if (!recs.empty() && recs.back().b) hipEventRecord(recs.back().b, s);
+}
+
+hipError_t Profiler::collect() {
+  hipError_t err = hipSuccess;
+  for (Rec& r : recs) {
+    if (r.a && r.b) {
+      hipError_t e = hipEventSynchronize(r.b);
+      float t = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+      if (e == hipSuccess) {
+        ms[r.phase] += t;
+        count[r.phase] += 1;
+      } else {
+        err = e;
+      }
+    }
+    if (r.a) pool.push_back(r.a);
+    if (r.b) pool.push_back(r.b);
+  }
+  recs.clear();
+  return err;
+}
+
+void Profiler::release() {
+  collect();
+  for (hipEvent_t e : pool) hipEventDestroy(e);
+  pool.clear();
+}
+
+}  // namespace lf
+
+extern "C" lf_status lf_profile_enable(lf_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->prof.on = enable != 0;
+  return LF_OK;
+}
+
+extern "C" lf_status lf_profile_read(lf_ctx* ctx, double* ms, int64_t* count, int32_t reset) {
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  if (!ms || !count) return fail(LF_ERR_INVALID_ARG, "ms/count is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = ctx->prof.collect();
+  for (int i = 0; i < LF_NUM_PHASES; ++i) {
+    ms[i] = ctx->prof.ms[i];
+    count[i] = ctx->prof.count[i];
+    if (reset) {
+      ctx->prof.ms[i] = 0.0;
+      ctx->prof.count[i] = 0;
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "profiling events");
+  return LF_OK;
+}
 
 extern "C" lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
                                   int32_t n_views, int32_t interp, int32_t out_dtype, void* out, void* stream) {
@@ -103,7 +185,17 @@ extern "C" lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camer
     a->interp = interp;
     a->out_dtype = out_dtype;
     a->out = out;
-    hipError_t e = composite_launch(*a, (hipStream_t)stream);
+    hipError_t e = hipSuccess;
+    const size_t need = composite_table_bytes(a->K, a->n_views);
+    if (ctx->table_bytes < need) {
+      // grown on demand; a call under stream capture needs an earlier call of at least this size
+      if (ctx->table) hipFree(ctx->table);
+      ctx->table = nullptr;
+      ctx->table_bytes = 0;
+      e = hipMalloc(&ctx->table, need);
+      if (e == hipSuccess) ctx->table_bytes = need;
+    }
+    if (e == hipSuccess) e = composite_launch(*a, ctx->table, (hipStream_t)stream, &ctx->prof);
     if (e != hipSuccess) s = hip_fail(e, "composite launch");
   }
   delete a;

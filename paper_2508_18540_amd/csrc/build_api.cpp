@@ -48,22 +48,32 @@ BuildLayout build_layout(int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t c
   L.o_bucket = take((size_t)(L.n_buckets + 1) * 4);
   L.o_scan32 = take(scan_tmp_elems(L.n_buckets) * 4);
   L.o_radix = take(radix_tmp_u32(n > cap ? n : cap) * 4);
-  const size_t uc = (size_t)(cap > 0 ? cap : 1);
+  const size_t uc = (size_t)(cap > 0 ? cap : 1) + kEntryPad;
   L.o_ekeys = take(uc * 4);
   L.o_evals = take(uc * 4);
   L.o_ekeys_alt = take(uc * 4);
   L.o_evals_alt = take(uc * 4);
+  const int64_t segs = (cap + kSegment - 1) / kSegment;
+  L.max_items = L.n_buckets + segs + 1;
+  L.max_partial = 2 * segs + 16;
+  L.o_pcnt = take((size_t)(L.n_buckets + 1) * 4);
+  L.o_item_start = take((size_t)(L.n_buckets + 1) * 4);
+  L.o_pslot = take((size_t)(L.n_buckets + 1) * 4);
+  L.o_items = take((size_t)L.max_items * 8);
+  L.o_partial = take((size_t)L.max_partial * kTile * kTile * 16);
   L.total = o;
   return L;
 }
 
 namespace {
 
-constexpr int64_t kMaxPrimitives = (1LL << 31) - 1;
+constexpr int64_t kMaxPrimitives = (1LL << 28) - 1;   // entry values keep 28 index bits
 constexpr int64_t kMaxEntries = (1LL << 31) - 1;
+// per list entry: four u32 sort arrays, item records and 2/kSegment partial tiles of 4 KB
+constexpr size_t kBytesPerEntry = 16 + 8 + 2 * kTile * kTile * 16 / kSegment + 1;
 
 int64_t default_capacity(int64_t n) {
-  const int64_t c = 32 * n;
+  const int64_t c = 16 * n;
   return c < 65536 ? 65536 : (c > kMaxEntries ? kMaxEntries : c);
 }
 
@@ -71,7 +81,7 @@ int64_t default_capacity(int64_t n) {
 int64_t capacity_of(int64_t n, int32_t K, int32_t wp, int32_t hp, size_t bytes) {
   const size_t fixed = build_layout(n, K, wp, hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
   if (bytes <= fixed) return 0;
-  int64_t cap = (int64_t)((bytes - fixed) / 16);
+  int64_t cap = (int64_t)((bytes - fixed) / kBytesPerEntry);
   if (cap > kMaxEntries) cap = kMaxEntries;
   while (cap > 0 && build_layout(n, K, wp, hp, cap).total > bytes) cap -= 64;
   return cap > 0 ? cap : 0;
@@ -79,7 +89,7 @@ int64_t capacity_of(int64_t n, int32_t K, int32_t wp, int32_t hp, size_t bytes) 
 
 lf_status check_field(const lf_field* f) {
   if (!f) return fail(LF_ERR_INVALID_ARG, "field is NULL");
-  if (f->n < 0 || f->n > kMaxPrimitives) return fail(LF_ERR_INVALID_ARG, "field size %lld outside [0, 2^31)", (long long)f->n);
+  if (f->n < 0 || f->n > kMaxPrimitives) return fail(LF_ERR_INVALID_ARG, "field size %lld outside [0, 2^28)", (long long)f->n);
   if (f->kind == LF_GAUSSIANS) {
     if (f->n > 0 && !(f->means && f->log_scales && f->quats && f->opacity && f->rgb))
       return fail(LF_ERR_INVALID_ARG, "a Gaussian attribute pointer is NULL");
@@ -112,7 +122,7 @@ extern "C" lf_status lf_build_mpi_workspace(const lf_field* field, const lf_came
   if (entry_capacity > kMaxEntries) return fail(LF_ERR_INVALID_ARG, "entry_capacity exceeds 2^31 - 1");
   const int64_t cap = entry_capacity > 0 ? entry_capacity : default_capacity(field->n);
   const size_t fixed = build_layout(field->n, n_chunk, g.wp, g.hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
-  *bytes = fixed + (size_t)cap * 16 + 4096;
+  *bytes = fixed + (size_t)cap * kBytesPerEntry + 4096;
   return LF_OK;
 }
 
@@ -196,6 +206,12 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   a.evals = reinterpret_cast<uint32_t*>(w + L.o_evals);
   a.ekeys_alt = reinterpret_cast<uint32_t*>(w + L.o_ekeys_alt);
   a.evals_alt = reinterpret_cast<uint32_t*>(w + L.o_evals_alt);
+  a.pcnt = reinterpret_cast<uint32_t*>(w + L.o_pcnt);
+  a.item_start = reinterpret_cast<uint32_t*>(w + L.o_item_start);
+  a.pslot = reinterpret_cast<uint32_t*>(w + L.o_pslot);
+  a.items = reinterpret_cast<uint2*>(w + L.o_items);
+  a.partial = reinterpret_cast<float4*>(w + L.o_partial);
+  a.max_items = L.max_items;
 
   if (binning == LF_BIN_INV_DEPTH) {
     // K planes uniform in 1/z over [z_lo, z_hi]: interior edges E_i and plane depths at i = k + 1/2
@@ -206,7 +222,7 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
     if ((e = upload_table(a.edges, edges.data(), n_chunk, st)) != hipSuccess) return hip_fail(e, "table upload");
     if ((e = upload_table(a.dtab, dtab.data(), n_chunk, st)) != hipSuccess) return hip_fail(e, "table upload");
   }
-  if ((e = build_gaussians(a, L, st)) != hipSuccess) return hip_fail(e, "build launch");
+  if ((e = build_gaussians(a, L, st, &ctx->prof)) != hipSuccess) return hip_fail(e, "build launch");
   return LF_OK;
 }
 

@@ -218,30 +218,67 @@ __global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
   a.depth[k] = d;
 }
 
+// One (tile, Gaussian) entry per covered tile, written in rank order.  A block takes 256
+// consecutive ranks and spreads their entries evenly over its threads (each output slot
+// finds its rank by binary search over the block's offsets), so one Gaussian covering
+// hundreds of tiles does not serialise a thread.  The entry value carries the Gaussian index
+// in its low 28 bits and, in bits 28..31, which 8x8 quadrants of the tile its support box
+// touches (bit = 2 * qy + qx).
 __global__ __launch_bounds__(256) void emit_entries(BuildArgs a, const uint32_t* svals) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= a.n || r >= a.hdr->n_vis) return;
-  const uint64_t base = a.offsets[r];
-  const uint64_t nt = a.ntiles_r[r];
-  if (nt == 0) return;
-  if (base + nt > (uint64_t)a.capacity) {
-    atomicOr(&a.hdr->overflow, 1);
+  __shared__ uint32_t lofs[257];
+  __shared__ int32_t sx0[256], sy0[256], sw[256], sbox[256][4];
+  __shared__ uint32_t sidx[256], schunk[256];
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  const int64_t nvis = a.hdr->n_vis;
+  if (r0 >= nvis) return;
+  const uint64_t total = a.offsets[a.n];
+  if (total > (uint64_t)a.capacity) {
+    if (threadIdx.x == 0) atomicOr(&a.hdr->overflow, 1);
     return;
   }
-  const uint32_t idx = svals[r];
-  const GRec& g = a.rec[idx];
-  const int chunk = (int)a.chunk_r[r];
-  const int tx0 = g.x0 >> kTileShift, tx1 = g.x1 >> kTileShift;
-  const int ty0 = g.y0 >> kTileShift, ty1 = g.y1 >> kTileShift;
-  uint64_t o = base;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      const uint32_t tile = (uint32_t)(ty * a.ntx + tx);
-      a.ekeys[o] = tile;
-      a.evals[o] = idx;
-      atomicAdd(&a.hist[(int64_t)tile * a.K + chunk], 1u);
-      ++o;
+  const int nr = (int)min((int64_t)256, nvis - r0);
+  const uint64_t O0 = a.offsets[r0];
+  const int t = threadIdx.x;
+  if (t < nr) lofs[t] = (uint32_t)(a.offsets[r0 + t] - O0);
+  if (t == 0) lofs[nr] = (uint32_t)(a.offsets[r0 + nr] - O0);   // nr may be 256 = blockDim
+  if (t < nr) {
+    const uint32_t idx = svals[r0 + t];
+    const GRec& g = a.rec[idx];
+    sidx[t] = idx;
+    schunk[t] = a.chunk_r[r0 + t];
+    sx0[t] = g.x0 >> kTileShift;
+    sy0[t] = g.y0 >> kTileShift;
+    sw[t] = (g.x1 >> kTileShift) - (g.x0 >> kTileShift) + 1;
+    sbox[t][0] = g.x0;
+    sbox[t][1] = g.y0;
+    sbox[t][2] = g.x1;
+    sbox[t][3] = g.y1;
+  }
+  __syncthreads();
+  const uint32_t n_out = lofs[nr];
+  for (uint32_t o = t; o < n_out; o += 256) {
+    int lo = 0, hi = nr - 1;                               // last j with lofs[j] <= o
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (lofs[mid] <= o) lo = mid;
+      else hi = mid - 1;
     }
+    const int j = lo;
+    const uint32_t u = o - lofs[j];
+    const int tx = sx0[j] + (int)(u % (uint32_t)sw[j]), ty = sy0[j] + (int)(u / (uint32_t)sw[j]);
+    const int ox = tx << kTileShift, oy = ty << kTileShift;
+    uint32_t mask = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int bx = ox + ((q & 1) << 3), by = oy + ((q >> 1) << 3);
+      if (sbox[j][2] >= bx && sbox[j][0] <= bx + 7 && sbox[j][3] >= by && sbox[j][1] <= by + 7) mask |= 1u << q;
+    }
+    const uint32_t tile = (uint32_t)(ty * a.ntx + tx);
+    const uint64_t dst = O0 + o;
+    a.ekeys[dst] = tile;
+    a.evals[dst] = sidx[j] | (mask << 28);
+    atomicAdd(&a.hist[(int64_t)tile * a.K + schunk[j]], 1u);
+  }
 }
 
 __global__ void finalize(BuildArgs a) {
@@ -251,14 +288,11 @@ __global__ void finalize(BuildArgs a) {
 
 // ---------------------------------------------------------------------------------------
 // Splat: one work-group per (tile, chunk).  Wave w of the 256 threads owns the 8x8 texel
-// block at ((w & 1) * 8, (w >> 1) * 8) of the 16x16 tile and skips Gaussians whose support
-// box misses that block.
+// block at ((w & 1) * 8, (w >> 1) * 8) of the 16x16 tile and walks the bucket on its own:
+// the entry and the 64-byte Gaussian record are wave-uniform, so they arrive through
+// scalar loads, the support-box test against the wave's block is a scalar branch, and
+// only the per-texel footprint and blend run on the vector ALUs.  No LDS, no barriers.
 // ---------------------------------------------------------------------------------------
-struct LRec {
-  float mrx, mry, ca, cb, cc, l2o, r, g, b;
-  int x0, x1, y0, y1;
-};
-
 template <typename T>
 __device__ __forceinline__ void store_rgba(T* p, size_t i, float r, float g, float b, float al);
 
@@ -290,57 +324,99 @@ __device__ __forceinline__ void store_rgba<__hip_bfloat16>(__hip_bfloat16* p, si
   reinterpret_cast<uint2*>(p)[i] = u;
 }
 
+// Split every (tile, chunk) bucket into segments of at most kSegment entries: nseg per
+// bucket (into hist, free after the bucket scan) and the partial-tile slots of split buckets.
+__global__ void bucket_segments(BuildArgs a, int64_t n_buckets) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_buckets) return;
+  const uint32_t len = a.bucket[b + 1] - a.bucket[b];
+  const uint32_t ns = len ? (len + kSegment - 1) / kSegment : 1u;
+  a.hist[b] = ns;
+  a.pcnt[b] = ns > 1 ? ns : 0u;
+}
+
+__global__ void emit_items(BuildArgs a, int64_t n_buckets) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_buckets) return;
+  const uint32_t i0 = a.item_start[b], ns = a.item_start[b + 1] - i0;
+  for (uint32_t s = 0; s < ns; ++s) a.items[i0 + s] = make_uint2((uint32_t)b, s);
+}
+
 template <typename PT>
-__global__ __launch_bounds__(256) void splat_gs(BuildArgs a) {
-  __shared__ LRec recs[256];
-  const int tile = blockIdx.x, k = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) {
+  const uint32_t item = blockIdx.x;
+  if (item >= a.item_start[n_buckets]) return;             // beyond this frame's work list
+  const uint2 it = a.items[item];
+  const int64_t bidx = it.x;
+  const int tile = (int)(bidx / a.K), k = (int)(bidx % a.K);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
   const int bx = ox + ((wave & 1) << 3), by = oy + ((wave >> 1) << 3);
   const int px = bx + (lane & 7), py = by + (lane >> 3);
-  const float lx = (float)(px - ox), ly = (float)(py - oy);
+  const float pxf = (float)px, pyf = (float)py;
+  const uint32_t* __restrict__ ev = a.evals;
+  const GRec* __restrict__ rec = a.rec;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
   const bool ok = a.hdr->overflow == 0;
-  const int64_t bidx = (int64_t)tile * a.K + k;
-  const uint32_t b0 = ok ? a.bucket[bidx] : 0u, b1 = ok ? a.bucket[bidx + 1] : 0u;
-  for (uint32_t base = b0; base < b1; base += 256) {
-    const uint32_t n = min(256u, b1 - base);
-    if (tid < (int)n) {
-      uint32_t idx = a.evals[base + tid];
-      if (idx >= (uint32_t)a.n) idx = 0;
-      const GRec& g = a.rec[idx];
-      LRec l;
-      l.mrx = (g.mx_hi - (float)ox) + g.mx_lo;
-      l.mry = (g.my_hi - (float)oy) + g.my_lo;
-      l.ca = g.ca;
-      l.cb = g.cb;
-      l.cc = g.cc;
-      l.l2o = g.l2o;
-      l.r = g.rgb[0];
-      l.g = g.rgb[1];
-      l.b = g.rgb[2];
-      l.x0 = g.x0;
-      l.x1 = g.x1;
-      l.y0 = g.y0;
-      l.y1 = g.y1;
-      recs[tid] = l;
-    }
-    __syncthreads();
-    for (uint32_t j = 0; j < n; ++j) {
-      const LRec& l = recs[j];
-      if (l.x1 < bx || l.x0 > bx + 7 || l.y1 < by || l.y0 > by + 7) continue;   // uniform per wave
-      const float dx = lx - l.mrx, dy = ly - l.mry;
-      const float e = fmaf(l.ca * dx, dx, fmaf(l.cc * dy, dy, fmaf(l.cb * dx, dy, l.l2o)));
-      if (e >= kLog2AlphaMin) {
-        const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
+  const uint32_t bb0 = a.bucket[bidx], bb1 = a.bucket[bidx + 1];
+  const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
+  if (ok) {
+    const uint32_t b0 = bb0 + it.y * kSegment;
+    const uint32_t b1 = min(bb1, b0 + kSegment);
+    // entries in groups of 8 (one 32-byte scalar load; the entry arrays are padded so a group
+    // may run past the segment end).  The wave tests its quadrant bit before touching the record.
+    struct Group { uint32_t v[8]; };
+    const uint32_t qbit = 1u << (28 + wave);
+    for (uint32_t e0 = b0; e0 < b1; e0 += 8) {
+      const Group grp = *reinterpret_cast<const Group*>(ev + e0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t ent = grp.v[u];
+        if (e0 + u >= b1) break;
+        if (!(ent & qbit)) continue;                          // scalar: support misses this quadrant
+        const uint32_t idx = min(ent & 0x0fffffffu, (uint32_t)a.n - 1u);
+        const GRec& g = rec[idx];
+        const float dx = (pxf - g.mx_hi) - g.mx_lo;
+        const float dy = (pyf - g.my_hi) - g.my_lo;
+        const float q = fmaf(g.ca * dx, dx, fmaf(g.cc * dy, dy, fmaf(g.cb * dx, dy, g.l2o)));
+        // excluded texels get alpha 0 (a select, not a branch: keeps the scalar unit free)
+        const float alpha = q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f;
         const float w = alpha * T;
-        C0 = fmaf(w, l.r, C0);
-        C1 = fmaf(w, l.g, C1);
-        C2 = fmaf(w, l.b, C2);
+        C0 = fmaf(w, g.rgb[0], C0);
+        C1 = fmaf(w, g.rgb[1], C1);
+        C2 = fmaf(w, g.rgb[2], C2);
         T = T - w;
       }
     }
-    __syncthreads();
+  }
+  if (nseg > 1) {
+    // partial (C, T) of this segment; the combine pass composes the segments in order
+    const size_t slot = (size_t)a.pslot[bidx] + it.y;
+    a.partial[slot * (kTile * kTile) + ((py - oy) << kTileShift) + (px - ox)] = make_float4(C0, C1, C2, T);
+  } else if (px < a.c.wp && py < a.c.hp) {
+    store_rgba(static_cast<PT*>(a.planes), ((size_t)k * a.c.hp + py) * a.c.wp + px, C0, C1, C2, 1.0f - T);
+  }
+}
+
+// Over-composite the segments of every split bucket (one work-group per bucket).
+template <typename PT>
+__global__ __launch_bounds__(256) void combine_segments(BuildArgs a) {
+  const int64_t bidx = blockIdx.x;
+  const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
+  if (nseg <= 1) return;
+  const int tile = (int)(bidx / a.K), k = (int)(bidx % a.K);
+  const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int px = ox + ((wave & 1) << 3) + (lane & 7), py = oy + ((wave >> 1) << 3) + (lane >> 3);
+  const float4* p = a.partial + (size_t)a.pslot[bidx] * (kTile * kTile) + ((py - oy) << kTileShift) + (px - ox);
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+  for (uint32_t s = 0; s < nseg; ++s) {
+    const float4 v = p[(size_t)s * (kTile * kTile)];
+    C0 = fmaf(T, v.x, C0);
+    C1 = fmaf(T, v.y, C1);
+    C2 = fmaf(T, v.z, C2);
+    T = T * v.w;
   }
   if (px < a.c.wp && py < a.c.hp)
     store_rgba(static_cast<PT*>(a.planes), ((size_t)k * a.c.hp + py) * a.c.wp + px, C0, C1, C2, 1.0f - T);
@@ -364,48 +440,74 @@ hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s) {
+hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
   hipError_t e;
   const unsigned gN = (unsigned)((a.n + 255) / 256);
-  // zero the header and the (tile, chunk) histogram
-  if ((e = fill(reinterpret_cast<uint32_t*>(a.hdr), sizeof(BuildHeader) / 4, 0u, s)) != hipSuccess) return e;
-  if ((e = fill(a.hist, L.n_buckets + 1, 0u, s)) != hipSuccess) return e;
-  if (a.n == 0) {
-    // nothing to rasterise: transparent planes at D_focal (or the inverse-depth table)
-    const size_t words = (size_t)a.K * a.c.hp * a.c.wp * (a.plane_dtype == LF_F32 ? 4 : 2);
-    if ((e = fill(reinterpret_cast<uint32_t*>(a.planes), (int64_t)words, 0u, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, a.keys);
-    hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, a.keys);
-    return hipGetLastError();
+  {
+    PhaseScope ps(prof, LF_PHASE_PREPROCESS, s);
+    // zero the header and the (tile, chunk) histogram
+    if ((e = fill(reinterpret_cast<uint32_t*>(a.hdr), sizeof(BuildHeader) / 4, 0u, s)) != hipSuccess) return e;
+    if ((e = fill(a.hist, L.n_buckets + 1, 0u, s)) != hipSuccess) return e;
+    if (a.n == 0) {
+      // nothing to rasterise: transparent planes at D_focal (or the inverse-depth table)
+      const size_t words = (size_t)a.K * a.c.hp * a.c.wp * (a.plane_dtype == LF_F32 ? 4 : 2);
+      if ((e = fill(reinterpret_cast<uint32_t*>(a.planes), (int64_t)words, 0u, s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, a.keys);
+      hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, a.keys);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL(preprocess_gs, dim3(gN), dim3(256), 0, s, a);
   }
-  hipLaunchKernelGGL(preprocess_gs, dim3(gN), dim3(256), 0, s, a);
   // (key, index) order
   int alt = 0;
-  if ((e = radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.n, nullptr, 32, a.radix_tmp, &alt, s)) !=
-      hipSuccess)
-    return e;
+  {
+    PhaseScope ps(prof, LF_PHASE_SORT, s);
+    if ((e = radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.n, nullptr, 32, a.radix_tmp, &alt, s)) !=
+        hipSuccess)
+      return e;
+  }
   const uint32_t* skeys = alt ? a.keys_alt : a.keys;
   const uint32_t* svals = alt ? a.vals_alt : a.vals;
-  hipLaunchKernelGGL(rank_pass, dim3(gN), dim3(256), 0, s, a, skeys, svals);
-  hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, skeys);
-  hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, skeys);
-  if ((e = exclusive_scan<uint64_t>(a.ntiles_r, a.offsets, a.n, a.scan_tmp64, s)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(emit_entries, dim3(gN), dim3(256), 0, s, a, svals);
-  hipLaunchKernelGGL(finalize, dim3(1), dim3(1), 0, s, a);
-  // stable sort of the entries by tile (entries beyond the capacity are never read)
-  int ealt = 0;
-  if ((e = radix_sort_pairs(a.ekeys, a.evals, a.ekeys_alt, a.evals_alt, a.capacity,
-                            reinterpret_cast<const int64_t*>(&a.hdr->entries), L.tile_bits, a.radix_tmp, &ealt,
-                            s)) != hipSuccess)
-    return e;
-  if (ealt) a.evals = a.evals_alt;
-  if ((e = exclusive_scan<uint32_t>(a.hist, a.bucket, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
-  const dim3 grid(L.n_tiles, a.K);
-  switch (a.plane_dtype) {
-    case LF_F16: hipLaunchKernelGGL((splat_gs<__half>), grid, dim3(256), 0, s, a); break;
-    case LF_BF16: hipLaunchKernelGGL((splat_gs<__hip_bfloat16>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((splat_gs<float>), grid, dim3(256), 0, s, a); break;
+  {
+    PhaseScope ps(prof, LF_PHASE_BIN, s);
+    hipLaunchKernelGGL(rank_pass, dim3(gN), dim3(256), 0, s, a, skeys, svals);
+    hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, skeys);
+    hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, skeys);
+    if ((e = exclusive_scan<uint64_t>(a.ntiles_r, a.offsets, a.n, a.scan_tmp64, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(emit_entries, dim3(gN), dim3(256), 0, s, a, svals);
+    hipLaunchKernelGGL(finalize, dim3(1), dim3(1), 0, s, a);
+    // stable sort of the entries by tile (entries beyond the capacity are never read)
+    int ealt = 0;
+    if ((e = radix_sort_pairs(a.ekeys, a.evals, a.ekeys_alt, a.evals_alt, a.capacity,
+                              reinterpret_cast<const int64_t*>(&a.hdr->entries), L.tile_bits, a.radix_tmp, &ealt,
+                              s)) != hipSuccess)
+      return e;
+    if (ealt) a.evals = a.evals_alt;
+    if ((e = exclusive_scan<uint32_t>(a.hist, a.bucket, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
+    // work items: buckets split into segments of at most kSegment entries
+    const unsigned gB = (unsigned)((L.n_buckets + 255) / 256);
+    hipLaunchKernelGGL(bucket_segments, dim3(gB), dim3(256), 0, s, a, L.n_buckets);
+    if ((e = exclusive_scan<uint32_t>(a.hist, a.item_start, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
+    if ((e = exclusive_scan<uint32_t>(a.pcnt, a.pslot, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(emit_items, dim3(gB), dim3(256), 0, s, a, L.n_buckets);
+  }
+  {
+    PhaseScope ps(prof, LF_PHASE_SPLAT, s);
+    const dim3 grid((unsigned)L.max_items);
+    switch (a.plane_dtype) {
+      case LF_F16:
+        hipLaunchKernelGGL((splat_gs<__half>), grid, dim3(256), 0, s, a, L.n_buckets);
+        hipLaunchKernelGGL((combine_segments<__half>), dim3((unsigned)L.n_buckets), dim3(256), 0, s, a);
+        break;
+      case LF_BF16:
+        hipLaunchKernelGGL((splat_gs<__hip_bfloat16>), grid, dim3(256), 0, s, a, L.n_buckets);
+        hipLaunchKernelGGL((combine_segments<__hip_bfloat16>), dim3((unsigned)L.n_buckets), dim3(256), 0, s, a);
+        break;
+      default:
+        hipLaunchKernelGGL((splat_gs<float>), grid, dim3(256), 0, s, a, L.n_buckets);
+        hipLaunchKernelGGL((combine_segments<float>), dim3((unsigned)L.n_buckets), dim3(256), 0, s, a);
+        break;
+    }
   }
   return hipGetLastError();
 }

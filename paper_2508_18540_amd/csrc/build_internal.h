@@ -18,21 +18,25 @@ struct BuildHeader {
   int32_t pad;
 };
 
-// One projected Gaussian (64 bytes).
+// One projected Gaussian (64 bytes, four 16-byte groups).
 struct GRec {
+  int32_t x0, y0, x1, y1;             // inclusive texel box of the support (x1 < x0: empty)
   float mx_hi, my_hi, mx_lo, my_lo;   // projected mean, double-float, texels
   float ca, cb, cc, l2o;              // log2(o G(d)) = l2o + ca dx^2 + cb dx dy + cc dy^2
   float rgb[3];
   float pad;
-  int32_t x0, y0, x1, y1;             // inclusive texel box of the support (x1 < x0: empty)
 };
+
+constexpr int kEntryPad = 8;          // readable entries past the end of the tile lists
+constexpr int kSegment = 256;         // entries per splat work item (longer buckets are split)
 
 struct BuildLayout {
   int64_t n, cap, n_buckets;
   int32_t K, ntx, nty, n_tiles, tile_bits;
   size_t o_hdr, o_keys, o_vals, o_keys_alt, o_vals_alt, o_rec, o_ntiles_i, o_ntiles_r, o_chunk_r, o_offsets,
       o_scan64, o_chunk_start, o_edges, o_dtab, o_hist, o_bucket, o_scan32, o_radix, o_ekeys, o_evals, o_ekeys_alt,
-      o_evals_alt;
+      o_evals_alt, o_pcnt, o_item_start, o_pslot, o_items, o_partial;
+  int64_t max_items, max_partial;
   size_t total;
 };
 
@@ -62,6 +66,11 @@ struct BuildArgs {
   float *edges, *dtab;
   uint32_t *hist, *bucket, *scan_tmp32, *radix_tmp;
   uint32_t *ekeys, *evals, *ekeys_alt, *evals_alt;
+  // splat work items: bucket segments and their partial (C, T) tiles
+  uint32_t *pcnt, *item_start, *pslot;
+  uint2* items;
+  float4* partial;
+  int64_t max_items;
 };
 
 struct TableChunk {
@@ -70,6 +79,6 @@ struct TableChunk {
 };
 
 hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s);
-hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s);
+hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof);
 
 }  // namespace lf

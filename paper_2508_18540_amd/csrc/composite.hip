@@ -9,16 +9,24 @@
 // -ffp-contract=off and fuses only where fmaf is written).  Nearest sampling takes the
 // texel floor(X); bilinear takes floor(X), floor(X)+1 with weight X - floor(X).
 //
+// A small table kernel evaluates these coefficients once per launch: per plane (bx, by,
+// the row offset Cy of the shared dy, a validity flag) and per (plane, view) Cx.
+//
 // Row kernel (all views share dy, e.g. a horizontal-parallax quilt).  Y depends only on
 // (k, y), so one work-group owns one output row y for a group of G views and every x of
-// a row segment.  Per plane it stages the plane row Y_k(y) (bilinear: the two rows,
-// pre-blended vertically) into LDS as float32 with transparent guard texels on both
-// sides, so each sample is one clamped LDS read plus four FMAs into float32 registers
-// that hold (Q, T) for G views.  Planes whose row misses the plane are skipped.
+// a row segment; (Q, T) of the G views live in float32 registers.  Per plane it stages
+// into LDS the window of the plane row Y_k(y) (bilinear: the two rows blended
+// vertically) that holds every sample of the work-group, double-buffered so the next
+// plane's texels are in flight while the current one is sampled.  A sample is then one
+// LDS read plus four FMAs; the per-view offsets come through scalar loads.  Planes whose
+// row misses the plane are skipped.
 // General kernel (views with different dy): one thread per output pixel, texels read
 // straight from global memory.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
+
+#include <cstdlib>
+#include <type_traits>
 
 #include "lf_internal.h"
 
@@ -26,7 +34,6 @@ namespace lf {
 namespace {
 
 constexpr int kRowThreads = 512;
-constexpr int kRowLdsBytes = 60 * 1024;
 
 struct PlaneCo {
   float bx, by, gx, gy;
@@ -87,24 +94,125 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Row kernel.  grid = (ny, view groups, x segments), block = kRowThreads (or fewer).
-// LDS: nearest  -> row[i] = texel i-1, i in [0, wp+2)   (texels -1 and wp are zero)
-//      bilinear -> row[e] = (t_{e-2}, t_{e-1} - t_{e-2}), e in [0, wp+3)
+// Table kernel: pt[k] = (bx, by, Cy, valid) for the shared dy, ct[k][v] = Cx with rows padded
+// to kViewPad views (the padding repeats the last view).  Nearest sampling folds the 1/2 of
+// floor(X + 1/2) into Cx and Cy.
 // ---------------------------------------------------------------------------------------
+constexpr int kViewPad = 16;
+
+__host__ __device__ inline int padded_views(int V) { return (V + kViewPad - 1) / kViewPad * kViewPad; }
+
+__global__ void coeff_table(CompositeArgs a, float4* __restrict__ pt, float* __restrict__ ct) {
+  const int vp = padded_views(a.n_views);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.K * vp) return;
+  const int k = i / vp, v = min(i % vp, a.n_views - 1);
+  const float d = a.depth[k];
+  const PlaneCo pc = plane_co(d, a.c);
+  const float half = a.interp == LF_BILINEAR ? 0.0f : 0.5f;
+  const float cx = a.c.cpx + pc.gx * a.dx[v];
+  ct[i] = a.interp == LF_BILINEAR ? cx : cx + half;
+  if (i % vp == 0) {
+    const float cy = a.c.cpy + pc.gy * a.dy[0];
+    pt[k] = make_float4(pc.bx, pc.by, a.interp == LF_BILINEAR ? cy : cy + half, d - a.c.d_fwd > 0.0f ? 1.0f : 0.0f);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Row kernel.  grid = (ny, view groups, x segments), block = up to kRowThreads threads, one
+// output pixel x per thread and G views per work-group.
+//
+// Planes are processed in batches of kBatch.  A prologue (one thread per plane) derives
+// the plane row and the texel window [f0, f0 + len) that contains every sample of this
+// work-group: X is monotone in x and in Cx, so its extremes are the samples at the segment
+// ends with the extreme offsets.  Windows are staged into LDS with zeros outside the
+// plane, and a sample is floor(X) - f0 without a clamp.  A window longer than the buffer
+// falls back to the whole row [-2, wp + 1] with samples clamped onto its zero guards.
+//   nearest  : win[i] = texel f0 + i (FP16 planes keep FP16 texels, others float32)
+//   bilinear : win[2i] = t(f0 + i), win[2i+1] = t(f0 + i + 1) - t(f0 + i), float32, with t
+//              the row pair blended vertically by the plane's weight wy
+// ---------------------------------------------------------------------------------------
+constexpr int kBatch = 64;
+constexpr int kWin = 2048;                    // float4 entries per window buffer
+constexpr int kPrefetch = kWin / kRowThreads; // window entries prefetched per thread (nearest)
+constexpr int kSub = 4;                       // views sampled per scheduling block
+
+struct PlaneInfo {
+  float wy;
+  int32_t iy, f0, len;
+};
+
+__device__ __forceinline__ int cvt_flr(float x) {
+  int r;
+  asm volatile("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// LDS texel of the nearest window: FP16 planes stay FP16 (8 bytes), others are float32.
+template <typename PT> struct LdsTexel { using type = float4; };
+template <> struct LdsTexel<__half> { using type = uint2; };
+
+template <typename LT>
+__device__ __forceinline__ float4 lds_texel(const char* p);
+
+template <>
+__device__ __forceinline__ float4 lds_texel<float4>(const char* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+
+template <>
+__device__ __forceinline__ float4 lds_texel<uint2>(const char* p) {
+  const uint2 u = *reinterpret_cast<const uint2*>(p);
+  const __half2 lo = *reinterpret_cast<const __half2*>(&u.x);
+  const __half2 hi = *reinterpret_cast<const __half2*>(&u.y);
+  return make_float4(__low2float(lo), __high2float(lo), __low2float(hi), __high2float(hi));
+}
+
+template <typename PT>
+__device__ __forceinline__ uint2 load_raw_half4(const PT* p, size_t i) {
+  return reinterpret_cast<const uint2*>(p)[i];
+}
+
+// Bilinear window entry i of a plane: the vertically blended texel and its forward difference.
+template <typename PT>
+__device__ __forceinline__ void bilinear_entry(const PT* __restrict__ planes, size_t pbase, int wp, int hp,
+                                               const PlaneInfo& pi, int i, float4& t0, float4& dd) {
+  const int ix = pi.f0 + i;
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  const bool r0 = pi.iy >= 0, r1 = pi.iy + 1 < hp;
+  const size_t b0 = pbase + (size_t)pi.iy * wp, b1 = b0 + wp;
+  float4 t1 = z;
+  t0 = z;
+  if (ix >= 0 && ix < wp) t0 = lerp4(r0 ? load_texel(planes, b0 + ix) : z, r1 ? load_texel(planes, b1 + ix) : z, pi.wy);
+  if (ix + 1 >= 0 && ix + 1 < wp)
+    t1 = lerp4(r0 ? load_texel(planes, b0 + ix + 1) : z, r1 ? load_texel(planes, b1 + ix + 1) : z, pi.wy);
+  dd = make_float4(t1.x - t0.x, t1.y - t0.y, t1.z - t0.z, t1.w - t0.w);
+}
+
 template <typename PT, typename OT, int G, bool BIL>
-__global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, int seg_len) {
-  extern __shared__ float4 lds[];
-  __shared__ float sC[G];
+__global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, int seg_len,
+                                                              const float4* __restrict__ pt,
+                                                              const float* __restrict__ ct) {
+  using LT = typename std::conditional<BIL, float4, typename LdsTexel<PT>::type>::type;
+  constexpr bool RAW = std::is_same<LT, uint2>::value;     // FP16 texels copied unconverted
+  constexpr int PF = BIL ? kPrefetch / 2 : kPrefetch;
+  extern __shared__ float4 win[];                          // 2 buffers of kWin float4
+  __shared__ PlaneInfo pinfo[kBatch];
+  __shared__ int slist[kBatch];
+  __shared__ int scount[2];                                // valid planes, any clamped window
   const int y = blockIdx.x;
   const int v0 = blockIdx.y * G;
   const int nv = min(G, a.n_views - v0);
-  const int tid = threadIdx.x;
-  const int x = blockIdx.z * seg_len + tid;
-  const int wp = a.wp, hp = a.hp;
-  const PT* planes = static_cast<const PT*>(a.planes);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int xs0 = blockIdx.z * seg_len;
+  const int x = xs0 + tid;
+  const int xs1 = min(xs0 + seg_len, a.nx) - 1;
+  const int wp = a.wp, hp = a.hp, V = padded_views(a.n_views);
+  const PT* __restrict__ planes = static_cast<const PT*>(a.planes);
   const float xr = (float)x - a.c.cx;
   const float yr = (float)y - a.c.cy;
-  const float dy0 = a.dy[0];
+  const float xr_lo = (float)xs0 - a.c.cx, xr_hi = (float)xs1 - a.c.cx;
+  const size_t plane_elems = (size_t)hp * wp;
 
   float Qr[G], Qg[G], Qb[G], Tr[G];
 #pragma unroll
@@ -113,79 +221,162 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
     Tr[j] = 1.0f;
   }
 
-  for (int k = 0; k < a.K; ++k) {
-    const float d = a.depth[k];
-    const PlaneCo pc = plane_co(d, a.c);
-    const float cy = a.c.cpy + pc.gy * dy0;
-    int iy0;
-    float wy = 0.0f;
-    if (!BIL) {
-      const float Y = pc.by * yr + (cy + 0.5f);
-      iy0 = __float2int_rd(Y);
-      if (!(iy0 >= 0 && iy0 < hp)) continue;           // uniform across the work-group
-    } else {
-      const float Y = pc.by * yr + cy;
-      const float fy0 = floorf(Y);
-      wy = Y - fy0;
-      iy0 = __float2int_rd(fy0);
-      if (!(iy0 >= -1 && iy0 < hp)) continue;
-    }
-    __syncthreads();                                     // previous plane's samples are done
-    const size_t plane_base = (size_t)k * hp * wp;
-    if (!BIL) {
-      const size_t rbase = plane_base + (size_t)iy0 * wp;
-      for (int i = tid; i < wp + 2; i += blockDim.x) {
-        const int ix = i - 1;
-        lds[i] = (ix >= 0 && ix < wp) ? load_texel(planes, rbase + ix) : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int kb = 0; kb < a.K; kb += kBatch) {
+    const int nk = min(kBatch, a.K - kb);
+    __syncthreads();                                       // previous batch fully consumed
+    if (tid < 2) scount[tid] = 0;
+    __syncthreads();
+    if (tid < nk) {
+      const int k = kb + tid;
+      const float4 p = pt[k];                              // (bx, by, Cy, valid)
+      PlaneInfo pi;
+      pi.wy = 0.0f;
+      bool ok = p.w != 0.0f;
+      if (!BIL) {
+        pi.iy = __float2int_rd(p.y * yr + p.z);
+        ok = ok && pi.iy >= 0 && pi.iy < hp;
+      } else {
+        const float Y = p.y * yr + p.z;
+        const float fy0 = floorf(Y);
+        pi.wy = Y - fy0;
+        pi.iy = __float2int_rd(fy0);
+        ok = ok && pi.iy >= -1 && pi.iy < hp;
       }
-    } else {
-      const bool r0 = iy0 >= 0, r1 = iy0 + 1 < hp;
-      const size_t b0 = plane_base + (size_t)iy0 * wp, b1 = b0 + wp;
-      for (int e = tid; e < wp + 3; e += blockDim.x) {
-        const int ix = e - 2;
-        float4 t0 = make_float4(0.f, 0.f, 0.f, 0.f), t1 = t0;
-        if (ix >= 0 && ix < wp) {
-          const float4 u = r0 ? load_texel(planes, b0 + ix) : t0;
-          const float4 w = r1 ? load_texel(planes, b1 + ix) : t0;
-          t0 = lerp4(u, w, wy);
-        }
-        if (ix + 1 >= 0 && ix + 1 < wp) {
-          const float4 u = r0 ? load_texel(planes, b0 + ix + 1) : t1;
-          const float4 w = r1 ? load_texel(planes, b1 + ix + 1) : t1;
-          t1 = lerp4(u, w, wy);
-        }
-        lds[2 * e] = t0;
-        lds[2 * e + 1] = make_float4(t1.x - t0.x, t1.y - t0.y, t1.z - t0.z, t1.w - t0.w);
+      const float* crow = ct + (size_t)k * V + v0;
+      float cmin = crow[0], cmax = crow[0];
+      for (int j = 1; j < nv; ++j) {
+        cmin = fminf(cmin, crow[j]);
+        cmax = fmaxf(cmax, crow[j]);
       }
-    }
-    if (tid < nv) {
-      const float cx = a.c.cpx + pc.gx * a.dx[v0 + tid];
-      sC[tid] = BIL ? cx : cx + 0.5f;
+      const float lo = floorf(p.x * xr_lo + cmin);
+      const float hi = floorf(p.x * xr_hi + cmax) + (BIL ? 1.0f : 0.0f);
+      const int cap = BIL ? kWin / 2 : kWin;
+      bool clamp = false;
+      if (lo >= -1.0e9f && hi <= 1.0e9f && hi - lo + 1.0f <= (float)cap) {
+        pi.f0 = (int)lo;
+        pi.len = (int)(hi - lo) + 1;
+      } else {
+        pi.f0 = -2;                                        // whole row [-2, wp + 1], clamped
+        pi.len = wp + 4;
+        clamp = true;
+      }
+      pinfo[tid] = pi;
+      if (ok) {
+        slist[atomicAdd(&scount[0], 1)] = tid;             // order restored below
+        if (clamp) atomicOr(&scount[1], 1);
+      }
     }
     __syncthreads();
-    const float bxr = pc.bx * xr;
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-      if (j < nv) {
-        const float X = bxr + sC[j];
-        float4 s;
-        if (!BIL) {
-          const int ix = min(max(__float2int_rd(X), -1), wp);
-          s = lds[ix + 1];
-        } else {
-          const float fx0 = floorf(X);
-          const float w = X - fx0;
-          const int ix = min(max(__float2int_rd(fx0), -2), wp);
-          const float4 t = lds[2 * (ix + 2)];
-          const float4 dd = lds[2 * (ix + 2) + 1];
-          s = make_float4(fmaf(w, dd.x, t.x), fmaf(w, dd.y, t.y), fmaf(w, dd.z, t.z), fmaf(w, dd.w, t.w));
+    const int nvalid = __builtin_amdgcn_readfirstlane(scount[0]);
+    const bool any_clamp = __builtin_amdgcn_readfirstlane(scount[1]) != 0;
+    if (nvalid == 0) continue;
+    if (tid == 0) {                                        // front-to-back order of the valid planes
+      for (int i = 1; i < nvalid; ++i) {
+        const int v = slist[i];
+        int j = i - 1;
+        while (j >= 0 && slist[j] > v) {
+          slist[j + 1] = slist[j];
+          --j;
         }
-        Qr[j] = fmaf(Tr[j], s.x, Qr[j]);
-        Qg[j] = fmaf(Tr[j], s.y, Qg[j]);
-        Qb[j] = fmaf(Tr[j], s.z, Qb[j]);
-        Tr[j] = fmaf(-Tr[j], s.w, Tr[j]);
+        slist[j + 1] = v;
       }
     }
+    __syncthreads();
+
+    float4 pre0[PF], pre1[PF];
+    uint2 praw[RAW ? PF : 1];
+    auto fetch = [&](int k) {
+      const PlaneInfo pi = pinfo[k];
+      const size_t pbase = (size_t)(kb + k) * plane_elems;
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int i = tid + q * nt;
+        if (i < pi.len) {
+          const int ix = pi.f0 + i;
+          if constexpr (RAW) {
+            praw[q] = (ix >= 0 && ix < wp) ? load_raw_half4(planes, pbase + (size_t)pi.iy * wp + ix) : make_uint2(0u, 0u);
+          } else if constexpr (!BIL) {
+            pre0[q] = (ix >= 0 && ix < wp) ? load_texel(planes, pbase + (size_t)pi.iy * wp + ix)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+          } else {
+            bilinear_entry<PT>(planes, pbase, wp, hp, pi, i, pre0[q], pre1[q]);
+          }
+        }
+      }
+    };
+    auto store = [&](int buf, int k) {
+      const int len = pinfo[k].len;
+      float4* w = win + buf * kWin;
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int i = tid + q * nt;
+        if (i < len) {
+          if constexpr (RAW) {
+            reinterpret_cast<uint2*>(w)[i] = praw[q];
+          } else if constexpr (!BIL) {
+            w[i] = pre0[q];
+          } else {
+            w[2 * i] = pre0[q];
+            w[2 * i + 1] = pre1[q];
+          }
+        }
+      }
+    };
+    auto run = [&](auto clamp_tag) {
+      constexpr bool CLAMP = decltype(clamp_tag)::value;
+      fetch(slist[0]);
+      store(0, slist[0]);
+      __syncthreads();
+      for (int n = 0; n < nvalid; ++n) {
+        const int k = __builtin_amdgcn_readfirstlane(slist[n]);
+        const bool more = n + 1 < nvalid;
+        if (more) fetch(slist[n + 1]);
+        const int f0 = __builtin_amdgcn_readfirstlane(pinfo[k].f0);
+        const int len = __builtin_amdgcn_readfirstlane(pinfo[k].len);
+        const float* crow = ct + (size_t)(kb + k) * V + v0;
+        float Cv[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) Cv[j] = crow[j];          // scalar loads, one wait
+        const float bxr = pt[kb + k].x * xr;
+        const float xmin = (float)f0, xmax = (float)(f0 + len) - 0.5f;
+        const char* wbytes = reinterpret_cast<const char*>(win) + (n & 1) * (kWin * 16) -
+                             (ptrdiff_t)f0 * (ptrdiff_t)(BIL ? 32 : (int)sizeof(LT));
+#pragma unroll
+        for (int j0 = 0; j0 < G; j0 += kSub) {
+          // views in sub-blocks: kSub LDS reads in flight, then their blends (bounds live registers)
+          float4 sv[kSub];
+#pragma unroll
+          for (int jj = 0; jj < kSub; ++jj) {
+            const int j = j0 + jj;
+            float X = bxr + Cv[j];
+            if (CLAMP) X = __builtin_amdgcn_fmed3f(X, xmin, xmax);
+            const int ix = cvt_flr(X);
+            if (!BIL) {
+              sv[jj] = lds_texel<LT>(wbytes + (ptrdiff_t)ix * (ptrdiff_t)sizeof(LT));
+            } else {
+              const float w = __builtin_amdgcn_fractf(X);
+              const char* e = wbytes + (ptrdiff_t)ix * 32;
+              const float4 t = *reinterpret_cast<const float4*>(e);
+              const float4 dd = *reinterpret_cast<const float4*>(e + 16);
+              sv[jj] = make_float4(fmaf(w, dd.x, t.x), fmaf(w, dd.y, t.y), fmaf(w, dd.z, t.z), fmaf(w, dd.w, t.w));
+            }
+          }
+#pragma unroll
+          for (int jj = 0; jj < kSub; ++jj) {
+            const int j = j0 + jj;
+            Qr[j] = fmaf(Tr[j], sv[jj].x, Qr[j]);
+            Qg[j] = fmaf(Tr[j], sv[jj].y, Qg[j]);
+            Qb[j] = fmaf(Tr[j], sv[jj].z, Qb[j]);
+            Tr[j] = fmaf(-Tr[j], sv[jj].w, Tr[j]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (more) store((n + 1) & 1, slist[n + 1]);
+        __syncthreads();
+      }
+    };
+    (void)any_clamp;
+    run(std::true_type{});                                 // the clamp is a no-op for fitting windows
   }
   if (tid < seg_len && x < a.nx) {
     OT* out = static_cast<OT*>(a.out);
@@ -269,25 +460,27 @@ template <int G>
 int pick_cost(int V) { return ((V + G - 1) / G) * (G + 4); }
 
 template <typename PT, typename OT, bool BIL>
-hipError_t launch_rows(const CompositeArgs& a, int G, hipStream_t s) {
+hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const float* ct, hipStream_t s) {
   const int nseg = (a.nx + kRowThreads - 1) / kRowThreads;
   const int seg = (a.nx + nseg - 1) / nseg;
   const int threads = ((seg + 63) / 64) * 64;
-  const size_t lds = BIL ? (size_t)(a.wp + 3) * 32 : (size_t)(a.wp + 2) * 16;
+  const size_t lds = (size_t)2 * kWin * 16;
   const dim3 grid(a.ny, (a.n_views + G - 1) / G, nseg);
   switch (G) {
-    case 4: hipLaunchKernelGGL((composite_rows<PT, OT, 4, BIL>), grid, dim3(threads), lds, s, a, seg); break;
-    case 8: hipLaunchKernelGGL((composite_rows<PT, OT, 8, BIL>), grid, dim3(threads), lds, s, a, seg); break;
-    case 12: hipLaunchKernelGGL((composite_rows<PT, OT, 12, BIL>), grid, dim3(threads), lds, s, a, seg); break;
-    default: hipLaunchKernelGGL((composite_rows<PT, OT, 16, BIL>), grid, dim3(threads), lds, s, a, seg); break;
+    case 4: hipLaunchKernelGGL((composite_rows<PT, OT, 4, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
+    case 8: hipLaunchKernelGGL((composite_rows<PT, OT, 8, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
+    case 12: hipLaunchKernelGGL((composite_rows<PT, OT, 12, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
+    default: hipLaunchKernelGGL((composite_rows<PT, OT, 16, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
   }
   return hipGetLastError();
 }
 
 template <typename PT, typename OT>
-hipError_t dispatch_interp(const CompositeArgs& a, bool rows, int G, hipStream_t s) {
+hipError_t dispatch_interp(const CompositeArgs& a, bool rows, int G, const float4* pt, const float* ct,
+                           hipStream_t s) {
   if (rows)
-    return a.interp == LF_BILINEAR ? launch_rows<PT, OT, true>(a, G, s) : launch_rows<PT, OT, false>(a, G, s);
+    return a.interp == LF_BILINEAR ? launch_rows<PT, OT, true>(a, G, pt, ct, s)
+                                   : launch_rows<PT, OT, false>(a, G, pt, ct, s);
   const int64_t n = (int64_t)a.n_views * a.ny * a.nx;
   const dim3 grid((unsigned)((n + 255) / 256));
   if (a.interp == LF_BILINEAR)
@@ -298,26 +491,43 @@ hipError_t dispatch_interp(const CompositeArgs& a, bool rows, int G, hipStream_t
 }
 
 template <typename PT>
-hipError_t dispatch_out(const CompositeArgs& a, bool rows, int G, hipStream_t s) {
-  return a.out_dtype == LF_F16 ? dispatch_interp<PT, __half>(a, rows, G, s)
-                               : dispatch_interp<PT, float>(a, rows, G, s);
+hipError_t dispatch_out(const CompositeArgs& a, bool rows, int G, const float4* pt, const float* ct, hipStream_t s) {
+  return a.out_dtype == LF_F16 ? dispatch_interp<PT, __half>(a, rows, G, pt, ct, s)
+                               : dispatch_interp<PT, float>(a, rows, G, pt, ct, s);
 }
 
 }  // namespace
 
-hipError_t composite_launch(const CompositeArgs& a, hipStream_t s) {
+size_t composite_table_bytes(int K, int n_views) {
+  return (size_t)K * 16 + (size_t)K * padded_views(n_views) * 4 + 256;
+}
+
+hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, Profiler* prof) {
+  PhaseScope ps(prof, LF_PHASE_COMPOSITE, s);
+  float4* pt = static_cast<float4*>(table);
+  float* ct = reinterpret_cast<float*>(static_cast<char*>(table) + (((size_t)a.K * 16 + 255) & ~(size_t)255));
   bool same_dy = true;
   for (int v = 1; v < a.n_views; ++v) same_dy = same_dy && a.dy[v] == a.dy[0];
-  const size_t lds = a.interp == LF_BILINEAR ? (size_t)(a.wp + 3) * 32 : (size_t)(a.wp + 2) * 16;
-  const bool rows = same_dy && lds <= (size_t)kRowLdsBytes;
+  // the clamped whole-row fallback must fit the window buffer
+  const int row_entries = a.interp == LF_BILINEAR ? 2 * (a.wp + 4) : a.wp + 4;
+  const bool rows = same_dy && row_entries <= kWin;
   int G = 16, best = pick_cost<16>(a.n_views);
   if (pick_cost<12>(a.n_views) < best) { G = 12; best = pick_cost<12>(a.n_views); }
   if (pick_cost<8>(a.n_views) < best) { G = 8; best = pick_cost<8>(a.n_views); }
   if (pick_cost<4>(a.n_views) < best) { G = 4; best = pick_cost<4>(a.n_views); }
+  // tuning override: LF_COMPOSITE_GROUP = views per work-group (4, 8, 12 or 16)
+  if (const char* e = getenv("LF_COMPOSITE_GROUP")) {
+    const int g = atoi(e);
+    if (g == 4 || g == 8 || g == 12 || g == 16) G = g;
+  }
+  if (rows) {
+    const int n = a.K * padded_views(a.n_views);
+    hipLaunchKernelGGL(coeff_table, dim3((n + 255) / 256), dim3(256), 0, s, a, pt, ct);
+  }
   switch (a.plane_dtype) {
-    case LF_F16: return dispatch_out<__half>(a, rows, G, s);
-    case LF_BF16: return dispatch_out<__hip_bfloat16>(a, rows, G, s);
-    default: return dispatch_out<float>(a, rows, G, s);
+    case LF_F16: return dispatch_out<__half>(a, rows, G, pt, ct, s);
+    case LF_BF16: return dispatch_out<__hip_bfloat16>(a, rows, G, pt, ct, s);
+    default: return dispatch_out<float>(a, rows, G, pt, ct, s);
   }
 }
 

@@ -5,11 +5,50 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "lf.h"
 
-// Library context: the device it was created on.
+namespace lf {
+
+// HIP-event timing of kernel phases (enabled per context).
+struct Profiler {
+  struct Rec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  bool on = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double ms[LF_NUM_PHASES] = {};
+  int64_t count[LF_NUM_PHASES] = {};
+  hipEvent_t take();
+  void begin(int phase, hipStream_t s);
+  void end(hipStream_t s);
+  hipError_t collect();
+  void release();
+};
+
+// RAII bracket of one phase; a no-op when profiling is off or p is null.
+struct PhaseScope {
+  Profiler* p;
+  hipStream_t s;
+  PhaseScope(Profiler* prof, int phase, hipStream_t st) : p(prof && prof->on ? prof : nullptr), s(st) {
+    if (p) p->begin(phase, s);
+  }
+  ~PhaseScope() {
+    if (p) p->end(s);
+  }
+};
+
+}  // namespace lf
+
+// Library context: the device it was created on and its profiler.
 struct lf_ctx {
   int device;
+  lf::Profiler prof;
+  void* table = nullptr;         // device scratch of the composite's coefficient table
+  size_t table_bytes = 0;
 };
 
 namespace lf {
@@ -56,7 +95,9 @@ struct CompositeArgs {
   float dy[LF_MAX_VIEWS];
 };
 
-hipError_t composite_launch(const CompositeArgs& a, hipStream_t s);
+// Bytes of the coefficient table lf_composite keeps in its context for K planes, V views.
+size_t composite_table_bytes(int K, int n_views);
+hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, Profiler* prof = nullptr);
 hipError_t plane_coeffs_launch(const CompositeArgs& a, float* bx, float* by, float* cx, float* cy,
                                float* cxn, float* cyn, hipStream_t s);
 
