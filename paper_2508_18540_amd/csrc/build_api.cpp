@@ -23,6 +23,9 @@ BuildLayout build_layout(int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t c
   int bits = 1;
   while ((1LL << bits) < L.n_tiles) ++bits;
   L.tile_bits = bits;
+  bits = 0;
+  while ((1LL << bits) < K) ++bits;
+  L.chunk_bits = bits;                 // entry sort keys are (tile << chunk_bits) | chunk
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -44,7 +47,7 @@ BuildLayout build_layout(int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t c
   L.o_chunk_start = take((size_t)(K + 1) * 8);
   L.o_edges = take((size_t)K * 4);
   L.o_dtab = take((size_t)K * 4);
-  L.o_hist = take((size_t)(L.n_buckets + 1) * 4);
+  L.o_nseg = take((size_t)(L.n_buckets + 1) * 4);
   L.o_bucket = take((size_t)(L.n_buckets + 1) * 4);
   L.o_scan32 = take(scan_tmp_elems(L.n_buckets) * 4);
   L.o_radix = take(radix_tmp_u32(n > cap ? n : cap) * 4);
@@ -164,6 +167,8 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   hipStream_t st = (hipStream_t)stream;
 
   const BuildLayout L = build_layout(n, n_chunk, g.wp, g.hp, cap);
+  if (L.tile_bits + L.chunk_bits > 32)
+    return fail(LF_ERR_INVALID_ARG, "%d tiles x %d chunks do not fit a 32-bit (tile, chunk) key", L.n_tiles, n_chunk);
   char* w = static_cast<char*>(workspace);
   BuildArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -171,6 +176,7 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   a.capacity = cap;
   a.K = n_chunk;
   a.ntx = L.ntx;
+  a.chunk_bits = L.chunk_bits;
   a.binning = binning;
   a.plane_dtype = mpi->dtype;
   a.d_focal32 = cam->d_focal;
@@ -198,7 +204,7 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   a.chunk_start = reinterpret_cast<int64_t*>(w + L.o_chunk_start);
   a.edges = reinterpret_cast<float*>(w + L.o_edges);
   a.dtab = reinterpret_cast<float*>(w + L.o_dtab);
-  a.hist = reinterpret_cast<uint32_t*>(w + L.o_hist);
+  a.nseg = reinterpret_cast<uint32_t*>(w + L.o_nseg);
   a.bucket = reinterpret_cast<uint32_t*>(w + L.o_bucket);
   a.scan_tmp32 = reinterpret_cast<uint32_t*>(w + L.o_scan32);
   a.radix_tmp = reinterpret_cast<uint32_t*>(w + L.o_radix);

@@ -7,10 +7,11 @@
 //  sort        stable radix sort of (key, index): the (depth, index) order of Alg. 1
 //  rank        chunk of every rank (quantile: floor(r K / N_vis); inverse depth: edge count)
 //  chunks      chunk starts, counts and plane depths d_k (lower-median key)
-//  emit        one (tile, Gaussian) entry per covered tile, written in rank order, plus a
-//              (tile, chunk) histogram
-//  tile sort   stable radix sort of the entries by tile: each tile's list stays in rank
-//              order, so every (tile, chunk) bucket is a contiguous, depth-ordered run
+//  emit        one (tile, Gaussian) entry per covered tile, written in rank order, keyed
+//              (tile << chunk_bits) | chunk
+//  tile sort   stable radix sort of the entries by the tile bits only: each tile's list stays
+//              in rank order, so every (tile, chunk) bucket is a contiguous, depth-ordered
+//              run whose start a binary search over the sorted keys finds
 //  splat       one work-group per (tile, chunk): front-to-back blending of the bucket into
 //              premultiplied RGBA (C, 1 - T) with alpha = min(0.99, o G), only where
 //              o G >= 1/255, no early termination
@@ -51,9 +52,6 @@ __global__ __launch_bounds__(256) void preprocess_gs(BuildArgs a) {
   const float zr = key - c.d_fwd;
   const bool vis = in && isfinite(key) && isfinite(xc) && isfinite(yc) && zr > c.z_near &&
                    fabsf(xc) <= c.guard_x * zr && fabsf(yc) <= c.guard_y * zr;
-  const uint64_t wv = __ballot(vis);
-  if ((threadIdx.x & 63) == 0 && wv)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&a.hdr->n_vis), (unsigned long long)__popcll(wv));
   if (!in) return;
   a.keys[i] = vis ? orderable(key) : 0xffffffffu;
   a.vals[i] = (uint32_t)i;
@@ -144,6 +142,15 @@ __global__ __launch_bounds__(256) void preprocess_gs(BuildArgs a) {
   }
   a.rec[i] = r;
   a.ntiles_i[i] = nt;
+}
+
+// N_vis = number of visible keys: culled primitives carry the largest key and sort last, so
+// the one rank whose key is visible and whose successor is not (or is the end) sets it.
+// (The header starts at zero, which stays the answer when nothing is visible.)
+__global__ __launch_bounds__(256) void find_nvis(BuildArgs a, const uint32_t* skeys) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n) return;
+  if (skeys[r] != 0xffffffffu && (r + 1 == a.n || skeys[r + 1] == 0xffffffffu)) a.hdr->n_vis = r + 1;
 }
 
 // chunk of a visible key under inverse-depth binning: number of interior edges <= key
@@ -275,10 +282,29 @@ __global__ __launch_bounds__(256) void emit_entries(BuildArgs a, const uint32_t*
     }
     const uint32_t tile = (uint32_t)(ty * a.ntx + tx);
     const uint64_t dst = O0 + o;
-    a.ekeys[dst] = tile;
+    a.ekeys[dst] = (tile << a.chunk_bits) | schunk[j];
     a.evals[dst] = sidx[j] | (mask << 28);
-    atomicAdd(&a.hist[(int64_t)tile * a.K + schunk[j]], 1u);
   }
+}
+
+// Start of every (tile, chunk) bucket in the tile-sorted entry list: the first entry whose
+// (tile, chunk) key is not below the bucket's.  bucket[n_buckets] = number of entries.
+__global__ __launch_bounds__(256) void bucket_bounds(BuildArgs a, const uint32_t* sekeys, int64_t n_buckets) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > n_buckets) return;
+  const int64_t ne = a.hdr->overflow ? 0 : min(a.hdr->entries, a.capacity);
+  if (b == n_buckets) {
+    a.bucket[b] = (uint32_t)ne;
+    return;
+  }
+  const uint32_t key = ((uint32_t)(b / a.K) << a.chunk_bits) | (uint32_t)(b % a.K);
+  int64_t lo = 0, hi = ne;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (sekeys[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  a.bucket[b] = (uint32_t)lo;
 }
 
 __global__ void finalize(BuildArgs a) {
@@ -325,13 +351,13 @@ __device__ __forceinline__ void store_rgba<__hip_bfloat16>(__hip_bfloat16* p, si
 }
 
 // Split every (tile, chunk) bucket into segments of at most kSegment entries: nseg per
-// bucket (into hist, free after the bucket scan) and the partial-tile slots of split buckets.
+// bucket and the number of partial-tile slots of split buckets.
 __global__ void bucket_segments(BuildArgs a, int64_t n_buckets) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_buckets) return;
   const uint32_t len = a.bucket[b + 1] - a.bucket[b];
   const uint32_t ns = len ? (len + kSegment - 1) / kSegment : 1u;
-  a.hist[b] = ns;
+  a.nseg[b] = ns;
   a.pcnt[b] = ns > 1 ? ns : 0u;
 }
 
@@ -445,9 +471,7 @@ hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Pr
   const unsigned gN = (unsigned)((a.n + 255) / 256);
   {
     PhaseScope ps(prof, LF_PHASE_PREPROCESS, s);
-    // zero the header and the (tile, chunk) histogram
     if ((e = fill(reinterpret_cast<uint32_t*>(a.hdr), sizeof(BuildHeader) / 4, 0u, s)) != hipSuccess) return e;
-    if ((e = fill(a.hist, L.n_buckets + 1, 0u, s)) != hipSuccess) return e;
     if (a.n == 0) {
       // nothing to rasterise: transparent planes at D_focal (or the inverse-depth table)
       const size_t words = (size_t)a.K * a.c.hp * a.c.wp * (a.plane_dtype == LF_F32 ? 4 : 2);
@@ -462,7 +486,7 @@ hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Pr
   int alt = 0;
   {
     PhaseScope ps(prof, LF_PHASE_SORT, s);
-    if ((e = radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.n, nullptr, 32, a.radix_tmp, &alt, s)) !=
+    if ((e = radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.n, nullptr, 0, 32, a.radix_tmp, &alt, s)) !=
         hipSuccess)
       return e;
   }
@@ -470,6 +494,7 @@ hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Pr
   const uint32_t* svals = alt ? a.vals_alt : a.vals;
   {
     PhaseScope ps(prof, LF_PHASE_BIN, s);
+    hipLaunchKernelGGL(find_nvis, dim3(gN), dim3(256), 0, s, a, skeys);
     hipLaunchKernelGGL(rank_pass, dim3(gN), dim3(256), 0, s, a, skeys, svals);
     hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, skeys);
     hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, skeys);
@@ -479,15 +504,17 @@ hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Pr
     // stable sort of the entries by tile (entries beyond the capacity are never read)
     int ealt = 0;
     if ((e = radix_sort_pairs(a.ekeys, a.evals, a.ekeys_alt, a.evals_alt, a.capacity,
-                              reinterpret_cast<const int64_t*>(&a.hdr->entries), L.tile_bits, a.radix_tmp, &ealt,
-                              s)) != hipSuccess)
+                              reinterpret_cast<const int64_t*>(&a.hdr->entries), L.chunk_bits, L.tile_bits,
+                              a.radix_tmp, &ealt, s)) != hipSuccess)
       return e;
     if (ealt) a.evals = a.evals_alt;
-    if ((e = exclusive_scan<uint32_t>(a.hist, a.bucket, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
-    // work items: buckets split into segments of at most kSegment entries
+    const uint32_t* sekeys = ealt ? a.ekeys_alt : a.ekeys;
     const unsigned gB = (unsigned)((L.n_buckets + 255) / 256);
+    hipLaunchKernelGGL(bucket_bounds, dim3((unsigned)((L.n_buckets + 1 + 255) / 256)), dim3(256), 0, s, a, sekeys,
+                       L.n_buckets);
+    // work items: buckets split into segments of at most kSegment entries
     hipLaunchKernelGGL(bucket_segments, dim3(gB), dim3(256), 0, s, a, L.n_buckets);
-    if ((e = exclusive_scan<uint32_t>(a.hist, a.item_start, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
+    if ((e = exclusive_scan<uint32_t>(a.nseg, a.item_start, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
     if ((e = exclusive_scan<uint32_t>(a.pcnt, a.pslot, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(emit_items, dim3(gB), dim3(256), 0, s, a, L.n_buckets);
   }

@@ -32,9 +32,9 @@ constexpr int kSegment = 256;         // entries per splat work item (longer buc
 
 struct BuildLayout {
   int64_t n, cap, n_buckets;
-  int32_t K, ntx, nty, n_tiles, tile_bits;
+  int32_t K, ntx, nty, n_tiles, tile_bits, chunk_bits;
   size_t o_hdr, o_keys, o_vals, o_keys_alt, o_vals_alt, o_rec, o_ntiles_i, o_ntiles_r, o_chunk_r, o_offsets,
-      o_scan64, o_chunk_start, o_edges, o_dtab, o_hist, o_bucket, o_scan32, o_radix, o_ekeys, o_evals, o_ekeys_alt,
+      o_scan64, o_chunk_start, o_edges, o_dtab, o_nseg, o_bucket, o_scan32, o_radix, o_ekeys, o_evals, o_ekeys_alt,
       o_evals_alt, o_pcnt, o_item_start, o_pslot, o_items, o_partial;
   int64_t max_items, max_partial;
   size_t total;
@@ -45,7 +45,7 @@ BuildLayout build_layout(int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t c
 
 struct BuildArgs {
   int64_t n, capacity;
-  int32_t K, ntx, binning, plane_dtype;
+  int32_t K, ntx, binning, plane_dtype, chunk_bits;
   float d_focal32;
   Consts c;
   // field (Gaussians)
@@ -64,7 +64,7 @@ struct BuildArgs {
   uint64_t *offsets, *scan_tmp64;
   int64_t* chunk_start;
   float *edges, *dtab;
-  uint32_t *hist, *bucket, *scan_tmp32, *radix_tmp;
+  uint32_t *nseg, *bucket, *scan_tmp32, *radix_tmp;
   uint32_t *ekeys, *evals, *ekeys_alt, *evals_alt;
   // splat work items: bucket segments and their partial (C, T) tiles
   uint32_t *pcnt, *item_start, *pslot;

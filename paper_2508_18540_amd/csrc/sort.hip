@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_top(T* block_sums, int nb, 
       block_sums[b0 + i] = run;
       run += v;
     }
-  if (threadIdx.x == 0 && total_out) *total_out = total;
+  if (threadIdx.x == 0) *total_out = total;
 }
 
 template <typename T>
@@ -82,9 +82,6 @@ __global__ __launch_bounds__(kScanThreads) void scan_down(const T* in, T* out, i
   }
 }
 
-template <typename T>
-__global__ void scan_write_total(T* out, int64_t n, const T* total) { out[n] = *total; }
-
 // ---------------------------------------------------------------------------------------
 // Radix sort.  P blocks; block b sorts the elements [b*span, min(n, (b+1)*span)) where
 // span = ceil(n / (P*256)) * 256 and n is read from device memory.
@@ -102,27 +99,31 @@ __device__ __forceinline__ int64_t block_span(int64_t n) {
   return per * kRadixThreads;
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kRadixThreads) void radix_upsweep(const uint32_t* keys, const int64_t* n_dev,
                                                                int64_t n_host, int64_t cap, int shift,
-                                                               uint32_t* counts) {
-  __shared__ uint32_t hist[256];
+                                                               uint32_t mask, uint32_t* counts) {
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t hist[R];
   const int64_t n = sort_len(n_dev, n_host, cap);
   const int64_t span = block_span(n);
   const int64_t b0 = (int64_t)blockIdx.x * span;
   const int64_t b1 = min(n, b0 + span);
-  hist[threadIdx.x] = 0;
+  for (int d = threadIdx.x; d < R; d += kRadixThreads) hist[d] = 0;
   __syncthreads();
-  for (int64_t e = b0 + threadIdx.x; e < b1; e += kRadixThreads) atomicAdd(&hist[(keys[e] >> shift) & 255u], 1u);
+  for (int64_t e = b0 + threadIdx.x; e < b1; e += kRadixThreads) atomicAdd(&hist[(keys[e] >> shift) & mask], 1u);
   __syncthreads();
-  counts[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = hist[threadIdx.x];
+  for (int d = threadIdx.x; d < R; d += kRadixThreads) counts[(int64_t)d * gridDim.x + blockIdx.x] = hist[d];
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kRadixThreads) void radix_downsweep(const uint32_t* keys_in, const uint32_t* vals_in,
                                                                  uint32_t* keys_out, uint32_t* vals_out,
                                                                  const int64_t* n_dev, int64_t n_host, int64_t cap,
-                                                                 int shift, const uint32_t* offsets) {
-  __shared__ uint32_t running[256];
-  __shared__ uint32_t wcount[kWaves][256];
+                                                                 int shift, uint32_t mask, const uint32_t* offsets) {
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t running[R];
+  __shared__ uint32_t wcount[kWaves][R];
   const int64_t n = sort_len(n_dev, n_host, cap);
   const int64_t span = block_span(n);
   const int64_t b0 = (int64_t)blockIdx.x * span;
@@ -130,8 +131,10 @@ __global__ __launch_bounds__(kRadixThreads) void radix_downsweep(const uint32_t*
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  running[tid] = offsets[(int64_t)tid * gridDim.x + blockIdx.x];
-  for (int w = 0; w < kWaves; ++w) wcount[w][tid] = 0;
+  for (int d = tid; d < R; d += kRadixThreads) {
+    running[d] = offsets[(int64_t)d * gridDim.x + blockIdx.x];
+    for (int w = 0; w < kWaves; ++w) wcount[w][d] = 0;
+  }
   __syncthreads();
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   for (int64_t r0 = b0; r0 < b1; r0 += kRadixThreads) {
@@ -141,18 +144,20 @@ __global__ __launch_bounds__(kRadixThreads) void radix_downsweep(const uint32_t*
     if (valid) {
       key = keys_in[e];
       val = vals_in[e];
-      d = (key >> shift) & 255u;
+      d = (key >> shift) & mask;
     }
     // lanes of this wave holding the same digit
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
     const uint32_t rank = __popcll(peers & lt);
-    if (valid && rank == 0) wcount[wave][d] = __popcll(peers);
+    const uint32_t cnt = __popcll(peers);
+    const bool leader = valid && rank == 0;
+    if (leader) wcount[wave][d] = cnt;
     __syncthreads();
     if (valid) {
       uint32_t pos = running[d] + rank;
@@ -161,13 +166,13 @@ __global__ __launch_bounds__(kRadixThreads) void radix_downsweep(const uint32_t*
       vals_out[pos] = val;
     }
     __syncthreads();
-    uint32_t add = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      add += wcount[w][tid];
-      wcount[w][tid] = 0;
+    // Only the digits present in this round change: each wave's leader for a digit advances
+    // the running offset and clears its count.  The next round reads both only after its
+    // first barrier, which every wave reaches after these updates.
+    if (leader) {
+      atomicAdd(&running[d], cnt);
+      wcount[wave][d] = 0;
     }
-    running[tid] += add;
-    __syncthreads();
   }
 }
 
@@ -190,9 +195,8 @@ hipError_t exclusive_scan(const T* in, T* out, int64_t n, T* tmp, hipStream_t s)
   }
   if (nb > kScanChunk) return hipErrorInvalidValue;
   hipLaunchKernelGGL((scan_reduce<T>), dim3(nb), dim3(kScanThreads), 0, s, in, n, tmp);
-  hipLaunchKernelGGL((scan_top<T>), dim3(1), dim3(kScanThreads), 0, s, tmp, nb, tmp + nb);
+  hipLaunchKernelGGL((scan_top<T>), dim3(1), dim3(kScanThreads), 0, s, tmp, nb, out + n);
   hipLaunchKernelGGL((scan_down<T>), dim3(nb), dim3(kScanThreads), 0, s, in, out, n, tmp);
-  hipLaunchKernelGGL((scan_write_total<T>), dim3(1), dim3(1), 0, s, out, n, tmp + nb);
   return hipGetLastError();
 }
 
@@ -204,26 +208,44 @@ int radix_blocks(int64_t cap) {
   return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
 
+constexpr int kMaxDigitBits = 11;
+
 size_t radix_tmp_u32(int64_t cap) {
-  const int64_t nc = 256LL * radix_blocks(cap);
+  const int64_t nc = (1LL << kMaxDigitBits) * radix_blocks(cap);
   return (size_t)(2 * nc + scan_tmp_elems(nc) + 1);
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t cap,
-                            const int64_t* n_dev, int bits, uint32_t* tmp, int* result_in_alt, hipStream_t s) {
+                            const int64_t* n_dev, int lo_bit, int bits, uint32_t* tmp, int* result_in_alt,
+                            hipStream_t s) {
+  if (bits < 1 || lo_bit < 0 || lo_bit + bits > 32) return hipErrorInvalidValue;
   const int P = radix_blocks(cap);
-  const int64_t nc = 256LL * P;
+  // passes of at most kMaxDigitBits bits, as even as possible (32 bits: 11 + 11 + 10)
+  const int npass = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+  const int dbits = (bits + npass - 1) / npass;
+  const int64_t nc = (1LL << dbits) * P;
   uint32_t* counts = tmp;
   uint32_t* offs = tmp + nc;
-  uint32_t* stmp = tmp + 2 * nc;
+  uint32_t* stmp = tmp + 2 * nc + 1;       // offs holds nc + 1 values (the scan writes the total)
   uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
   int passes = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(radix_upsweep, dim3(P), dim3(kRadixThreads), 0, s, ki, n_dev, cap, cap, shift, counts);
+  for (int shift = lo_bit; shift < lo_bit + bits; shift += dbits) {
+    const int w = lo_bit + bits - shift < dbits ? lo_bit + bits - shift : dbits;
+    const uint32_t mask = (1u << w) - 1u;   // the last pass may be narrower
+    switch (dbits) {
+#define LF_RADIX_UP(B) case B: hipLaunchKernelGGL(radix_upsweep<B>, dim3(P), dim3(kRadixThreads), 0, s, ki, n_dev, cap, cap, shift, mask, counts); break;
+      LF_RADIX_UP(1) LF_RADIX_UP(2) LF_RADIX_UP(3) LF_RADIX_UP(4) LF_RADIX_UP(5) LF_RADIX_UP(6)
+      LF_RADIX_UP(7) LF_RADIX_UP(8) LF_RADIX_UP(9) LF_RADIX_UP(10) default: LF_RADIX_UP(11)
+#undef LF_RADIX_UP
+    }
     hipError_t e = exclusive_scan<uint32_t>(counts, offs, nc, stmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_downsweep, dim3(P), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, n_dev, cap, cap, shift,
-                       offs);
+    switch (dbits) {
+#define LF_RADIX_DOWN(B) case B: hipLaunchKernelGGL(radix_downsweep<B>, dim3(P), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, n_dev, cap, cap, shift, mask, offs); break;
+      LF_RADIX_DOWN(1) LF_RADIX_DOWN(2) LF_RADIX_DOWN(3) LF_RADIX_DOWN(4) LF_RADIX_DOWN(5) LF_RADIX_DOWN(6)
+      LF_RADIX_DOWN(7) LF_RADIX_DOWN(8) LF_RADIX_DOWN(9) LF_RADIX_DOWN(10) default: LF_RADIX_DOWN(11)
+#undef LF_RADIX_DOWN
+    }
     uint32_t* t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
     ++passes;
