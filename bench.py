@@ -27,6 +27,41 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
+
+# HBM traffic per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB
+# per dispatch) of `bench.py --steps 2 --warmup 1 --forms f32 --copy-calibration`, scaled by
+# what the same counters read for a plain 256 MiB device copy (FETCH_SIZE 131088 KiB,
+# WRITE_SIZE 262144 KiB): fetch x 2.0, write x 1.0.  Each entry records a digest of the
+# kernel's source text; when the kernel has changed since, the traffic is reported as null.
+COPY_FETCH_SCALE = 262144.0 / 131088.0
+COPY_WRITE_SCALE = 262144.0 / 262144.0
+MEASURED_TRAFFIC = {
+    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=146970, write_kib=286992,
+                     digest="d58eb10c8e858dce"),
+    "composite_rows": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=300919, write_kib=184320,
+                           digest="55e5949179a77c98"),
+}
+
+
+def kernel_digest(path, name):
+    """sha1 of a kernel's definition: from its signature to the closing brace in column 0."""
+    import hashlib
+    import re
+
+    text = open(os.path.join(ROOT, path)).read()
+    m = re.search(r"^(template <[^\n]*>\n)?__global__[^\n]*\b" + re.escape(name) + r"\(", text, re.M)
+    if not m:
+        return None
+    end = text.find("\n}\n", m.start())
+    return hashlib.sha1(text[m.start():end].encode()).hexdigest()[:16] if end > 0 else None
+
+
+def measured_traffic(name):
+    """Counter-measured HBM bytes per launch of `name`, or None if the kernel changed since."""
+    t = MEASURED_TRAFFIC.get(name)
+    if t is None or kernel_digest(t["src"], name) != t["digest"]:
+        return None
+    return int(round((t["fetch_kib"] * COPY_FETCH_SCALE + t["write_kib"] * COPY_WRITE_SCALE) * 1024))
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: float32 lane-ops/s (no packed math)
 FP32_PEAK_TFLOPS = 2 * VALU_LANE_OPS / 1e12   # one FMA = 2 flops per lane-op -> 78.6
 
@@ -38,8 +73,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--interp", default="nearest", choices=["nearest", "bilinear"])
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-planes", type=int, default=4, help="planes the CPU oracle rasterises")
-    p.add_argument("--cpu-views", type=int, default=2, help="views the CPU oracle composites")
+    p.add_argument("--cpu-planes", type=int, default=48, help="planes the CPU oracle rasterises")
+    p.add_argument("--cpu-views", type=int, default=6, help="views the CPU oracle composites")
     p.add_argument("--forms", default="f32,f16", help="plane storage forms to time (first one is `value`)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (for HBM counter scaling)")
@@ -141,7 +176,8 @@ def main():
         comp_ms = phases["composite"]
         comp_roof = dict(bound="hbm", achieved=round(comp_bytes / (comp_ms * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS,
                          unit="GB/s", frac=round(comp_bytes / (comp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                         traffic=None, kernel="composite_rows", bytes_per_launch=comp_bytes,
+                         traffic=measured_traffic("composite_rows") if form == "f32" else None,
+                         kernel="composite_rows", bytes_per_launch=comp_bytes,
                          avg_ms=round(comp_ms, 4))
         # splat: algorithmic work = (entry, texel) evaluations of the tile lists; one evaluation is
         # about 8 FMA-equivalent lane-ops on the included texels (quadratic form, exp2, blend)
@@ -150,7 +186,8 @@ def main():
         splat_roof = dict(bound="alu", achieved=round(evals * 16 / (splat_ms * 1e-3) / 1e12, 3),
                           peak=round(FP32_PEAK_TFLOPS, 1), unit="TFLOP/s",
                           frac=round(evals * 16 / (splat_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
-                          traffic=None, kernel="splat_gs", flops_per_launch=evals * 16, avg_ms=round(splat_ms, 4))
+                          traffic=measured_traffic("splat_gs") if form == "f32" else None, kernel="splat_gs",
+                          flops_per_launch=evals * 16, avg_ms=round(splat_ms, 4))
         return dict(form=form, ms_per_step=ms, views_per_s=V / (ms * 1e-3), phases_ms=phases,
                     composite_roofline=comp_roof, splat_roofline=splat_roof, entries=int(info.entries_needed),
                     n_visible=int(info.n_visible))

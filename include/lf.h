@@ -182,12 +182,14 @@ lf_status lf_plane_coeffs(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, 
 /* Per-phase device timing, a tracing aid.  While enabled, each entry point brackets its
  * kernel phases with HIP events recorded on the launch stream; lf_profile_read sums the
  * elapsed times.  Phases: PREPROCESS (cull, key, projection), SORT (depth sort), BIN
- * (chunking, tile lists), SPLAT (plane rasterisation), FILTER (voxel plane low-pass),
- * COMPOSITE (swizzle blending), and the two backward passes.                            */
+ * (chunking, tile lists), SPLAT (the plane rasterisation kernel alone), MERGE (over-
+ * composition of split tile lists), FILTER (voxel plane low-pass), COEFF (per-plane,
+ * per-view sampling coefficients), COMPOSITE (the swizzle-blend kernel alone), and the
+ * two backward passes.                                                                  */
 typedef enum {
   LF_PHASE_PREPROCESS = 0, LF_PHASE_SORT = 1, LF_PHASE_BIN = 2, LF_PHASE_SPLAT = 3,
-  LF_PHASE_FILTER = 4, LF_PHASE_COMPOSITE = 5, LF_PHASE_COMPOSITE_BWD = 6, LF_PHASE_BUILD_BWD = 7,
-  LF_NUM_PHASES = 8
+  LF_PHASE_MERGE = 4, LF_PHASE_FILTER = 5, LF_PHASE_COEFF = 6, LF_PHASE_COMPOSITE = 7,
+  LF_PHASE_COMPOSITE_BWD = 8, LF_PHASE_BUILD_BWD = 9, LF_NUM_PHASES = 10
 } lf_phase;
 
 lf_status lf_profile_enable(lf_ctx* ctx, int32_t enable);

@@ -29,7 +29,8 @@ EXPORTS = [
     "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_plane_coeffs",
     "lf_profile_enable", "lf_profile_read",
 ]
-PHASES = ["preprocess", "sort", "bin", "splat", "filter", "composite", "composite_bwd", "build_bwd"]
+PHASES = ["preprocess", "sort", "bin", "splat", "merge", "filter", "coeff", "composite", "composite_bwd",
+          "build_bwd"]
 
 
 class LFError(RuntimeError):

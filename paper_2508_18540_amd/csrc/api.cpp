@@ -107,14 +107,15 @@ hipEvent_t Profiler::take() {
   return e;
 }
 
-void Profiler::begin(int phase, hipStream_t s) {
+size_t Profiler::begin(int phase, hipStream_t s) {
   Rec r{phase, take(), take()};
   if (r.a) hipEventRecord(r.a, s);
   recs.push_back(r);
+  return recs.size() - 1;
 }
 
-void Profiler::end(hipStream_t s) {
-  if (!recs.empty() && recs.back().b) hipEventRecord(recs.back().b, s);
+void Profiler::end(size_t rec, hipStream_t s) {
+  if (rec < recs.size() && recs[rec].b) hipEventRecord(recs[rec].b, s);
 }
 
 hipError_t Profiler::collect() {

@@ -522,18 +522,18 @@ hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Pr
     PhaseScope ps(prof, LF_PHASE_SPLAT, s);
     const dim3 grid((unsigned)L.max_items);
     switch (a.plane_dtype) {
-      case LF_F16:
-        hipLaunchKernelGGL((splat_gs<__half>), grid, dim3(256), 0, s, a, L.n_buckets);
-        hipLaunchKernelGGL((combine_segments<__half>), dim3((unsigned)L.n_buckets), dim3(256), 0, s, a);
-        break;
-      case LF_BF16:
-        hipLaunchKernelGGL((splat_gs<__hip_bfloat16>), grid, dim3(256), 0, s, a, L.n_buckets);
-        hipLaunchKernelGGL((combine_segments<__hip_bfloat16>), dim3((unsigned)L.n_buckets), dim3(256), 0, s, a);
-        break;
-      default:
-        hipLaunchKernelGGL((splat_gs<float>), grid, dim3(256), 0, s, a, L.n_buckets);
-        hipLaunchKernelGGL((combine_segments<float>), dim3((unsigned)L.n_buckets), dim3(256), 0, s, a);
-        break;
+      case LF_F16: hipLaunchKernelGGL((splat_gs<__half>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+      case LF_BF16: hipLaunchKernelGGL((splat_gs<__hip_bfloat16>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+      default: hipLaunchKernelGGL((splat_gs<float>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+    }
+  }
+  {
+    PhaseScope ps(prof, LF_PHASE_MERGE, s);
+    const dim3 grid((unsigned)L.n_buckets);
+    switch (a.plane_dtype) {
+      case LF_F16: hipLaunchKernelGGL((combine_segments<__half>), grid, dim3(256), 0, s, a); break;
+      case LF_BF16: hipLaunchKernelGGL((combine_segments<__hip_bfloat16>), grid, dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL((combine_segments<float>), grid, dim3(256), 0, s, a); break;
     }
   }
   return hipGetLastError();

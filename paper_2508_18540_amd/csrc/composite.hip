@@ -503,7 +503,6 @@ size_t composite_table_bytes(int K, int n_views) {
 }
 
 hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, Profiler* prof) {
-  PhaseScope ps(prof, LF_PHASE_COMPOSITE, s);
   float4* pt = static_cast<float4*>(table);
   float* ct = reinterpret_cast<float*>(static_cast<char*>(table) + (((size_t)a.K * 16 + 255) & ~(size_t)255));
   bool same_dy = true;
@@ -521,9 +520,11 @@ hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, 
     if (g == 4 || g == 8 || g == 12 || g == 16) G = g;
   }
   if (rows) {
+    PhaseScope ps(prof, LF_PHASE_COEFF, s);
     const int n = a.K * padded_views(a.n_views);
     hipLaunchKernelGGL(coeff_table, dim3((n + 255) / 256), dim3(256), 0, s, a, pt, ct);
   }
+  PhaseScope ps(prof, LF_PHASE_COMPOSITE, s);
   switch (a.plane_dtype) {
     case LF_F16: return dispatch_out<__half>(a, rows, G, pt, ct, s);
     case LF_BF16: return dispatch_out<__hip_bfloat16>(a, rows, G, pt, ct, s);

@@ -23,8 +23,8 @@ struct Profiler {
   double ms[LF_NUM_PHASES] = {};
   int64_t count[LF_NUM_PHASES] = {};
   hipEvent_t take();
-  void begin(int phase, hipStream_t s);
-  void end(hipStream_t s);
+  size_t begin(int phase, hipStream_t s);   // returns the record's index for end()
+  void end(size_t rec, hipStream_t s);
   hipError_t collect();
   void release();
 };
@@ -33,11 +33,12 @@ struct Profiler {
 struct PhaseScope {
   Profiler* p;
   hipStream_t s;
+  size_t rec = 0;
   PhaseScope(Profiler* prof, int phase, hipStream_t st) : p(prof && prof->on ? prof : nullptr), s(st) {
-    if (p) p->begin(phase, s);
+    if (p) rec = p->begin(phase, s);
   }
   ~PhaseScope() {
-    if (p) p->end(s);
+    if (p) p->end(rec, s);
   }
 };
 
