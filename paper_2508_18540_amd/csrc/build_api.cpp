@@ -10,9 +10,15 @@ namespace lf {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-BuildLayout build_layout(int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t cap) {
+BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t cap) {
   BuildLayout L;
   std::memset(&L, 0, sizeof(L));
+  L.kind = kind;
+  L.rec_bytes = kind == LF_VOXELS ? (int32_t)sizeof(VRec) : (int32_t)sizeof(GRec);
+  if (kind == LF_VOXELS) {
+    L.filt_bands = (hp + kFiltRows - 1) / kFiltRows;
+    L.filt_segs = (wp + kFiltCols - 1) / kFiltCols;
+  }
   L.n = n;
   L.cap = cap;
   L.K = K;
@@ -38,7 +44,7 @@ BuildLayout build_layout(int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t c
   L.o_vals = take(un * 4);
   L.o_keys_alt = take(un * 4);
   L.o_vals_alt = take(un * 4);
-  L.o_rec = take(un * sizeof(GRec));
+  L.o_rec = take(un * (size_t)L.rec_bytes);
   L.o_ntiles_i = take(un * 4);
   L.o_ntiles_r = take(un * 8);
   L.o_chunk_r = take(un * 4);
@@ -64,6 +70,8 @@ BuildLayout build_layout(int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t c
   L.o_pslot = take((size_t)(L.n_buckets + 1) * 4);
   L.o_items = take((size_t)L.max_items * 8);
   L.o_partial = take((size_t)L.max_partial * kTile * kTile * 16);
+  L.o_halo_rows = take((size_t)K * L.filt_bands * 2 * wp * 16);
+  L.o_halo_cols = take((size_t)K * L.filt_segs * 2 * hp * 16);
   L.total = o;
   return L;
 }
@@ -81,12 +89,12 @@ int64_t default_capacity(int64_t n) {
 }
 
 // The largest entry capacity a workspace of `bytes` holds (0 if none).
-int64_t capacity_of(int64_t n, int32_t K, int32_t wp, int32_t hp, size_t bytes) {
-  const size_t fixed = build_layout(n, K, wp, hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
+int64_t capacity_of(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t hp, size_t bytes) {
+  const size_t fixed = build_layout(kind, n, K, wp, hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
   if (bytes <= fixed) return 0;
   int64_t cap = (int64_t)((bytes - fixed) / kBytesPerEntry);
   if (cap > kMaxEntries) cap = kMaxEntries;
-  while (cap > 0 && build_layout(n, K, wp, hp, cap).total > bytes) cap -= 64;
+  while (cap > 0 && build_layout(kind, n, K, wp, hp, cap).total > bytes) cap -= 64;
   return cap > 0 ? cap : 0;
 }
 
@@ -98,7 +106,15 @@ lf_status check_field(const lf_field* f) {
       return fail(LF_ERR_INVALID_ARG, "a Gaussian attribute pointer is NULL");
     return LF_OK;
   }
-  if (f->kind == LF_VOXELS) return fail(LF_ERR_UNSUPPORTED, "voxel fields are not supported by this build");
+  if (f->kind == LF_VOXELS) {
+    if (f->n > 0 && !(f->ijk && f->density && f->rgb))
+      return fail(LF_ERR_INVALID_ARG, "a voxel attribute pointer is NULL");
+    if (!(std::isfinite(f->voxel_size) && f->voxel_size > 0.0f))
+      return fail(LF_ERR_INVALID_ARG, "voxel_size must be finite and positive");
+    if (!(std::isfinite(f->origin[0]) && std::isfinite(f->origin[1]) && std::isfinite(f->origin[2])))
+      return fail(LF_ERR_INVALID_ARG, "voxel grid origin must be finite");
+    return LF_OK;
+  }
   return fail(LF_ERR_INVALID_ARG, "field kind %d is not GAUSSIANS/VOXELS", f->kind);
 }
 
@@ -124,7 +140,8 @@ extern "C" lf_status lf_build_mpi_workspace(const lf_field* field, const lf_came
   if (s != LF_OK) return s;
   if (entry_capacity > kMaxEntries) return fail(LF_ERR_INVALID_ARG, "entry_capacity exceeds 2^31 - 1");
   const int64_t cap = entry_capacity > 0 ? entry_capacity : default_capacity(field->n);
-  const size_t fixed = build_layout(field->n, n_chunk, g.wp, g.hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
+  const size_t fixed =
+      build_layout(field->kind, field->n, n_chunk, g.wp, g.hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
   *bytes = fixed + (size_t)cap * kBytesPerEntry + 4096;
   return LF_OK;
 }
@@ -155,7 +172,7 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   if (!mpi->rgba || !mpi->depth) return fail(LF_ERR_INVALID_ARG, "mpi rgba/depth is NULL");
   if (!workspace) return fail(LF_ERR_INVALID_ARG, "workspace is NULL");
   const int64_t n = field->n;
-  const int64_t cap = capacity_of(n, n_chunk, g.wp, g.hp, workspace_bytes);
+  const int64_t cap = capacity_of(field->kind, n, n_chunk, g.wp, g.hp, workspace_bytes);
   if (cap < 1) {
     size_t need = 0;
     lf_build_mpi_workspace(field, cam, n_chunk, 0, &need);
@@ -166,7 +183,7 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
 
-  const BuildLayout L = build_layout(n, n_chunk, g.wp, g.hp, cap);
+  const BuildLayout L = build_layout(field->kind, n, n_chunk, g.wp, g.hp, cap);
   if (L.tile_bits + L.chunk_bits > 32)
     return fail(LF_ERR_INVALID_ARG, "%d tiles x %d chunks do not fit a 32-bit (tile, chunk) key", L.n_tiles, n_chunk);
   char* w = static_cast<char*>(workspace);
@@ -177,6 +194,10 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   a.K = n_chunk;
   a.ntx = L.ntx;
   a.chunk_bits = L.chunk_bits;
+  a.kind = field->kind;
+  a.rec_bytes = L.rec_bytes;
+  a.filt_bands = L.filt_bands;
+  a.filt_segs = L.filt_segs;
   a.binning = binning;
   a.plane_dtype = mpi->dtype;
   a.d_focal32 = cam->d_focal;
@@ -218,6 +239,25 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   a.items = reinterpret_cast<uint2*>(w + L.o_items);
   a.partial = reinterpret_cast<float4*>(w + L.o_partial);
   a.max_items = L.max_items;
+  a.halo_rows = reinterpret_cast<float4*>(w + L.o_halo_rows);
+  a.halo_cols = reinterpret_cast<float4*>(w + L.o_halo_cols);
+  if (field->kind == LF_VOXELS) {
+    a.ijk = field->ijk;
+    a.density = field->density;
+    a.rgb = field->rgb;
+    for (int i = 0; i < 3; ++i) a.origin[i] = field->origin[i];
+    a.vsize = field->voxel_size;
+    a.inv_vsize = (float)(1.0 / (double)field->voxel_size);
+    // reference camera centre in world cell units: (R^T ((0, 0, D_fwd) - t) - origin) / h
+    const double h = field->voxel_size;
+    const double oc[3] = {-(double)cam->t[0], -(double)cam->t[1], g.d_forward - (double)cam->t[2]};
+    for (int i = 0; i < 3; ++i) {
+      const double w_i = (double)cam->R[i] * oc[0] + (double)cam->R[3 + i] * oc[1] + (double)cam->R[6 + i] * oc[2];
+      const double cell = (w_i - (double)field->origin[i]) / h;
+      a.cam_cell[i] = (float)cell;
+      a.cam_cell_lo[i] = (float)(cell - (double)a.cam_cell[i]);
+    }
+  }
 
   if (binning == LF_BIN_INV_DEPTH) {
     // K planes uniform in 1/z over [z_lo, z_hi]: interior edges E_i and plane depths at i = k + 1/2
@@ -228,7 +268,7 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
     if ((e = upload_table(a.edges, edges.data(), n_chunk, st)) != hipSuccess) return hip_fail(e, "table upload");
     if ((e = upload_table(a.dtab, dtab.data(), n_chunk, st)) != hipSuccess) return hip_fail(e, "table upload");
   }
-  if ((e = build_gaussians(a, L, st, &ctx->prof)) != hipSuccess) return hip_fail(e, "build launch");
+  if ((e = build_planes(a, L, st, &ctx->prof)) != hipSuccess) return hip_fail(e, "build launch");
   return LF_OK;
 }
 

@@ -15,10 +15,7 @@
 //  splat       one work-group per (tile, chunk): front-to-back blending of the bucket into
 //              premultiplied RGBA (C, 1 - T) with alpha = min(0.99, o G), only where
 //              o G >= 1/255, no early termination
-#include <hip/hip_bf16.h>
-#include <hip/hip_fp16.h>
-
-#include "build_internal.h"
+#include "build_device.h"
 #include "dfloat.h"
 #include "sort_internal.h"
 
@@ -29,15 +26,6 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLog2AlphaMin = -7.994353436858858f;   // log2(1/255)
 constexpr float kAlphaMax = 0.99f;
 
-__device__ __forceinline__ uint32_t orderable(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ __forceinline__ float unorderable(uint32_t u) {
-  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
-
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void preprocess_gs(BuildArgs a) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -45,15 +33,10 @@ __global__ __launch_bounds__(256) void preprocess_gs(BuildArgs a) {
   const int64_t i = in ? i0 : a.n - 1;
   const Consts& c = a.c;
   const float mx = a.means[3 * i], my = a.means[3 * i + 1], mz = a.means[3 * i + 2];
-  // base-camera coordinates, float32, fixed order: ((r0 x + r1 y) + r2 z) + t
-  const float xc = ((c.R[0] * mx + c.R[1] * my) + c.R[2] * mz) + c.t[0];
-  const float yc = ((c.R[3] * mx + c.R[4] * my) + c.R[5] * mz) + c.t[1];
-  const float key = (((c.R[6] * mx + c.R[7] * my) + c.R[8] * mz) + c.t[2]) + 0.0f;
-  const float zr = key - c.d_fwd;
-  const bool vis = in && isfinite(key) && isfinite(xc) && isfinite(yc) && zr > c.z_near &&
-                   fabsf(xc) <= c.guard_x * zr && fabsf(yc) <= c.guard_y * zr;
   if (!in) return;
-  a.keys[i] = vis ? orderable(key) : 0xffffffffu;
+  const KeyCull kc = key_and_cull(c, mx, my, mz);
+  const bool vis = kc.vis;
+  a.keys[i] = vis ? orderable(kc.key) : 0xffffffffu;
   a.vals[i] = (uint32_t)i;
   a.ntiles_i[i] = 0;
   if (a.chunk_of) a.chunk_of[i] = -1;
@@ -250,16 +233,17 @@ __global__ __launch_bounds__(256) void emit_entries(BuildArgs a, const uint32_t*
   if (t == 0) lofs[nr] = (uint32_t)(a.offsets[r0 + nr] - O0);   // nr may be 256 = blockDim
   if (t < nr) {
     const uint32_t idx = svals[r0 + t];
-    const GRec& g = a.rec[idx];
+    // the texel box leads every record kind
+    const int4 g = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(a.rec) + (size_t)idx * a.rec_bytes);
     sidx[t] = idx;
     schunk[t] = a.chunk_r[r0 + t];
-    sx0[t] = g.x0 >> kTileShift;
-    sy0[t] = g.y0 >> kTileShift;
-    sw[t] = (g.x1 >> kTileShift) - (g.x0 >> kTileShift) + 1;
-    sbox[t][0] = g.x0;
-    sbox[t][1] = g.y0;
-    sbox[t][2] = g.x1;
-    sbox[t][3] = g.y1;
+    sx0[t] = g.x >> kTileShift;
+    sy0[t] = g.y >> kTileShift;
+    sw[t] = (g.z >> kTileShift) - (g.x >> kTileShift) + 1;
+    sbox[t][0] = g.x;
+    sbox[t][1] = g.y;
+    sbox[t][2] = g.z;
+    sbox[t][3] = g.w;
   }
   __syncthreads();
   const uint32_t n_out = lofs[nr];
@@ -319,37 +303,6 @@ __global__ void finalize(BuildArgs a) {
 // scalar loads, the support-box test against the wave's block is a scalar branch, and
 // only the per-texel footprint and blend run on the vector ALUs.  No LDS, no barriers.
 // ---------------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void store_rgba(T* p, size_t i, float r, float g, float b, float al);
-
-template <>
-__device__ __forceinline__ void store_rgba<float>(float* p, size_t i, float r, float g, float b, float al) {
-  reinterpret_cast<float4*>(p)[i] = make_float4(r, g, b, al);
-}
-
-template <>
-__device__ __forceinline__ void store_rgba<__half>(__half* p, size_t i, float r, float g, float b, float al) {
-  const __half2 lo = __floats2half2_rn(r, g), hi = __floats2half2_rn(b, al);
-  uint2 u;
-  u.x = *reinterpret_cast<const uint32_t*>(&lo);
-  u.y = *reinterpret_cast<const uint32_t*>(&hi);
-  reinterpret_cast<uint2*>(p)[i] = u;
-}
-
-__device__ __forceinline__ uint32_t bf16_rn(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-
-template <>
-__device__ __forceinline__ void store_rgba<__hip_bfloat16>(__hip_bfloat16* p, size_t i, float r, float g, float b,
-                                                           float al) {
-  uint2 u;
-  u.x = bf16_rn(r) | (bf16_rn(g) << 16);
-  u.y = bf16_rn(b) | (bf16_rn(al) << 16);
-  reinterpret_cast<uint2*>(p)[i] = u;
-}
-
 // Split every (tile, chunk) bucket into segments of at most kSegment entries: nseg per
 // bucket and the number of partial-tile slots of split buckets.
 __global__ void bucket_segments(BuildArgs a, int64_t n_buckets) {
@@ -466,7 +419,7 @@ hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
+hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
   hipError_t e;
   const unsigned gN = (unsigned)((a.n + 255) / 256);
   {
@@ -480,7 +433,11 @@ hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Pr
       hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, a.keys);
       return hipGetLastError();
     }
-    hipLaunchKernelGGL(preprocess_gs, dim3(gN), dim3(256), 0, s, a);
+    if (a.kind == LF_VOXELS) {
+      if ((e = launch_preprocess_vox(a, s)) != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(preprocess_gs, dim3(gN), dim3(256), 0, s, a);
+    }
   }
   // (key, index) order
   int alt = 0;
@@ -521,7 +478,9 @@ hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Pr
   {
     PhaseScope ps(prof, LF_PHASE_SPLAT, s);
     const dim3 grid((unsigned)L.max_items);
-    switch (a.plane_dtype) {
+    if (a.kind == LF_VOXELS) {
+      if ((e = launch_splat_vox(a, L, s)) != hipSuccess) return e;
+    } else switch (a.plane_dtype) {
       case LF_F16: hipLaunchKernelGGL((splat_gs<__half>), grid, dim3(256), 0, s, a, L.n_buckets); break;
       case LF_BF16: hipLaunchKernelGGL((splat_gs<__hip_bfloat16>), grid, dim3(256), 0, s, a, L.n_buckets); break;
       default: hipLaunchKernelGGL((splat_gs<float>), grid, dim3(256), 0, s, a, L.n_buckets); break;
@@ -535,6 +494,10 @@ hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Pr
       case LF_BF16: hipLaunchKernelGGL((combine_segments<__hip_bfloat16>), grid, dim3(256), 0, s, a); break;
       default: hipLaunchKernelGGL((combine_segments<float>), grid, dim3(256), 0, s, a); break;
     }
+  }
+  if (a.kind == LF_VOXELS) {
+    PhaseScope ps(prof, LF_PHASE_FILTER, s);
+    if ((e = launch_lowpass(a, s)) != hipSuccess) return e;
   }
   return hipGetLastError();
 }

@@ -27,29 +27,52 @@ struct GRec {
   float pad;
 };
 
+// One sparse voxel (80 bytes).  The box comes first, as in GRec, so the shared tile-list
+// code reads both record kinds through the same first 16 bytes.
+struct VRec {
+  int32_t x0, y0, x1, y1;             // inclusive texel box of every ray that can meet the cube
+  float ax, ay, az, pad0;             // reference-camera centre in the cube's local units (world)
+  float dens[8];                      // corner densities (bit 0 = +x, bit 1 = +y, bit 2 = +z)
+  float rgb[3];
+  float pad1;
+};
+
+// Low-pass filter (voxel planes): regions of kFiltRows x kFiltCols texels; the original
+// texels around every region are saved first so the filter can run in place.
+constexpr int kFiltRows = 16;
+constexpr int kFiltCols = 64;
+
 constexpr int kEntryPad = 8;          // readable entries past the end of the tile lists
 constexpr int kSegment = 256;         // entries per splat work item (longer buckets are split)
 
 struct BuildLayout {
   int64_t n, cap, n_buckets;
-  int32_t K, ntx, nty, n_tiles, tile_bits, chunk_bits;
+  int32_t K, ntx, nty, n_tiles, tile_bits, chunk_bits, kind, rec_bytes;
+  int32_t filt_bands, filt_segs;      // voxel low-pass regions (0 for Gaussians)
   size_t o_hdr, o_keys, o_vals, o_keys_alt, o_vals_alt, o_rec, o_ntiles_i, o_ntiles_r, o_chunk_r, o_offsets,
       o_scan64, o_chunk_start, o_edges, o_dtab, o_nseg, o_bucket, o_scan32, o_radix, o_ekeys, o_evals, o_ekeys_alt,
-      o_evals_alt, o_pcnt, o_item_start, o_pslot, o_items, o_partial;
+      o_evals_alt, o_pcnt, o_item_start, o_pslot, o_items, o_partial, o_halo_rows, o_halo_cols;
   int64_t max_items, max_partial;
   size_t total;
 };
 
-// Fixed part of the layout for n primitives, K planes and a wp x hp plane; cap entries.
-BuildLayout build_layout(int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t cap);
+// Fixed part of the layout for n primitives of `kind`, K planes and a wp x hp plane; cap
+// entries.
+BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t cap);
 
 struct BuildArgs {
   int64_t n, capacity;
-  int32_t K, ntx, binning, plane_dtype, chunk_bits;
+  int32_t K, ntx, binning, plane_dtype, chunk_bits, kind, rec_bytes;
   float d_focal32;
   Consts c;
   // field (Gaussians)
   const float *means, *log_scales, *quats, *opacity, *rgb;
+  // field (voxels): cells, corner densities, grid origin and cell size; the reference camera
+  // centre in world cell units, (R^T ((0, 0, D_fwd) - t) - origin) / h, as double-float
+  const int32_t* ijk;
+  const float* density;
+  float origin[3], vsize, inv_vsize;
+  float cam_cell[3], cam_cell_lo[3];
   // outputs
   void* planes;
   float* depth;
@@ -71,6 +94,9 @@ struct BuildArgs {
   uint2* items;
   float4* partial;
   int64_t max_items;
+  // voxel low-pass: saved original rows [K][bands][2][wp] and columns [K][segs][2][hp]
+  float4 *halo_rows, *halo_cols;
+  int32_t filt_bands, filt_segs;
 };
 
 struct TableChunk {
@@ -79,6 +105,13 @@ struct TableChunk {
 };
 
 hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s);
-hipError_t build_gaussians(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof);
+// The whole build of one field (either kind) on stream s.
+hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof);
+
+// Voxel kernels (build_vox.hip): per-voxel preprocess, tile-list splat of one plane per
+// (tile, chunk) item, and the in-place plane low-pass.
+hipError_t launch_preprocess_vox(const BuildArgs& a, hipStream_t s);
+hipError_t launch_splat_vox(const BuildArgs& a, const BuildLayout& L, hipStream_t s);
+hipError_t launch_lowpass(const BuildArgs& a, hipStream_t s);
 
 }  // namespace lf

@@ -119,3 +119,61 @@ def test_geometry_rejects_null(lib):
     assert lib.lf_geometry(None, None) == L.LF_ERR_INVALID_ARG
     assert lib.lf_quilt_views(ctypes.byref(L.make_camera(CAMS["uniform10k"])), 0, 1,
                               (L.lf_view * 1)()) == L.LF_ERR_INVALID_ARG
+
+
+def _field(kind, n=10, **kw):
+    f = L.lf_field()
+    f.kind, f.n = kind, n
+    if kind == L.LF_GAUSSIANS:
+        f.means, f.log_scales, f.quats, f.opacity, f.rgb = 0x1000, 0x2000, 0x3000, 0x4000, 0x5000
+    else:
+        f.ijk, f.density, f.rgb = 0x1000, 0x2000, 0x3000
+        f.origin[:] = [-1.0, -1.0, 3.0]
+        f.voxel_size = 2.0 / 256
+    for k, v in kw.items():
+        if k == "origin":
+            f.origin[:] = v
+        else:
+            setattr(f, k, v)
+    return f
+
+
+@pytest.mark.parametrize("kind,kw,needle", [
+    (L.LF_GAUSSIANS, dict(means=0), "Gaussian attribute"),
+    (L.LF_GAUSSIANS, dict(n=-1), "field size"),
+    (L.LF_GAUSSIANS, dict(n=1 << 28), "field size"),
+    (L.LF_VOXELS, dict(density=0), "voxel attribute"),
+    (L.LF_VOXELS, dict(voxel_size=0.0), "voxel_size"),
+    (L.LF_VOXELS, dict(voxel_size=float("inf")), "voxel_size"),
+    (L.LF_VOXELS, dict(origin=[0.0, float("nan"), 0.0]), "origin"),
+    (7, dict(), "field kind"),
+])
+def test_build_rejects_invalid_fields(lib, kind, kw, needle):
+    cam = L.make_camera(CAMS["uniform10k"])
+    f = _field(kind, **kw)
+    nbytes = ctypes.c_size_t(0)
+    st = lib.lf_build_mpi_workspace(ctypes.byref(f), ctypes.byref(cam), 16, 0, ctypes.byref(nbytes))
+    assert st == L.LF_ERR_INVALID_ARG
+    assert needle in L.lf_last_error()
+
+
+@pytest.mark.parametrize("kind", [L.LF_GAUSSIANS, L.LF_VOXELS])
+def test_build_workspace_size_and_capacity_errors(lib, kind):
+    cam = L.make_camera(CAMS["uniform10k"])
+    f = _field(kind, n=10_000)
+    nbytes = ctypes.c_size_t(0)
+    assert lib.lf_build_mpi_workspace(ctypes.byref(f), ctypes.byref(cam), 16, 0, ctypes.byref(nbytes)) == L.LF_OK
+    assert nbytes.value > 10_000 * 64
+    big = ctypes.c_size_t(0)
+    assert lib.lf_build_mpi_workspace(ctypes.byref(f), ctypes.byref(cam), 16, 4_000_000, ctypes.byref(big)) == L.LF_OK
+    assert big.value > nbytes.value
+    # too small a workspace is a capacity error, reported before anything is enqueued
+    mpi = L.make_mpi(L.LF_F32, 16, 128, 128, 0x6000, 0x7000)
+    st = lib.lf_build_mpi(None, ctypes.byref(f), ctypes.byref(cam), 16, 0, None, ctypes.byref(mpi), 0x8000, 1024,
+                          None)
+    assert st == L.LF_ERR_CAPACITY
+    assert "too small" in L.lf_last_error()
+    # inverse-depth binning needs a range beyond D_forward
+    st = lib.lf_build_mpi(None, ctypes.byref(f), ctypes.byref(cam), 16, 1, None, ctypes.byref(mpi), 0x8000,
+                          nbytes.value, None)
+    assert st == L.LF_ERR_INVALID_ARG
