@@ -20,4 +20,4 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import it.  It shares no code with the GPU path; the only common
 dependency is the seeded input generator ``scenegen``.
 """
-from . import geometry, decisions, partition, project, splat, composite, render, voxels  # noqa: F401
+from . import geometry, decisions, partition, project, splat, composite, render, voxels, grad  # noqa: F401

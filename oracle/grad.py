@@ -1,0 +1,230 @@
+"""Gradients of a multi-view L2 loss through the whole light-field pipeline (test
+infrastructure; torch CPU float64 autograd).
+
+The forward is the oracle's own pipeline restated in torch: EWA projection into the
+reference camera (``project``), front-to-back rasterisation of each chunk into a
+premultiplied plane (``splat``), and the swizzle composite of the views (``composite``),
+with loss L = sum over views, pixels and RGB of (Q - Q*)^2.  Every discrete decision is
+taken once, at the parameters the gradient is evaluated at, and then held fixed (the
+gradient is that of the smooth piece containing those parameters):
+
+* the partition (chunk of every Gaussian, plane depths d_k: stop-gradient),
+* which (Gaussian, texel) pairs are included (o G >= 1/255) and which are clamped to 0.99,
+* the composite's texel indices (nearest) and bilinear weights, taken by the float32
+  coordinate program of ``decisions``.
+
+``frozen_loss`` evaluates the loss at other parameters with the same decisions, which is
+what central finite differences need.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import decisions, geometry, partition, project, splat
+
+KEYS = ("means", "log_scales", "quats", "opacity", "rgb")
+TD = torch.float64
+
+
+@dataclass
+class Decisions:
+    geom: geometry.Geometry
+    part: partition.Partition
+    # included (Gaussian, texel) pairs, sorted by (plane, texel, rank)
+    gauss: np.ndarray        # [P] Gaussian index
+    plane: np.ndarray        # [P] chunk k
+    texel: np.ndarray        # [P] flat texel index y * W + x within the plane
+    clamped: np.ndarray      # [P] bool: alpha = 0.99
+    group: np.ndarray        # [P] id of the (plane, texel) group
+    group_start: np.ndarray  # [G] first pair of each group
+    group_cell: np.ndarray   # [G] flat (k, texel) index of each group
+    # composite taps: for each plane, flat texel index and weight per (view, pixel, tap)
+    taps_idx: list           # K arrays [V*Ny*Nx, ntap] int64 (-1: outside the plane)
+    taps_w: list             # K arrays [V*Ny*Nx, ntap] float64
+    n_views: int
+
+
+def _pairs(scene, cam, g, part, K):
+    gs, ks, ts, cl = [], [], [], []
+    for k in range(K):
+        idx = part.order[part.chunk_start[k]:part.chunk_start[k + 1]]
+        if idx.size == 0:
+            continue
+        pr = project.project_reference(scene, idx, cam, g)
+        hx, hy, ok = splat.support_halfwidth(pr, np.zeros(idx.size))
+        for r, i in enumerate(idx):
+            if not ok[r]:
+                continue
+            mx, my = pr.mean2d[r]
+            x0, x1 = max(0, math.ceil(mx - hx[r])), min(g.wp - 1, math.floor(mx + hx[r]))
+            y0, y1 = max(0, math.ceil(my - hy[r])), min(g.hp - 1, math.floor(my + hy[r]))
+            if x0 > x1 or y0 > y1:
+                continue
+            yy, xx = np.meshgrid(np.arange(y0, y1 + 1), np.arange(x0, x1 + 1), indexing="ij")
+            dx, dy = xx - mx, yy - my
+            Q = pr.conic[r]
+            ln_a = math.log(pr.opacity[r]) - 0.5 * (Q[0, 0] * dx * dx + (Q[0, 1] + Q[1, 0]) * dx * dy + Q[1, 1] * dy * dy)
+            inc = ln_a >= splat.LN_ALPHA_MIN
+            n = int(inc.sum())
+            if n == 0:
+                continue
+            gs.append(np.full(n, i))
+            ks.append(np.full(n, k))
+            ts.append((yy * g.wp + xx)[inc])
+            cl.append((np.exp(ln_a) >= project.ALPHA_MAX)[inc])
+    if not gs:
+        z = np.zeros(0, dtype=np.int64)
+        return z, z, z, np.zeros(0, dtype=bool)
+    return np.concatenate(gs), np.concatenate(ks), np.concatenate(ts), np.concatenate(cl)
+
+
+def decide(scene: dict, cam, n_chunk: int, dx32, dy32, interp: str = "nearest", binning="quantile",
+           inv_depth_range=None) -> Decisions:
+    """Take every discrete decision of the forward at the scene's parameters."""
+    g = geometry.derive(cam)
+    part = partition.partition(scene["means"], cam, g, n_chunk, binning, inv_depth_range)
+    gauss, plane, texel, clamped = _pairs(scene, cam, g, part, n_chunk)
+    # pairs arrive per plane in rank order; a stable sort by (plane, texel) keeps rank order
+    order = np.lexsort((texel, plane))
+    gauss, plane, texel, clamped = gauss[order], plane[order], texel[order], clamped[order]
+    cell = plane.astype(np.int64) * (g.hp * g.wp) + texel
+    new = np.ones(cell.size, dtype=bool)
+    new[1:] = cell[1:] != cell[:-1]
+    group = np.cumsum(new) - 1
+    group_start = np.nonzero(new)[0]
+    c = decisions.constants(g, cam)
+    pc = decisions.plane_coeffs32(c, part.depth, np.asarray(dx32, np.float32), np.asarray(dy32, np.float32))
+    V = len(dx32)
+    ys, xs = np.meshgrid(np.arange(cam.ny), np.arange(cam.nx), indexing="ij")
+    xs, ys = xs.reshape(-1), ys.reshape(-1)
+    taps_idx, taps_w = [], []
+    nearest = interp == "nearest"
+    for k in range(n_chunk):
+        ii, ww = [], []
+        for v in range(V):
+            X, Y = decisions.texel_coords32(pc, c, k, v, xs, ys, nearest)
+            if nearest:
+                taps = [(np.floor(Y).astype(np.int64), np.floor(X).astype(np.int64), np.ones(xs.size))]
+            else:
+                x0, y0 = np.floor(X), np.floor(Y)
+                wx, wy = X.astype(np.float64) - x0, Y.astype(np.float64) - y0
+                x0, y0 = x0.astype(np.int64), y0.astype(np.int64)
+                taps = [(y0 + oy, x0 + ox, fy * fx) for oy, fy in ((0, 1 - wy), (1, wy)) for ox, fx in ((0, 1 - wx), (1, wx))]
+            idx = np.stack([np.where((iy >= 0) & (iy < g.hp) & (ix >= 0) & (ix < g.wp), iy * g.wp + ix, -1)
+                            for iy, ix, _ in taps], axis=1)
+            w = np.stack([w for _, _, w in taps], axis=1)
+            ii.append(idx)
+            ww.append(w)
+        taps_idx.append(np.concatenate(ii))
+        taps_w.append(np.concatenate(ww))
+    return Decisions(geom=g, part=part, gauss=gauss, plane=plane, texel=texel, clamped=clamped, group=group,
+                     group_start=group_start, group_cell=cell[group_start], taps_idx=taps_idx, taps_w=taps_w,
+                     n_views=V)
+
+
+def quat_to_rot(q: torch.Tensor) -> torch.Tensor:
+    q = q / torch.linalg.norm(q, dim=-1, keepdim=True)
+    w, x, y, z = q.unbind(-1)
+    return torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
+
+
+def project_reference(p: dict, cam, g: geometry.Geometry):
+    """Projected means [N,2] and inverse 2D covariances [N,2,2] (EWA, Eq. 8 dilation)."""
+    Rc = torch.tensor(np.asarray(cam.R, np.float64).reshape(3, 3), dtype=TD)
+    tc = torch.tensor(np.asarray(cam.t, np.float64), dtype=TD)
+    pc = p["means"] @ Rc.T + tc
+    x, y, z = pc[:, 0], pc[:, 1], pc[:, 2] - g.d_forward
+    mean2d = torch.stack([g.fpx * x / z + g.cpx, g.fpy * y / z + g.cpy], -1)
+    R = quat_to_rot(p["quats"])
+    sig = R @ torch.diag_embed(torch.exp(2.0 * p["log_scales"])) @ R.transpose(-1, -2)
+    sig_c = Rc @ sig @ Rc.T
+    zero = torch.zeros_like(z)
+    J = torch.stack([torch.stack([g.fpx / z, zero, -g.fpx * x / (z * z)], -1),
+                     torch.stack([zero, g.fpy / z, -g.fpy * y / (z * z)], -1)], -2)
+    cov = J @ sig_c @ J.transpose(-1, -2) + g.f_dilation * torch.eye(2, dtype=TD)
+    return mean2d, torch.linalg.inv(cov)
+
+
+def planes_of(p: dict, cam, d: Decisions, n_chunk: int) -> torch.Tensor:
+    """Premultiplied planes [K, H, W, 4] (C, 1 - T) from the frozen pair list."""
+    g = d.geom
+    mean2d, conic = project_reference(p, cam, g)
+    gi = torch.from_numpy(d.gauss)
+    px = torch.from_numpy((d.texel % g.wp).astype(np.float64))
+    py = torch.from_numpy((d.texel // g.wp).astype(np.float64))
+    dx, dy = px - mean2d[gi, 0], py - mean2d[gi, 1]
+    Q = conic[gi]
+    quad = Q[:, 0, 0] * dx * dx + (Q[:, 0, 1] + Q[:, 1, 0]) * dx * dy + Q[:, 1, 1] * dy * dy
+    a = p["opacity"][gi] * torch.exp(-0.5 * quad)
+    alpha = torch.where(torch.from_numpy(d.clamped), torch.full_like(a, project.ALPHA_MAX), a)
+    log1m = torch.log1p(-alpha)
+    cs = torch.cumsum(log1m, 0)
+    before = cs - log1m                                      # inclusive sum of the earlier pairs
+    start = torch.from_numpy(d.group_start)
+    base = before[start][torch.from_numpy(d.group)]
+    T = torch.exp(before - base)                             # transmittance in front of the pair
+    ncell = n_chunk * g.hp * g.wp
+    cells = torch.from_numpy(d.plane.astype(np.int64) * (g.hp * g.wp) + d.texel)
+    C = torch.zeros(ncell, 3, dtype=TD).index_add(0, cells, (T * alpha)[:, None] * p["rgb"][gi])
+    tot = torch.zeros(ncell, dtype=TD).index_add(0, cells, log1m)
+    A = 1.0 - torch.exp(tot)
+    return torch.cat([C, A[:, None]], 1).reshape(n_chunk, g.hp, g.wp, 4)
+
+
+def composite_of(planes: torch.Tensor, d: Decisions, cam) -> torch.Tensor:
+    """Views [V, Ny, Nx, 4] = (Q, T) of planes [K, H, W, 4] through the frozen taps."""
+    K = planes.shape[0]
+    n = d.n_views * cam.ny * cam.nx
+    Q = torch.zeros(n, 3, dtype=planes.dtype)
+    T = torch.ones(n, dtype=planes.dtype)
+    for k in range(K):
+        flat = planes[k].reshape(-1, 4)
+        idx = torch.from_numpy(d.taps_idx[k])
+        w = torch.from_numpy(d.taps_w[k]) * (idx >= 0)
+        s = (flat[idx.clamp(min=0)] * w[..., None]).sum(1)
+        Q = Q + T[:, None] * s[:, :3]
+        T = T * (1.0 - s[:, 3])
+    return torch.cat([Q, T[:, None]], 1).reshape(d.n_views, cam.ny, cam.nx, 4)
+
+
+def params_of(scene: dict, requires_grad: bool = True) -> dict:
+    return {k: torch.tensor(np.asarray(scene[k], np.float64), dtype=TD, requires_grad=requires_grad) for k in KEYS}
+
+
+def frozen_loss(p: dict, cam, d: Decisions, n_chunk: int, target: torch.Tensor):
+    """L = sum (Q - Q*)^2 over views, pixels and RGB, with the decisions ``d``."""
+    views = composite_of(planes_of(p, cam, d, n_chunk), d, cam)
+    return ((views[..., :3] - target[..., :3]) ** 2).sum(), views
+
+
+def loss_and_grad(scene: dict, cam, n_chunk: int, dx32, dy32, target, interp="nearest", d: Decisions = None):
+    """Loss, views and the gradient w.r.t. every Gaussian parameter (dict of numpy arrays)."""
+    if d is None:
+        d = decide(scene, cam, n_chunk, dx32, dy32, interp)
+    p = params_of(scene)
+    tgt = torch.as_tensor(np.asarray(target, np.float64))
+    loss, views = frozen_loss(p, cam, d, n_chunk, tgt)
+    loss.backward()
+    return float(loss.detach()), views.detach().numpy(), {k: p[k].grad.numpy() for k in KEYS}, d
+
+
+def planes_vjp(scene: dict, cam, n_chunk: int, d: Decisions, d_planes: np.ndarray) -> dict:
+    """Gradient w.r.t. the Gaussian parameters of <d_planes, planes(params)> (the build's VJP)."""
+    p = params_of(scene)
+    planes = planes_of(p, cam, d, n_chunk)
+    (planes * torch.as_tensor(d_planes, dtype=TD)).sum().backward()
+    return {k: p[k].grad.numpy() for k in KEYS}
+
+
+def composite_vjp(planes: np.ndarray, d: Decisions, cam, d_out: np.ndarray) -> np.ndarray:
+    """Gradient w.r.t. the planes of <d_out, composite(planes)> (the composite's VJP)."""
+    pt = torch.tensor(np.asarray(planes, np.float64), dtype=TD, requires_grad=True)
+    (composite_of(pt, d, cam) * torch.as_tensor(d_out, dtype=TD)).sum().backward()
+    return pt.grad.numpy()
