@@ -125,6 +125,16 @@ typedef struct {
   int32_t overflow;         /* 1 if entries_needed > entry_capacity (planes are invalid)  */
 } lf_build_info;
 
+/* Gradients of a Gaussian field's parameters, device float32 arrays written whole by
+ * lf_build_mpi_backward (culled Gaussians get zeros).                                    */
+typedef struct {
+  float* means;           /* [n][3]                                                       */
+  float* log_scales;      /* [n][3]                                                       */
+  float* quats;           /* [n][4], with respect to the un-normalised input quaternion   */
+  float* opacity;         /* [n]                                                          */
+  float* rgb;             /* [n][3]                                                       */
+} lf_gaussian_grads;
+
 /* Library version string.                                                               */
 const char* lf_version(void);
 
@@ -170,6 +180,29 @@ lf_status lf_build_stats(lf_ctx* ctx, const void* workspace, size_t workspace_by
  * (F32 or F16).  views: host array of n_views (1..LF_MAX_VIEWS) offsets.                */
 lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
                        int32_t n_views, int32_t interp, int32_t out_dtype, void* out, void* stream);
+
+/* Vector-Jacobian product of lf_composite (the over operator of Eq. 7 with the Eq. 6
+ * sampling held fixed): given d_out = dL/d(Q_r, Q_g, Q_b, T) (device float32
+ * [n_views][ny][nx][4]), writes d_planes = dL/d(C_r, C_g, C_b, A) (device float32
+ * [n_chunk][height][width][4]; zero-filled by the callee, then accumulated).  The planes
+ * of `mpi` are read in their own dtype; per-pixel transmittance is recomputed, not
+ * stored.  Arguments as lf_composite.                                                     */
+lf_status lf_composite_backward(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
+                                int32_t n_views, int32_t interp, const float* d_out, float* d_planes,
+                                void* stream);
+
+/* Vector-Jacobian product of lf_build_mpi for a Gaussian field: given d_planes =
+ * dL/d(C, A) of the planes (device float32 [n_chunk][height][width][4]), writes the
+ * gradients of means, log-scales, quaternions, opacities and colours.  The partition, the
+ * tile lists, the inclusion test o G >= 1/255 and the 0.99 clamp are held fixed (the
+ * gradient of the smooth piece the parameters lie in; plane depths are constants).  It
+ * reads the tile lists and per-Gaussian records that lf_build_mpi left in `workspace`, so
+ * it must follow the lf_build_mpi call that produced `mpi` with the same field, camera,
+ * n_chunk and workspace, with no other build on that workspace in between.  Voxel fields
+ * return LF_ERR_UNSUPPORTED.                                                             */
+lf_status lf_build_mpi_backward(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, const lf_mpi* mpi,
+                                const float* d_planes, const lf_gaussian_grads* grads, void* workspace,
+                                size_t workspace_bytes, void* stream);
 
 /* The float32 texel-coordinate coefficients lf_composite uses (Eq. 6 in affine form):
  * X = fl(fl(bx[k] * fl(x - c_x)) + Cx[k][v]) and Y likewise; the *_n offsets are the

@@ -96,14 +96,24 @@ def decide(scene: dict, cam, n_chunk: int, dx32, dy32, interp: str = "nearest", 
     new[1:] = cell[1:] != cell[:-1]
     group = np.cumsum(new) - 1
     group_start = np.nonzero(new)[0]
+    taps_idx, taps_w = composite_taps(cam, g, part.depth, dx32, dy32, interp)
+    return Decisions(geom=g, part=part, gauss=gauss, plane=plane, texel=texel, clamped=clamped, group=group,
+                     group_start=group_start, group_cell=cell[group_start], taps_idx=taps_idx, taps_w=taps_w,
+                     n_views=len(dx32))
+
+
+def composite_taps(cam, g: geometry.Geometry, depth32, dx32, dy32, interp: str):
+    """Per plane: texel indices [V*Ny*Nx, ntap] (-1 outside the plane) and weights of every
+    view pixel's sample, from the float32 coordinate program (nearest: 1 tap, bilinear: 4)."""
     c = decisions.constants(g, cam)
-    pc = decisions.plane_coeffs32(c, part.depth, np.asarray(dx32, np.float32), np.asarray(dy32, np.float32))
+    pc = decisions.plane_coeffs32(c, np.asarray(depth32, np.float32), np.asarray(dx32, np.float32),
+                                  np.asarray(dy32, np.float32))
     V = len(dx32)
     ys, xs = np.meshgrid(np.arange(cam.ny), np.arange(cam.nx), indexing="ij")
     xs, ys = xs.reshape(-1), ys.reshape(-1)
     taps_idx, taps_w = [], []
     nearest = interp == "nearest"
-    for k in range(n_chunk):
+    for k in range(len(depth32)):
         ii, ww = [], []
         for v in range(V):
             X, Y = decisions.texel_coords32(pc, c, k, v, xs, ys, nearest)
@@ -116,14 +126,26 @@ def decide(scene: dict, cam, n_chunk: int, dx32, dy32, interp: str = "nearest", 
                 taps = [(y0 + oy, x0 + ox, fy * fx) for oy, fy in ((0, 1 - wy), (1, wy)) for ox, fx in ((0, 1 - wx), (1, wx))]
             idx = np.stack([np.where((iy >= 0) & (iy < g.hp) & (ix >= 0) & (ix < g.wp), iy * g.wp + ix, -1)
                             for iy, ix, _ in taps], axis=1)
-            w = np.stack([w for _, _, w in taps], axis=1)
             ii.append(idx)
-            ww.append(w)
+            ww.append(np.stack([w for _, _, w in taps], axis=1))
         taps_idx.append(np.concatenate(ii))
         taps_w.append(np.concatenate(ww))
-    return Decisions(geom=g, part=part, gauss=gauss, plane=plane, texel=texel, clamped=clamped, group=group,
-                     group_start=group_start, group_cell=cell[group_start], taps_idx=taps_idx, taps_w=taps_w,
-                     n_views=V)
+    return taps_idx, taps_w
+
+
+@dataclass
+class CompositeTaps:
+    geom: geometry.Geometry
+    taps_idx: list
+    taps_w: list
+    n_views: int
+
+
+def composite_decisions(cam, depth32, dx32, dy32, interp: str = "nearest") -> CompositeTaps:
+    """The composite's frozen sampling for given plane depths (no scene needed)."""
+    g = geometry.derive(cam)
+    ti, tw = composite_taps(cam, g, depth32, dx32, dy32, interp)
+    return CompositeTaps(geom=g, taps_idx=ti, taps_w=tw, n_views=len(dx32))
 
 
 def quat_to_rot(q: torch.Tensor) -> torch.Tensor:

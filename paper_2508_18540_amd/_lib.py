@@ -26,8 +26,8 @@ STATUS_NAMES = {0: "LF_OK", 1: "LF_ERR_INVALID_ARG", 2: "LF_ERR_UNSUPPORTED", 3:
 # every symbol include/lf.h declares
 EXPORTS = [
     "lf_version", "lf_last_error", "lf_create", "lf_destroy", "lf_geometry", "lf_quilt_views",
-    "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_plane_coeffs",
-    "lf_profile_enable", "lf_profile_read",
+    "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_composite_backward",
+    "lf_build_mpi_backward", "lf_plane_coeffs", "lf_profile_enable", "lf_profile_read",
 ]
 PHASES = ["preprocess", "sort", "bin", "splat", "merge", "filter", "coeff", "composite", "composite_bwd",
           "build_bwd"]
@@ -79,6 +79,11 @@ class lf_build_info(C.Structure):
                 ("overflow", C.c_int32)]
 
 
+class lf_gaussian_grads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p), ("opacity", C.c_void_p),
+                ("rgb", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -105,6 +110,10 @@ def load():
         "lf_build_stats": ([P, P, C.c_size_t, C.POINTER(lf_build_info), P], C.c_int),
         "lf_composite": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32, C.c_int32,
                           C.c_int32, P, P], C.c_int),
+        "lf_composite_backward": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
+                                   C.c_int32, P, P, P], C.c_int),
+        "lf_build_mpi_backward": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.POINTER(lf_mpi), P,
+                                   C.POINTER(lf_gaussian_grads), P, C.c_size_t, P], C.c_int),
         "lf_plane_coeffs": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
                              P, P, P, P, P, P, P], C.c_int),
         "lf_profile_enable": ([P, C.c_int32], C.c_int),
@@ -220,6 +229,18 @@ def lf_composite(ctx: int, mpi: lf_mpi, cam: lf_camera, views, interp: int, out_
                  stream: int = 0) -> None:
     _check(load().lf_composite(ctx, C.byref(mpi), C.byref(cam), views, len(views), interp, out_dtype, out, stream),
            "lf_composite")
+
+
+def lf_composite_backward(ctx: int, mpi: lf_mpi, cam: lf_camera, views, interp: int, d_out: int, d_planes: int,
+                          stream: int = 0) -> None:
+    _check(load().lf_composite_backward(ctx, C.byref(mpi), C.byref(cam), views, len(views), interp, d_out, d_planes,
+                                        stream), "lf_composite_backward")
+
+
+def lf_build_mpi_backward(ctx: int, field: lf_field, cam: lf_camera, mpi: lf_mpi, d_planes: int,
+                          grads: lf_gaussian_grads, workspace: int, workspace_bytes: int, stream: int = 0) -> None:
+    _check(load().lf_build_mpi_backward(ctx, C.byref(field), C.byref(cam), C.byref(mpi), d_planes, C.byref(grads),
+                                        workspace, workspace_bytes, stream), "lf_build_mpi_backward")
 
 
 def lf_plane_coeffs(ctx: int, mpi: lf_mpi, cam: lf_camera, views, bx: int, by: int, cx: int, cy: int,

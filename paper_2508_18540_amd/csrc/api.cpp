@@ -203,6 +203,26 @@ extern "C" lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camer
   return s;
 }
 
+extern "C" lf_status lf_composite_backward(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
+                                           int32_t n_views, int32_t interp, const float* d_out, float* d_planes,
+                                           void* stream) {
+  CompositeArgs* a = new (std::nothrow) CompositeArgs;
+  if (!a) return fail(LF_ERR_OUT_OF_MEMORY, "argument block allocation failed");
+  lf_status s = composite_args(mpi, cam, views, n_views, a);
+  if (s == LF_OK && interp != LF_NEAREST && interp != LF_BILINEAR)
+    s = fail(LF_ERR_INVALID_ARG, "interp %d is not NEAREST/BILINEAR", interp);
+  if (s == LF_OK && !d_out) s = fail(LF_ERR_INVALID_ARG, "d_out is NULL");
+  if (s == LF_OK && !d_planes) s = fail(LF_ERR_INVALID_ARG, "d_planes is NULL");
+  if (s == LF_OK) s = check_ctx(ctx);
+  if (s == LF_OK) {
+    a->interp = interp;
+    hipError_t e = composite_backward_launch(*a, d_out, d_planes, (hipStream_t)stream, &ctx->prof);
+    if (e != hipSuccess) s = hip_fail(e, "composite backward launch");
+  }
+  delete a;
+  return s;
+}
+
 extern "C" lf_status lf_plane_coeffs(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
                                      int32_t n_views, float* bx, float* by, float* cx, float* cy, float* cxn,
                                      float* cyn, void* stream) {

@@ -72,6 +72,7 @@ BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t
   L.o_partial = take((size_t)L.max_partial * kTile * kTile * 16);
   L.o_halo_rows = take((size_t)K * L.filt_bands * 2 * wp * 16);
   L.o_halo_cols = take((size_t)K * L.filt_segs * 2 * hp * 16);
+  L.o_ggrad = take(kind == LF_VOXELS ? 0 : un * kGradSlots * 4);
   L.total = o;
   return L;
 }
@@ -127,67 +128,11 @@ lf_status check_common(const lf_field* field, const lf_camera* cam, int32_t n_ch
   return LF_OK;
 }
 
-}  // namespace
-}  // namespace lf
-
-using namespace lf;
-
-extern "C" lf_status lf_build_mpi_workspace(const lf_field* field, const lf_camera* cam, int32_t n_chunk,
-                                            int64_t entry_capacity, size_t* bytes) {
-  if (!bytes) return fail(LF_ERR_INVALID_ARG, "bytes is NULL");
-  Geom g;
-  lf_status s = check_common(field, cam, n_chunk, &g);
-  if (s != LF_OK) return s;
-  if (entry_capacity > kMaxEntries) return fail(LF_ERR_INVALID_ARG, "entry_capacity exceeds 2^31 - 1");
-  const int64_t cap = entry_capacity > 0 ? entry_capacity : default_capacity(field->n);
-  const size_t fixed =
-      build_layout(field->kind, field->n, n_chunk, g.wp, g.hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
-  *bytes = fixed + (size_t)cap * kBytesPerEntry + 4096;
-  return LF_OK;
-}
-
-extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
-                                  int32_t binning, const float* inv_depth_range, lf_mpi* mpi, void* workspace,
-                                  size_t workspace_bytes, void* stream) {
-  Geom g;
-  lf_status s = check_common(field, cam, n_chunk, &g);
-  if (s != LF_OK) return s;
-  if (binning != LF_BIN_QUANTILE && binning != LF_BIN_INV_DEPTH)
-    return fail(LF_ERR_INVALID_ARG, "binning %d is not QUANTILE/INV_DEPTH", binning);
-  float zlo = 0.f, zhi = 0.f;
-  if (binning == LF_BIN_INV_DEPTH) {
-    if (!inv_depth_range) return fail(LF_ERR_INVALID_ARG, "inv_depth_range is NULL");
-    zlo = inv_depth_range[0];
-    zhi = inv_depth_range[1];
-    if (!(std::isfinite(zlo) && std::isfinite(zhi) && zlo < zhi && (double)zlo > g.d_forward))
-      return fail(LF_ERR_INVALID_ARG, "inverse-depth range must satisfy D_forward < z_lo < z_hi < inf");
-  }
-  if (!mpi) return fail(LF_ERR_INVALID_ARG, "mpi is NULL");
-  if (mpi->dtype != LF_F32 && mpi->dtype != LF_F16 && mpi->dtype != LF_BF16)
-    return fail(LF_ERR_INVALID_ARG, "mpi dtype %d is not F32/F16/BF16", mpi->dtype);
-  if (mpi->n_chunk != n_chunk) return fail(LF_ERR_INVALID_ARG, "mpi n_chunk %d != %d", mpi->n_chunk, n_chunk);
-  if (mpi->width != g.wp || mpi->height != g.hp)
-    return fail(LF_ERR_INVALID_ARG, "mpi is %dx%d but the camera's planes are %dx%d", mpi->width, mpi->height, g.wp,
-                g.hp);
-  if (!mpi->rgba || !mpi->depth) return fail(LF_ERR_INVALID_ARG, "mpi rgba/depth is NULL");
-  if (!workspace) return fail(LF_ERR_INVALID_ARG, "workspace is NULL");
+// Kernel arguments of a build (or its backward) on `workspace` laid out as L.
+void build_args(BuildArgs& a, const BuildLayout& L, const lf_field* field, const lf_camera* cam, const Geom& g,
+                int32_t n_chunk, int32_t binning, const lf_mpi* mpi, void* workspace, int64_t cap) {
   const int64_t n = field->n;
-  const int64_t cap = capacity_of(field->kind, n, n_chunk, g.wp, g.hp, workspace_bytes);
-  if (cap < 1) {
-    size_t need = 0;
-    lf_build_mpi_workspace(field, cam, n_chunk, 0, &need);
-    return fail(LF_ERR_CAPACITY, "workspace of %zu bytes is too small; %zu bytes needed", workspace_bytes, need);
-  }
-  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
-  hipError_t e = hipSetDevice(ctx->device);
-  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  hipStream_t st = (hipStream_t)stream;
-
-  const BuildLayout L = build_layout(field->kind, n, n_chunk, g.wp, g.hp, cap);
-  if (L.tile_bits + L.chunk_bits > 32)
-    return fail(LF_ERR_INVALID_ARG, "%d tiles x %d chunks do not fit a 32-bit (tile, chunk) key", L.n_tiles, n_chunk);
   char* w = static_cast<char*>(workspace);
-  BuildArgs a;
   std::memset(&a, 0, sizeof(a));
   a.n = n;
   a.capacity = cap;
@@ -258,7 +203,70 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
       a.cam_cell_lo[i] = (float)(cell - (double)a.cam_cell[i]);
     }
   }
+  a.ggrad = reinterpret_cast<float*>(w + L.o_ggrad);
+}
 
+}  // namespace
+}  // namespace lf
+
+using namespace lf;
+
+extern "C" lf_status lf_build_mpi_workspace(const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                                            int64_t entry_capacity, size_t* bytes) {
+  if (!bytes) return fail(LF_ERR_INVALID_ARG, "bytes is NULL");
+  Geom g;
+  lf_status s = check_common(field, cam, n_chunk, &g);
+  if (s != LF_OK) return s;
+  if (entry_capacity > kMaxEntries) return fail(LF_ERR_INVALID_ARG, "entry_capacity exceeds 2^31 - 1");
+  const int64_t cap = entry_capacity > 0 ? entry_capacity : default_capacity(field->n);
+  const size_t fixed =
+      build_layout(field->kind, field->n, n_chunk, g.wp, g.hp, 0).total + radix_tmp_u32(kMaxEntries) * 4 + 4 * 256;
+  *bytes = fixed + (size_t)cap * kBytesPerEntry + 4096;
+  return LF_OK;
+}
+
+extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                                  int32_t binning, const float* inv_depth_range, lf_mpi* mpi, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+  Geom g;
+  lf_status s = check_common(field, cam, n_chunk, &g);
+  if (s != LF_OK) return s;
+  if (binning != LF_BIN_QUANTILE && binning != LF_BIN_INV_DEPTH)
+    return fail(LF_ERR_INVALID_ARG, "binning %d is not QUANTILE/INV_DEPTH", binning);
+  float zlo = 0.f, zhi = 0.f;
+  if (binning == LF_BIN_INV_DEPTH) {
+    if (!inv_depth_range) return fail(LF_ERR_INVALID_ARG, "inv_depth_range is NULL");
+    zlo = inv_depth_range[0];
+    zhi = inv_depth_range[1];
+    if (!(std::isfinite(zlo) && std::isfinite(zhi) && zlo < zhi && (double)zlo > g.d_forward))
+      return fail(LF_ERR_INVALID_ARG, "inverse-depth range must satisfy D_forward < z_lo < z_hi < inf");
+  }
+  if (!mpi) return fail(LF_ERR_INVALID_ARG, "mpi is NULL");
+  if (mpi->dtype != LF_F32 && mpi->dtype != LF_F16 && mpi->dtype != LF_BF16)
+    return fail(LF_ERR_INVALID_ARG, "mpi dtype %d is not F32/F16/BF16", mpi->dtype);
+  if (mpi->n_chunk != n_chunk) return fail(LF_ERR_INVALID_ARG, "mpi n_chunk %d != %d", mpi->n_chunk, n_chunk);
+  if (mpi->width != g.wp || mpi->height != g.hp)
+    return fail(LF_ERR_INVALID_ARG, "mpi is %dx%d but the camera's planes are %dx%d", mpi->width, mpi->height, g.wp,
+                g.hp);
+  if (!mpi->rgba || !mpi->depth) return fail(LF_ERR_INVALID_ARG, "mpi rgba/depth is NULL");
+  if (!workspace) return fail(LF_ERR_INVALID_ARG, "workspace is NULL");
+  const int64_t n = field->n;
+  const int64_t cap = capacity_of(field->kind, n, n_chunk, g.wp, g.hp, workspace_bytes);
+  if (cap < 1) {
+    size_t need = 0;
+    lf_build_mpi_workspace(field, cam, n_chunk, 0, &need);
+    return fail(LF_ERR_CAPACITY, "workspace of %zu bytes is too small; %zu bytes needed", workspace_bytes, need);
+  }
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+
+  const BuildLayout L = build_layout(field->kind, n, n_chunk, g.wp, g.hp, cap);
+  if (L.tile_bits + L.chunk_bits > 32)
+    return fail(LF_ERR_INVALID_ARG, "%d tiles x %d chunks do not fit a 32-bit (tile, chunk) key", L.n_tiles, n_chunk);
+  BuildArgs a;
+  build_args(a, L, field, cam, g, n_chunk, binning, mpi, workspace, cap);
   if (binning == LF_BIN_INV_DEPTH) {
     // K planes uniform in 1/z over [z_lo, z_hi]: interior edges E_i and plane depths at i = k + 1/2
     std::vector<float> edges((size_t)n_chunk, 0.0f), dtab((size_t)n_chunk);
@@ -269,6 +277,41 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
     if ((e = upload_table(a.dtab, dtab.data(), n_chunk, st)) != hipSuccess) return hip_fail(e, "table upload");
   }
   if ((e = build_planes(a, L, st, &ctx->prof)) != hipSuccess) return hip_fail(e, "build launch");
+  return LF_OK;
+}
+
+extern "C" lf_status lf_build_mpi_backward(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, const lf_mpi* mpi,
+                                           const float* d_planes, const lf_gaussian_grads* grads, void* workspace,
+                                           size_t workspace_bytes, void* stream) {
+  if (!mpi) return fail(LF_ERR_INVALID_ARG, "mpi is NULL");
+  Geom g;
+  lf_status s = check_common(field, cam, mpi->n_chunk, &g);
+  if (s != LF_OK) return s;
+  if (field->kind != LF_GAUSSIANS) return fail(LF_ERR_UNSUPPORTED, "the build backward covers Gaussian fields only");
+  if (mpi->width != g.wp || mpi->height != g.hp)
+    return fail(LF_ERR_INVALID_ARG, "mpi is %dx%d but the camera's planes are %dx%d", mpi->width, mpi->height, g.wp,
+                g.hp);
+  if (!d_planes) return fail(LF_ERR_INVALID_ARG, "d_planes is NULL");
+  if (!grads) return fail(LF_ERR_INVALID_ARG, "grads is NULL");
+  if (field->n > 0 && !(grads->means && grads->log_scales && grads->quats && grads->opacity && grads->rgb))
+    return fail(LF_ERR_INVALID_ARG, "a gradient output pointer is NULL");
+  if (!workspace) return fail(LF_ERR_INVALID_ARG, "workspace is NULL");
+  const int64_t cap = capacity_of(field->kind, field->n, mpi->n_chunk, g.wp, g.hp, workspace_bytes);
+  if (cap < 1) return fail(LF_ERR_CAPACITY, "workspace of %zu bytes is too small for this field", workspace_bytes);
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const BuildLayout L = build_layout(field->kind, field->n, mpi->n_chunk, g.wp, g.hp, cap);
+  if (L.tile_bits + L.chunk_bits > 32)
+    return fail(LF_ERR_INVALID_ARG, "%d tiles x %d chunks do not fit a 32-bit (tile, chunk) key", L.n_tiles,
+                mpi->n_chunk);
+  BuildArgs a;
+  build_args(a, L, field, cam, g, mpi->n_chunk, LF_BIN_QUANTILE, mpi, workspace, cap);
+  // the forward left the tile-sorted entries in the array its radix passes ended on
+  if (radix_passes(L.tile_bits) & 1) a.evals = a.evals_alt;
+  a.d_planes = d_planes;
+  a.grads = *grads;
+  if ((e = build_backward(a, L, (hipStream_t)stream, &ctx->prof)) != hipSuccess) return hip_fail(e, "build backward launch");
   return LF_OK;
 }
 

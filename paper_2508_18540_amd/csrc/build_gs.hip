@@ -401,6 +401,254 @@ __global__ __launch_bounds__(256) void combine_segments(BuildArgs a) {
     store_rgba(static_cast<PT*>(a.planes), ((size_t)k * a.c.hp + py) * a.c.wp + px, C0, C1, C2, 1.0f - T);
 }
 
+// ---------------------------------------------------------------------------------------
+// Backward of the splat.  Per texel of a bucket with cotangents gC = dL/dC, gA = dL/dA of
+// its plane texel, over the bucket's Gaussians i (front to back, alpha_i, colour c_i):
+//   dL/dc_i     = T_i alpha_i gC
+//   dL/dalpha_i = T_i (gC . (c_i - R_{i+1}) + gA S_{i+1}),
+//   R_i = alpha_i c_i + (1 - alpha_i) R_{i+1},  S_i = (1 - alpha_i) S_{i+1},
+// with R, S of the bucket's end = (0, 1), evaluated back to front.  A work item is one
+// segment of a bucket: its T at the segment start and (R, S) at its end come from the
+// other segments' forward partials (C_s, T_s).  Inside the segment T_i is recomputed: a
+// forward sweep stores T every 16 entries (LDS), then each block of 16 is swept forward
+// again into registers and walked backwards.  alpha = min(0.99, 2^q), q = l2o + ca dx^2 +
+// cb dx dy + cc dy^2, included iff q >= log2(1/255): d alpha/dq = alpha ln 2 where included
+// and not clamped.  Each wave reduces its 64 texels' contributions per Gaussian and adds
+// them to the Gaussian's accumulators.
+// ---------------------------------------------------------------------------------------
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr int kBwdBlock = 16;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+struct Eval {
+  float alpha, q, dx, dy;
+};
+
+__device__ __forceinline__ Eval eval_gauss(const GRec& g, float pxf, float pyf) {
+  Eval r;
+  r.dx = (pxf - g.mx_hi) - g.mx_lo;
+  r.dy = (pyf - g.my_hi) - g.my_lo;
+  r.q = fmaf(g.ca * r.dx, r.dx, fmaf(g.cc * r.dy, r.dy, fmaf(g.cb * r.dx, r.dy, g.l2o)));
+  r.alpha = r.q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(r.q)) : 0.0f;
+  return r;
+}
+
+__global__ __launch_bounds__(256) void splat_bwd_gs(BuildArgs a, int64_t n_buckets) {
+  __shared__ float ckpt[kSegment / kBwdBlock][256];
+  const uint32_t item = blockIdx.x;
+  if (item >= a.item_start[n_buckets]) return;
+  if (a.hdr->overflow) return;
+  const uint2 it = a.items[item];
+  const int64_t bidx = it.x;
+  const int tile = (int)(bidx / a.K), k = (int)(bidx % a.K);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
+  const int px = ox + ((wave & 1) << 3) + (lane & 7), py = oy + ((wave >> 1) << 3) + (lane >> 3);
+  const float pxf = (float)px, pyf = (float)py;
+  const uint32_t* __restrict__ ev = a.evals;
+  const GRec* __restrict__ rec = a.rec;
+  const uint32_t bb0 = a.bucket[bidx], bb1 = a.bucket[bidx + 1];
+  const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
+  const uint32_t b0 = bb0 + it.y * kSegment, b1 = min(bb1, b0 + kSegment);
+  const bool in_plane = px < a.c.wp && py < a.c.hp;
+  float4 gp = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (in_plane) gp = reinterpret_cast<const float4*>(a.d_planes)[((size_t)k * a.c.hp + py) * a.c.wp + px];
+  // transmittance in front of the segment, colour and transmittance behind it
+  float Tin = 1.0f, Rr = 0.f, Rg = 0.f, Rb = 0.f, Sf = 1.0f;
+  if (nseg > 1) {
+    const float4* part = a.partial + (size_t)a.pslot[bidx] * (kTile * kTile) + ((py - oy) << kTileShift) + (px - ox);
+    for (uint32_t s = 0; s < it.y; ++s) Tin *= part[(size_t)s * (kTile * kTile)].w;
+    for (uint32_t s = nseg - 1; s > it.y; --s) {
+      const float4 p = part[(size_t)s * (kTile * kTile)];
+      Rr = fmaf(p.w, Rr, p.x);
+      Rg = fmaf(p.w, Rg, p.y);
+      Rb = fmaf(p.w, Rb, p.z);
+      Sf *= p.w;
+    }
+  }
+  const uint32_t qbit = 1u << (28 + wave);
+  // forward sweep: T (within the segment) at the start of every block of kBwdBlock entries
+  float T = 1.0f;
+  for (uint32_t e = b0; e < b1; ++e) {
+    if (((e - b0) & (kBwdBlock - 1)) == 0) ckpt[(e - b0) / kBwdBlock][tid] = T;
+    const uint32_t ent = ev[e];
+    if (!(ent & qbit)) continue;
+    const Eval r = eval_gauss(rec[min(ent & 0x0fffffffu, (uint32_t)a.n - 1u)], pxf, pyf);
+    T = T - r.alpha * T;
+  }
+  const int nblk = (int)((b1 - b0 + kBwdBlock - 1) / kBwdBlock);
+  for (int blk = nblk - 1; blk >= 0; --blk) {
+    const uint32_t e0 = b0 + (uint32_t)blk * kBwdBlock;
+    float Tv[kBwdBlock];
+    float Tb = ckpt[blk][tid];
+#pragma unroll
+    for (int j = 0; j < kBwdBlock; ++j) {
+      Tv[j] = Tb;
+      const uint32_t e = e0 + j;
+      if (e < b1) {
+        const uint32_t ent = ev[e];
+        if (ent & qbit) {
+          const Eval r = eval_gauss(rec[min(ent & 0x0fffffffu, (uint32_t)a.n - 1u)], pxf, pyf);
+          Tb = Tb - r.alpha * Tb;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = kBwdBlock - 1; j >= 0; --j) {
+      const uint32_t e = e0 + j;
+      if (e >= b1) continue;
+      const uint32_t ent = ev[e];
+      if (!(ent & qbit)) continue;                          // scalar: the box misses this quadrant
+      const uint32_t idx = min(ent & 0x0fffffffu, (uint32_t)a.n - 1u);
+      const GRec& g = rec[idx];
+      const Eval r = eval_gauss(g, pxf, pyf);
+      const float W = Tin * Tv[j];
+      const float gal = W * ((gp.x * (g.rgb[0] - Rr) + gp.y * (g.rgb[1] - Rg) + gp.z * (g.rgb[2] - Rb)) + gp.w * Sf);
+      const float wa = W * r.alpha;
+      const float om = 1.0f - r.alpha;
+      Rr = fmaf(om, Rr, r.alpha * g.rgb[0]);
+      Rg = fmaf(om, Rg, r.alpha * g.rgb[1]);
+      Rb = fmaf(om, Rb, r.alpha * g.rgb[2]);
+      Sf = om * Sf;
+      const bool smooth = r.q >= kLog2AlphaMin && __builtin_amdgcn_exp2f(r.q) < kAlphaMax;
+      const float gq = smooth ? gal * r.alpha * kLn2 : 0.0f;
+      float v[kGradSlots];
+      v[0] = gq * r.dx * r.dx;
+      v[1] = gq * r.dx * r.dy;
+      v[2] = gq * r.dy * r.dy;
+      v[3] = -gq * fmaf(2.0f * g.ca, r.dx, g.cb * r.dy);
+      v[4] = -gq * fmaf(2.0f * g.cc, r.dy, g.cb * r.dx);
+      v[5] = gq;
+      v[6] = wa * gp.x;
+      v[7] = wa * gp.y;
+      v[8] = wa * gp.z;
+#pragma unroll
+      for (int q = 0; q < kGradSlots; ++q) v[q] = wave_sum(v[q]);
+      if (lane == 0) {
+        float* dst = a.ggrad + (size_t)idx * kGradSlots;
+#pragma unroll
+        for (int q = 0; q < kGradSlots; ++q)
+          if (v[q] != 0.0f) atomicAdd(dst + q, v[q]);
+      }
+    }
+  }
+}
+
+// Chain rule of the projection (preprocess_gs, in reverse), one thread per Gaussian.
+// Accumulators -> conic (ca, cb, cc) -> Sigma'^-1 -> Sigma' = (J M)(J M)^T + f' I with
+// M = W R(q) diag(e^l) -> J (camera-space mean), M -> (R(q), e^l) -> quaternion (through
+// its normalisation) and log-scales; projected mean -> camera-space mean -> means; log2 o
+// -> opacity.
+__global__ __launch_bounds__(256) void preprocess_bwd_gs(BuildArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const Consts& c = a.c;
+  float gm[3] = {0.f, 0.f, 0.f}, gl[3] = {0.f, 0.f, 0.f}, gqt[4] = {0.f, 0.f, 0.f, 0.f}, go = 0.f, gc[3] = {0.f, 0.f, 0.f};
+  const float mx = a.means[3 * i], my = a.means[3 * i + 1], mz = a.means[3 * i + 2];
+  const KeyCull kc = key_and_cull(c, mx, my, mz);
+  if (kc.vis) {
+    const float* acc = a.ggrad + (size_t)i * kGradSlots;
+    const float g_ca = acc[0], g_cb = acc[1], g_cc = acc[2], g_mux = acc[3], g_muy = acc[4], g_l2o = acc[5];
+    gc[0] = acc[6];
+    gc[1] = acc[7];
+    gc[2] = acc[8];
+    // forward quantities (float32, as preprocess_gs)
+    float qw = a.quats[4 * i], qx = a.quats[4 * i + 1], qy = a.quats[4 * i + 2], qz = a.quats[4 * i + 3];
+    const float qnorm = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    const float qn = 1.0f / qnorm;
+    qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+    const float Rg[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                         2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                         2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+    const float s[3] = {expf(a.log_scales[3 * i]), expf(a.log_scales[3 * i + 1]), expf(a.log_scales[3 * i + 2])};
+    float M[9];
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k)
+        M[3 * r + k] = (c.R[3 * r] * Rg[k] + c.R[3 * r + 1] * Rg[3 + k] + c.R[3 * r + 2] * Rg[6 + k]) * s[k];
+    const float x = kc.xc, y = kc.yc, z = kc.key - c.d_fwd;
+    const float iz = 1.0f / z;
+    const float j00 = c.fpx * iz, j02 = -c.fpx * x * iz * iz, j11 = c.fpy * iz, j12 = -c.fpy * y * iz * iz;
+    float u[3], v[3];
+    for (int k = 0; k < 3; ++k) {
+      u[k] = j00 * M[k] + j02 * M[6 + k];
+      v[k] = j11 * M[3 + k] + j12 * M[6 + k];
+    }
+    const float sa = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + c.f_dil;
+    const float sb = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+    const float sc = (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) + c.f_dil;
+    const float bb = sb * sb;
+    const float det = fmaxf(fmaf(sa, sc, -bb) + fmaf(-sb, sb, bb), fmaxf(c.f_dil * c.f_dil, 1e-10f));
+    const float idet = 1.0f / det;
+    // conic = -1/2 log2e Sigma'^-1 with cb carrying both off-diagonal entries
+    const float h = 0.5f * kLog2e;
+    const float G00 = -h * g_ca, G01 = -h * g_cb, G11 = -h * g_cc;     // dL/d(Sigma'^-1) per entry
+    const float I00 = sc * idet, I01 = -sb * idet, I11 = sa * idet;
+    const float m00 = G00 * I00 + G01 * I01, m01 = G00 * I01 + G01 * I11;
+    const float m10 = G01 * I00 + G11 * I01, m11 = G01 * I01 + G11 * I11;
+    const float S00 = -(I00 * m00 + I01 * m10), S11 = -(I01 * m01 + I11 * m11);
+    const float S01 = -0.5f * ((I00 * m01 + I01 * m11) + (I01 * m00 + I11 * m10));
+    // Sigma' = U U^T + f' I, U rows u, v:  dL/dU = 2 S U
+    float gu[3], gv[3];
+    for (int k = 0; k < 3; ++k) {
+      gu[k] = 2.0f * (S00 * u[k] + S01 * v[k]);
+      gv[k] = 2.0f * (S01 * u[k] + S11 * v[k]);
+    }
+    // U = J M
+    float gM[9];
+    float g_j00 = 0.f, g_j02 = 0.f, g_j11 = 0.f, g_j12 = 0.f;
+    for (int k = 0; k < 3; ++k) {
+      gM[k] = gu[k] * j00;
+      gM[3 + k] = gv[k] * j11;
+      gM[6 + k] = gu[k] * j02 + gv[k] * j12;
+      g_j00 += gu[k] * M[k];
+      g_j02 += gu[k] * M[6 + k];
+      g_j11 += gv[k] * M[3 + k];
+      g_j12 += gv[k] * M[6 + k];
+    }
+    // J and the projected mean as functions of the camera-space mean (x, y, z)
+    const float iz2 = iz * iz, iz3 = iz2 * iz;
+    const float g_x = g_j02 * (-c.fpx * iz2) + g_mux * c.fpx * iz;
+    const float g_y = g_j12 * (-c.fpy * iz2) + g_muy * c.fpy * iz;
+    const float g_z = g_j00 * (-c.fpx * iz2) + g_j02 * (2.0f * c.fpx * x * iz3) + g_j11 * (-c.fpy * iz2) +
+                      g_j12 * (2.0f * c.fpy * y * iz3) - g_mux * c.fpx * x * iz2 - g_muy * c.fpy * y * iz2;
+    for (int j = 0; j < 3; ++j) gm[j] = c.R[j] * g_x + c.R[3 + j] * g_y + c.R[6 + j] * g_z;
+    // M = W R diag(s):  dL/dl_k = sum_r gM[r][k] M[r][k];  dL/dR[j][k] = s_k sum_r W[r][j] gM[r][k]
+    float gR[9];
+    for (int k = 0; k < 3; ++k) {
+      gl[k] = gM[k] * M[k] + gM[3 + k] * M[3 + k] + gM[6 + k] * M[6 + k];
+      for (int j = 0; j < 3; ++j)
+        gR[3 * j + k] = s[k] * (c.R[j] * gM[k] + c.R[3 + j] * gM[3 + k] + c.R[6 + j] * gM[6 + k]);
+    }
+    // rotation of the normalised quaternion (w, x, y, z)
+    const float gw = 2.f * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+    const float gx = 2.f * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.f * qx * gR[4] - qw * gR[5] + qz * gR[6] +
+                            qw * gR[7] - 2.f * qx * gR[8]);
+    const float gy = 2.f * (-2.f * qy * gR[0] + qx * gR[1] + qw * gR[2] + qx * gR[3] + qz * gR[5] - qw * gR[6] +
+                            qz * gR[7] - 2.f * qy * gR[8]);
+    const float gz = 2.f * (-2.f * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.f * qz * gR[4] +
+                            qy * gR[5] + qx * gR[6] + qy * gR[7]);
+    const float dot = gw * qw + gx * qx + gy * qy + gz * qz;
+    gqt[0] = (gw - qw * dot) * qn;
+    gqt[1] = (gx - qx * dot) * qn;
+    gqt[2] = (gy - qy * dot) * qn;
+    gqt[3] = (gz - qz * dot) * qn;
+    go = g_l2o / (a.opacity[i] * kLn2);
+  }
+  for (int j = 0; j < 3; ++j) {
+    a.grads.means[3 * i + j] = gm[j];
+    a.grads.log_scales[3 * i + j] = gl[j];
+    a.grads.rgb[3 * i + j] = gc[j];
+  }
+  for (int j = 0; j < 4; ++j) a.grads.quats[4 * i + j] = gqt[j];
+  a.grads.opacity[i] = go;
+}
+
 __global__ void write_table(float* dst, TableChunk t) {
   const int i = threadIdx.x;
   if (i < t.count) dst[t.offset + i] = t.v[i];
@@ -499,6 +747,16 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     PhaseScope ps(prof, LF_PHASE_FILTER, s);
     if ((e = launch_lowpass(a, s)) != hipSuccess) return e;
   }
+  return hipGetLastError();
+}
+
+hipError_t build_backward(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
+  PhaseScope ps(prof, LF_PHASE_BUILD_BWD, s);
+  hipError_t e;
+  if (a.n == 0) return hipSuccess;
+  if ((e = fill(reinterpret_cast<uint32_t*>(a.ggrad), a.n * kGradSlots, 0u, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(splat_bwd_gs, dim3((unsigned)L.max_items), dim3(256), 0, s, a, L.n_buckets);
+  hipLaunchKernelGGL(preprocess_bwd_gs, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ struct BuildLayout {
   int32_t filt_bands, filt_segs;      // voxel low-pass regions (0 for Gaussians)
   size_t o_hdr, o_keys, o_vals, o_keys_alt, o_vals_alt, o_rec, o_ntiles_i, o_ntiles_r, o_chunk_r, o_offsets,
       o_scan64, o_chunk_start, o_edges, o_dtab, o_nseg, o_bucket, o_scan32, o_radix, o_ekeys, o_evals, o_ekeys_alt,
-      o_evals_alt, o_pcnt, o_item_start, o_pslot, o_items, o_partial, o_halo_rows, o_halo_cols;
+      o_evals_alt, o_pcnt, o_item_start, o_pslot, o_items, o_partial, o_halo_rows, o_halo_cols, o_ggrad;
   int64_t max_items, max_partial;
   size_t total;
 };
@@ -97,7 +97,15 @@ struct BuildArgs {
   // voxel low-pass: saved original rows [K][bands][2][wp] and columns [K][segs][2][hp]
   float4 *halo_rows, *halo_cols;
   int32_t filt_bands, filt_segs;
+  // backward: plane cotangents, per-Gaussian accumulators [n][kGradSlots], outputs
+  const float* d_planes;
+  float* ggrad;
+  lf_gaussian_grads grads;
 };
+
+// Per-Gaussian accumulators of the splat backward: d/d(ca, cb, cc) of the log2-domain
+// conic, d/d(projected mean x, y), d/d(log2 o), d/d(rgb).
+constexpr int kGradSlots = 9;
 
 struct TableChunk {
   int32_t offset, count;
@@ -113,5 +121,9 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
 hipError_t launch_preprocess_vox(const BuildArgs& a, hipStream_t s);
 hipError_t launch_splat_vox(const BuildArgs& a, const BuildLayout& L, hipStream_t s);
 hipError_t launch_lowpass(const BuildArgs& a, hipStream_t s);
+
+// Backward of the Gaussian build (build_gs.hip): splat VJP into the per-Gaussian
+// accumulators, then the projection's chain rule into the parameter gradients.
+hipError_t build_backward(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof);
 
 }  // namespace lf

@@ -456,6 +456,149 @@ __global__ void plane_coeffs_kernel(CompositeArgs a, float* bx, float* by, float
   cyn[i] = Y + 0.5f;
 }
 
+// ---------------------------------------------------------------------------------------
+// Backward of the composite (Eq. 7 over operator), one thread per output pixel.  With
+// Q = sum_k T_k c_k, T_{k+1} = T_k (1 - a_k) and cotangents g = dL/dQ, g_T = dL/dT_final:
+//   dL/dc_k = T_k g,   dL/da_k = -T_k (g . R_{k+1} + g_T S_{k+1}),
+//   R_k = c_k + (1 - a_k) R_{k+1},  S_k = (1 - a_k) S_{k+1},  R_K = 0, S_K = 1,
+// evaluated back to front.  T_k is recomputed, not stored: a forward sweep keeps T at the
+// start of every segment of ceil(K / 64) planes (LDS), and each segment is swept forward
+// again (T of its planes into LDS) before it is walked backwards.  Sampled texel values are
+// re-read per sweep; the cotangents of a sample go to its texels through the transposed
+// interpolation weights (float atomics into the FP32 plane gradient).
+// ---------------------------------------------------------------------------------------
+constexpr int kBwdThreads = 128;
+constexpr int kBwdCkpt = 64;
+
+struct Tap {
+  int ix, iy;      // nearest: the texel; bilinear: the lower corner
+  float wx, wy;    // bilinear weights of the upper neighbours
+};
+
+template <bool BIL>
+__device__ __forceinline__ Tap sample_tap(const CompositeArgs& a, int k, float xr, float yr, float dx, float dy) {
+  const PlaneCo pc = plane_co(a.depth[k], a.c);
+  const float cx = a.c.cpx + pc.gx * dx;
+  const float cy = a.c.cpy + pc.gy * dy;
+  Tap t;
+  if (!BIL) {
+    t.ix = __float2int_rd(pc.bx * xr + (cx + 0.5f));
+    t.iy = __float2int_rd(pc.by * yr + (cy + 0.5f));
+    t.wx = t.wy = 0.0f;
+  } else {
+    const float X = pc.bx * xr + cx, Y = pc.by * yr + cy;
+    const float fx0 = floorf(X), fy0 = floorf(Y);
+    t.wx = X - fx0;
+    t.wy = Y - fy0;
+    t.ix = __float2int_rd(fx0);
+    t.iy = __float2int_rd(fy0);
+  }
+  return t;
+}
+
+template <typename PT, bool BIL>
+__device__ __forceinline__ float4 sample_value(const CompositeArgs& a, const PT* planes, int k, const Tap& t) {
+  const size_t base = (size_t)k * a.hp * a.wp;
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (!BIL) {
+    return (t.ix >= 0 && t.ix < a.wp && t.iy >= 0 && t.iy < a.hp) ? load_texel(planes, base + (size_t)t.iy * a.wp + t.ix)
+                                                                    : z;
+  }
+  float4 q[2][2];
+#pragma unroll
+  for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+    for (int ox = 0; ox < 2; ++ox) {
+      const int xx = t.ix + ox, yy = t.iy + oy;
+      q[oy][ox] = (xx >= 0 && xx < a.wp && yy >= 0 && yy < a.hp) ? load_texel(planes, base + (size_t)yy * a.wp + xx) : z;
+    }
+  return lerp4(lerp4(q[0][0], q[0][1], t.wx), lerp4(q[1][0], q[1][1], t.wx), t.wy);
+}
+
+__device__ __forceinline__ void add_texel_grad(float* dp, const CompositeArgs& a, int k, int ix, int iy, float w,
+                                               float gr, float gg, float gb, float ga) {
+  if (ix < 0 || ix >= a.wp || iy < 0 || iy >= a.hp || w == 0.0f) return;
+  float* q = dp + (((size_t)k * a.hp + iy) * a.wp + ix) * 4;
+  atomicAdd(q + 0, w * gr);
+  atomicAdd(q + 1, w * gg);
+  atomicAdd(q + 2, w * gb);
+  atomicAdd(q + 3, w * ga);
+}
+
+template <typename PT, bool BIL>
+__global__ __launch_bounds__(kBwdThreads) void composite_bwd(CompositeArgs a, const float* __restrict__ d_out,
+                                                             float* __restrict__ d_planes) {
+  __shared__ float ckpt[kBwdCkpt][kBwdThreads];
+  __shared__ float tseg[kBwdCkpt][kBwdThreads];
+  const int64_t n = (int64_t)a.n_views * a.ny * a.nx;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;                                       // no barriers below: LDS columns are per thread
+  const int tid = threadIdx.x;
+  const int x = (int)(i % a.nx);
+  const int y = (int)((i / a.nx) % a.ny);
+  const int v = (int)(i / ((int64_t)a.nx * a.ny));
+  const PT* planes = static_cast<const PT*>(a.planes);
+  const float xr = (float)x - a.c.cx, yr = (float)y - a.c.cy;
+  const float dx = a.dx[v], dy = a.dy[v];
+  const int S = (a.K + kBwdCkpt - 1) / kBwdCkpt;          // planes per segment
+  const int nseg = (a.K + S - 1) / S;
+  float T = 1.0f;
+  for (int k = 0; k < a.K; ++k) {
+    if (k % S == 0) ckpt[k / S][tid] = T;
+    const float4 s = sample_value<PT, BIL>(a, planes, k, sample_tap<BIL>(a, k, xr, yr, dx, dy));
+    T = fmaf(-T, s.w, T);
+  }
+  const float4 g = reinterpret_cast<const float4*>(d_out)[i];
+  float Rr = 0.f, Rg = 0.f, Rb = 0.f, Sf = 1.0f;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int k0 = sg * S, k1 = min(a.K, k0 + S);
+    float Tk = ckpt[sg][tid];
+    for (int k = k0; k < k1; ++k) {
+      tseg[k - k0][tid] = Tk;
+      const float4 s = sample_value<PT, BIL>(a, planes, k, sample_tap<BIL>(a, k, xr, yr, dx, dy));
+      Tk = fmaf(-Tk, s.w, Tk);
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+      const Tap t = sample_tap<BIL>(a, k, xr, yr, dx, dy);
+      const float4 s = sample_value<PT, BIL>(a, planes, k, t);
+      const float Tb = tseg[k - k0][tid];
+      const float gr = Tb * g.x, gg = Tb * g.y, gb = Tb * g.z;
+      const float ga = -Tb * ((g.x * Rr + g.y * Rg + g.z * Rb) + g.w * Sf);
+      if (!BIL) {
+        add_texel_grad(d_planes, a, k, t.ix, t.iy, 1.0f, gr, gg, gb, ga);
+      } else {
+        const float w00 = (1.0f - t.wx) * (1.0f - t.wy), w01 = t.wx * (1.0f - t.wy);
+        const float w10 = (1.0f - t.wx) * t.wy, w11 = t.wx * t.wy;
+        add_texel_grad(d_planes, a, k, t.ix, t.iy, w00, gr, gg, gb, ga);
+        add_texel_grad(d_planes, a, k, t.ix + 1, t.iy, w01, gr, gg, gb, ga);
+        add_texel_grad(d_planes, a, k, t.ix, t.iy + 1, w10, gr, gg, gb, ga);
+        add_texel_grad(d_planes, a, k, t.ix + 1, t.iy + 1, w11, gr, gg, gb, ga);
+      }
+      const float om = 1.0f - s.w;
+      Rr = fmaf(om, Rr, s.x);
+      Rg = fmaf(om, Rg, s.y);
+      Rb = fmaf(om, Rb, s.z);
+      Sf = om * Sf;
+    }
+  }
+}
+
+__global__ void zero_f32(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+template <typename PT>
+hipError_t launch_bwd(const CompositeArgs& a, const float* d_out, float* d_planes, hipStream_t s) {
+  const int64_t n = (int64_t)a.n_views * a.ny * a.nx;
+  const dim3 grid((unsigned)((n + kBwdThreads - 1) / kBwdThreads));
+  if (a.interp == LF_BILINEAR)
+    hipLaunchKernelGGL((composite_bwd<PT, true>), grid, dim3(kBwdThreads), 0, s, a, d_out, d_planes);
+  else
+    hipLaunchKernelGGL((composite_bwd<PT, false>), grid, dim3(kBwdThreads), 0, s, a, d_out, d_planes);
+  return hipGetLastError();
+}
+
 template <int G>
 int pick_cost(int V) { return ((V + G - 1) / G) * (G + 4); }
 
@@ -529,6 +672,18 @@ hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, 
     case LF_F16: return dispatch_out<__half>(a, rows, G, pt, ct, s);
     case LF_BF16: return dispatch_out<__hip_bfloat16>(a, rows, G, pt, ct, s);
     default: return dispatch_out<float>(a, rows, G, pt, ct, s);
+  }
+}
+
+hipError_t composite_backward_launch(const CompositeArgs& a, const float* d_out, float* d_planes, hipStream_t s,
+                                    Profiler* prof) {
+  PhaseScope ps(prof, LF_PHASE_COMPOSITE_BWD, s);
+  const int64_t np = (int64_t)a.K * a.hp * a.wp * 4;
+  if (np > 0) hipLaunchKernelGGL(zero_f32, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, d_planes, np);
+  switch (a.plane_dtype) {
+    case LF_F16: return launch_bwd<__half>(a, d_out, d_planes, s);
+    case LF_BF16: return launch_bwd<__hip_bfloat16>(a, d_out, d_planes, s);
+    default: return launch_bwd<float>(a, d_out, d_planes, s);
   }
 }
 

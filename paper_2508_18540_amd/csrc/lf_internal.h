@@ -101,5 +101,8 @@ size_t composite_table_bytes(int K, int n_views);
 hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, Profiler* prof = nullptr);
 hipError_t plane_coeffs_launch(const CompositeArgs& a, float* bx, float* by, float* cx, float* cy,
                                float* cxn, float* cyn, hipStream_t s);
+// Zero-fills d_planes [K][hp][wp][4] and accumulates the composite's VJP of d_out into it.
+hipError_t composite_backward_launch(const CompositeArgs& a, const float* d_out, float* d_planes, hipStream_t s,
+                                    Profiler* prof = nullptr);
 
 }  // namespace lf

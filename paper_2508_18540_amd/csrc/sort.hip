@@ -254,6 +254,8 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
   return hipGetLastError();
 }
 
+int radix_passes(int bits) { return bits < 1 ? 0 : (bits + kMaxDigitBits - 1) / kMaxDigitBits; }
+
 hipError_t fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);

@@ -27,4 +27,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
 
 hipError_t fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
+// Number of passes radix_sort_pairs makes over `bits` key bits (odd: result in the alt arrays).
+int radix_passes(int bits);
+
 }  // namespace lf

@@ -167,3 +167,67 @@ def build_stats(ctx: Context, workspace: Workspace, check: bool = True):
     info, status = L.lf_build_stats(ctx.handle, workspace.ptr, workspace.nbytes,
                                     torch.cuda.current_stream(ctx.device).cuda_stream, check=check)
     return info, status
+
+
+def composite_backward(ctx: Context, rgba: torch.Tensor, depth: torch.Tensor, cam, views, d_out: torch.Tensor,
+                       interp: str = "nearest", d_planes: torch.Tensor | None = None) -> torch.Tensor:
+    """lf_composite_backward: dL/d(planes) [K, H, W, 4] float32 from dL/d(views) [V, ny, nx, 4]."""
+    m = mpi_of(rgba, depth)
+    _need(d_out, "d_out", (torch.float32,), 4)
+    if tuple(d_out.shape) != (len(views), cam.ny, cam.nx, 4):
+        raise ValueError(f"d_out must be [{len(views)}, {cam.ny}, {cam.nx}, 4]")
+    if d_planes is None:
+        d_planes = torch.empty(rgba.shape, dtype=torch.float32, device=rgba.device)
+    _need(d_planes, "d_planes", (torch.float32,), 4)
+    L.lf_composite_backward(ctx.handle, m, L.make_camera(cam), views, _INTERP[interp], d_out.data_ptr(),
+                            d_planes.data_ptr(), _stream(rgba))
+    return d_planes
+
+
+def build_mpi_backward(ctx: Context, scene: dict, cam, out: dict, d_planes: torch.Tensor) -> dict:
+    """lf_build_mpi_backward: gradients (means, log_scales, quats, opacity, rgb) of a Gaussian
+    field from dL/d(planes), using the workspace of the build that produced ``out``."""
+    f = field_of(scene)
+    _need(d_planes, "d_planes", (torch.float32,), 4)
+    if tuple(d_planes.shape) != tuple(out["rgba"].shape):
+        raise ValueError("d_planes must have the planes' shape")
+    grads = {k: torch.empty_like(scene[k]) for k in GAUSSIAN_KEYS}
+    g = L.lf_gaussian_grads(*[grads[k].data_ptr() for k in GAUSSIAN_KEYS])
+    m = mpi_of(out["rgba"], out["depth"])
+    ws = out["workspace"]
+    L.lf_build_mpi_backward(ctx.handle, f, L.make_camera(cam), m, d_planes.data_ptr(), g, ws.ptr, ws.nbytes,
+                            torch.cuda.current_stream(ctx.device).cuda_stream)
+    return grads
+
+
+class LFRender(torch.autograd.Function):
+    """Light field of a Gaussian field: lf_build_mpi then lf_composite forward, and
+    lf_composite_backward then lf_build_mpi_backward backward.  Returns views
+    [V, ny, nx, 4] = (Q_r, Q_g, Q_b, T) in float32; gradients flow to the five Gaussian
+    parameter tensors.  Planes are kept (not recomputed) for the backward, with the build's
+    workspace."""
+
+    @staticmethod
+    def forward(fctx, means, log_scales, quats, opacity, rgb, ctx, cam, views, n_chunk, interp="nearest",
+                plane_dtype=torch.float32, binning="quantile", inv_depth_range=None, workspace=None):
+        scene = dict(means=means.detach().contiguous(), log_scales=log_scales.detach().contiguous(),
+                     quats=quats.detach().contiguous(), opacity=opacity.detach().contiguous(),
+                     rgb=rgb.detach().contiguous())
+        out = build_mpi(ctx, scene, cam, n_chunk, binning, inv_depth_range, dtype=plane_dtype, workspace=workspace)
+        img = composite(ctx, out["rgba"], out["depth"], cam, views, interp)
+        fctx.lf = (ctx, cam, views, interp, scene, out)
+        return img
+
+    @staticmethod
+    def backward(fctx, d_img):
+        ctx, cam, views, interp, scene, out = fctx.lf
+        d_planes = composite_backward(ctx, out["rgba"], out["depth"], cam, views, d_img.contiguous().float(), interp)
+        g = build_mpi_backward(ctx, scene, cam, out, d_planes)
+        return (g["means"], g["log_scales"], g["quats"], g["opacity"], g["rgb"]) + (None,) * 9
+
+
+def render_light_field(ctx: Context, params: dict, cam, views, n_chunk: int, interp: str = "nearest",
+                       plane_dtype=torch.float32, binning: str = "quantile", inv_depth_range=None, workspace=None):
+    """Differentiable light-field render of a Gaussian field (see LFRender)."""
+    return LFRender.apply(params["means"], params["log_scales"], params["quats"], params["opacity"], params["rgb"],
+                          ctx, cam, views, n_chunk, interp, plane_dtype, binning, inv_depth_range, workspace)
