@@ -250,3 +250,107 @@ def composite_vjp(planes: np.ndarray, d: Decisions, cam, d_out: np.ndarray) -> n
     pt = torch.tensor(np.asarray(planes, np.float64), dtype=TD, requires_grad=True)
     (composite_of(pt, d, cam) * torch.as_tensor(d_out, dtype=TD)).sum().backward()
     return pt.grad.numpy()
+
+
+def texel_vjp_local(scene: dict, cam, part: partition.Partition, texels: np.ndarray, cot: np.ndarray,
+                    ambiguous: np.ndarray | None = None) -> dict:
+    """Gradient w.r.t. every Gaussian parameter of sum_j <cot_j, plane texel j> for a few plane
+    texels ``texels`` [m, 3] = (k, y, x) with cotangents ``cot`` [m, 4] (dense arrays, zero for
+    Gaussians that touch none of them).  Each texel is blended from all Gaussians of its chunk
+    in (key, index) order with the frozen inclusion and clamp decisions taken at these
+    parameters, so the cost is local: it serves full-size checks.  If ``ambiguous`` (bool [N])
+    is given, Gaussians whose inclusion (o G vs 1/255) or clamp (o G vs 0.99) decision at one
+    of these texels lies within float32 rounding of the threshold are flagged in it."""
+    g = geometry.derive(cam)
+    out = {k: np.zeros(np.asarray(scene[k]).shape) for k in KEYS}
+    texels = np.asarray(texels, dtype=np.int64).reshape(-1, 3)
+    cot = np.asarray(cot, dtype=np.float64).reshape(-1, 4)
+    for k in np.unique(texels[:, 0]):
+        idx = part.order[part.chunk_start[k]:part.chunk_start[k + 1]]
+        if idx.size == 0:
+            continue
+        sel = texels[:, 0] == k
+        ty, tx = texels[sel, 1].astype(np.float64), texels[sel, 2].astype(np.float64)
+        sub = {key: np.asarray(scene[key])[idx] for key in KEYS}
+        p = params_of(sub)
+        mean2d, conic = project_reference(p, cam, g)
+        dx = torch.from_numpy(tx)[:, None] - mean2d[None, :, 0]
+        dy = torch.from_numpy(ty)[:, None] - mean2d[None, :, 1]
+        quad = conic[None, :, 0, 0] * dx * dx + (conic[None, :, 0, 1] + conic[None, :, 1, 0]) * dx * dy + \
+            conic[None, :, 1, 1] * dy * dy
+        ln_a = torch.log(p["opacity"])[None, :] - 0.5 * quad
+        with torch.no_grad():
+            inc = ln_a >= splat.LN_ALPHA_MIN
+            clamped = torch.exp(ln_a) >= project.ALPHA_MAX
+            if ambiguous is not None:
+                eps = torch.from_numpy(splat.ambiguity_eps(np.linalg.inv(conic.detach().numpy())))[None, :]
+                near = ((ln_a - splat.LN_ALPHA_MIN).abs() <= eps) | ((ln_a - math.log(project.ALPHA_MAX)).abs() <= eps)
+                ambiguous[idx[near.any(0).numpy()]] = True
+        a = torch.exp(torch.clamp(ln_a, max=0.0))
+        alpha = torch.where(inc, torch.where(clamped, torch.full_like(a, project.ALPHA_MAX), a), torch.zeros_like(a))
+        Tin = torch.cumprod(torch.cat([torch.ones_like(alpha[:, :1]), 1.0 - alpha[:, :-1]], 1), 1)
+        C = (Tin * alpha) @ p["rgb"]
+        A = 1.0 - Tin[:, -1] * (1.0 - alpha[:, -1])
+        val = (torch.cat([C, A[:, None]], 1) * torch.from_numpy(cot[sel])).sum()
+        val.backward()
+        for key in KEYS:
+            out[key][idx] += p[key].grad.numpy()
+    return out
+
+
+def pixel_vjp_sparse(texel_fn, depth32, cam, dx32, dy32, interp: str, pix: np.ndarray, cot: np.ndarray):
+    """The composite's VJP for a few view pixels ``pix`` [n, 3] = (v, y, x) with cotangents
+    ``cot`` [n, 4] on (Q_rgb, T): returns {(k, y, x): dL/d(C, A)} over the touched texels.
+    ``texel_fn(k, iy, ix)`` gives plane texels [m, 4] at in-range indices.  Back to front with
+    R_k = c_k + (1 - a_k) R_{k+1}, S_k = (1 - a_k) S_{k+1}, float64."""
+    g = geometry.derive(cam)
+    c = decisions.constants(g, cam)
+    K = len(depth32)
+    pc = decisions.plane_coeffs32(c, np.asarray(depth32, np.float32), np.asarray(dx32, np.float32),
+                                  np.asarray(dy32, np.float32))
+    pix = np.asarray(pix, dtype=np.int64).reshape(-1, 3)
+    cot = np.asarray(cot, dtype=np.float64).reshape(-1, 4)
+    n = pix.shape[0]
+    nearest = interp == "nearest"
+    taps_all, vals = [], []
+    for k in range(K):
+        X = np.empty(n, dtype=np.float32)
+        Y = np.empty(n, dtype=np.float32)
+        for v in np.unique(pix[:, 0]):
+            s = pix[:, 0] == v
+            X[s], Y[s] = decisions.texel_coords32(pc, c, k, int(v), pix[s, 2], pix[s, 1], nearest)
+        if nearest:
+            taps = [(np.floor(Y).astype(np.int64), np.floor(X).astype(np.int64), np.ones(n))]
+        else:
+            x0, y0 = np.floor(X), np.floor(Y)
+            wx, wy = X.astype(np.float64) - x0, Y.astype(np.float64) - y0
+            x0, y0 = x0.astype(np.int64), y0.astype(np.int64)
+            taps = [(y0 + oy, x0 + ox, fy * fx) for oy, fy in ((0, 1 - wy), (1, wy)) for ox, fx in ((0, 1 - wx), (1, wx))]
+        s = np.zeros((n, 4))
+        for iy, ix, w in taps:
+            ok = (iy >= 0) & (iy < g.hp) & (ix >= 0) & (ix < g.wp)
+            if np.any(ok):
+                s[ok] += w[ok, None] * texel_fn(k, iy[ok], ix[ok])
+        taps_all.append(taps)
+        vals.append(s)
+    T = np.ones(n)
+    Ts = []
+    for k in range(K):
+        Ts.append(T.copy())
+        T = T * (1.0 - vals[k][:, 3])
+    R = np.zeros((n, 3))
+    S = np.ones(n)
+    out = {}
+    for k in range(K - 1, -1, -1):
+        s = vals[k]
+        gc = Ts[k][:, None] * cot[:, :3]
+        ga = -Ts[k] * ((cot[:, :3] * R).sum(1) + cot[:, 3] * S)
+        for iy, ix, w in taps_all[k]:
+            ok = (iy >= 0) & (iy < g.hp) & (ix >= 0) & (ix < g.wp) & (w != 0.0)
+            for j in np.nonzero(ok)[0]:
+                key = (k, int(iy[j]), int(ix[j]))
+                gv = np.concatenate([w[j] * gc[j], [w[j] * ga[j]]])
+                out[key] = out.get(key, 0.0) + gv
+        R = s[:, :3] + (1.0 - s[:, 3])[:, None] * R
+        S = (1.0 - s[:, 3]) * S
+    return out

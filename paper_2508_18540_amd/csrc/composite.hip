@@ -518,6 +518,7 @@ __device__ __forceinline__ float4 sample_value(const CompositeArgs& a, const PT*
 __device__ __forceinline__ void add_texel_grad(float* dp, const CompositeArgs& a, int k, int ix, int iy, float w,
                                                float gr, float gg, float gb, float ga) {
   if (ix < 0 || ix >= a.wp || iy < 0 || iy >= a.hp || w == 0.0f) return;
+  if (gr == 0.0f && gg == 0.0f && gb == 0.0f && ga == 0.0f) return;
   float* q = dp + (((size_t)k * a.hp + iy) * a.wp + ix) * 4;
   atomicAdd(q + 0, w * gr);
   atomicAdd(q + 1, w * gg);
@@ -537,6 +538,8 @@ __global__ __launch_bounds__(kBwdThreads) void composite_bwd(CompositeArgs a, co
   const int x = (int)(i % a.nx);
   const int y = (int)((i / a.nx) % a.ny);
   const int v = (int)(i / ((int64_t)a.nx * a.ny));
+  const float4 g = reinterpret_cast<const float4*>(d_out)[i];
+  if (g.x == 0.0f && g.y == 0.0f && g.z == 0.0f && g.w == 0.0f) return;   // contributes nothing
   const PT* planes = static_cast<const PT*>(a.planes);
   const float xr = (float)x - a.c.cx, yr = (float)y - a.c.cy;
   const float dx = a.dx[v], dy = a.dy[v];
@@ -548,7 +551,6 @@ __global__ __launch_bounds__(kBwdThreads) void composite_bwd(CompositeArgs a, co
     const float4 s = sample_value<PT, BIL>(a, planes, k, sample_tap<BIL>(a, k, xr, yr, dx, dy));
     T = fmaf(-T, s.w, T);
   }
-  const float4 g = reinterpret_cast<const float4*>(d_out)[i];
   float Rr = 0.f, Rg = 0.f, Rb = 0.f, Sf = 1.0f;
   for (int sg = nseg - 1; sg >= 0; --sg) {
     const int k0 = sg * S, k1 = min(a.K, k0 + S);

@@ -134,3 +134,70 @@ def test_build_backward_culled_and_empty():
         a = host(gg[k])
         assert np.all(a[:10] == 0.0) and np.isfinite(a).all()
     assert np.abs(host(gg["rgb"])[10:]).max() > 0.0
+
+
+def test_grad200k_full_size_sparse_cotangents():
+    """The differentiation workload at full size (200,000 Gaussians, 512^2, 128 planes, 45
+    views, FP32 planes): the composite backward for 300 random view pixels and the build
+    backward for 40 covered plane texels, each against the oracle's local VJP (every
+    texel / Gaussian compared; Gaussians whose inclusion or clamp decision at a chosen texel
+    is within float32 rounding of its threshold are reported and skipped)."""
+    from oracle import partition
+    announce("grad200k full size")
+    scene, cam, cfg = scenegen.config("grad200k")
+    K = cfg["n_chunk"]
+    ds = T.to_device(scene)
+    ws = T.workspace_for(ds, cam, K)
+    out = T.build_mpi(ctx(), ds, cam, K, workspace=ws)
+    T.build_stats(ctx(), ws, check=True)
+    g = geometry.derive(cam)
+    part = partition.partition(scene["means"], cam, g, K)
+    torch.cuda.synchronize()
+    assert np.array_equal(out["chunk_of"].cpu().numpy(), part.chunk_of)
+    dx, dy = _views(cam, cfg["vx"])
+    views = T.views_of(dx, dy)
+    rng = np.random.default_rng(12)
+    # composite backward
+    pix = np.unique(np.stack([rng.integers(0, len(dx), 300), rng.integers(0, cam.ny, 300),
+                              rng.integers(0, cam.nx, 300)], 1), axis=0)
+    cot = rng.normal(size=(pix.shape[0], 4))
+    d_out = torch.zeros((len(dx), cam.ny, cam.nx, 4), dtype=torch.float32, device="cuda")
+    d_out[tuple(torch.from_numpy(pix.T).cuda())] = torch.from_numpy(cot).float().cuda()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    dp = T.composite_backward(ctx(), out["rgba"], out["depth"], cam, views, d_out, "nearest")
+    t1.record()
+    torch.cuda.synchronize()
+    print("composite backward ms", t0.elapsed_time(t1))
+    planes32 = out["rgba"].cpu().numpy()
+    ref = grad.pixel_vjp_sparse(lambda k, iy, ix: planes32[k, iy, ix].astype(np.float64), out["depth"].cpu().numpy(),
+                                cam, dx, dy, "nearest", pix, cot.astype(np.float32).astype(np.float64))
+    nz = torch.nonzero(dp.abs().sum(-1)).cpu().numpy()
+    keys = list(ref.keys())
+    assert {tuple(map(int, r)) for r in nz} <= set(keys)
+    kk = np.array(keys)
+    got = dp[tuple(torch.from_numpy(kk.T).cuda())].cpu().numpy()
+    _check(got, np.stack([ref[k] for k in keys]), "d_planes (sparse, full size)")
+    del dp, planes32
+    # build backward
+    alpha = out["rgba"][..., 3]
+    cand = torch.nonzero(alpha > 0.05).cpu().numpy()
+    tex = cand[rng.choice(cand.shape[0], 40, replace=False)]
+    tcot = rng.normal(size=(tex.shape[0], 4)).astype(np.float32)
+    dpl = torch.zeros(tuple(out["rgba"].shape), dtype=torch.float32, device="cuda")
+    dpl[tuple(torch.from_numpy(tex.T).cuda())] = torch.from_numpy(tcot).cuda()
+    t0.record()
+    gg = T.build_mpi_backward(ctx(), ds, cam, out, dpl)
+    t1.record()
+    torch.cuda.synchronize()
+    print("build backward ms", t0.elapsed_time(t1))
+    amb = np.zeros(scene["means"].shape[0], dtype=bool)
+    rg = grad.texel_vjp_local(scene, cam, part, tex, tcot.astype(np.float64), amb)
+    print("Gaussians with a threshold-ambiguous decision:", int(amb.sum()))
+    keep = ~amb
+    touched = np.abs(rg["rgb"]).sum(1) > 0
+    print("Gaussians touched:", int(touched.sum()))
+    assert touched.sum() >= 40
+    for k in grad.KEYS:
+        _check(host(gg[k])[keep], rg[k][keep], k + " (full size)")

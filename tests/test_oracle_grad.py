@@ -118,3 +118,34 @@ def test_composite_vjp_matches_finite_differences_on_planes():
         e[k, y, x, c] = 1e-6
         fd = (f(planes + e) - f(planes - e)) / 2e-6
         assert abs(fd - gp[k, y, x, c]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_local_vjps_match_the_dense_oracle():
+    """The footprint-local texel VJP and the sparse pixel VJP (used at full size) equal the
+    dense oracle VJPs on a small problem."""
+    scene, cam, K, dx, dy, _ = _setup(seed=7, n=60)
+    for interp in ("nearest", "bilinear"):
+        d = grad.decide(scene, cam, K, dx, dy, interp)
+        rng = np.random.default_rng(3)
+        g = d.geom
+        tex = np.stack([rng.integers(0, K, 12), rng.integers(0, g.hp, 12), rng.integers(0, g.wp, 12)], 1)
+        tex = np.unique(tex, axis=0)
+        cot = rng.normal(size=(tex.shape[0], 4))
+        dense = np.zeros((K, g.hp, g.wp, 4))
+        dense[tex[:, 0], tex[:, 1], tex[:, 2]] = cot
+        ref = grad.planes_vjp(scene, cam, K, d, dense)
+        got = grad.texel_vjp_local(scene, cam, d.part, tex, cot)
+        for k in grad.KEYS:
+            np.testing.assert_allclose(got[k], ref[k], rtol=1e-9, atol=1e-12)
+        planes = grad.planes_of(grad.params_of(scene, False), cam, d, K).numpy()
+        pix = np.stack([rng.integers(0, len(dx), 15), rng.integers(0, cam.ny, 15), rng.integers(0, cam.nx, 15)], 1)
+        pix = np.unique(pix, axis=0)
+        pc = rng.normal(size=(pix.shape[0], 4))
+        d_out = np.zeros((len(dx), cam.ny, cam.nx, 4))
+        d_out[pix[:, 0], pix[:, 1], pix[:, 2]] = pc
+        dref = grad.composite_vjp(planes, d, cam, d_out)
+        sp = grad.pixel_vjp_sparse(lambda k, iy, ix: planes[k, iy, ix], d.part.depth, cam, dx, dy, interp, pix, pc)
+        dsp = np.zeros_like(dref)
+        for (k, y, x), v in sp.items():
+            dsp[k, y, x] = v
+        np.testing.assert_allclose(dsp, dref, rtol=1e-9, atol=1e-12)
