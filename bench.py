@@ -76,6 +76,9 @@ def parse():
     p.add_argument("--cpu-planes", type=int, default=48, help="planes the CPU oracle rasterises")
     p.add_argument("--cpu-views", type=int, default=6, help="views the CPU oracle composites")
     p.add_argument("--forms", default="f32,f16", help="plane storage forms to time (first one is `value`)")
+    p.add_argument("--extra", default="voxel256,grad200k,batch8",
+                   help="further workloads timed into the same line (voxel256, grad200k, batch8; empty for none)")
+    p.add_argument("--extra-steps", type=int, default=5)
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (for HBM counter scaling)")
     return p.parse_args()
@@ -110,6 +113,122 @@ def cpu_baseline(scene, cam, views_dx, views_dy, n_chunk, n_planes, n_views, int
                         f"{len(views_dx)} views composited over them ({t_comp:.2f} s); scaled to one frame "
                         f"= {frame_s:.1f} s"),
                 measured_s=round(t_part + t_planes + t_comp, 2))
+
+
+def _timed(fn, warmup, steps, ctx, L):
+    """Run fn warmup + steps times; returns (ms per step, {phase: ms per step})."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    L.lf_profile_read(ctx.handle, reset=True)
+    L.lf_profile_enable(ctx.handle, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.lf_profile_enable(ctx.handle, False)
+    prof = L.lf_profile_read(ctx.handle, reset=True)
+    return (t1 - t0) * 1e3 / steps, {k: round(v[0] / steps, 4) for k, v in prof.items() if v[1]}
+
+
+def extra_voxel256(ctx, steps, warmup):
+    """Sparse-voxel light field: 335,544 voxels (256^3 grid, 2 %), 512^2, 64 planes, 96 views,
+    FP16 planes, build (with the plane low-pass) + composite."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2508_18540_amd import _lib as L
+    from paper_2508_18540_amd import torch_api as T
+
+    vox, cam, cfg = scenegen.config("voxel256")
+    K, V = cfg["n_chunk"], cfg["vx"]
+    vlist = L.lf_quilt_views(L.make_camera(cam), V, 1)
+    ds = T.to_device(vox)
+    ws = T.workspace_for(ds, cam, K)
+    out = T.build_mpi(ctx, ds, cam, K, dtype=torch.float16, workspace=ws)
+    img = torch.empty((V, cam.ny, cam.nx, 4), dtype=torch.float16, device="cuda")
+
+    def step():
+        T.build_mpi(ctx, ds, cam, K, dtype=torch.float16, workspace=ws, out=out)
+        T.composite(ctx, out["rgba"], out["depth"], cam, vlist, "nearest", out=img)
+    ms, ph = _timed(step, warmup, steps, ctx, L)
+    T.build_stats(ctx, ws, check=True)
+    return dict(workload="voxel256: 335,544 voxels, 512x512, 64 quantile planes, 96 views, FP16 planes and views",
+                views_per_s=round(V / (ms * 1e-3), 1), ms_per_step=round(ms, 4), phases_ms=ph)
+
+
+def extra_grad200k(ctx, steps, warmup):
+    """Differentiation step: 200k Gaussians, 512^2, 128 planes, 45 views, FP32; forward
+    (build + composite), L2 loss against a target light field, backward through the
+    composite and the build to the five parameter tensors."""
+    import torch
+
+    import scenegen
+    from paper_2508_18540_amd import _lib as L
+    from paper_2508_18540_amd import torch_api as T
+
+    scene, cam, cfg = scenegen.config("grad200k")
+    K, V = cfg["n_chunk"], cfg["vx"]
+    vlist = L.lf_quilt_views(L.make_camera(cam), V, 1)
+    target = scenegen.perturbed_target(scene, cfg["target_seed"])
+    with torch.no_grad():
+        tout = T.build_mpi(ctx, T.to_device(target), cam, K)
+        timg = T.composite(ctx, tout["rgba"], tout["depth"], cam, vlist, "nearest")
+    del tout
+    params = {k: v.clone().requires_grad_(True) for k, v in T.to_device(scene).items()}
+    ws = T.workspace_for(params, cam, K)
+
+    def step():
+        img = T.render_light_field(ctx, params, cam, vlist, K, "nearest", workspace=ws)
+        loss = ((img[..., :3] - timg[..., :3]) ** 2).sum()
+        loss.backward()
+    ms, ph = _timed(step, warmup, steps, ctx, L)
+    return dict(workload="grad200k: 200k Gaussians, 512x512, 128 quantile planes, 45 views, FP32; forward + "
+                         "L2 loss + backward to means, log-scales, quaternions, opacities, colours",
+                ms_per_step=round(ms, 4), views_per_s=round(V / (ms * 1e-3), 1), phases_ms=ph)
+
+
+def extra_batch8(ctx, steps, warmup):
+    """Eight clustered-Gaussian scenes of uneven size in one batch (seeds 30+i): (N, res,
+    N_chunk, views) from 50k / 256^2 / 64 / 9 up to 2M / 768^2 / 128 / 45, FP16 planes and
+    views, autotuned view groups, one HIP graph replay per step; beside it the same scenes
+    rendered one after another with the single-scene entry points."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2508_18540_amd import _lib as L
+    from paper_2508_18540_amd import torch_api as T
+
+    scenes = []
+    for i, (n, res, K, V) in enumerate(scenegen.BATCH_SCENES):
+        cam = scenegen.camera(res, res, 50.0, 2.0, math.radians(40.0))
+        vl = L.lf_quilt_views(L.make_camera(cam), V, 1)
+        scenes.append(dict(scene=T.to_device(scenegen.cluster_scene(n, seed=30 + i)), cam=cam, n_chunk=K, views=vl,
+                           plane_dtype=torch.float16, out_dtype=torch.float16))
+    b = T.Batch(ctx, scenes, graph=True, autotune=True)
+    groups = b.groups()
+    ms, _ = _timed(b.run, warmup, steps, ctx, L)
+    for o in b.outs:
+        T.build_stats(ctx, o["workspace"], check=True)
+    total_views = sum(len(sc["views"]) for sc in scenes)
+
+    def sequential():
+        for sc, o in zip(scenes, b.outs):
+            T.build_mpi(ctx, sc["scene"], sc["cam"], sc["n_chunk"], dtype=torch.float16, workspace=o["workspace"],
+                        out=o)
+            T.composite(ctx, o["rgba"], o["depth"], sc["cam"], sc["views"], "nearest", out=o["views"])
+    ms_seq, _ = _timed(sequential, warmup, steps, ctx, L)
+    b.close()
+    return dict(workload="batch8: 8 scenes, 50k-2M Gaussians, 256^2-768^2, N_chunk 64/128/512, 9-100 views, "
+                         "FP16 planes and views",
+                views_per_s=round(total_views / (ms * 1e-3), 1), ms_per_step=round(ms, 4), total_views=total_views,
+                sequential_ms=round(ms_seq, 4), autotuned_view_groups=groups)
 
 
 def main():
@@ -237,6 +356,9 @@ def main():
                                    round(ph["composite"] / r["phases_ms"]["composite"], 3),
                                "composite_roofline": r["composite_roofline"],
                                "phases_ms": {k: round(v, 4) for k, v in r["phases_ms"].items()}}
+    for name in [x.strip() for x in args.extra.split(",") if x.strip()]:
+        fn = {"voxel256": extra_voxel256, "grad200k": extra_grad200k, "batch8": extra_batch8}[name]
+        line[name] = fn(ctx, args.extra_steps, 2)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, cam, dx, dy, K, args.cpu_planes, args.cpu_views, args.interp)
     print(json.dumps(line), flush=True)

@@ -212,6 +212,51 @@ lf_status lf_plane_coeffs(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, 
                           int32_t n_views, float* bx, float* by, float* cx, float* cy, float* cxn,
                           float* cyn, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Batches.  Several scenes (fields, cameras, plane counts, view lists) rendered by one
+ * call.  Each scene's build and composite go to a stream of their own, forked from and
+ * joined back into the caller's stream, so small scenes run side by side on the GPU.
+ * With LF_BATCH_GRAPH the first lf_batch_run captures the whole batch into a HIP graph and
+ * every run (the first included) replays it with one launch.  With LF_BATCH_AUTOTUNE,
+ * lf_batch_create times the composite of every scene with each view-group size (4, 8,
+ * 12, 16 views per work-group) and keeps the fastest (it builds each scene once and
+ * synchronises the device).
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+  lf_field field;           /* device field, as for lf_build_mpi                          */
+  lf_camera cam;
+  int32_t n_chunk;
+  int32_t binning;          /* LF_BIN_QUANTILE or LF_BIN_INV_DEPTH                        */
+  float inv_depth_range[2]; /* used with LF_BIN_INV_DEPTH                                 */
+  const lf_view* views;     /* host array, copied by lf_batch_create                      */
+  int32_t n_views;
+  int32_t interp;           /* lf_interp                                                  */
+  int32_t out_dtype;        /* F32 or F16                                                 */
+  lf_mpi mpi;               /* caller-allocated planes (and optional chunk outputs)       */
+  void* out;                /* caller-allocated views [n_views][ny][nx][4]                */
+  void* workspace;          /* caller-allocated build workspace of this scene             */
+  size_t workspace_bytes;
+} lf_batch_item;
+
+enum { LF_BATCH_GRAPH = 1, LF_BATCH_AUTOTUNE = 2 };
+
+typedef struct lf_batch lf_batch;
+
+/* Validates and records n_items scenes (1..LF_MAX_BATCH).  Every device buffer an item
+ * names must stay valid, and keep its address, while the batch is used.                  */
+#define LF_MAX_BATCH 64
+lf_status lf_batch_create(lf_ctx* ctx, const lf_batch_item* items, int32_t n_items, int32_t flags,
+                          lf_batch** out);
+
+/* Renders every scene (build then composite) on `stream`.  Asynchronous; capacity
+ * overflows are reported per scene by lf_build_stats on its workspace.                   */
+lf_status lf_batch_run(lf_batch* batch, void* stream);
+
+/* The view-group size the composite of scene `item` uses (autotuned, or 0 for default). */
+lf_status lf_batch_group(const lf_batch* batch, int32_t item, int32_t* group);
+
+void lf_batch_destroy(lf_batch* batch);
+
 /* Per-phase device timing, a tracing aid.  While enabled, each entry point brackets its
  * kernel phases with HIP events recorded on the launch stream; lf_profile_read sums the
  * elapsed times.  Phases: PREPROCESS (cull, key, projection), SORT (depth sort), BIN

@@ -27,8 +27,10 @@ STATUS_NAMES = {0: "LF_OK", 1: "LF_ERR_INVALID_ARG", 2: "LF_ERR_UNSUPPORTED", 3:
 EXPORTS = [
     "lf_version", "lf_last_error", "lf_create", "lf_destroy", "lf_geometry", "lf_quilt_views",
     "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_composite_backward",
-    "lf_build_mpi_backward", "lf_plane_coeffs", "lf_profile_enable", "lf_profile_read",
+    "lf_build_mpi_backward", "lf_plane_coeffs", "lf_batch_create", "lf_batch_run", "lf_batch_group",
+    "lf_batch_destroy", "lf_profile_enable", "lf_profile_read",
 ]
+LF_BATCH_GRAPH, LF_BATCH_AUTOTUNE = 1, 2
 PHASES = ["preprocess", "sort", "bin", "splat", "merge", "filter", "coeff", "composite", "composite_bwd",
           "build_bwd"]
 
@@ -79,6 +81,13 @@ class lf_build_info(C.Structure):
                 ("overflow", C.c_int32)]
 
 
+class lf_batch_item(C.Structure):
+    _fields_ = [("field", lf_field), ("cam", lf_camera), ("n_chunk", C.c_int32), ("binning", C.c_int32),
+                ("inv_depth_range", C.c_float * 2), ("views", C.POINTER(lf_view)), ("n_views", C.c_int32),
+                ("interp", C.c_int32), ("out_dtype", C.c_int32), ("mpi", lf_mpi), ("out", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+
+
 class lf_gaussian_grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p), ("opacity", C.c_void_p),
                 ("rgb", C.c_void_p)]
@@ -114,6 +123,10 @@ def load():
                                    C.c_int32, P, P, P], C.c_int),
         "lf_build_mpi_backward": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.POINTER(lf_mpi), P,
                                    C.POINTER(lf_gaussian_grads), P, C.c_size_t, P], C.c_int),
+        "lf_batch_create": ([P, C.POINTER(lf_batch_item), C.c_int32, C.c_int32, C.POINTER(P)], C.c_int),
+        "lf_batch_run": ([P, P], C.c_int),
+        "lf_batch_group": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+        "lf_batch_destroy": ([P], None),
         "lf_plane_coeffs": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
                              P, P, P, P, P, P, P], C.c_int),
         "lf_profile_enable": ([P, C.c_int32], C.c_int),
@@ -247,6 +260,27 @@ def lf_plane_coeffs(ctx: int, mpi: lf_mpi, cam: lf_camera, views, bx: int, by: i
                     cxn: int, cyn: int, stream: int = 0) -> None:
     _check(load().lf_plane_coeffs(ctx, C.byref(mpi), C.byref(cam), views, len(views), bx, by, cx, cy, cxn, cyn,
                                   stream), "lf_plane_coeffs")
+
+
+def lf_batch_create(ctx: int, items, flags: int = 0) -> int:
+    arr = (lf_batch_item * len(items))(*items)
+    h = C.c_void_p()
+    _check(load().lf_batch_create(ctx, arr, len(items), flags, C.byref(h)), "lf_batch_create")
+    return h.value
+
+
+def lf_batch_run(batch: int, stream: int = 0) -> None:
+    _check(load().lf_batch_run(batch, stream), "lf_batch_run")
+
+
+def lf_batch_group(batch: int, item: int) -> int:
+    g = C.c_int32()
+    _check(load().lf_batch_group(batch, item, C.byref(g)), "lf_batch_group")
+    return g.value
+
+
+def lf_batch_destroy(batch: int) -> None:
+    load().lf_batch_destroy(batch)
 
 
 def lf_profile_enable(ctx: int, enable: bool) -> None:

@@ -32,6 +32,8 @@ lf_status check_views(const lf_view* views, int32_t n_views) {
   return LF_OK;
 }
 
+}  // namespace
+
 lf_status composite_args(const lf_mpi* mpi, const lf_camera* cam, const lf_view* views, int32_t n_views,
                          CompositeArgs* a) {
   Geom g;
@@ -56,6 +58,8 @@ lf_status composite_args(const lf_mpi* mpi, const lf_camera* cam, const lf_view*
   }
   return LF_OK;
 }
+
+namespace {
 
 lf_status check_ctx(lf_ctx* ctx) {
   if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
@@ -171,6 +175,23 @@ extern "C" lf_status lf_profile_read(lf_ctx* ctx, double* ms, int64_t* count, in
   return LF_OK;
 }
 
+// The context's coefficient table, grown on demand (a call under stream capture needs an
+// earlier call of at least this size).  The old table may still be in use by enqueued work,
+// so the device is synchronised before it is freed.
+static hipError_t grow_table(lf_ctx* ctx, size_t need) {
+  if (ctx->table_bytes >= need) return hipSuccess;
+  if (ctx->table) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    hipFree(ctx->table);
+  }
+  ctx->table = nullptr;
+  ctx->table_bytes = 0;
+  hipError_t e = hipMalloc(&ctx->table, need);
+  if (e == hipSuccess) ctx->table_bytes = need;
+  return e;
+}
+
 extern "C" lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
                                   int32_t n_views, int32_t interp, int32_t out_dtype, void* out, void* stream) {
   CompositeArgs* a = new (std::nothrow) CompositeArgs;
@@ -186,16 +207,7 @@ extern "C" lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camer
     a->interp = interp;
     a->out_dtype = out_dtype;
     a->out = out;
-    hipError_t e = hipSuccess;
-    const size_t need = composite_table_bytes(a->K, a->n_views);
-    if (ctx->table_bytes < need) {
-      // grown on demand; a call under stream capture needs an earlier call of at least this size
-      if (ctx->table) hipFree(ctx->table);
-      ctx->table = nullptr;
-      ctx->table_bytes = 0;
-      e = hipMalloc(&ctx->table, need);
-      if (e == hipSuccess) ctx->table_bytes = need;
-    }
+    hipError_t e = grow_table(ctx, composite_table_bytes(a->K, a->n_views));
     if (e == hipSuccess) e = composite_launch(*a, ctx->table, (hipStream_t)stream, &ctx->prof);
     if (e != hipSuccess) s = hip_fail(e, "composite launch");
   }
@@ -216,7 +228,8 @@ extern "C" lf_status lf_composite_backward(lf_ctx* ctx, const lf_mpi* mpi, const
   if (s == LF_OK) s = check_ctx(ctx);
   if (s == LF_OK) {
     a->interp = interp;
-    hipError_t e = composite_backward_launch(*a, d_out, d_planes, (hipStream_t)stream, &ctx->prof);
+    hipError_t e = grow_table(ctx, composite_table_bytes(a->K, a->n_views));
+    if (e == hipSuccess) e = composite_backward_launch(*a, ctx->table, d_out, d_planes, (hipStream_t)stream, &ctx->prof);
     if (e != hipSuccess) s = hip_fail(e, "composite backward launch");
   }
   delete a;

@@ -250,7 +250,8 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
       }
       const float lo = floorf(p.x * xr_lo + cmin);
       const float hi = floorf(p.x * xr_hi + cmax) + (BIL ? 1.0f : 0.0f);
-      const int cap = BIL ? kWin / 2 : kWin;
+      // a window must fit the buffer and be covered by the fetch (PF entries per thread)
+      const int cap = min(BIL ? kWin / 2 : kWin, PF * nt);
       bool clamp = false;
       if (lo >= -1.0e9f && hi <= 1.0e9f && hi - lo + 1.0f <= (float)cap) {
         pi.f0 = (int)lo;
@@ -585,6 +586,312 @@ __global__ __launch_bounds__(kBwdThreads) void composite_bwd(CompositeArgs a, co
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Row backward (all views share dy).  One work-group per (output row y, group of G views,
+// segment of 256 pixels); a thread owns pixel x for the G views.  T_k is not checkpointed:
+// the forward sweep keeps, per view, the last plane m whose incoming transmittance T_m is
+// at least kTinyT, and the backward sweep recovers T_k = T_{k+1} / (1 - a_k) for k < m
+// (exact up to rounding: T_{k+1} > 0 there, so a_k < 1).  Planes behind m see T < kTinyT and
+// get no gradient (it would be below 1e-30 |g|).
+// Per plane the work-group stages the window of the plane row its samples fall in (as the
+// forward row kernel does).  The samples' cotangents are then summed per texel without
+// atomics: pixel threads store them (with their texel index) in LDS and mark where each
+// view's run of equal texels starts (x -> texel is monotone), and texel threads add the runs
+// of all views, in a fixed order, before one global atomic per texel channel adds the
+// window into the plane gradient (windows of other rows and view groups overlap it).
+// ---------------------------------------------------------------------------------------
+constexpr int kRowBwdThreads = 256;
+constexpr int kRowBwdWin = 512;
+constexpr float kTinyT = 1e-30f;
+constexpr int kNoTexel = -(1 << 30);
+
+struct BwdPlane {
+  bool ok, direct;
+  int iy, f0, len;
+  float wy, bx, by;
+};
+
+template <bool BIL>
+__device__ __forceinline__ BwdPlane bwd_plane(const CompositeArgs& a, const float4* pt, const float* ct, int k, int v0,
+                                              int nv, float yr, float xr_lo, float xr_hi, int Vp) {
+  const float4 p = pt[k];                                  // (bx, by, Cy, valid)
+  BwdPlane b;
+  b.bx = p.x;
+  b.by = p.y;
+  b.wy = 0.0f;
+  b.ok = p.w != 0.0f;
+  if (!BIL) {
+    b.iy = __float2int_rd(p.y * yr + p.z);
+    b.ok = b.ok && b.iy >= 0 && b.iy < a.hp;
+  } else {
+    const float Y = p.y * yr + p.z;
+    const float fy0 = floorf(Y);
+    b.wy = Y - fy0;
+    b.iy = __float2int_rd(fy0);
+    b.ok = b.ok && b.iy >= -1 && b.iy < a.hp;
+  }
+  const float* crow = ct + (size_t)k * Vp + v0;
+  float cmin = crow[0], cmax = crow[0];
+  for (int j = 1; j < nv; ++j) {
+    cmin = fminf(cmin, crow[j]);
+    cmax = fmaxf(cmax, crow[j]);
+  }
+  const float lo = floorf(p.x * xr_lo + cmin);
+  const float hi = floorf(p.x * xr_hi + cmax) + (BIL ? 1.0f : 0.0f);
+  b.direct = !(lo >= -1.0e9f && hi <= 1.0e9f && hi - lo + 1.0f <= (float)kRowBwdWin);
+  b.f0 = b.direct ? 0 : (int)lo;
+  b.len = b.direct ? 0 : (int)(hi - lo) + 1;
+  return b;
+}
+
+// texel of the (bilinear: vertically blended) plane row at column ix, zero outside the plane
+template <typename PT, bool BIL>
+__device__ __forceinline__ float4 row_texel(const PT* planes, const CompositeArgs& a, size_t pbase, const BwdPlane& b,
+                                            int ix) {
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (ix < 0 || ix >= a.wp) return z;
+  if (!BIL) return load_texel(planes, pbase + (size_t)b.iy * a.wp + ix);
+  const float4 r0 = b.iy >= 0 ? load_texel(planes, pbase + (size_t)b.iy * a.wp + ix) : z;
+  const float4 r1 = b.iy + 1 < a.hp ? load_texel(planes, pbase + (size_t)(b.iy + 1) * a.wp + ix) : z;
+  return lerp4(r0, r1, b.wy);
+}
+
+__device__ __forceinline__ void add_row_grad(float* d_planes, const CompositeArgs& a, int k, int iy, int ix, int c,
+                                             float v) {
+  if (iy < 0 || iy >= a.hp || ix < 0 || ix >= a.wp || v == 0.0f) return;
+  atomicAdd(d_planes + (((size_t)k * a.hp + iy) * a.wp + ix) * 4 + c, v);
+}
+
+template <typename PT, int G, bool BIL>
+__global__ __launch_bounds__(kRowBwdThreads) void composite_rows_bwd(CompositeArgs a, const float4* __restrict__ pt,
+                                                                     const float* __restrict__ ct,
+                                                                     const float4* __restrict__ d_out,
+                                                                     float* __restrict__ d_planes) {
+  __shared__ float4 val[kRowBwdWin];
+  __shared__ float4 slot[G][kRowBwdThreads];               // cotangent of sample (view, x)
+  __shared__ int sx[G][kRowBwdThreads];                    // its texel (lower texel for bilinear)
+  __shared__ float swx[BIL ? G : 1][kRowBwdThreads];       // its bilinear weight
+  __shared__ short first[G][kRowBwdWin];                   // first x of each view's run per texel
+  const int y = blockIdx.x;
+  const int v0 = blockIdx.y * G;
+  const int nv = min(G, a.n_views - v0);
+  const int tid = threadIdx.x;
+  const int xs0 = blockIdx.z * kRowBwdThreads;
+  const int x = xs0 + tid;
+  const bool xin = x < a.nx;
+  const int xs1 = min(xs0 + kRowBwdThreads, a.nx) - 1;
+  const int Vp = padded_views(a.n_views);
+  const PT* __restrict__ planes = static_cast<const PT*>(a.planes);
+  const float xr = (float)x - a.c.cx, yr = (float)y - a.c.cy;
+  const float xrp = (float)(x - 1) - a.c.cx;
+  const float xr_lo = (float)xs0 - a.c.cx, xr_hi = (float)xs1 - a.c.cx;
+  const size_t plane_elems = (size_t)a.hp * a.wp;
+  float4 g[G];
+  float T[G], Tm[G];
+  int m[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    g[j] = (xin && j < nv) ? d_out[((size_t)(v0 + j) * a.ny + y) * a.nx + x] : make_float4(0.f, 0.f, 0.f, 0.f);
+    T[j] = 1.0f;
+    Tm[j] = 1.0f;
+    m[j] = -1;
+  }
+  // sample of view j (slot) at plane k: value, texel (bilinear: lower texel) and weight
+  auto sample = [&](const BwdPlane& b, size_t pbase, float c, int& ix, float& wx) -> float4 {
+    const float X = b.bx * xr + c;
+    if (!BIL) {
+      ix = __float2int_rd(X);
+      wx = 0.0f;
+      if (b.direct) return row_texel<PT, false>(planes, a, pbase, b, ix);
+      return val[min(max(ix - b.f0, 0), b.len - 1)];
+    }
+    const float fx0 = floorf(X);
+    wx = X - fx0;
+    ix = __float2int_rd(fx0);
+    if (b.direct)
+      return lerp4(row_texel<PT, true>(planes, a, pbase, b, ix), row_texel<PT, true>(planes, a, pbase, b, ix + 1), wx);
+    const int i0 = min(max(ix - b.f0, 0), b.len - 1), i1 = min(max(ix + 1 - b.f0, 0), b.len - 1);
+    return lerp4(val[i0], val[i1], wx);
+  };
+  // window texels are fetched one plane ahead into registers (kPre per thread), so the
+  // global loads of plane k+1 are in flight while plane k is sampled
+  constexpr int kPre = kRowBwdWin / kRowBwdThreads;
+  float4 pre0[kPre], pre1[kPre];
+  auto fetch = [&](const BwdPlane& b, int k) {
+    if (!b.ok || b.direct) return;
+    const size_t pbase = (size_t)k * plane_elems;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int i = tid + q * kRowBwdThreads;
+      const int ix = b.f0 + i;
+      pre0[q] = pre1[q] = z;
+      if (i < b.len && ix >= 0 && ix < a.wp) {
+        if (!BIL) {
+          pre0[q] = load_texel(planes, pbase + (size_t)b.iy * a.wp + ix);
+        } else {
+          if (b.iy >= 0) pre0[q] = load_texel(planes, pbase + (size_t)b.iy * a.wp + ix);
+          if (b.iy + 1 < a.hp) pre1[q] = load_texel(planes, pbase + (size_t)(b.iy + 1) * a.wp + ix);
+        }
+      }
+    }
+  };
+  auto commit = [&](const BwdPlane& b) {
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int i = tid + q * kRowBwdThreads;
+      if (i < b.len) val[i] = BIL ? lerp4(pre0[q], pre1[q], b.wy) : pre0[q];
+    }
+  };
+  auto plane_at = [&](int k) { return bwd_plane<BIL>(a, pt, ct, k, v0, nv, yr, xr_lo, xr_hi, Vp); };
+  // forward sweep: transmittance per view, last plane with T >= kTinyT
+  {
+    BwdPlane b = a.K > 0 ? plane_at(0) : BwdPlane{};
+    fetch(b, 0);
+    for (int k = 0; k < a.K; ++k) {
+      const BwdPlane bn = k + 1 < a.K ? plane_at(k + 1) : BwdPlane{};
+      if (b.ok) {
+        const size_t pbase = (size_t)k * plane_elems;
+        if (!b.direct) {
+          __syncthreads();
+          commit(b);
+          __syncthreads();
+        }
+        fetch(bn, k + 1);
+        if (xin) {
+#pragma unroll
+          for (int j = 0; j < G; ++j) {
+            if (j >= nv) continue;
+            int ix;
+            float wx;
+            const float4 s = sample(b, pbase, ct[(size_t)k * Vp + v0 + j], ix, wx);
+            if (T[j] >= kTinyT) {
+              m[j] = k;
+              Tm[j] = T[j];
+            }
+            T[j] = fmaf(-T[j], s.w, T[j]);
+          }
+        }
+      } else {
+        fetch(bn, k + 1);
+      }
+      b = bn;
+    }
+  }
+  // backward sweep
+  float Rr[G], Rg[G], Rb[G], S[G], Tc[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    Rr[j] = Rg[j] = Rb[j] = 0.0f;
+    S[j] = 1.0f;
+    Tc[j] = Tm[j];
+  }
+  BwdPlane bnext = a.K > 0 ? plane_at(a.K - 1) : BwdPlane{};
+  fetch(bnext, a.K - 1);
+  for (int k = a.K - 1; k >= 0; --k) {
+    const BwdPlane b = bnext;
+    bnext = k > 0 ? plane_at(k - 1) : BwdPlane{};
+    if (!b.ok) {
+      fetch(bnext, k - 1);
+      continue;
+    }
+    const size_t pbase = (size_t)k * plane_elems;
+    if (!b.direct) {
+      __syncthreads();                                     // previous plane's gather is done
+      commit(b);
+      for (int i = tid; i < G * b.len; i += kRowBwdThreads) first[i / b.len][i % b.len] = -1;
+      __syncthreads();
+    }
+    fetch(bnext, k - 1);
+    #pragma unroll
+    for (int j = 0; j < G; ++j) {
+      float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+      int ix = kNoTexel;
+      float wx = 0.0f;
+      if (xin && j < nv) {
+        const float c = ct[(size_t)k * Vp + v0 + j];
+        const float4 s = sample(b, pbase, c, ix, wx);
+        const float om = 1.0f - s.w;
+        // T_k = T_{k+1} / (1 - a_k) below m (reciprocal to ~1 ulp); no gradient behind m.
+        // Branch free: om may be 0 behind m, where the quotient is discarded.
+        const bool live = k <= m[j];
+        const float Tk = live ? (k == m[j] ? Tm[j] : Tc[j] * __builtin_amdgcn_rcpf(om)) : 0.0f;
+        Tc[j] = live ? Tk : Tc[j];
+        d = make_float4(Tk * g[j].x, Tk * g[j].y, Tk * g[j].z,
+                        -Tk * ((g[j].x * Rr[j] + g[j].y * Rg[j] + g[j].z * Rb[j]) + g[j].w * S[j]));
+        Rr[j] = fmaf(om, Rr[j], s.x);
+        Rg[j] = fmaf(om, Rg[j], s.y);
+        Rb[j] = fmaf(om, Rb[j], s.z);
+        S[j] = om * S[j];
+        if (!b.direct) {
+          // x -> texel is monotone: a run of equal texels starts where the left neighbour differs
+          const float Xp = b.bx * xrp + c;
+          const int ixp = BIL ? __float2int_rd(floorf(Xp)) : __float2int_rd(Xp);
+          if (tid == 0 || ixp != ix) first[j][ix - b.f0] = (short)tid;
+        }
+      }
+      if (!b.direct) {
+        slot[j][tid] = d;
+        sx[j][tid] = ix;
+        if (BIL) swx[BIL ? j : 0][tid] = wx;
+      } else if (ix != kNoTexel) {
+        const float d4[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (!BIL) {
+            add_row_grad(d_planes, a, k, b.iy, ix, c, d4[c]);
+          } else {
+            add_row_grad(d_planes, a, k, b.iy, ix, c, (1.0f - b.wy) * (1.0f - wx) * d4[c]);
+            add_row_grad(d_planes, a, k, b.iy + 1, ix, c, b.wy * (1.0f - wx) * d4[c]);
+            add_row_grad(d_planes, a, k, b.iy, ix + 1, c, (1.0f - b.wy) * wx * d4[c]);
+            add_row_grad(d_planes, a, k, b.iy + 1, ix + 1, c, b.wy * wx * d4[c]);
+          }
+        }
+      }
+    }
+    if (!b.direct) {
+      __syncthreads();
+      // texel threads: sum every view's runs (fixed order), then add the window to the plane
+      for (int t = tid; t < b.len; t += kRowBwdThreads) {
+        const int X = b.f0 + t;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          if (j >= nv) continue;
+          for (int q = first[j][t]; q >= 0 && q < kRowBwdThreads && sx[j][q] == X; ++q) {
+            const float w = BIL ? 1.0f - swx[BIL ? j : 0][q] : 1.0f;
+            const float4 d = slot[j][q];
+            acc.x = fmaf(w, d.x, acc.x);
+            acc.y = fmaf(w, d.y, acc.y);
+            acc.z = fmaf(w, d.z, acc.z);
+            acc.w = fmaf(w, d.w, acc.w);
+          }
+          if (BIL && t > 0) {
+            for (int q = first[j][t - 1]; q >= 0 && q < kRowBwdThreads && sx[j][q] == X - 1; ++q) {
+              const float w = swx[BIL ? j : 0][q];
+              const float4 d = slot[j][q];
+              acc.x = fmaf(w, d.x, acc.x);
+              acc.y = fmaf(w, d.y, acc.y);
+              acc.z = fmaf(w, d.z, acc.z);
+              acc.w = fmaf(w, d.w, acc.w);
+            }
+          }
+        }
+        const float a4[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (!BIL) {
+            add_row_grad(d_planes, a, k, b.iy, X, c, a4[c]);
+          } else {
+            add_row_grad(d_planes, a, k, b.iy, X, c, (1.0f - b.wy) * a4[c]);
+            add_row_grad(d_planes, a, k, b.iy + 1, X, c, b.wy * a4[c]);
+          }
+        }
+      }
+    }
+  }
+}
+
 __global__ void zero_f32(float* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0f;
@@ -599,6 +906,20 @@ hipError_t launch_bwd(const CompositeArgs& a, const float* d_out, float* d_plane
   else
     hipLaunchKernelGGL((composite_bwd<PT, false>), grid, dim3(kBwdThreads), 0, s, a, d_out, d_planes);
   return hipGetLastError();
+}
+
+// threads of a row work-group, and whether the whole-row window fits its buffer and fetch
+int row_threads(int nx) {
+  const int nseg = (nx + kRowThreads - 1) / kRowThreads;
+  const int seg = (nx + nseg - 1) / nseg;
+  return ((seg + 63) / 64) * 64;
+}
+
+bool rows_fit(const CompositeArgs& a) {
+  const bool bil = a.interp == LF_BILINEAR;
+  const int entries = a.wp + 4;
+  const int per_thread = bil ? kPrefetch / 2 : kPrefetch;
+  return entries <= (bil ? kWin / 2 : kWin) && entries <= per_thread * row_threads(a.nx);
 }
 
 template <int G>
@@ -652,15 +973,17 @@ hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, 
   float* ct = reinterpret_cast<float*>(static_cast<char*>(table) + (((size_t)a.K * 16 + 255) & ~(size_t)255));
   bool same_dy = true;
   for (int v = 1; v < a.n_views; ++v) same_dy = same_dy && a.dy[v] == a.dy[0];
-  // the clamped whole-row fallback must fit the window buffer
-  const int row_entries = a.interp == LF_BILINEAR ? 2 * (a.wp + 4) : a.wp + 4;
-  const bool rows = same_dy && row_entries <= kWin;
+  // the clamped whole-row fallback must fit the window buffer and the fetch of one
+  // work-group (kPrefetch entries per thread, half of them for bilinear)
+  const bool rows = same_dy && rows_fit(a);
   int G = 16, best = pick_cost<16>(a.n_views);
   if (pick_cost<12>(a.n_views) < best) { G = 12; best = pick_cost<12>(a.n_views); }
   if (pick_cost<8>(a.n_views) < best) { G = 8; best = pick_cost<8>(a.n_views); }
   if (pick_cost<4>(a.n_views) < best) { G = 4; best = pick_cost<4>(a.n_views); }
-  // tuning override: LF_COMPOSITE_GROUP = views per work-group (4, 8, 12 or 16)
-  if (const char* e = getenv("LF_COMPOSITE_GROUP")) {
+  // an explicit group (autotuned) wins; else the LF_COMPOSITE_GROUP tuning override
+  if (a.group == 4 || a.group == 8 || a.group == 12 || a.group == 16) {
+    G = a.group;
+  } else if (const char* e = getenv("LF_COMPOSITE_GROUP")) {
     const int g = atoi(e);
     if (g == 4 || g == 8 || g == 12 || g == 16) G = g;
   }
@@ -677,11 +1000,50 @@ hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, 
   }
 }
 
-hipError_t composite_backward_launch(const CompositeArgs& a, const float* d_out, float* d_planes, hipStream_t s,
-                                    Profiler* prof) {
+template <typename PT>
+hipError_t launch_rows_bwd(const CompositeArgs& a, const float4* pt, const float* ct, const float* d_out,
+                           float* d_planes, hipStream_t s) {
+  // views per work-group (8: two work-groups per CU fit the LDS); LF_BWD_GROUP overrides
+  int G = 8;
+  if (const char* e = getenv("LF_BWD_GROUP")) {
+    const int g = atoi(e);
+    if (g == 8 || g == 16) G = g;
+  }
+  const dim3 grid((unsigned)a.ny, (unsigned)((a.n_views + G - 1) / G),
+                  (unsigned)((a.nx + kRowBwdThreads - 1) / kRowBwdThreads));
+  const float4* go = reinterpret_cast<const float4*>(d_out);
+  const dim3 blk(kRowBwdThreads);
+  if (G == 16) {
+    if (a.interp == LF_BILINEAR) hipLaunchKernelGGL((composite_rows_bwd<PT, 16, true>), grid, blk, 0, s, a, pt, ct, go, d_planes);
+    else hipLaunchKernelGGL((composite_rows_bwd<PT, 16, false>), grid, blk, 0, s, a, pt, ct, go, d_planes);
+  } else {
+    if (a.interp == LF_BILINEAR) hipLaunchKernelGGL((composite_rows_bwd<PT, 8, true>), grid, blk, 0, s, a, pt, ct, go, d_planes);
+    else hipLaunchKernelGGL((composite_rows_bwd<PT, 8, false>), grid, blk, 0, s, a, pt, ct, go, d_planes);
+  }
+  return hipGetLastError();
+}
+
+hipError_t composite_backward_launch(const CompositeArgs& a, void* table, const float* d_out, float* d_planes,
+                                    hipStream_t s, Profiler* prof) {
+  float4* pt = static_cast<float4*>(table);
+  float* ct = reinterpret_cast<float*>(static_cast<char*>(table) + (((size_t)a.K * 16 + 255) & ~(size_t)255));
+  bool same_dy = true;
+  for (int v = 1; v < a.n_views; ++v) same_dy = same_dy && a.dy[v] == a.dy[0];
+  if (same_dy) {
+    PhaseScope ps(prof, LF_PHASE_COEFF, s);
+    const int n = a.K * padded_views(a.n_views);
+    hipLaunchKernelGGL(coeff_table, dim3((n + 255) / 256), dim3(256), 0, s, a, pt, ct);
+  }
   PhaseScope ps(prof, LF_PHASE_COMPOSITE_BWD, s);
   const int64_t np = (int64_t)a.K * a.hp * a.wp * 4;
   if (np > 0) hipLaunchKernelGGL(zero_f32, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, d_planes, np);
+  if (same_dy) {
+    switch (a.plane_dtype) {
+      case LF_F16: return launch_rows_bwd<__half>(a, pt, ct, d_out, d_planes, s);
+      case LF_BF16: return launch_rows_bwd<__hip_bfloat16>(a, pt, ct, d_out, d_planes, s);
+      default: return launch_rows_bwd<float>(a, pt, ct, d_out, d_planes, s);
+    }
+  }
   switch (a.plane_dtype) {
     case LF_F16: return launch_bwd<__half>(a, d_out, d_planes, s);
     case LF_BF16: return launch_bwd<__hip_bfloat16>(a, d_out, d_planes, s);

@@ -91,6 +91,7 @@ struct CompositeArgs {
   void* out;
   int32_t K, hp, wp, nx, ny, n_views;
   int32_t plane_dtype, out_dtype, interp;
+  int32_t group;            // views per row work-group (4, 8, 12, 16); 0 picks by view count
   Consts c;
   float dx[LF_MAX_VIEWS];
   float dy[LF_MAX_VIEWS];
@@ -99,10 +100,14 @@ struct CompositeArgs {
 // Bytes of the coefficient table lf_composite keeps in its context for K planes, V views.
 size_t composite_table_bytes(int K, int n_views);
 hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, Profiler* prof = nullptr);
+// Validated composite arguments (host); shared by lf_composite and the batch entry points.
+lf_status composite_args(const lf_mpi* mpi, const lf_camera* cam, const lf_view* views, int32_t n_views,
+                         CompositeArgs* a);
 hipError_t plane_coeffs_launch(const CompositeArgs& a, float* bx, float* by, float* cx, float* cy,
                                float* cxn, float* cyn, hipStream_t s);
-// Zero-fills d_planes [K][hp][wp][4] and accumulates the composite's VJP of d_out into it.
-hipError_t composite_backward_launch(const CompositeArgs& a, const float* d_out, float* d_planes, hipStream_t s,
-                                    Profiler* prof = nullptr);
+// Zero-fills d_planes [K][hp][wp][4] and accumulates the composite's VJP of d_out into it
+// (table: composite_table_bytes(K, V) of device scratch for the sampling coefficients).
+hipError_t composite_backward_launch(const CompositeArgs& a, void* table, const float* d_out, float* d_planes,
+                                    hipStream_t s, Profiler* prof = nullptr);
 
 }  // namespace lf

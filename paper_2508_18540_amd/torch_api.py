@@ -231,3 +231,71 @@ def render_light_field(ctx: Context, params: dict, cam, views, n_chunk: int, int
     """Differentiable light-field render of a Gaussian field (see LFRender)."""
     return LFRender.apply(params["means"], params["log_scales"], params["quats"], params["opacity"], params["rgb"],
                           ctx, cam, views, n_chunk, interp, plane_dtype, binning, inv_depth_range, workspace)
+
+
+class Batch:
+    """lf_batch over torch tensors: ``scenes`` is a list of dicts with keys scene (device
+    field dict), cam, n_chunk, views (lf_view array), and optionally binning,
+    inv_depth_range, interp, plane_dtype, out_dtype.  Allocates every scene's planes, views
+    and workspace; ``run()`` renders them all (``outs[i]`` = dict(rgba, depth, views))."""
+
+    def __init__(self, ctx: Context, scenes: list, graph: bool = True, autotune: bool = False, probe: bool = True):
+        self.ctx = ctx
+        self.outs, self._keep, items = [], [], []
+        for sc in scenes:
+            cam, K, views = sc["cam"], sc["n_chunk"], sc["views"]
+            info = L.lf_geometry(L.make_camera(cam))
+            dev = ctx.device
+            ws = workspace_for(sc["scene"], cam, K, device=dev)
+            if probe:
+                # one build sizes the tile-list capacity (re-allocated once if the default is short)
+                tmp = build_mpi(ctx, sc["scene"], cam, K, sc.get("binning", "quantile"), sc.get("inv_depth_range"),
+                                dtype=sc.get("plane_dtype", torch.float16), workspace=ws)
+                st_info, st = build_stats(ctx, ws, check=False)
+                del tmp
+                if st == L.LF_ERR_CAPACITY:
+                    ws = workspace_for(sc["scene"], cam, K, entry_capacity=int(st_info.entries_needed * 1.25) + 1024,
+                                       device=dev)
+            o = dict(rgba=torch.empty((K, info.plane_height, info.plane_width, 4), dtype=sc.get("plane_dtype", torch.float16),
+                                      device=dev),
+                     depth=torch.empty(K, dtype=torch.float32, device=dev),
+                     views=torch.empty((len(views), cam.ny, cam.nx, 4), dtype=sc.get("out_dtype", torch.float32), device=dev),
+                     workspace=ws)
+            it = L.lf_batch_item()
+            it.field = field_of(sc["scene"])
+            it.cam = L.make_camera(cam)
+            it.n_chunk = K
+            it.binning = _BIN[sc.get("binning", "quantile")]
+            if sc.get("inv_depth_range") is not None:
+                it.inv_depth_range[:] = [float(v) for v in sc["inv_depth_range"]]
+            it.views = views
+            it.n_views = len(views)
+            it.interp = _INTERP[sc.get("interp", "nearest")]
+            it.out_dtype = _DT[o["views"].dtype]
+            it.mpi = mpi_of(o["rgba"], o["depth"])
+            it.out = o["views"].data_ptr()
+            it.workspace = ws.ptr
+            it.workspace_bytes = ws.nbytes
+            items.append(it)
+            self.outs.append(o)
+            self._keep.append((sc, views))
+        flags = (L.LF_BATCH_GRAPH if graph else 0) | (L.LF_BATCH_AUTOTUNE if autotune else 0)
+        self.handle = L.lf_batch_create(ctx.handle, items, flags)
+
+    def run(self):
+        L.lf_batch_run(self.handle, torch.cuda.current_stream(self.ctx.device).cuda_stream)
+        return self.outs
+
+    def groups(self):
+        return [L.lf_batch_group(self.handle, i) for i in range(len(self.outs))]
+
+    def close(self):
+        if getattr(self, "handle", 0):
+            L.lf_batch_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

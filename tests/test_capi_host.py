@@ -177,3 +177,28 @@ def test_build_workspace_size_and_capacity_errors(lib, kind):
     st = lib.lf_build_mpi(None, ctypes.byref(f), ctypes.byref(cam), 16, 1, None, ctypes.byref(mpi), 0x8000,
                           nbytes.value, None)
     assert st == L.LF_ERR_INVALID_ARG
+
+
+def test_batch_rejects_invalid_items(lib):
+    cam = L.make_camera(CAMS["uniform10k"])
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(0x1000)                 # never dereferenced: validation fails first
+    assert lib.lf_batch_create(dummy, None, 1, 0, ctypes.byref(h)) == L.LF_ERR_INVALID_ARG
+    it = L.lf_batch_item()
+    it.field = _field(L.LF_GAUSSIANS)
+    it.cam = cam
+    it.n_chunk = 16
+    it.views = L.make_views([0.0], [0.0])
+    it.n_views = 1
+    it.mpi = L.make_mpi(L.LF_F32, 16, 128, 128, 0x6000, 0x7000)
+    it.out, it.workspace, it.workspace_bytes = 0x9000, 0x8000, 1 << 30
+    arr = (L.lf_batch_item * 1)(it)
+    assert lib.lf_batch_create(dummy, arr, 0, 0, ctypes.byref(h)) == L.LF_ERR_INVALID_ARG
+    assert lib.lf_batch_create(dummy, arr, 1, 8, ctypes.byref(h)) == L.LF_ERR_INVALID_ARG
+    for field, value, needle in [("interp", 3, "interp"), ("out_dtype", 5, "out_dtype"), ("binning", 4, "binning"),
+                                 ("n_views", 0, "n_views"), ("out", 0, "NULL")]:
+        bad = L.lf_batch_item.from_buffer_copy(it)
+        setattr(bad, field, value)
+        st = lib.lf_batch_create(dummy, (L.lf_batch_item * 1)(bad), 1, 0, ctypes.byref(h))
+        assert st == L.LF_ERR_INVALID_ARG, field
+        assert needle in L.lf_last_error(), (field, L.lf_last_error())

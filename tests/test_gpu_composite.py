@@ -128,3 +128,20 @@ def test_composite_deterministic():
     b = T.composite(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy), "bilinear")
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+@pytest.mark.parametrize("nx", [160, 96])
+def test_composite_magnified_near_planes_narrow_rows(interp, nx):
+    """Planes just behind the reference camera are sampled at several texels per pixel, so a
+    row's window spans far more texels than a narrow work-group has threads: the window
+    must still be staged whole (or the row fall back), never read stale."""
+    announce("composite magnified", nx, interp)
+    cam, g, p, dx, dy = _setup(nx, 96, 6, 9, 1, 5)
+    p["depth"] = np.array([g.d_forward + 0.02, g.d_forward + 0.05, g.d_forward + 0.1, g.d_forward + 0.3, 1.5, 4.0],
+                          dtype=np.float32)
+    ref, _ = composite.composite(p["rgba"], p["depth"], cam, g, dx, dy, interp)
+    outs = [host(T.composite(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy), interp)) for _ in range(3)]
+    for got in outs:
+        err = np.abs(got - ref).max()
+        assert err <= 1e-4, err
