@@ -79,6 +79,8 @@ def parse():
     p.add_argument("--extra", default="voxel256,grad200k,batch8",
                    help="further workloads timed into the same line (voxel256, grad200k, batch8; empty for none)")
     p.add_argument("--extra-steps", type=int, default=5)
+    p.add_argument("--only-extra", action="store_true",
+                   help="time only the --extra workloads (for profiling them on their own)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (for HBM counter scaling)")
     return p.parse_args()
@@ -247,9 +249,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
+    ctx = T.Context(0)
+    if args.only_extra:
+        line = {"only_extra": True}
+        for name in [x.strip() for x in args.extra.split(",") if x.strip()]:
+            fn = {"voxel256": extra_voxel256, "grad200k": extra_grad200k, "batch8": extra_batch8}[name]
+            line[name] = fn(ctx, args.extra_steps, 2)
+        print(json.dumps(line), flush=True)
+        return
     scene, cam, cfg = scenegen.config("cluster500k")
     K, V = cfg["n_chunk"], cfg["vx"] * cfg["vy"]
-    ctx = T.Context(0)
     camc = L.make_camera(cam)
     vlist = L.lf_quilt_views(camc, cfg["vx"], cfg["vy"])
     dx = np.array([v.dx for v in vlist], dtype=np.float32)
