@@ -11,7 +11,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblf.so")
+LIB_PATH = os.environ.get("LF_LIBRARY") or os.path.join(HERE, "liblf.so")   # LF_LIBRARY: another build
 
 LF_OK, LF_ERR_INVALID_ARG, LF_ERR_UNSUPPORTED, LF_ERR_CAPACITY, LF_ERR_OUT_OF_MEMORY, LF_ERR_HIP = range(6)
 LF_F32, LF_F16, LF_BF16 = 0, 1, 2

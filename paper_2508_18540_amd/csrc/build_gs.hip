@@ -297,11 +297,13 @@ __global__ void finalize(BuildArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Splat: one work-group per (tile, chunk).  Wave w of the 256 threads owns the 8x8 texel
-// block at ((w & 1) * 8, (w >> 1) * 8) of the 16x16 tile and walks the bucket on its own:
-// the entry and the 64-byte Gaussian record are wave-uniform, so they arrive through
-// scalar loads, the support-box test against the wave's block is a scalar branch, and
-// only the per-texel footprint and blend run on the vector ALUs.  No LDS, no barriers.
+// Splat: one work-group per (tile, chunk) segment of at most kSegment = 256 entries.
+// Wave w of the 256 threads owns the 8x8 texel block at ((w & 1) * 8, (w >> 1) * 8) of the
+// 16x16 tile.  First every thread stages one entry's Gaussian record in LDS (one coalesced
+// 64-byte load per Gaussian, shared by the four waves) and the work-group compacts, per
+// quadrant, the entries whose support box touches it (stable, so depth order is kept).
+// Then each wave walks its own list reading records from LDS (broadcast reads): no scalar
+// memory traffic and no per-entry test on the critical path.
 // ---------------------------------------------------------------------------------------
 // Split every (tile, chunk) bucket into segments of at most kSegment entries: nseg per
 // bucket and the number of partial-tile slots of split buckets.
@@ -323,51 +325,72 @@ __global__ void emit_items(BuildArgs a, int64_t n_buckets) {
 
 template <typename PT>
 __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) {
+  __shared__ float4 s_mean[kSegment];                      // (mx_hi, my_hi, mx_lo, my_lo)
+  __shared__ float4 s_conic[kSegment];                     // (ca, cb, cc, l2o)
+  __shared__ float4 s_rgb[kSegment];
+  __shared__ uint16_t s_list[4][kSegment];                 // per quadrant: entries touching it
+  __shared__ int s_cnt[4][4];                              // [quadrant][loading wave]
   const uint32_t item = blockIdx.x;
   if (item >= a.item_start[n_buckets]) return;             // beyond this frame's work list
   const uint2 it = a.items[item];
   const int64_t bidx = it.x;
   const int tile = (int)(bidx / a.K), k = (int)(bidx % a.K);
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
   const int bx = ox + ((wave & 1) << 3), by = oy + ((wave >> 1) << 3);
   const int px = bx + (lane & 7), py = by + (lane >> 3);
   const float pxf = (float)px, pyf = (float)py;
-  const uint32_t* __restrict__ ev = a.evals;
-  const GRec* __restrict__ rec = a.rec;
-  float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
   const bool ok = a.hdr->overflow == 0;
   const uint32_t bb0 = a.bucket[bidx], bb1 = a.bucket[bidx + 1];
   const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
-  if (ok) {
-    const uint32_t b0 = bb0 + it.y * kSegment;
-    const uint32_t b1 = min(bb1, b0 + kSegment);
-    // entries in groups of 8 (one 32-byte scalar load; the entry arrays are padded so a group
-    // may run past the segment end).  The wave tests its quadrant bit before touching the record.
-    struct Group { uint32_t v[8]; };
-    const uint32_t qbit = 1u << (28 + wave);
-    for (uint32_t e0 = b0; e0 < b1; e0 += 8) {
-      const Group grp = *reinterpret_cast<const Group*>(ev + e0);
+  const uint32_t b0 = bb0 + it.y * kSegment;
+  const int n = ok ? (int)(min(bb1, b0 + kSegment) - b0) : 0;
+  // stage: thread t holds entry t of the segment
+  uint32_t qm = 0;
+  if (tid < n) {
+    const uint32_t ent = a.evals[b0 + tid];
+    const GRec& g = a.rec[min(ent & 0x0fffffffu, (uint32_t)a.n - 1u)];
+    s_mean[tid] = make_float4(g.mx_hi, g.my_hi, g.mx_lo, g.my_lo);
+    s_conic[tid] = make_float4(g.ca, g.cb, g.cc, g.l2o);
+    s_rgb[tid] = make_float4(g.rgb[0], g.rgb[1], g.rgb[2], 0.0f);
+    qm = ent >> 28;
+  }
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint32_t rank[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const uint32_t ent = grp.v[u];
-        if (e0 + u >= b1) break;
-        if (!(ent & qbit)) continue;                          // scalar: support misses this quadrant
-        const uint32_t idx = min(ent & 0x0fffffffu, (uint32_t)a.n - 1u);
-        const GRec& g = rec[idx];
-        const float dx = (pxf - g.mx_hi) - g.mx_lo;
-        const float dy = (pyf - g.my_hi) - g.my_lo;
-        const float q = fmaf(g.ca * dx, dx, fmaf(g.cc * dy, dy, fmaf(g.cb * dx, dy, g.l2o)));
-        // excluded texels get alpha 0 (a select, not a branch: keeps the scalar unit free)
-        const float alpha = q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f;
-        const float w = alpha * T;
-        C0 = fmaf(w, g.rgb[0], C0);
-        C1 = fmaf(w, g.rgb[1], C1);
-        C2 = fmaf(w, g.rgb[2], C2);
-        T = T - w;
-      }
-    }
+  for (int q = 0; q < 4; ++q) {
+    const uint64_t m = __ballot((qm >> q) & 1u);
+    rank[q] = __popcll(m & below);
+    if (lane == 0) s_cnt[q][wave] = __popcll(m);
+  }
+  __syncthreads();
+  int my_count = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int off = 0;
+    for (int w = 0; w < 4; ++w) off += w < wave ? s_cnt[q][w] : 0;
+    if ((qm >> q) & 1u) s_list[q][off + rank[q]] = (uint16_t)tid;
+    if (q == wave) my_count = s_cnt[q][0] + s_cnt[q][1] + s_cnt[q][2] + s_cnt[q][3];
+  }
+  __syncthreads();
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+  const int cnt = __builtin_amdgcn_readfirstlane(my_count);
+  for (int i = 0; i < cnt; ++i) {
+    const int e = s_list[wave][i];
+    const float4 m = s_mean[e];
+    const float4 c = s_conic[e];
+    const float4 col = s_rgb[e];
+    const float dx = (pxf - m.x) - m.z;
+    const float dy = (pyf - m.y) - m.w;
+    const float q = fmaf(c.x * dx, dx, fmaf(c.z * dy, dy, fmaf(c.y * dx, dy, c.w)));
+    // excluded texels get alpha 0 (a select, not a branch)
+    const float alpha = q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f;
+    const float w = alpha * T;
+    C0 = fmaf(w, col.x, C0);
+    C1 = fmaf(w, col.y, C1);
+    C2 = fmaf(w, col.z, C2);
+    T = T - w;
   }
   if (nseg > 1) {
     // partial (C, T) of this segment; the combine pass composes the segments in order

@@ -88,6 +88,14 @@ __device__ __forceinline__ void store_pixel<__half>(__half* out, size_t i, float
   reinterpret_cast<uint2*>(out)[i] = u;
 }
 
+// a if ok, else zero, selected per component (a select of whole vectors can turn into a
+// select of their addresses, which forces them into scratch memory)
+__device__ __forceinline__ float4 keep_if(bool ok, float4 a) {
+  return make_float4(ok ? a.x : 0.0f, ok ? a.y : 0.0f, ok ? a.z : 0.0f, ok ? a.w : 0.0f);
+}
+
+__device__ __forceinline__ uint2 keep_if(bool ok, uint2 a) { return make_uint2(ok ? a.x : 0u, ok ? a.y : 0u); }
+
 __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
   return make_float4(fmaf(w, b.x - a.x, a.x), fmaf(w, b.y - a.y, a.y), fmaf(w, b.z - a.z, a.z),
                      fmaf(w, b.w - a.w, a.w));
@@ -134,6 +142,7 @@ __global__ void coeff_table(CompositeArgs a, float4* __restrict__ pt, float* __r
 // ---------------------------------------------------------------------------------------
 constexpr int kBatch = 64;
 constexpr int kWin = 2048;                    // float4 entries per window buffer
+constexpr int kWinStride = kWin + 2;          // plus a trash slot for inactive stores
 constexpr int kPrefetch = kWin / kRowThreads; // window entries prefetched per thread (nearest)
 constexpr int kSub = 4;                       // views sampled per scheduling block
 
@@ -284,42 +293,62 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
     }
     __syncthreads();
 
-    float4 pre0[PF], pre1[PF];
+    // Window fetch, split in two: fetch() issues every load of the next plane's window with
+    // clamped (always valid) addresses and no branches, so the loads stay in flight while the
+    // current plane is sampled; store() masks the out-of-plane texels to zero and writes LDS.
+    float4 ra[RAW ? 1 : PF], rb[BIL ? PF : 1], rc[BIL ? PF : 1], rd[BIL ? PF : 1];
     uint2 praw[RAW ? PF : 1];
+    uint32_t valid = 0;                                    // bit (q * 4 + r): raw texel in the plane
     auto fetch = [&](int k) {
       const PlaneInfo pi = pinfo[k];
       const size_t pbase = (size_t)(kb + k) * plane_elems;
+      valid = 0;
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
+        if (q * nt >= pi.len) break;                       // uniform: the window is shorter
         const int i = tid + q * nt;
-        if (i < pi.len) {
-          const int ix = pi.f0 + i;
-          if constexpr (RAW) {
-            praw[q] = (ix >= 0 && ix < wp) ? load_raw_half4(planes, pbase + (size_t)pi.iy * wp + ix) : make_uint2(0u, 0u);
-          } else if constexpr (!BIL) {
-            pre0[q] = (ix >= 0 && ix < wp) ? load_texel(planes, pbase + (size_t)pi.iy * wp + ix)
-                                           : make_float4(0.f, 0.f, 0.f, 0.f);
-          } else {
-            bilinear_entry<PT>(planes, pbase, wp, hp, pi, i, pre0[q], pre1[q]);
-          }
+        const int ix = pi.f0 + i;
+        const bool in = i < pi.len;
+        if constexpr (!BIL) {
+          const bool ok = in && ix >= 0 && ix < wp;
+          const size_t at = pbase + (size_t)pi.iy * wp + (size_t)min(max(ix, 0), wp - 1);
+          if constexpr (RAW) praw[q] = load_raw_half4(planes, at);
+          else ra[q] = load_texel(planes, at);
+          valid |= (ok ? 1u : 0u) << (q * 4);
+        } else {
+          const int r0 = min(max(pi.iy, 0), hp - 1), r1 = min(max(pi.iy + 1, 0), hp - 1);
+          const size_t c0 = (size_t)min(max(ix, 0), wp - 1), c1 = (size_t)min(max(ix + 1, 0), wp - 1);
+          ra[q] = load_texel(planes, pbase + (size_t)r0 * wp + c0);
+          rb[q] = load_texel(planes, pbase + (size_t)r1 * wp + c0);
+          rc[q] = load_texel(planes, pbase + (size_t)r0 * wp + c1);
+          rd[q] = load_texel(planes, pbase + (size_t)r1 * wp + c1);
+          const bool x0 = in && ix >= 0 && ix < wp, x1 = in && ix + 1 >= 0 && ix + 1 < wp;
+          const bool y0 = pi.iy >= 0, y1 = pi.iy + 1 < hp;
+          valid |= ((x0 && y0 ? 1u : 0u) | (x0 && y1 ? 2u : 0u) | (x1 && y0 ? 4u : 0u) | (x1 && y1 ? 8u : 0u))
+                   << (q * 4);
         }
       }
     };
+    // branch free: entries past the window go to a trash slot behind the buffer (a branch
+    // here would split the loop into blocks the compiler then schedules across)
     auto store = [&](int buf, int k) {
-      const int len = pinfo[k].len;
-      float4* w = win + buf * kWin;
+      const PlaneInfo pi = pinfo[k];
+      float4* w = win + buf * kWinStride;
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
-        const int i = tid + q * nt;
-        if (i < len) {
-          if constexpr (RAW) {
-            reinterpret_cast<uint2*>(w)[i] = praw[q];
-          } else if constexpr (!BIL) {
-            w[i] = pre0[q];
-          } else {
-            w[2 * i] = pre0[q];
-            w[2 * i + 1] = pre1[q];
-          }
+        if (q * nt >= pi.len) break;                       // uniform: the window is shorter
+        const int i0 = tid + q * nt;
+        const int i = i0 < pi.len ? i0 : (BIL ? kWin / 2 : kWin);
+        const uint32_t m = valid >> (q * 4);
+        if constexpr (RAW) {
+          reinterpret_cast<uint2*>(w)[i] = keep_if((m & 1u) != 0u, praw[q]);
+        } else if constexpr (!BIL) {
+          w[i] = keep_if((m & 1u) != 0u, ra[q]);
+        } else {
+          const float4 t0 = lerp4(keep_if((m & 1u) != 0u, ra[q]), keep_if((m & 2u) != 0u, rb[q]), pi.wy);
+          const float4 t1 = lerp4(keep_if((m & 4u) != 0u, rc[q]), keep_if((m & 8u) != 0u, rd[q]), pi.wy);
+          w[2 * i] = t0;
+          w[2 * i + 1] = make_float4(t1.x - t0.x, t1.y - t0.y, t1.z - t0.z, t1.w - t0.w);
         }
       }
     };
@@ -340,7 +369,7 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
         for (int j = 0; j < G; ++j) Cv[j] = crow[j];          // scalar loads, one wait
         const float bxr = pt[kb + k].x * xr;
         const float xmin = (float)f0, xmax = (float)(f0 + len) - 0.5f;
-        const char* wbytes = reinterpret_cast<const char*>(win) + (n & 1) * (kWin * 16) -
+        const char* wbytes = reinterpret_cast<const char*>(win) + (n & 1) * (kWinStride * 16) -
                              (ptrdiff_t)f0 * (ptrdiff_t)(BIL ? 32 : (int)sizeof(LT));
 #pragma unroll
         for (int j0 = 0; j0 < G; j0 += kSub) {
@@ -370,6 +399,11 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
             Qb[j] = fmaf(Tr[j], sv[jj].z, Qb[j]);
             Tr[j] = fmaf(-Tr[j], sv[jj].w, Tr[j]);
           }
+          // blend this sub-block before the next one's LDS reads are issued: bounds the
+          // live sample registers (occupancy) instead of holding all G samples at once
+#pragma unroll
+          for (int jj = 0; jj < kSub; ++jj)
+            asm volatile("" ::"v"(Qr[j0 + jj]), "v"(Qg[j0 + jj]), "v"(Qb[j0 + jj]), "v"(Tr[j0 + jj]) : "memory");
           __builtin_amdgcn_sched_barrier(0);
         }
         if (more) store((n + 1) & 1, slist[n + 1]);
@@ -930,7 +964,7 @@ hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const fl
   const int nseg = (a.nx + kRowThreads - 1) / kRowThreads;
   const int seg = (a.nx + nseg - 1) / nseg;
   const int threads = ((seg + 63) / 64) * 64;
-  const size_t lds = (size_t)2 * kWin * 16;
+  const size_t lds = (size_t)2 * kWinStride * 16;
   const dim3 grid(a.ny, (a.n_views + G - 1) / G, nseg);
   switch (G) {
     case 4: hipLaunchKernelGGL((composite_rows<PT, OT, 4, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
