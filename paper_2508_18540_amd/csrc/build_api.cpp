@@ -308,7 +308,7 @@ extern "C" lf_status lf_build_mpi_backward(lf_ctx* ctx, const lf_field* field, c
   BuildArgs a;
   build_args(a, L, field, cam, g, mpi->n_chunk, LF_BIN_QUANTILE, mpi, workspace, cap);
   // the forward left the tile-sorted entries in the array its radix passes ended on
-  if (radix_passes(L.tile_bits) & 1) a.evals = a.evals_alt;
+  if (radix_passes(L.tile_bits, tile_digit_bits()) & 1) a.evals = a.evals_alt;
   a.d_planes = d_planes;
   a.grads = *grads;
   if ((e = build_backward(a, L, (hipStream_t)stream, &ctx->prof)) != hipSuccess) return hip_fail(e, "build backward launch");

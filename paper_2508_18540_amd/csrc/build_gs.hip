@@ -15,6 +15,8 @@
 //  splat       one work-group per (tile, chunk): front-to-back blending of the bucket into
 //              premultiplied RGBA (C, 1 - T) with alpha = min(0.99, o G), only where
 //              o G >= 1/255, no early termination
+#include <cstdlib>
+
 #include "build_device.h"
 #include "dfloat.h"
 #include "sort_internal.h"
@@ -208,67 +210,80 @@ __global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
   a.depth[k] = d;
 }
 
-// One (tile, Gaussian) entry per covered tile, written in rank order.  A block takes 256
-// consecutive ranks and spreads their entries evenly over its threads (each output slot
-// finds its rank by binary search over the block's offsets), so one Gaussian covering
-// hundreds of tiles does not serialise a thread.  The entry value carries the Gaussian index
+// One (tile, Gaussian) entry per covered tile, written in rank order.  Work is balanced by
+// output: block b writes entries [256 b, 256 b + 256) of the rank-ordered list, whatever
+// ranks they come from (a Gaussian near the camera can cover hundreds of tiles).  Thread 0
+// finds the block's rank range in the tile-count offsets, the block stages those offsets
+// in LDS, and each thread finds its entry's rank by binary search there (or in the global
+// offsets when the range is too long to stage).  The entry value carries the Gaussian index
 // in its low 28 bits and, in bits 28..31, which 8x8 quadrants of the tile its support box
 // touches (bit = 2 * qy + qx).
+constexpr int kEmitRanks = 512;
+constexpr int kTileDigitBits = 6;   // tile sort: two narrow passes write more coalesced runs than one wide one
+
+__device__ __forceinline__ int64_t last_le(const uint64_t* off, int64_t lo, int64_t hi, uint64_t v) {
+  // last r in [lo, hi] with off[r] <= v (off is non-decreasing, off[lo] <= v)
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= v) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(256) void emit_entries(BuildArgs a, const uint32_t* svals) {
-  __shared__ uint32_t lofs[257];
-  __shared__ int32_t sx0[256], sy0[256], sw[256], sbox[256][4];
-  __shared__ uint32_t sidx[256], schunk[256];
-  const int64_t r0 = (int64_t)blockIdx.x * 256;
-  const int64_t nvis = a.hdr->n_vis;
-  if (r0 >= nvis) return;
+  __shared__ uint64_t soff[kEmitRanks + 1];
+  __shared__ int64_t srange[2];
   const uint64_t total = a.offsets[a.n];
   if (total > (uint64_t)a.capacity) {
-    if (threadIdx.x == 0) atomicOr(&a.hdr->overflow, 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr->overflow, 1);
     return;
   }
-  const int nr = (int)min((int64_t)256, nvis - r0);
-  const uint64_t O0 = a.offsets[r0];
+  const uint64_t o0 = (uint64_t)blockIdx.x * 256;
+  if (o0 >= total) return;
+  const uint64_t olast = min(total, o0 + 256) - 1;
   const int t = threadIdx.x;
-  if (t < nr) lofs[t] = (uint32_t)(a.offsets[r0 + t] - O0);
-  if (t == 0) lofs[nr] = (uint32_t)(a.offsets[r0 + nr] - O0);   // nr may be 256 = blockDim
-  if (t < nr) {
-    const uint32_t idx = svals[r0 + t];
-    // the texel box leads every record kind
-    const int4 g = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(a.rec) + (size_t)idx * a.rec_bytes);
-    sidx[t] = idx;
-    schunk[t] = a.chunk_r[r0 + t];
-    sx0[t] = g.x >> kTileShift;
-    sy0[t] = g.y >> kTileShift;
-    sw[t] = (g.z >> kTileShift) - (g.x >> kTileShift) + 1;
-    sbox[t][0] = g.x;
-    sbox[t][1] = g.y;
-    sbox[t][2] = g.z;
-    sbox[t][3] = g.w;
+  if (t == 0) {
+    const int64_t r_lo = last_le(a.offsets, 0, a.n, o0);
+    srange[0] = r_lo;
+    srange[1] = last_le(a.offsets, r_lo, a.n, olast);
   }
   __syncthreads();
-  const uint32_t n_out = lofs[nr];
-  for (uint32_t o = t; o < n_out; o += 256) {
-    int lo = 0, hi = nr - 1;                               // last j with lofs[j] <= o
+  const int64_t r_lo = srange[0], r_hi = srange[1];
+  const int64_t nr = r_hi - r_lo + 1;
+  const bool staged = nr <= kEmitRanks;
+  if (staged)
+    for (int i = t; i <= nr; i += 256) soff[i] = a.offsets[r_lo + i];
+  __syncthreads();
+  const uint64_t o = o0 + t;
+  if (o > olast) return;
+  int64_t r;
+  if (staged) {
+    int lo = 0, hi = (int)nr - 1;                          // last j with soff[j] <= o
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (lofs[mid] <= o) lo = mid;
+      if (soff[mid] <= o) lo = mid;
       else hi = mid - 1;
     }
-    const int j = lo;
-    const uint32_t u = o - lofs[j];
-    const int tx = sx0[j] + (int)(u % (uint32_t)sw[j]), ty = sy0[j] + (int)(u / (uint32_t)sw[j]);
-    const int ox = tx << kTileShift, oy = ty << kTileShift;
-    uint32_t mask = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int bx = ox + ((q & 1) << 3), by = oy + ((q >> 1) << 3);
-      if (sbox[j][2] >= bx && sbox[j][0] <= bx + 7 && sbox[j][3] >= by && sbox[j][1] <= by + 7) mask |= 1u << q;
-    }
-    const uint32_t tile = (uint32_t)(ty * a.ntx + tx);
-    const uint64_t dst = O0 + o;
-    a.ekeys[dst] = (tile << a.chunk_bits) | schunk[j];
-    a.evals[dst] = sidx[j] | (mask << 28);
+    r = r_lo + lo;
+  } else {
+    r = last_le(a.offsets, r_lo, r_hi, o);
   }
+  const uint32_t idx = svals[r];
+  const int4 g = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(a.rec) + (size_t)idx * a.rec_bytes);
+  const uint32_t u = (uint32_t)(o - a.offsets[r]);
+  const int sx0 = g.x >> kTileShift, sw = (g.z >> kTileShift) - sx0 + 1;
+  const int tx = sx0 + (int)(u % (uint32_t)sw), ty = (g.y >> kTileShift) + (int)(u / (uint32_t)sw);
+  const int ox = tx << kTileShift, oy = ty << kTileShift;
+  uint32_t mask = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int bx = ox + ((q & 1) << 3), by = oy + ((q >> 1) << 3);
+    if (g.z >= bx && g.x <= bx + 7 && g.w >= by && g.y <= by + 7) mask |= 1u << q;
+  }
+  const uint32_t tile = (uint32_t)(ty * a.ntx + tx);
+  a.ekeys[o] = (tile << a.chunk_bits) | a.chunk_r[r];
+  a.evals[o] = idx | (mask << 28);
 }
 
 // Start of every (tile, chunk) bucket in the tile-sorted entry list: the first entry whose
@@ -690,6 +705,15 @@ hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Digit width of the entry sort by tile (LF_TILE_DIGIT_BITS overrides, 1..11).
+int tile_digit_bits() {
+  if (const char* e = getenv("LF_TILE_DIGIT_BITS")) {
+    const int b = atoi(e);
+    if (b >= 1 && b <= 11) return b;
+  }
+  return kTileDigitBits;
+}
+
 hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
   hipError_t e;
   const unsigned gN = (unsigned)((a.n + 255) / 256);
@@ -727,13 +751,13 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, skeys);
     hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, skeys);
     if ((e = exclusive_scan<uint64_t>(a.ntiles_r, a.offsets, a.n, a.scan_tmp64, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(emit_entries, dim3(gN), dim3(256), 0, s, a, svals);
+    hipLaunchKernelGGL(emit_entries, dim3((unsigned)((a.capacity + 255) / 256)), dim3(256), 0, s, a, svals);
     hipLaunchKernelGGL(finalize, dim3(1), dim3(1), 0, s, a);
     // stable sort of the entries by tile (entries beyond the capacity are never read)
     int ealt = 0;
     if ((e = radix_sort_pairs(a.ekeys, a.evals, a.ekeys_alt, a.evals_alt, a.capacity,
                               reinterpret_cast<const int64_t*>(&a.hdr->entries), L.chunk_bits, L.tile_bits,
-                              a.radix_tmp, &ealt, s)) != hipSuccess)
+                              a.radix_tmp, &ealt, s, tile_digit_bits())) != hipSuccess)
       return e;
     if (ealt) a.evals = a.evals_alt;
     const uint32_t* sekeys = ealt ? a.ekeys_alt : a.ekeys;

@@ -115,6 +115,8 @@ struct TableChunk {
 hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s);
 // The whole build of one field (either kind) on stream s.
 hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof);
+// Digit width the tile sort of the entries uses (its pass count decides where they end up).
+int tile_digit_bits();
 
 // Voxel kernels (build_vox.hip): per-voxel preprocess, tile-list splat of one plane per
 // (tile, chunk) item, and the in-place plane low-pass.

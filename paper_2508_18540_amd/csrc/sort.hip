@@ -217,11 +217,12 @@ size_t radix_tmp_u32(int64_t cap) {
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t cap,
                             const int64_t* n_dev, int lo_bit, int bits, uint32_t* tmp, int* result_in_alt,
-                            hipStream_t s) {
+                            hipStream_t s, int max_digit_bits) {
   if (bits < 1 || lo_bit < 0 || lo_bit + bits > 32) return hipErrorInvalidValue;
+  if (max_digit_bits < 1 || max_digit_bits > kMaxDigitBits) return hipErrorInvalidValue;
   const int P = radix_blocks(cap);
-  // passes of at most kMaxDigitBits bits, as even as possible (32 bits: 11 + 11 + 10)
-  const int npass = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+  // passes of at most max_digit_bits bits, as even as possible (32 bits at 11: 11 + 11 + 10)
+  const int npass = (bits + max_digit_bits - 1) / max_digit_bits;
   const int dbits = (bits + npass - 1) / npass;
   const int64_t nc = (1LL << dbits) * P;
   uint32_t* counts = tmp;
@@ -254,7 +255,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
   return hipGetLastError();
 }
 
-int radix_passes(int bits) { return bits < 1 ? 0 : (bits + kMaxDigitBits - 1) / kMaxDigitBits; }
+int radix_passes(int bits, int max_digit_bits) { return bits < 1 ? 0 : (bits + max_digit_bits - 1) / max_digit_bits; }
 
 hipError_t fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
