@@ -219,6 +219,7 @@ __global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
 // in its low 28 bits and, in bits 28..31, which 8x8 quadrants of the tile its support box
 // touches (bit = 2 * qy + qx).
 constexpr int kEmitRanks = 512;
+constexpr int kKeyDigitBits = 8;    // key sort: four passes over a grid wide enough to fill the CUs
 constexpr int kTileDigitBits = 6;   // tile sort: two narrow passes write more coalesced runs than one wide one
 
 __device__ __forceinline__ int64_t last_le(const uint64_t* off, int64_t lo, int64_t hi, uint64_t v) {
@@ -714,6 +715,15 @@ int tile_digit_bits() {
   return kTileDigitBits;
 }
 
+// Digit width of the depth-key sort (LF_KEY_DIGIT_BITS overrides, 1..11).
+int key_digit_bits() {
+  if (const char* e = getenv("LF_KEY_DIGIT_BITS")) {
+    const int b = atoi(e);
+    if (b >= 1 && b <= 11) return b;
+  }
+  return kKeyDigitBits;
+}
+
 hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
   hipError_t e;
   const unsigned gN = (unsigned)((a.n + 255) / 256);
@@ -738,8 +748,8 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
   int alt = 0;
   {
     PhaseScope ps(prof, LF_PHASE_SORT, s);
-    if ((e = radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.n, nullptr, 0, 32, a.radix_tmp, &alt, s)) !=
-        hipSuccess)
+    if ((e = radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.n, nullptr, 0, 32, a.radix_tmp, &alt, s,
+                              key_digit_bits())) != hipSuccess)
       return e;
   }
   const uint32_t* skeys = alt ? a.keys_alt : a.keys;

@@ -203,16 +203,22 @@ hipError_t exclusive_scan(const T* in, T* out, int64_t n, T* tmp, hipStream_t s)
 template hipError_t exclusive_scan<uint32_t>(const uint32_t*, uint32_t*, int64_t, uint32_t*, hipStream_t);
 template hipError_t exclusive_scan<uint64_t>(const uint64_t*, uint64_t*, int64_t, uint64_t*, hipStream_t);
 
-int radix_blocks(int64_t cap) {
-  const int64_t b = (cap + 4095) / 4096;
-  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+// Blocks of the radix grid: about 1024 elements per block, so small sorts still spread
+// over the CUs, with the per-block digit counts (2^digit_bits * blocks) kept to 2^18.
+constexpr int64_t kMaxCounts = 1 << 18;
+
+int radix_blocks(int64_t cap, int digit_bits) {
+  int64_t b = (cap + 1023) / 1024;
+  const int64_t lim = kMaxCounts >> digit_bits;
+  if (b > lim) b = lim;
+  return (int)(b < 1 ? 1 : b);
 }
 
 constexpr int kMaxDigitBits = 11;
 
 size_t radix_tmp_u32(int64_t cap) {
-  const int64_t nc = (1LL << kMaxDigitBits) * radix_blocks(cap);
-  return (size_t)(2 * nc + scan_tmp_elems(nc) + 1);
+  (void)cap;
+  return (size_t)(2 * kMaxCounts + scan_tmp_elems(kMaxCounts) + 1);
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t cap,
@@ -220,10 +226,10 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
                             hipStream_t s, int max_digit_bits) {
   if (bits < 1 || lo_bit < 0 || lo_bit + bits > 32) return hipErrorInvalidValue;
   if (max_digit_bits < 1 || max_digit_bits > kMaxDigitBits) return hipErrorInvalidValue;
-  const int P = radix_blocks(cap);
   // passes of at most max_digit_bits bits, as even as possible (32 bits at 11: 11 + 11 + 10)
   const int npass = (bits + max_digit_bits - 1) / max_digit_bits;
   const int dbits = (bits + npass - 1) / npass;
+  const int P = radix_blocks(cap, dbits);
   const int64_t nc = (1LL << dbits) * P;
   uint32_t* counts = tmp;
   uint32_t* offs = tmp + nc;

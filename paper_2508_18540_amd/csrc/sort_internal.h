@@ -14,8 +14,9 @@ size_t scan_tmp_elems(int64_t n);
 template <typename T>
 hipError_t exclusive_scan(const T* in, T* out, int64_t n, T* tmp, hipStream_t s);
 
-// Blocks of the fixed radix-sort grid for up to `cap` elements, and its scratch size (u32).
-int radix_blocks(int64_t cap);
+// Blocks of the fixed radix-sort grid for up to `cap` elements with digit_bits-bit digits,
+// and the scratch size (u32) of any sort.
+int radix_blocks(int64_t cap, int digit_bits);
 size_t radix_tmp_u32(int64_t cap);
 
 // Stable LSD sort of (key, value) pairs by the key bits [lo_bit, lo_bit + bits) (keys are
