@@ -339,12 +339,40 @@ __global__ void emit_items(BuildArgs a, int64_t n_buckets) {
   for (uint32_t s = 0; s < ns; ++s) a.items[i0 + s] = make_uint2((uint32_t)b, s);
 }
 
+// Upper bound on log2(o G) over the texel rectangle u in [u0, u0 + 7], v in [v0, v0 + 7]
+// (offsets from the mean) of the concave form q(u, v) = ca u^2 + cb u v + cc v^2 + l2o: the
+// centre value if the centre lies inside, else the best point of the four edges (each a 1-D
+// concave quadratic), each raised by 1e-5 of the magnitude of its terms, far above the
+// float32 rounding of q at that point, so a rectangle whose texels pass the 1/255 test is
+// never reported below it.
+__device__ __forceinline__ float block_max_q(float ca, float cb, float cc, float l2o, float u0, float v0) {
+  const float u1 = u0 + 7.0f, v1 = v0 + 7.0f;
+  if (u0 <= 0.0f && 0.0f <= u1 && v0 <= 0.0f && 0.0f <= v1) return l2o;
+  float best = -INFINITY;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    // e = 0, 1: edge u = u0 | u1 with v free; e = 2, 3: edge v = v0 | v1 with u free
+    float u, v;
+    if (e < 2) {
+      u = e ? u1 : u0;
+      v = fminf(fmaxf(-cb * u / (2.0f * cc), v0), v1);
+    } else {
+      v = e == 3 ? v1 : v0;
+      u = fminf(fmaxf(-cb * v / (2.0f * ca), u0), u1);
+    }
+    const float tu = ca * u * u, tv = cc * v * v, tx = cb * u * v;
+    const float mag = fabsf(tu) + fabsf(tv) + fabsf(tx);
+    best = fmaxf(best, fmaf(1e-5f, mag, tu + tv + tx + l2o));
+  }
+  return best;
+}
+
 template <typename PT>
 __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) {
-  __shared__ float4 s_mean[kSegment];                      // (mx_hi, my_hi, mx_lo, my_lo)
+  __shared__ float2 s_rel[kSegment];                       // tile origin minus the mean (texels)
   __shared__ float4 s_conic[kSegment];                     // (ca, cb, cc, l2o)
   __shared__ float4 s_rgb[kSegment];
-  __shared__ uint16_t s_list[4][kSegment];                 // per quadrant: entries touching it
+  __shared__ uint16_t s_list[4][kSegment];                 // per quadrant: entries reaching it
   __shared__ int s_cnt[4][4];                              // [quadrant][loading wave]
   const uint32_t item = blockIdx.x;
   if (item >= a.item_start[n_buckets]) return;             // beyond this frame's work list
@@ -354,23 +382,33 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
-  const int bx = ox + ((wave & 1) << 3), by = oy + ((wave >> 1) << 3);
-  const int px = bx + (lane & 7), py = by + (lane >> 3);
-  const float pxf = (float)px, pyf = (float)py;
+  const int lxi = ((wave & 1) << 3) + (lane & 7), lyi = ((wave >> 1) << 3) + (lane >> 3);
+  const int px = ox + lxi, py = oy + lyi;
+  const float lx = (float)lxi, ly = (float)lyi;
   const bool ok = a.hdr->overflow == 0;
   const uint32_t bb0 = a.bucket[bidx], bb1 = a.bucket[bidx + 1];
   const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
   const uint32_t b0 = bb0 + it.y * kSegment;
   const int n = ok ? (int)(min(bb1, b0 + kSegment) - b0) : 0;
-  // stage: thread t holds entry t of the segment
+  // stage: thread t holds entry t of the segment.  Its mean is kept relative to the tile
+  // origin (double-float difference, so a texel offset is one exact-enough add), and the
+  // 8x8 blocks its support box touches are kept only if the ellipse o G >= 1/255 reaches
+  // them (with a margin far above the float32 error of q, so no texel is dropped).
   uint32_t qm = 0;
   if (tid < n) {
     const uint32_t ent = a.evals[b0 + tid];
     const GRec& g = a.rec[min(ent & 0x0fffffffu, (uint32_t)a.n - 1u)];
-    s_mean[tid] = make_float4(g.mx_hi, g.my_hi, g.mx_lo, g.my_lo);
+    const float sx = ((float)ox - g.mx_hi) - g.mx_lo, sy = ((float)oy - g.my_hi) - g.my_lo;
+    s_rel[tid] = make_float2(sx, sy);
     s_conic[tid] = make_float4(g.ca, g.cb, g.cc, g.l2o);
     s_rgb[tid] = make_float4(g.rgb[0], g.rgb[1], g.rgb[2], 0.0f);
-    qm = ent >> 28;
+    const uint32_t box = ent >> 28;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((box >> q) & 1u)) continue;
+      const float u0 = (float)((q & 1) << 3) + sx, v0 = (float)((q >> 1) << 3) + sy;
+      if (block_max_q(g.ca, g.cb, g.cc, g.l2o, u0, v0) >= kLog2AlphaMin - 1e-2f) qm |= 1u << q;
+    }
   }
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   uint32_t rank[4];
@@ -394,11 +432,11 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
   const int cnt = __builtin_amdgcn_readfirstlane(my_count);
   for (int i = 0; i < cnt; ++i) {
     const int e = s_list[wave][i];
-    const float4 m = s_mean[e];
+    const float2 r = s_rel[e];
     const float4 c = s_conic[e];
     const float4 col = s_rgb[e];
-    const float dx = (pxf - m.x) - m.z;
-    const float dy = (pyf - m.y) - m.w;
+    const float dx = lx + r.x;
+    const float dy = ly + r.y;
     const float q = fmaf(c.x * dx, dx, fmaf(c.z * dy, dy, fmaf(c.y * dx, dy, c.w)));
     // excluded texels get alpha 0 (a select, not a branch)
     const float alpha = q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f;
