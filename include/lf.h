@@ -123,6 +123,8 @@ typedef struct {
   int64_t entries_needed;   /* (tile, chunk) list entries the last build needed           */
   int64_t entry_capacity;   /* entries the workspace holds                                */
   int32_t overflow;         /* 1 if entries_needed > entry_capacity (planes are invalid)  */
+  int32_t stalled;          /* 1 if a bounded device-wide wait of the sorts or scans gave
+                             * up (planes are invalid; reported as LF_ERR_HIP)            */
 } lf_build_info;
 
 /* Gradients of a Gaussian field's parameters, device float32 arrays written whole by
@@ -169,7 +171,8 @@ lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam,
                        void* workspace, size_t workspace_bytes, void* stream);
 
 /* Counters of the last lf_build_mpi that used `workspace`.  SYNCHRONISES `stream`.
- * Returns LF_ERR_CAPACITY (with *out filled) if that build overflowed.                   */
+ * Returns LF_ERR_CAPACITY (with *out filled) if that build overflowed, LF_ERR_HIP (with
+ * *out filled) if one of its bounded device-wide waits gave up.                          */
 lf_status lf_build_stats(lf_ctx* ctx, const void* workspace, size_t workspace_bytes,
                          lf_build_info* out, void* stream);
 

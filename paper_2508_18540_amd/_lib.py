@@ -78,7 +78,7 @@ class lf_geometry_info(C.Structure):
 
 class lf_build_info(C.Structure):
     _fields_ = [("n_visible", C.c_int64), ("entries_needed", C.c_int64), ("entry_capacity", C.c_int64),
-                ("overflow", C.c_int32)]
+                ("overflow", C.c_int32), ("stalled", C.c_int32)]
 
 
 class lf_batch_item(C.Structure):

@@ -40,6 +40,8 @@ BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t
   };
   const size_t un = (size_t)(n > 0 ? n : 1);
   L.o_hdr = take(sizeof(BuildHeader));
+  L.o_sync = take((size_t)2 * kRadixHistWordsMax * 4 +
+                  (scan_state_words((int64_t)un) + scan_state_words(L.n_buckets)) * 8);
   L.o_keys = take(un * 4);
   L.o_vals = take(un * 4);
   L.o_keys_alt = take(un * 4);
@@ -49,13 +51,11 @@ BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t
   L.o_ntiles_r = take(un * 8);
   L.o_chunk_r = take(un * 4);
   L.o_offsets = take((un + 1) * 8);
-  L.o_scan64 = take(scan_tmp_elems((int64_t)un) * 8);
   L.o_chunk_start = take((size_t)(K + 1) * 8);
   L.o_edges = take((size_t)K * 4);
   L.o_dtab = take((size_t)K * 4);
   L.o_nseg = take((size_t)(L.n_buckets + 1) * 4);
   L.o_bucket = take((size_t)(L.n_buckets + 1) * 4);
-  L.o_scan32 = take(scan_tmp_elems(L.n_buckets) * 4);
   L.o_radix = take(radix_tmp_u32(n > cap ? n : cap) * 4);
   const size_t uc = (size_t)(cap > 0 ? cap : 1) + kEntryPad;
   L.o_ekeys = take(uc * 4);
@@ -73,6 +73,7 @@ BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t
   L.o_halo_rows = take((size_t)K * L.filt_bands * 2 * wp * 16);
   L.o_halo_cols = take((size_t)K * L.filt_segs * 2 * hp * 16);
   L.o_ggrad = take(kind == LF_VOXELS ? 0 : un * kGradSlots * 4);
+  L.clear_words = (int64_t)(L.o_keys - L.o_hdr) / 4;   // header and sync region
   L.total = o;
   return L;
 }
@@ -166,14 +167,17 @@ void build_args(BuildArgs& a, const BuildLayout& L, const lf_field* field, const
   a.ntiles_r = reinterpret_cast<uint64_t*>(w + L.o_ntiles_r);
   a.chunk_r = reinterpret_cast<uint32_t*>(w + L.o_chunk_r);
   a.offsets = reinterpret_cast<uint64_t*>(w + L.o_offsets);
-  a.scan_tmp64 = reinterpret_cast<uint64_t*>(w + L.o_scan64);
   a.chunk_start = reinterpret_cast<int64_t*>(w + L.o_chunk_start);
   a.edges = reinterpret_cast<float*>(w + L.o_edges);
   a.dtab = reinterpret_cast<float*>(w + L.o_dtab);
   a.nseg = reinterpret_cast<uint32_t*>(w + L.o_nseg);
   a.bucket = reinterpret_cast<uint32_t*>(w + L.o_bucket);
-  a.scan_tmp32 = reinterpret_cast<uint32_t*>(w + L.o_scan32);
   a.radix_tmp = reinterpret_cast<uint32_t*>(w + L.o_radix);
+  a.ghist_key = reinterpret_cast<uint32_t*>(w + L.o_sync);
+  a.ghist_tile = a.ghist_key + kRadixHistWordsMax;
+  a.scan_state_offsets = reinterpret_cast<uint64_t*>(a.ghist_tile + kRadixHistWordsMax);
+  a.scan_state_items = a.scan_state_offsets + scan_state_words(L.n > 0 ? L.n : 1);
+  a.clear_words = L.clear_words;
   a.ekeys = reinterpret_cast<uint32_t*>(w + L.o_ekeys);
   a.evals = reinterpret_cast<uint32_t*>(w + L.o_evals);
   a.ekeys_alt = reinterpret_cast<uint32_t*>(w + L.o_ekeys_alt);
@@ -330,6 +334,9 @@ extern "C" lf_status lf_build_stats(lf_ctx* ctx, const void* workspace, size_t w
   out->entries_needed = h.entries;
   out->entry_capacity = h.capacity;
   out->overflow = h.overflow;
+  out->stalled = h.stalled ? 1 : 0;
+  if (h.stalled)
+    return fail(LF_ERR_HIP, "a device-wide wait of the last build's sorts or scans timed out (planes are invalid)");
   if (h.overflow)
     return fail(LF_ERR_CAPACITY, "the last build needed %lld entries but the workspace holds %lld",
                 (long long)h.entries, (long long)h.capacity);

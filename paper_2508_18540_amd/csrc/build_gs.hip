@@ -744,20 +744,20 @@ hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Digit width of the entry sort by tile (LF_TILE_DIGIT_BITS overrides, 1..11).
+// Digit width of the entry sort by tile (LF_TILE_DIGIT_BITS overrides, 4..11).
 int tile_digit_bits() {
   if (const char* e = getenv("LF_TILE_DIGIT_BITS")) {
     const int b = atoi(e);
-    if (b >= 1 && b <= 11) return b;
+    if (b >= 4 && b <= 11) return b;
   }
   return kTileDigitBits;
 }
 
-// Digit width of the depth-key sort (LF_KEY_DIGIT_BITS overrides, 1..11).
+// Digit width of the depth-key sort (LF_KEY_DIGIT_BITS overrides, 4..11).
 int key_digit_bits() {
   if (const char* e = getenv("LF_KEY_DIGIT_BITS")) {
     const int b = atoi(e);
-    if (b >= 1 && b <= 11) return b;
+    if (b >= 4 && b <= 11) return b;
   }
   return kKeyDigitBits;
 }
@@ -767,7 +767,8 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
   const unsigned gN = (unsigned)((a.n + 255) / 256);
   {
     PhaseScope ps(prof, LF_PHASE_PREPROCESS, s);
-    if ((e = fill(reinterpret_cast<uint32_t*>(a.hdr), sizeof(BuildHeader) / 4, 0u, s)) != hipSuccess) return e;
+    // counters, digit totals of both sorts and the scan states start at zero
+    if ((e = fill(reinterpret_cast<uint32_t*>(a.hdr), a.clear_words, 0u, s)) != hipSuccess) return e;
     if (a.n == 0) {
       // nothing to rasterise: transparent planes at D_focal (or the inverse-depth table)
       const size_t words = (size_t)a.K * a.c.hp * a.c.wp * (a.plane_dtype == LF_F32 ? 4 : 2);
@@ -786,8 +787,8 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
   int alt = 0;
   {
     PhaseScope ps(prof, LF_PHASE_SORT, s);
-    if ((e = radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.n, nullptr, 0, 32, a.radix_tmp, &alt, s,
-                              key_digit_bits())) != hipSuccess)
+    if ((e = radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.n, nullptr, 0, 32, a.radix_tmp, a.ghist_key,
+                              &a.hdr->stalled, &alt, s, key_digit_bits())) != hipSuccess)
       return e;
   }
   const uint32_t* skeys = alt ? a.keys_alt : a.keys;
@@ -798,14 +799,15 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     hipLaunchKernelGGL(rank_pass, dim3(gN), dim3(256), 0, s, a, skeys, svals);
     hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, skeys);
     hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, skeys);
-    if ((e = exclusive_scan<uint64_t>(a.ntiles_r, a.offsets, a.n, a.scan_tmp64, s)) != hipSuccess) return e;
+    if ((e = exclusive_scan_u64(a.ntiles_r, a.offsets, a.n, a.scan_state_offsets, &a.hdr->stalled, s)) != hipSuccess)
+      return e;
     hipLaunchKernelGGL(emit_entries, dim3((unsigned)((a.capacity + 255) / 256)), dim3(256), 0, s, a, svals);
     hipLaunchKernelGGL(finalize, dim3(1), dim3(1), 0, s, a);
     // stable sort of the entries by tile (entries beyond the capacity are never read)
     int ealt = 0;
     if ((e = radix_sort_pairs(a.ekeys, a.evals, a.ekeys_alt, a.evals_alt, a.capacity,
                               reinterpret_cast<const int64_t*>(&a.hdr->entries), L.chunk_bits, L.tile_bits,
-                              a.radix_tmp, &ealt, s, tile_digit_bits())) != hipSuccess)
+                              a.radix_tmp, a.ghist_tile, &a.hdr->stalled, &ealt, s, tile_digit_bits())) != hipSuccess)
       return e;
     if (ealt) a.evals = a.evals_alt;
     const uint32_t* sekeys = ealt ? a.ekeys_alt : a.ekeys;
@@ -814,8 +816,9 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
                        L.n_buckets);
     // work items: buckets split into segments of at most kSegment entries
     hipLaunchKernelGGL(bucket_segments, dim3(gB), dim3(256), 0, s, a, L.n_buckets);
-    if ((e = exclusive_scan<uint32_t>(a.nseg, a.item_start, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
-    if ((e = exclusive_scan<uint32_t>(a.pcnt, a.pslot, L.n_buckets, a.scan_tmp32, s)) != hipSuccess) return e;
+    if ((e = exclusive_scan_pair_u32(a.nseg, a.item_start, a.pcnt, a.pslot, L.n_buckets, a.scan_state_items,
+                                     &a.hdr->stalled, s)) != hipSuccess)
+      return e;
     hipLaunchKernelGGL(emit_items, dim3(gB), dim3(256), 0, s, a, L.n_buckets);
   }
   {

@@ -15,7 +15,7 @@ struct BuildHeader {
   int64_t entries;
   int64_t capacity;
   int32_t overflow;
-  int32_t pad;
+  uint32_t stalled;                   // a device-wide wait of the sorts or scans gave up
 };
 
 // One projected Gaussian (64 bytes, four 16-byte groups).
@@ -50,9 +50,12 @@ struct BuildLayout {
   int32_t K, ntx, nty, n_tiles, tile_bits, chunk_bits, kind, rec_bytes;
   int32_t filt_bands, filt_segs;      // voxel low-pass regions (0 for Gaussians)
   size_t o_hdr, o_keys, o_vals, o_keys_alt, o_vals_alt, o_rec, o_ntiles_i, o_ntiles_r, o_chunk_r, o_offsets,
-      o_scan64, o_chunk_start, o_edges, o_dtab, o_nseg, o_bucket, o_scan32, o_radix, o_ekeys, o_evals, o_ekeys_alt,
+      o_sync, o_chunk_start, o_edges, o_dtab, o_nseg, o_bucket, o_radix, o_ekeys, o_evals, o_ekeys_alt,
       o_evals_alt, o_pcnt, o_item_start, o_pslot, o_items, o_partial, o_halo_rows, o_halo_cols, o_ggrad;
   int64_t max_items, max_partial;
+  // zero-initialised synchronisation words after the header (digit totals of both sorts,
+  // scan states); the build clears [o_hdr, o_hdr + 4 clear_words) first
+  int64_t clear_words;
   size_t total;
 };
 
@@ -84,10 +87,14 @@ struct BuildArgs {
   uint32_t* ntiles_i;
   uint64_t* ntiles_r;
   uint32_t* chunk_r;
-  uint64_t *offsets, *scan_tmp64;
+  uint64_t* offsets;
   int64_t* chunk_start;
   float *edges, *dtab;
-  uint32_t *nseg, *bucket, *scan_tmp32, *radix_tmp;
+  uint32_t *nseg, *bucket, *radix_tmp;
+  // cleared at the start of every build: digit totals of the two sorts, scan states
+  uint32_t *ghist_key, *ghist_tile;
+  uint64_t *scan_state_offsets, *scan_state_items;
+  int64_t clear_words;
   uint32_t *ekeys, *evals, *ekeys_alt, *evals_alt;
   // splat work items: bucket segments and their partial (C, T) tiles
   uint32_t *pcnt, *item_start, *pslot;
