@@ -62,6 +62,7 @@ BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t
   L.o_evals = take(uc * 4);
   L.o_ekeys_alt = take(uc * 4);
   L.o_evals_alt = take(uc * 4);
+  L.o_heads = take(((size_t)(cap > 0 ? cap : 1) / 256 + 2) * 4);
   const int64_t segs = (cap + kSegment - 1) / kSegment;
   L.max_items = L.n_buckets + segs + 1;
   L.max_partial = 2 * segs + 16;
@@ -182,6 +183,8 @@ void build_args(BuildArgs& a, const BuildLayout& L, const lf_field* field, const
   a.evals = reinterpret_cast<uint32_t*>(w + L.o_evals);
   a.ekeys_alt = reinterpret_cast<uint32_t*>(w + L.o_ekeys_alt);
   a.evals_alt = reinterpret_cast<uint32_t*>(w + L.o_evals_alt);
+  a.heads = reinterpret_cast<uint32_t*>(w + L.o_heads);
+  a.n_heads = (L.cap > 0 ? L.cap : 1) / 256 + 2;
   a.pcnt = reinterpret_cast<uint32_t*>(w + L.o_pcnt);
   a.item_start = reinterpret_cast<uint32_t*>(w + L.o_item_start);
   a.pslot = reinterpret_cast<uint32_t*>(w + L.o_pslot);

@@ -212,10 +212,11 @@ __global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
 
 // One (tile, Gaussian) entry per covered tile, written in rank order.  Work is balanced by
 // output: block b writes entries [256 b, 256 b + 256) of the rank-ordered list, whatever
-// ranks they come from (a Gaussian near the camera can cover hundreds of tiles).  Thread 0
-// finds the block's rank range in the tile-count offsets, the block stages those offsets
-// in LDS, and each thread finds its entry's rank by binary search there (or in the global
-// offsets when the range is too long to stage).  The entry value carries the Gaussian index
+// ranks they come from (a Gaussian near the camera can cover hundreds of tiles).  The
+// block's first rank comes from the offsets scan (heads), the block stages the offsets of
+// its rank range in LDS, and each thread finds its entry's rank by binary search there (or
+// in the global offsets when the range is too long to stage).  Block 0 also records the
+// number of entries.  The entry value carries the Gaussian index
 // in its low 28 bits and, in bits 28..31, which 8x8 quadrants of the tile its support box
 // touches (bit = 2 * qy + qx).
 constexpr int kEmitRanks = 512;
@@ -236,21 +237,24 @@ __global__ __launch_bounds__(256) void emit_entries(BuildArgs a, const uint32_t*
   __shared__ uint64_t soff[kEmitRanks + 1];
   __shared__ int64_t srange[2];
   const uint64_t total = a.offsets[a.n];
+  const int t = threadIdx.x;
+  if (blockIdx.x == 0 && t == 0) {
+    a.hdr->entries = (int64_t)total;
+    a.hdr->capacity = a.capacity;
+  }
   if (total > (uint64_t)a.capacity) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr->overflow, 1);
+    if (blockIdx.x == 0 && t == 0) atomicOr(&a.hdr->overflow, 1);
     return;
   }
   const uint64_t o0 = (uint64_t)blockIdx.x * 256;
   if (o0 >= total) return;
   const uint64_t olast = min(total, o0 + 256) - 1;
-  const int t = threadIdx.x;
-  if (t == 0) {
-    const int64_t r_lo = last_le(a.offsets, 0, a.n, o0);
-    srange[0] = r_lo;
-    srange[1] = last_le(a.offsets, r_lo, a.n, olast);
-  }
+  // the rank holding entry o0 comes from the offsets scan; the one holding entry o0 + 256
+  // (if any) bounds the rank of the last entry from above
+  const int64_t r_lo = a.heads[blockIdx.x];
+  if (t == 0) srange[1] = o0 + 256 < total ? (int64_t)a.heads[blockIdx.x + 1] : last_le(a.offsets, r_lo, a.n, olast);
   __syncthreads();
-  const int64_t r_lo = srange[0], r_hi = srange[1];
+  const int64_t r_hi = srange[1];
   const int64_t nr = r_hi - r_lo + 1;
   const bool staged = nr <= kEmitRanks;
   if (staged)
@@ -259,6 +263,7 @@ __global__ __launch_bounds__(256) void emit_entries(BuildArgs a, const uint32_t*
   const uint64_t o = o0 + t;
   if (o > olast) return;
   int64_t r;
+  uint64_t start;
   if (staged) {
     int lo = 0, hi = (int)nr - 1;                          // last j with soff[j] <= o
     while (lo < hi) {
@@ -267,12 +272,14 @@ __global__ __launch_bounds__(256) void emit_entries(BuildArgs a, const uint32_t*
       else hi = mid - 1;
     }
     r = r_lo + lo;
+    start = soff[lo];
   } else {
     r = last_le(a.offsets, r_lo, r_hi, o);
+    start = a.offsets[r];
   }
   const uint32_t idx = svals[r];
   const int4 g = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(a.rec) + (size_t)idx * a.rec_bytes);
-  const uint32_t u = (uint32_t)(o - a.offsets[r]);
+  const uint32_t u = (uint32_t)(o - start);
   const int sx0 = g.x >> kTileShift, sw = (g.z >> kTileShift) - sx0 + 1;
   const int tx = sx0 + (int)(u % (uint32_t)sw), ty = (g.y >> kTileShift) + (int)(u / (uint32_t)sw);
   const int ox = tx << kTileShift, oy = ty << kTileShift;
@@ -305,11 +312,6 @@ __global__ __launch_bounds__(256) void bucket_bounds(BuildArgs a, const uint32_t
     else hi = mid;
   }
   a.bucket[b] = (uint32_t)lo;
-}
-
-__global__ void finalize(BuildArgs a) {
-  a.hdr->entries = (int64_t)a.offsets[a.n];
-  a.hdr->capacity = a.capacity;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -799,10 +801,10 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     hipLaunchKernelGGL(rank_pass, dim3(gN), dim3(256), 0, s, a, skeys, svals);
     hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, skeys);
     hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, skeys);
-    if ((e = exclusive_scan_u64(a.ntiles_r, a.offsets, a.n, a.scan_state_offsets, &a.hdr->stalled, s)) != hipSuccess)
+    if ((e = exclusive_scan_u64(a.ntiles_r, a.offsets, a.n, a.scan_state_offsets, &a.hdr->stalled, s, a.heads,
+                                a.n_heads, 8)) != hipSuccess)
       return e;
     hipLaunchKernelGGL(emit_entries, dim3((unsigned)((a.capacity + 255) / 256)), dim3(256), 0, s, a, svals);
-    hipLaunchKernelGGL(finalize, dim3(1), dim3(1), 0, s, a);
     // stable sort of the entries by tile (entries beyond the capacity are never read)
     int ealt = 0;
     if ((e = radix_sort_pairs(a.ekeys, a.evals, a.ekeys_alt, a.evals_alt, a.capacity,

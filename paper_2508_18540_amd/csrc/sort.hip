@@ -145,7 +145,8 @@ __device__ T block_exclusive_scan(T v, T* sh, T* total) {
 template <bool PAIR>
 __global__ __launch_bounds__(kScanThreads) void scan_onepass(const uint64_t* in, uint64_t* out, const uint32_t* a,
                                                              uint32_t* oa, const uint32_t* b, uint32_t* ob,
-                                                             int64_t n, uint64_t* state, uint32_t* err) {
+                                                             int64_t n, uint64_t* state, uint32_t* err,
+                                                             uint32_t* heads, int64_t n_heads, int head_shift) {
   __shared__ uint64_t sh[kScanThreads];
   __shared__ uint64_t s_excl;
   const int tid = threadIdx.x;
@@ -195,6 +196,14 @@ __global__ __launch_bounds__(kScanThreads) void scan_onepass(const uint64_t* in,
         ob[e] = (uint32_t)(run >> 32);
       } else {
         out[e] = run;
+        if (heads && v[i] > 0) {
+          // the element holds the outputs [run, run + v): it heads every multiple of
+          // 2^head_shift among them
+          const uint64_t end = run + v[i];
+          for (uint64_t h = (run + ((1ull << head_shift) - 1)) >> head_shift;
+               (h << head_shift) < end && (int64_t)h < n_heads; ++h)
+            heads[h] = (uint32_t)e;
+        }
       }
     }
     run += v[i];
@@ -460,7 +469,7 @@ size_t scan_state_words(int64_t n) { return (size_t)((n + kScanChunk - 1) / kSca
 
 static hipError_t scan_launch(bool pair, const uint64_t* in, uint64_t* out, const uint32_t* a, uint32_t* oa,
                               const uint32_t* b, uint32_t* ob, int64_t n, uint64_t* state, uint32_t* err,
-                              hipStream_t s) {
+                              uint32_t* heads, int64_t n_heads, int head_shift, hipStream_t s) {
   if (n < 0 || !state || !err) return hipErrorInvalidValue;
   if (n == 0) {
     // totals only
@@ -476,21 +485,22 @@ static hipError_t scan_launch(bool pair, const uint64_t* in, uint64_t* out, cons
   if (nb > (1LL << 31)) return hipErrorInvalidValue;
   if (pair)
     hipLaunchKernelGGL(scan_onepass<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, nullptr, nullptr, a, oa, b,
-                       ob, n, state, err);
+                       ob, n, state, err, nullptr, (int64_t)0, 0);
   else
     hipLaunchKernelGGL(scan_onepass<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, nullptr, nullptr,
-                       nullptr, nullptr, n, state, err);
+                       nullptr, nullptr, n, state, err, heads, n_heads, head_shift);
   return hipGetLastError();
 }
 
 hipError_t exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* state, uint32_t* err,
-                              hipStream_t s) {
-  return scan_launch(false, in, out, nullptr, nullptr, nullptr, nullptr, n, state, err, s);
+                              hipStream_t s, uint32_t* heads, int64_t n_heads, int head_shift) {
+  if (heads && (head_shift < 0 || head_shift > 40)) return hipErrorInvalidValue;
+  return scan_launch(false, in, out, nullptr, nullptr, nullptr, nullptr, n, state, err, heads, n_heads, head_shift, s);
 }
 
 hipError_t exclusive_scan_pair_u32(const uint32_t* a, uint32_t* oa, const uint32_t* b, uint32_t* ob, int64_t n,
                                    uint64_t* state, uint32_t* err, hipStream_t s) {
-  return scan_launch(true, nullptr, nullptr, a, oa, b, ob, n, state, err, s);
+  return scan_launch(true, nullptr, nullptr, a, oa, b, ob, n, state, err, nullptr, 0, 0, s);
 }
 
 // ---- radix sort -----------------------------------------------------------------------

@@ -21,9 +21,11 @@ size_t scan_state_words(int64_t n);
 
 // out[0..n) = exclusive prefix sums of in[0..n), out[n] = total.  out holds n + 1 values;
 // `state` (scan_state_words(n) u64) must be zero on entry and is not reusable afterwards.
-// Sums must stay below 2^62.
+// Sums must stay below 2^62.  With `heads`, in[] are taken as lengths of consecutive
+// output segments, and heads[h] (h < n_heads, h 2^head_shift < total) receives the index
+// of the segment holding output h 2^head_shift (the one with a non-zero length).
 hipError_t exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* state, uint32_t* err,
-                              hipStream_t s);
+                              hipStream_t s, uint32_t* heads = nullptr, int64_t n_heads = 0, int head_shift = 0);
 
 // Two u32 scans in one pass (oa from a, ob from b, each with its total at [n]); the totals
 // of a must stay below 2^32 and those of b below 2^30.
