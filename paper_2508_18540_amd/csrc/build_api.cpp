@@ -69,8 +69,10 @@ BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t
   L.o_pcnt = take((size_t)(L.n_buckets + 1) * 4);
   L.o_item_start = take((size_t)(L.n_buckets + 1) * 4);
   L.o_pslot = take((size_t)(L.n_buckets + 1) * 4);
+
   L.o_items = take((size_t)L.max_items * 8);
   L.o_partial = take((size_t)L.max_partial * kTile * kTile * 16);
+  L.o_split = take((size_t)L.max_partial * 4);
   L.o_halo_rows = take((size_t)K * L.filt_bands * 2 * wp * 16);
   L.o_halo_cols = take((size_t)K * L.filt_segs * 2 * hp * 16);
   L.o_ggrad = take(kind == LF_VOXELS ? 0 : un * kGradSlots * 4);
@@ -188,6 +190,7 @@ void build_args(BuildArgs& a, const BuildLayout& L, const lf_field* field, const
   a.pcnt = reinterpret_cast<uint32_t*>(w + L.o_pcnt);
   a.item_start = reinterpret_cast<uint32_t*>(w + L.o_item_start);
   a.pslot = reinterpret_cast<uint32_t*>(w + L.o_pslot);
+  a.split = reinterpret_cast<uint32_t*>(w + L.o_split);
   a.items = reinterpret_cast<uint2*>(w + L.o_items);
   a.partial = reinterpret_cast<float4*>(w + L.o_partial);
   a.max_items = L.max_items;

@@ -220,6 +220,7 @@ __global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
 // in its low 28 bits and, in bits 28..31, which 8x8 quadrants of the tile its support box
 // touches (bit = 2 * qy + qx).
 constexpr int kEmitRanks = 512;
+constexpr int64_t kCombineGroups = 2048;
 constexpr int kKeyDigitBits = 8;    // key sort: four passes over a grid wide enough to fill the CUs
 constexpr int kTileDigitBits = 6;   // tile sort: two narrow passes write more coalesced runs than one wide one
 
@@ -339,6 +340,11 @@ __global__ void emit_items(BuildArgs a, int64_t n_buckets) {
   if (b >= n_buckets) return;
   const uint32_t i0 = a.item_start[b], ns = a.item_start[b + 1] - i0;
   for (uint32_t s = 0; s < ns; ++s) a.items[i0 + s] = make_uint2((uint32_t)b, s);
+  if (ns > 1) {
+    // the partial slots of a split bucket: the first names the bucket, the others nothing
+    const uint32_t p0 = a.pslot[b];
+    for (uint32_t s = 0; s < ns; ++s) a.split[p0 + s] = s ? 0xffffffffu : (uint32_t)b;
+  }
 }
 
 // Upper bound on log2(o G) over the texel rectangle u in [u0, u0 + 7], v in [v0, v0 + 7]
@@ -457,12 +463,9 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
   }
 }
 
-// Over-composite the segments of every split bucket (one work-group per bucket).
 template <typename PT>
-__global__ __launch_bounds__(256) void combine_segments(BuildArgs a) {
-  const int64_t bidx = blockIdx.x;
+__device__ void combine_bucket(const BuildArgs& a, int64_t bidx) {
   const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
-  if (nseg <= 1) return;
   const int tile = (int)(bidx / a.K), k = (int)(bidx % a.K);
   const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -478,6 +481,17 @@ __global__ __launch_bounds__(256) void combine_segments(BuildArgs a) {
   }
   if (px < a.c.wp && py < a.c.hp)
     store_rgba(static_cast<PT*>(a.planes), ((size_t)k * a.c.hp + py) * a.c.wp + px, C0, C1, C2, 1.0f - T);
+}
+
+// Over-composite the segments of every split bucket: work-groups stride over the partial
+// slots, and the first slot of each split bucket takes that bucket.
+template <typename PT>
+__global__ __launch_bounds__(256) void combine_segments(BuildArgs a, int64_t n_buckets) {
+  const uint32_t nslots = a.pslot[n_buckets];
+  for (uint32_t i = blockIdx.x; i < nslots; i += gridDim.x) {
+    const uint32_t b = a.split[i];
+    if (b != 0xffffffffu) combine_bucket<PT>(a, b);
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -836,11 +850,11 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
   }
   {
     PhaseScope ps(prof, LF_PHASE_MERGE, s);
-    const dim3 grid((unsigned)L.n_buckets);
+    const dim3 grid((unsigned)std::min<int64_t>(L.n_buckets, kCombineGroups));
     switch (a.plane_dtype) {
-      case LF_F16: hipLaunchKernelGGL((combine_segments<__half>), grid, dim3(256), 0, s, a); break;
-      case LF_BF16: hipLaunchKernelGGL((combine_segments<__hip_bfloat16>), grid, dim3(256), 0, s, a); break;
-      default: hipLaunchKernelGGL((combine_segments<float>), grid, dim3(256), 0, s, a); break;
+      case LF_F16: hipLaunchKernelGGL((combine_segments<__half>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+      case LF_BF16: hipLaunchKernelGGL((combine_segments<__hip_bfloat16>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+      default: hipLaunchKernelGGL((combine_segments<float>), grid, dim3(256), 0, s, a, L.n_buckets); break;
     }
   }
   if (a.kind == LF_VOXELS) {

@@ -51,7 +51,7 @@ struct BuildLayout {
   int32_t filt_bands, filt_segs;      // voxel low-pass regions (0 for Gaussians)
   size_t o_hdr, o_keys, o_vals, o_keys_alt, o_vals_alt, o_rec, o_ntiles_i, o_ntiles_r, o_chunk_r, o_offsets,
       o_sync, o_chunk_start, o_edges, o_dtab, o_nseg, o_bucket, o_radix, o_ekeys, o_evals, o_ekeys_alt, o_heads,
-      o_evals_alt, o_pcnt, o_item_start, o_pslot, o_items, o_partial, o_halo_rows, o_halo_cols, o_ggrad;
+      o_evals_alt, o_pcnt, o_item_start, o_pslot, o_split, o_items, o_partial, o_halo_rows, o_halo_cols, o_ggrad;
   int64_t max_items, max_partial;
   // zero-initialised synchronisation words after the header (digit totals of both sorts,
   // scan states); the build clears [o_hdr, o_hdr + 4 clear_words) first
@@ -101,6 +101,7 @@ struct BuildArgs {
   int64_t n_heads;
   // splat work items: bucket segments and their partial (C, T) tiles
   uint32_t *pcnt, *item_start, *pslot;
+  uint32_t* split;                    // per partial slot: its bucket if first of a split bucket, else ~0
   uint2* items;
   float4* partial;
   int64_t max_items;

@@ -24,8 +24,9 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Exclusive scan of one u32 per thread over a 256-thread work-group: wave scans by
-// shuffles, then the four wave totals (LDS scratch `wt`).  *total = the work-group's sum.
+// Exclusive scan of one u32 per thread over a work-group of NW waves: wave scans by
+// shuffles, then the wave totals (LDS scratch `wt`).  *total = the work-group's sum.
+template <int NW>
 __device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* wt, uint32_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = v;
@@ -38,7 +39,7 @@ __device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* wt, uin
   lds_barrier();
   uint32_t before = 0, sum = 0;
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
+  for (int w = 0; w < NW; ++w) {
     const uint32_t t = wt[w];
     before += w < wave ? t : 0u;
     sum += t;
@@ -226,11 +227,11 @@ __global__ __launch_bounds__(kScanThreads) void scan_onepass(const uint64_t* in,
 // of an element = (elements of smaller digits) + (elements of its digit in earlier spans,
 // from the look-back over per-(span, digit) status words) + (its rank in its own span).
 // ---------------------------------------------------------------------------------------
-constexpr int kRadixThreads = 256;
+constexpr int kRadixThreads = 512;
 constexpr int kWaves = kRadixThreads / 64;
 constexpr int kMaxPasses = 8;
 constexpr int kHistPerBlock = 4096;
-constexpr int kItems = 16;                          // elements per thread loaded together
+constexpr int kItems = 8;                           // elements per thread loaded together
 constexpr int kChunk = kItems * kRadixThreads;
 constexpr int kHistBlocksMax = 256;
 
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(kRadixThreads) void radix_onesweep(const uint32_t* 
       s += loc[i];
     }
     uint32_t total;
-    uint32_t run = block_scan_u32(s, wt, &total);
+    uint32_t run = block_scan_u32<kWaves>(s, wt, &total);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int d = tid * PER + i;
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(kRadixThreads) void radix_onesweep(const uint32_t* 
         s += c;
       }
       uint32_t tot;
-      uint32_t run = block_scan_u32(s, wt, &tot);
+      uint32_t run = block_scan_u32<kWaves>(s, wt, &tot);
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int d = tid * PER + q;
