@@ -220,7 +220,7 @@ __global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
 // in its low 28 bits and, in bits 28..31, which 8x8 quadrants of the tile its support box
 // touches (bit = 2 * qy + qx).
 constexpr int kEmitRanks = 512;
-constexpr int64_t kCombineGroups = 2048;
+constexpr int64_t kCombineGroups = 8192;
 constexpr int kKeyDigitBits = 8;    // key sort: four passes over a grid wide enough to fill the CUs
 constexpr int kTileDigitBits = 6;   // tile sort: two narrow passes write more coalesced runs than one wide one
 
@@ -472,12 +472,19 @@ __device__ void combine_bucket(const BuildArgs& a, int64_t bidx) {
   const int px = ox + ((wave & 1) << 3) + (lane & 7), py = oy + ((wave >> 1) << 3) + (lane >> 3);
   const float4* p = a.partial + (size_t)a.pslot[bidx] * (kTile * kTile) + ((py - oy) << kTileShift) + (px - ox);
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
-  for (uint32_t s = 0; s < nseg; ++s) {
-    const float4 v = p[(size_t)s * (kTile * kTile)];
-    C0 = fmaf(T, v.x, C0);
-    C1 = fmaf(T, v.y, C1);
-    C2 = fmaf(T, v.z, C2);
-    T = T * v.w;
+  for (uint32_t s0 = 0; s0 < nseg; s0 += 4) {
+    float4 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)                            // the loads in flight together
+      v[q] = s0 + q < nseg ? p[(size_t)(s0 + q) * (kTile * kTile)] : make_float4(0.f, 0.f, 0.f, 1.f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (s0 + q >= nseg) break;
+      C0 = fmaf(T, v[q].x, C0);
+      C1 = fmaf(T, v[q].y, C1);
+      C2 = fmaf(T, v[q].z, C2);
+      T = T * v[q].w;
+    }
   }
   if (px < a.c.wp && py < a.c.hp)
     store_rgba(static_cast<PT*>(a.planes), ((size_t)k * a.c.hp + py) * a.c.wp + px, C0, C1, C2, 1.0f - T);
@@ -850,7 +857,7 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
   }
   {
     PhaseScope ps(prof, LF_PHASE_MERGE, s);
-    const dim3 grid((unsigned)std::min<int64_t>(L.n_buckets, kCombineGroups));
+    const dim3 grid((unsigned)std::min<int64_t>(L.max_partial, kCombineGroups));
     switch (a.plane_dtype) {
       case LF_F16: hipLaunchKernelGGL((combine_segments<__half>), grid, dim3(256), 0, s, a, L.n_buckets); break;
       case LF_BF16: hipLaunchKernelGGL((combine_segments<__hip_bfloat16>), grid, dim3(256), 0, s, a, L.n_buckets); break;

@@ -505,10 +505,9 @@ hipError_t exclusive_scan_pair_u32(const uint32_t* a, uint32_t* oa, const uint32
 }
 
 // ---- radix sort -----------------------------------------------------------------------
-// About 4096 elements per work-group and at most 512 work-groups: every work-group of a
-// pass is resident at once (so a look-back only meets running or finished predecessors),
-// and the look-back traffic (digits x predecessors visited) stays small.  The status words
-// of one pass (2^digit_bits * work-groups) are kept to 2^18.
+// About 4096 elements per work-group and at most 512 work-groups, so the look-back
+// traffic (digits x predecessors visited) stays small; the status words of one pass
+// (2^digit_bits * work-groups) are kept to 2^18.
 constexpr int64_t kMaxStatus = 1 << 18;
 constexpr int64_t kSpanTarget = 4096;
 constexpr int64_t kMaxRadixBlocks = 512;
