@@ -29,6 +29,7 @@
 #include <type_traits>
 
 #include "lf_internal.h"
+#include "lds_sync.h"
 
 namespace lf {
 namespace {
@@ -632,7 +633,8 @@ __global__ __launch_bounds__(kBwdThreads) void composite_bwd(CompositeArgs a, co
 // atomics: pixel threads store them (with their texel index) in LDS and mark where each
 // view's run of equal texels starts (x -> texel is monotone), and texel threads add the runs
 // of all views, in a fixed order, before one global atomic per texel channel adds the
-// window into the plane gradient (windows of other rows and view groups overlap it).
+// window into the plane gradient (windows of other rows and view groups overlap it); the
+// atomics go one channel word per lane, so each instruction covers whole cache lines.
 // ---------------------------------------------------------------------------------------
 constexpr int kRowBwdThreads = 256;
 constexpr int kRowBwdWin = 512;
@@ -787,9 +789,9 @@ __global__ __launch_bounds__(kRowBwdThreads) void composite_rows_bwd(CompositeAr
       if (b.ok) {
         const size_t pbase = (size_t)k * plane_elems;
         if (!b.direct) {
-          __syncthreads();
+          lds_barrier();
           commit(b);
-          __syncthreads();
+          lds_barrier();
         }
         fetch(bn, k + 1);
         if (xin) {
@@ -831,10 +833,10 @@ __global__ __launch_bounds__(kRowBwdThreads) void composite_rows_bwd(CompositeAr
     }
     const size_t pbase = (size_t)k * plane_elems;
     if (!b.direct) {
-      __syncthreads();                                     // previous plane's gather is done
+      lds_barrier();                                     // previous plane's gather is done
       commit(b);
       for (int i = tid; i < G * b.len; i += kRowBwdThreads) first[i / b.len][i % b.len] = -1;
-      __syncthreads();
+      lds_barrier();
     }
     fetch(bnext, k - 1);
     #pragma unroll
@@ -884,7 +886,7 @@ __global__ __launch_bounds__(kRowBwdThreads) void composite_rows_bwd(CompositeAr
       }
     }
     if (!b.direct) {
-      __syncthreads();
+      lds_barrier();
       // texel threads: sum every view's runs (fixed order), then add the window to the plane
       for (int t = tid; t < b.len; t += kRowBwdThreads) {
         const int X = b.f0 + t;
@@ -911,15 +913,20 @@ __global__ __launch_bounds__(kRowBwdThreads) void composite_rows_bwd(CompositeAr
             }
           }
         }
-        const float a4[4] = {acc.x, acc.y, acc.z, acc.w};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (!BIL) {
-            add_row_grad(d_planes, a, k, b.iy, X, c, a4[c]);
-          } else {
-            add_row_grad(d_planes, a, k, b.iy, X, c, (1.0f - b.wy) * a4[c]);
-            add_row_grad(d_planes, a, k, b.iy + 1, X, c, b.wy * a4[c]);
-          }
+        val[t] = acc;                                      // (the samples have read val)
+      }
+      lds_barrier();
+      // add the window to the plane gradient one channel word per lane: consecutive lanes
+      // hit consecutive words, so an atomic instruction covers whole cache lines
+      const float* vw = reinterpret_cast<const float*>(val);
+      for (int w = tid; w < 4 * b.len; w += kRowBwdThreads) {
+        const int X = b.f0 + (w >> 2), c = w & 3;
+        const float v = vw[w];
+        if (!BIL) {
+          add_row_grad(d_planes, a, k, b.iy, X, c, v);
+        } else {
+          add_row_grad(d_planes, a, k, b.iy, X, c, (1.0f - b.wy) * v);
+          add_row_grad(d_planes, a, k, b.iy + 1, X, c, b.wy * v);
         }
       }
     }
@@ -1037,11 +1044,12 @@ hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, 
 template <typename PT>
 hipError_t launch_rows_bwd(const CompositeArgs& a, const float4* pt, const float* ct, const float* d_out,
                            float* d_planes, hipStream_t s) {
-  // views per work-group (8: two work-groups per CU fit the LDS); LF_BWD_GROUP overrides
-  int G = 8;
+  // views per work-group (4: few enough registers and LDS for four or five work-groups
+  // per CU, which hides the latency of the per-plane staging); LF_BWD_GROUP overrides
+  int G = 4;
   if (const char* e = getenv("LF_BWD_GROUP")) {
     const int g = atoi(e);
-    if (g == 8 || g == 16) G = g;
+    if (g == 4 || g == 8 || g == 16) G = g;
   }
   const dim3 grid((unsigned)a.ny, (unsigned)((a.n_views + G - 1) / G),
                   (unsigned)((a.nx + kRowBwdThreads - 1) / kRowBwdThreads));
@@ -1050,6 +1058,9 @@ hipError_t launch_rows_bwd(const CompositeArgs& a, const float4* pt, const float
   if (G == 16) {
     if (a.interp == LF_BILINEAR) hipLaunchKernelGGL((composite_rows_bwd<PT, 16, true>), grid, blk, 0, s, a, pt, ct, go, d_planes);
     else hipLaunchKernelGGL((composite_rows_bwd<PT, 16, false>), grid, blk, 0, s, a, pt, ct, go, d_planes);
+  } else if (G == 4) {
+    if (a.interp == LF_BILINEAR) hipLaunchKernelGGL((composite_rows_bwd<PT, 4, true>), grid, blk, 0, s, a, pt, ct, go, d_planes);
+    else hipLaunchKernelGGL((composite_rows_bwd<PT, 4, false>), grid, blk, 0, s, a, pt, ct, go, d_planes);
   } else {
     if (a.interp == LF_BILINEAR) hipLaunchKernelGGL((composite_rows_bwd<PT, 8, true>), grid, blk, 0, s, a, pt, ct, go, d_planes);
     else hipLaunchKernelGGL((composite_rows_bwd<PT, 8, false>), grid, blk, 0, s, a, pt, ct, go, d_planes);

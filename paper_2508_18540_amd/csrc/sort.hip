@@ -2,6 +2,7 @@
 // sort of (u32 key, u32 value) pairs, and a fill kernel.  Every launch has a host-fixed grid;
 // data dependent lengths are read from device memory, so nothing here waits on the host.
 #include "sort_internal.h"
+#include "lds_sync.h"
 
 namespace lf {
 namespace {
@@ -15,14 +16,6 @@ constexpr uint64_t kStAgg = 1ull << 62;   // the work-group's own aggregate
 constexpr uint64_t kStPre = 2ull << 62;   // inclusive prefix through the work-group
 constexpr uint64_t kStVal = kStAgg - 1;
 constexpr int kSpinLimit = 1 << 18;       // polls before a wait gives up (about 0.1-0.3 s)
-
-// Work-group barrier that orders LDS only: global stores still in flight (the scattered
-// outputs) do not have to complete first, as they do at __syncthreads().
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // Exclusive scan of one u32 per thread over a work-group of NW waves: wave scans by
 // shuffles, then the wave totals (LDS scratch `wt`).  *total = the work-group's sum.
