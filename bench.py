@@ -29,17 +29,18 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 
 # HBM traffic per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB
-# per dispatch) of `bench.py --steps 2 --warmup 1 --forms f32 --copy-calibration`, scaled by
-# what the same counters read for a plain 256 MiB device copy (FETCH_SIZE 131088 KiB,
-# WRITE_SIZE 262144 KiB): fetch x 2.0, write x 1.0.  Each entry records a digest of the
-# kernel's source text; when the kernel has changed since, the traffic is reported as null.
-COPY_FETCH_SCALE = 262144.0 / 131088.0
+# per dispatch) of `bench.py --steps 2 --warmup 1 --forms f32 --extra "" --copy-calibration`,
+# scaled by what the same counters read for a plain 256 MiB device copy (FETCH_SIZE
+# 131084 KiB, WRITE_SIZE 262144 KiB): fetch x 2.0, write x 1.0.  Each entry records a digest
+# of the kernel's source text; when the kernel has changed since, the traffic is reported as
+# null.
+COPY_FETCH_SCALE = 262144.0 / 131084.0
 COPY_WRITE_SCALE = 262144.0 / 262144.0
 MEASURED_TRAFFIC = {
-    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=146970, write_kib=286992,
-                     digest="d58eb10c8e858dce"),
-    "composite_rows": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=300919, write_kib=184320,
-                           digest="55e5949179a77c98"),
+    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133421, write_kib=286992,
+                     digest="a2a5b3574439f74c"),
+    "composite_rows": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=349989, write_kib=184320,
+                           digest="f0e7b90ef0537f83"),
 }
 
 
