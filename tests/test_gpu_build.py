@@ -200,6 +200,28 @@ def test_build_deterministic():
     assert torch.equal(a["rgba"], b["rgba"]) and torch.equal(a["depth"], b["depth"])
 
 
+@pytest.mark.parametrize("key_bits,tile_bits", [(4, 4), (11, 11), (7, 9)])
+def test_sort_digit_widths_agree(key_bits, tile_bits, monkeypatch):
+    """The depth sort and the tile sort are stable sorts of unique (key, index) orders, so any
+    digit width gives the same planes, bit for bit, as the default (8 / 6 bits).  4 bits: 8
+    depth passes of 16 digits and 3 tile passes (an odd count: result in the alternate
+    arrays); 11 bits: 3 depth passes of 2048 digits (several digits per thread) and 1 tile
+    pass of 1024 digits; 7 / 9 bits: a narrower last depth pass."""
+    announce("sort digit widths", key_bits, tile_bits)
+    scene = scenegen.cluster_scene(100_000, seed=8)
+    cam = scenegen.camera(384, 384, 50.0, 2.0, math.radians(40))
+    ref, info0, st0 = _gpu_build(scene, cam, 32)
+    assert st0 == L.LF_OK
+    monkeypatch.setenv("LF_KEY_DIGIT_BITS", str(key_bits))
+    monkeypatch.setenv("LF_TILE_DIGIT_BITS", str(tile_bits))
+    got, info, st = _gpu_build(scene, cam, 32)
+    assert st == L.LF_OK, L.lf_last_error()
+    assert info.entries_needed == info0.entries_needed and info.stalled == 0
+    torch.cuda.synchronize()
+    assert torch.equal(ref["chunk_of"], got["chunk_of"]) and torch.equal(ref["depth"], got["depth"])
+    assert torch.equal(ref["rgba"], got["rgba"])
+
+
 def test_empty_field():
     scene = {k: v[:0] for k, v in scenegen.small_scene(4, 0).items()}
     cam = scenegen.camera(32, 32, 50.0, 2.0, math.radians(20))
