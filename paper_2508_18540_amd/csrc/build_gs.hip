@@ -377,10 +377,9 @@ __device__ __forceinline__ float block_max_q(float ca, float cb, float cc, float
 
 template <typename PT>
 __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) {
-  __shared__ float2 s_rel[kSegment];                       // tile origin minus the mean (texels)
-  __shared__ float4 s_conic[kSegment];                     // (ca, cb, cc, l2o)
-  __shared__ float4 s_rgb[kSegment];
-  __shared__ uint16_t s_list[4][kSegment];                 // per quadrant: entries reaching it
+  // entry e: (tile origin minus the mean (texels), ca, cb), (cc, l2o, r, g), (b, -, -, -)
+  __shared__ float4 s_p[kSegment], s_q[kSegment], s_c[kSegment];
+  __shared__ uint32_t s_list[4][kSegment];                 // per quadrant: 16 e of the entries reaching it
   __shared__ int s_cnt[4][4];                              // [quadrant][loading wave]
   const uint32_t item = blockIdx.x;
   if (item >= a.item_start[n_buckets]) return;             // beyond this frame's work list
@@ -407,9 +406,9 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
     const uint32_t ent = a.evals[b0 + tid];
     const GRec& g = a.rec[min(ent & 0x0fffffffu, (uint32_t)a.n - 1u)];
     const float sx = ((float)ox - g.mx_hi) - g.mx_lo, sy = ((float)oy - g.my_hi) - g.my_lo;
-    s_rel[tid] = make_float2(sx, sy);
-    s_conic[tid] = make_float4(g.ca, g.cb, g.cc, g.l2o);
-    s_rgb[tid] = make_float4(g.rgb[0], g.rgb[1], g.rgb[2], 0.0f);
+    s_p[tid] = make_float4(sx, sy, g.ca, g.cb);
+    s_q[tid] = make_float4(g.cc, g.l2o, g.rgb[0], g.rgb[1]);
+    s_c[tid] = make_float4(g.rgb[2], 0.0f, 0.0f, 0.0f);
     const uint32_t box = ent >> 28;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -432,19 +431,21 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
   for (int q = 0; q < 4; ++q) {
     int off = 0;
     for (int w = 0; w < 4; ++w) off += w < wave ? s_cnt[q][w] : 0;
-    if ((qm >> q) & 1u) s_list[q][off + rank[q]] = (uint16_t)tid;
+    if ((qm >> q) & 1u) s_list[q][off + rank[q]] = (uint32_t)tid * 16u;   // byte offset: no index math below
     if (q == wave) my_count = s_cnt[q][0] + s_cnt[q][1] + s_cnt[q][2] + s_cnt[q][3];
   }
   __syncthreads();
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
   const int cnt = __builtin_amdgcn_readfirstlane(my_count);
   for (int i = 0; i < cnt; ++i) {
-    const int e = s_list[wave][i];
-    const float2 r = s_rel[e];
-    const float4 c = s_conic[e];
-    const float4 col = s_rgb[e];
-    const float dx = lx + r.x;
-    const float dy = ly + r.y;
+    const uint32_t e16 = s_list[wave][i];
+    const float4 P = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_p) + e16);
+    const float4 Q = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_q) + e16);
+    const float cb = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_c) + e16)->x;
+    const float4 c = make_float4(P.z, P.w, Q.x, Q.y);      // (ca, cb, cc, l2o)
+    const float4 col = make_float4(Q.z, Q.w, cb, 0.0f);
+    const float dx = lx + P.x;
+    const float dy = ly + P.y;
     const float q = fmaf(c.x * dx, dx, fmaf(c.z * dy, dy, fmaf(c.y * dx, dy, c.w)));
     // excluded texels get alpha 0 (a select, not a branch)
     const float alpha = q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f;
