@@ -347,6 +347,32 @@ __global__ void emit_items(BuildArgs a, int64_t n_buckets) {
   }
 }
 
+// log2(o G) about the centre of the tile with origin (ox, oy), as the splat and its backward
+// both evaluate it.  With (u, v) the centre minus the mean,
+//   q(u + du, v + dv) = A + B du + C dv + ca du^2 + cb du dv + cc dv^2   (exact algebra);
+// its float32 rounding is of the same size as that of evaluating at (u + du, v + dv)
+// directly, and it costs five FMAs per texel instead of eight operations.  (sx, sy) = tile
+// origin minus the mean, a double-float difference.
+struct TileTaylor {
+  float A, B, C, sx, sy;
+};
+
+__device__ __forceinline__ TileTaylor tile_taylor(const GRec& g, int ox, int oy) {
+  TileTaylor t;
+  t.sx = ((float)ox - g.mx_hi) - g.mx_lo;
+  t.sy = ((float)oy - g.my_hi) - g.my_lo;
+  const float uc = t.sx + 7.5f, vc = t.sy + 7.5f;
+  t.A = fmaf(g.ca * uc, uc, fmaf(g.cc * vc, vc, fmaf(g.cb * uc, vc, g.l2o)));
+  t.B = fmaf(2.0f * g.ca, uc, g.cb * vc);
+  t.C = fmaf(g.cb, uc, 2.0f * g.cc * vc);
+  return t;
+}
+
+__device__ __forceinline__ float taylor_q(float ca, float cb, float cc, float A, float B, float C, float du, float dv,
+                                          float duu, float duv, float dvv) {
+  return fmaf(ca, duu, fmaf(cb, duv, fmaf(cc, dvv, fmaf(B, du, fmaf(C, dv, A)))));
+}
+
 // Upper bound on log2(o G) over the texel rectangle u in [u0, u0 + 7], v in [v0, v0 + 7]
 // (offsets from the mean) of the concave form q(u, v) = ca u^2 + cb u v + cc v^2 + l2o: the
 // centre value if the centre lies inside, else the best point of the four edges (each a 1-D
@@ -373,6 +399,19 @@ __device__ __forceinline__ float block_max_q(float ca, float cb, float cc, float
     best = fmaxf(best, fmaf(1e-5f, mag, tu + tv + tx + l2o));
   }
   return best;
+}
+
+// The 8x8 quadrants of the tile (bit q = 2 qy + qx, among those of `box`) that the 1/255
+// ellipse of the Gaussian reaches; (sx, sy) = tile origin minus the mean.
+__device__ __forceinline__ uint32_t reached_quadrants(const GRec& g, uint32_t box, float sx, float sy) {
+  uint32_t qm = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (!((box >> q) & 1u)) continue;
+    const float u0 = (float)((q & 1) << 3) + sx, v0 = (float)((q >> 1) << 3) + sy;
+    if (block_max_q(g.ca, g.cb, g.cc, g.l2o, u0, v0) >= kLog2AlphaMin - 1e-2f) qm |= 1u << q;
+  }
+  return qm;
 }
 
 template <typename PT>
@@ -409,24 +448,12 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
   if (tid < n) {
     const uint32_t ent = a.evals[b0 + tid];
     const GRec& g = a.rec[min(ent & 0x0fffffffu, (uint32_t)a.n - 1u)];
-    const float sx = ((float)ox - g.mx_hi) - g.mx_lo, sy = ((float)oy - g.my_hi) - g.my_lo;
-    // Taylor form about the tile centre (u, v) = (sx + 7.5, sy + 7.5):
-    // q(u + du, v + dv) = A + B du + C dv + ca du^2 + cb du dv + cc dv^2 (exact algebra;
-    // its float32 rounding is of the same size as that of evaluating at (u + du, v + dv)
-    // directly, and it costs five FMAs per texel instead of eight operations)
-    const float uc = sx + 7.5f, vc = sy + 7.5f;
-    const float A = fmaf(g.ca * uc, uc, fmaf(g.cc * vc, vc, fmaf(g.cb * uc, vc, g.l2o)));
-    const float B = fmaf(2.0f * g.ca, uc, g.cb * vc), C = fmaf(g.cb, uc, 2.0f * g.cc * vc);
-    s_p[tid] = make_float4(g.ca, g.cb, g.cc, A);
-    s_q[tid] = make_float4(B, C, g.rgb[0], g.rgb[1]);
+    const TileTaylor tt = tile_taylor(g, ox, oy);
+    const float sx = tt.sx, sy = tt.sy;
+    s_p[tid] = make_float4(g.ca, g.cb, g.cc, tt.A);
+    s_q[tid] = make_float4(tt.B, tt.C, g.rgb[0], g.rgb[1]);
     s_c[tid] = make_float4(g.rgb[2], 0.0f, 0.0f, 0.0f);
-    const uint32_t box = ent >> 28;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (!((box >> q) & 1u)) continue;
-      const float u0 = (float)((q & 1) << 3) + sx, v0 = (float)((q >> 1) << 3) + sy;
-      if (block_max_q(g.ca, g.cb, g.cc, g.l2o, u0, v0) >= kLog2AlphaMin - 1e-2f) qm |= 1u << q;
-    }
+    qm = reached_quadrants(g, ent >> 28, sx, sy);
   }
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   uint32_t rank[4];
@@ -454,7 +481,7 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
     const float4 Q = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_q) + e16);
     const float cb = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_c) + e16)->x;
     const float4 col = make_float4(Q.z, Q.w, cb, 0.0f);
-    const float q = fmaf(P.x, duu, fmaf(P.y, duv, fmaf(P.z, dvv, fmaf(Q.x, du, fmaf(Q.y, dv, P.w)))));
+    const float q = taylor_q(P.x, P.y, P.z, P.w, Q.x, Q.y, du, dv, duu, duv, dvv);
     // excluded texels get alpha 0 (a select, not a branch)
     const float alpha = q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f;
     const float w = alpha * T;
@@ -521,9 +548,10 @@ __global__ __launch_bounds__(256) void combine_segments(BuildArgs a, int64_t n_b
 // other segments' forward partials (C_s, T_s).  Inside the segment T_i is recomputed: a
 // forward sweep stores T every 16 entries (LDS), then each block of 16 is swept forward
 // again into registers and walked backwards.  alpha = min(0.99, 2^q), q = l2o + ca dx^2 +
-// cb dx dy + cc dy^2, included iff q >= log2(1/255): d alpha/dq = alpha ln 2 where included
-// and not clamped.  Each wave reduces its 64 texels' contributions per Gaussian and adds
-// them to the Gaussian's accumulators.
+// cb dx dy + cc dy^2 (evaluated in the forward's Taylor form, so both take the same
+// decisions), included iff q >= log2(1/255): d alpha/dq = alpha ln 2 where included and not
+// clamped.  The segment's Gaussians are staged in LDS once.  Each wave reduces its 64
+// texels' contributions per Gaussian and adds them to the Gaussian's accumulators.
 // ---------------------------------------------------------------------------------------
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr int kBwdBlock = 16;
@@ -534,21 +562,11 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-struct Eval {
-  float alpha, q, dx, dy;
-};
-
-__device__ __forceinline__ Eval eval_gauss(const GRec& g, float pxf, float pyf) {
-  Eval r;
-  r.dx = (pxf - g.mx_hi) - g.mx_lo;
-  r.dy = (pyf - g.my_hi) - g.my_lo;
-  r.q = fmaf(g.ca * r.dx, r.dx, fmaf(g.cc * r.dy, r.dy, fmaf(g.cb * r.dx, r.dy, g.l2o)));
-  r.alpha = r.q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(r.q)) : 0.0f;
-  return r;
-}
-
 __global__ __launch_bounds__(256) void splat_bwd_gs(BuildArgs a, int64_t n_buckets) {
   __shared__ float ckpt[kSegment / kBwdBlock][256];
+  // entry e of the segment, staged once: (ca, cb, cc, A), (B, C, r, g), (b, sx, sy, entry
+  // bits: Gaussian index and quadrant mask); the same Taylor form the forward evaluated
+  __shared__ float4 s_p[kSegment], s_q[kSegment], s_c[kSegment];
   const uint32_t item = blockIdx.x;
   if (item >= a.item_start[n_buckets]) return;
   if (a.hdr->overflow) return;
@@ -558,13 +576,27 @@ __global__ __launch_bounds__(256) void splat_bwd_gs(BuildArgs a, int64_t n_bucke
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
-  const int px = ox + ((wave & 1) << 3) + (lane & 7), py = oy + ((wave >> 1) << 3) + (lane >> 3);
-  const float pxf = (float)px, pyf = (float)py;
+  const int lxi = ((wave & 1) << 3) + (lane & 7), lyi = ((wave >> 1) << 3) + (lane >> 3);
+  const int px = ox + lxi, py = oy + lyi;
+  const float lx = (float)lxi, ly = (float)lyi;
+  const float du = lx - 7.5f, dv = ly - 7.5f;
+  const float duu = du * du, duv = du * dv, dvv = dv * dv;
   const uint32_t* __restrict__ ev = a.evals;
-  const GRec* __restrict__ rec = a.rec;
   const uint32_t bb0 = a.bucket[bidx], bb1 = a.bucket[bidx + 1];
   const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
   const uint32_t b0 = bb0 + it.y * kSegment, b1 = min(bb1, b0 + kSegment);
+  const int n = (int)(b1 - b0);
+  if (tid < n) {
+    const uint32_t ent = ev[b0 + tid];
+    const uint32_t idx = min(ent & 0x0fffffffu, (uint32_t)a.n - 1u);
+    const GRec& g = a.rec[idx];
+    const TileTaylor tt = tile_taylor(g, ox, oy);
+    s_p[tid] = make_float4(g.ca, g.cb, g.cc, tt.A);
+    s_q[tid] = make_float4(tt.B, tt.C, g.rgb[0], g.rgb[1]);
+    // the quadrants the forward evaluated
+    const uint32_t qm = reached_quadrants(g, ent >> 28, tt.sx, tt.sy) << 28;
+    s_c[tid] = make_float4(g.rgb[2], tt.sx, tt.sy, __uint_as_float(idx | qm));
+  }
   const bool in_plane = px < a.c.wp && py < a.c.hp;
   float4 gp = make_float4(0.f, 0.f, 0.f, 0.f);
   if (in_plane) gp = reinterpret_cast<const float4*>(a.d_planes)[((size_t)k * a.c.hp + py) * a.c.wp + px];
@@ -581,69 +613,76 @@ __global__ __launch_bounds__(256) void splat_bwd_gs(BuildArgs a, int64_t n_bucke
       Sf *= p.w;
     }
   }
+  __syncthreads();
   const uint32_t qbit = 1u << (28 + wave);
+  // entry bits (uniform over the work-group)
+  auto bits_of = [&](int e) { return __builtin_amdgcn_readfirstlane(__float_as_uint(s_c[e].w)); };
+  auto q_of = [&](int e) {
+    const float4 P = s_p[e];
+    const float4 Q = s_q[e];
+    return taylor_q(P.x, P.y, P.z, P.w, Q.x, Q.y, du, dv, duu, duv, dvv);
+  };
+  auto alpha_of = [](float q) { return q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f; };
   // forward sweep: T (within the segment) at the start of every block of kBwdBlock entries
   float T = 1.0f;
-  for (uint32_t e = b0; e < b1; ++e) {
-    if (((e - b0) & (kBwdBlock - 1)) == 0) ckpt[(e - b0) / kBwdBlock][tid] = T;
-    const uint32_t ent = ev[e];
-    if (!(ent & qbit)) continue;
-    const Eval r = eval_gauss(rec[min(ent & 0x0fffffffu, (uint32_t)a.n - 1u)], pxf, pyf);
-    T = T - r.alpha * T;
+  for (int e = 0; e < n; ++e) {
+    if ((e & (kBwdBlock - 1)) == 0) ckpt[e / kBwdBlock][tid] = T;
+    if (!(bits_of(e) & qbit)) continue;
+    T = T - alpha_of(q_of(e)) * T;
   }
-  const int nblk = (int)((b1 - b0 + kBwdBlock - 1) / kBwdBlock);
+  const int nblk = (n + kBwdBlock - 1) / kBwdBlock;
   for (int blk = nblk - 1; blk >= 0; --blk) {
-    const uint32_t e0 = b0 + (uint32_t)blk * kBwdBlock;
+    const int e0 = blk * kBwdBlock;
     float Tv[kBwdBlock];
     float Tb = ckpt[blk][tid];
 #pragma unroll
     for (int j = 0; j < kBwdBlock; ++j) {
       Tv[j] = Tb;
-      const uint32_t e = e0 + j;
-      if (e < b1) {
-        const uint32_t ent = ev[e];
-        if (ent & qbit) {
-          const Eval r = eval_gauss(rec[min(ent & 0x0fffffffu, (uint32_t)a.n - 1u)], pxf, pyf);
-          Tb = Tb - r.alpha * Tb;
-        }
-      }
+      const int e = e0 + j;
+      if (e < n && (bits_of(e) & qbit)) Tb = Tb - alpha_of(q_of(e)) * Tb;
     }
 #pragma unroll
     for (int j = kBwdBlock - 1; j >= 0; --j) {
-      const uint32_t e = e0 + j;
-      if (e >= b1) continue;
-      const uint32_t ent = ev[e];
-      if (!(ent & qbit)) continue;                          // scalar: the box misses this quadrant
-      const uint32_t idx = min(ent & 0x0fffffffu, (uint32_t)a.n - 1u);
-      const GRec& g = rec[idx];
-      const Eval r = eval_gauss(g, pxf, pyf);
+      const int e = e0 + j;
+      if (e >= n) continue;
+      const uint32_t bits = bits_of(e);
+      if (!(bits & qbit)) continue;                         // the Gaussian misses this quadrant
+      const uint32_t idx = bits & 0x0fffffffu;
+      const float4 P = s_p[e];
+      const float4 Q = s_q[e];
+      const float4 Cc = s_c[e];
+      const float ca = P.x, cb = P.y, cc = P.z;
+      const float cr = Q.z, cg = Q.w, cbl = Cc.x;
+      const float q = taylor_q(ca, cb, cc, P.w, Q.x, Q.y, du, dv, duu, duv, dvv);
+      const float alpha = alpha_of(q);
+      const float dx = lx + Cc.y, dy = ly + Cc.z;           // texel minus the mean
       const float W = Tin * Tv[j];
-      const float gal = W * ((gp.x * (g.rgb[0] - Rr) + gp.y * (g.rgb[1] - Rg) + gp.z * (g.rgb[2] - Rb)) + gp.w * Sf);
-      const float wa = W * r.alpha;
-      const float om = 1.0f - r.alpha;
-      Rr = fmaf(om, Rr, r.alpha * g.rgb[0]);
-      Rg = fmaf(om, Rg, r.alpha * g.rgb[1]);
-      Rb = fmaf(om, Rb, r.alpha * g.rgb[2]);
+      const float gal = W * ((gp.x * (cr - Rr) + gp.y * (cg - Rg) + gp.z * (cbl - Rb)) + gp.w * Sf);
+      const float wa = W * alpha;
+      const float om = 1.0f - alpha;
+      Rr = fmaf(om, Rr, alpha * cr);
+      Rg = fmaf(om, Rg, alpha * cg);
+      Rb = fmaf(om, Rb, alpha * cbl);
       Sf = om * Sf;
-      const bool smooth = r.q >= kLog2AlphaMin && __builtin_amdgcn_exp2f(r.q) < kAlphaMax;
-      const float gq = smooth ? gal * r.alpha * kLn2 : 0.0f;
+      const bool smooth = q >= kLog2AlphaMin && __builtin_amdgcn_exp2f(q) < kAlphaMax;
+      const float gq = smooth ? gal * alpha * kLn2 : 0.0f;
       float v[kGradSlots];
-      v[0] = gq * r.dx * r.dx;
-      v[1] = gq * r.dx * r.dy;
-      v[2] = gq * r.dy * r.dy;
-      v[3] = -gq * fmaf(2.0f * g.ca, r.dx, g.cb * r.dy);
-      v[4] = -gq * fmaf(2.0f * g.cc, r.dy, g.cb * r.dx);
+      v[0] = gq * dx * dx;
+      v[1] = gq * dx * dy;
+      v[2] = gq * dy * dy;
+      v[3] = -gq * fmaf(2.0f * ca, dx, cb * dy);
+      v[4] = -gq * fmaf(2.0f * cc, dy, cb * dx);
       v[5] = gq;
       v[6] = wa * gp.x;
       v[7] = wa * gp.y;
       v[8] = wa * gp.z;
 #pragma unroll
-      for (int q = 0; q < kGradSlots; ++q) v[q] = wave_sum(v[q]);
+      for (int s = 0; s < kGradSlots; ++s) v[s] = wave_sum(v[s]);
       if (lane == 0) {
         float* dst = a.ggrad + (size_t)idx * kGradSlots;
 #pragma unroll
-        for (int q = 0; q < kGradSlots; ++q)
-          if (v[q] != 0.0f) atomicAdd(dst + q, v[q]);
+        for (int s = 0; s < kGradSlots; ++s)
+          if (v[s] != 0.0f) atomicAdd(dst + s, v[s]);
       }
     }
   }
