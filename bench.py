@@ -8,8 +8,8 @@ lf_build_mpi (cull, key, depth sort, chunking, tile binning, splat into planes) 
 by lf_composite (swizzle blending of all 45 views).  Inputs are seeded synthetic scenes
 (scenegen) resident in HBM before timing starts.
 
-The JSON line reports views/s of the FP32-plane form as ``value`` and the FP16-plane form
-beside it, the roofline of the dominant kernel and of the composite, per-phase kernel
+The JSON line reports views/s of the FP32-plane form as ``value`` and the FP16- and
+UNORM8-plane forms beside it, the roofline of the dominant kernel and of the composite, per-phase kernel
 times measured with HIP events on the launch stream, and the FP64 CPU oracle's rate on
 a bounded sample of the same frame.
 """
@@ -76,7 +76,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-planes", type=int, default=48, help="planes the CPU oracle rasterises")
     p.add_argument("--cpu-views", type=int, default=6, help="views the CPU oracle composites")
-    p.add_argument("--forms", default="f32,f16", help="plane storage forms to time (first one is `value`)")
+    p.add_argument("--forms", default="f32,f16,u8", help="plane storage forms to time (first one is `value`)")
     p.add_argument("--extra", default="voxel256,grad200k,batch8",
                    help="further workloads timed into the same line (voxel256, grad200k, batch8; empty for none)")
     p.add_argument("--extra-steps", type=int, default=5)
@@ -276,7 +276,7 @@ def main():
         ws = T.workspace_for(ds, cam, K, entry_capacity=int(info.entries_needed * 1.25), device=dev)
 
     def one_form(form):
-        pdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[form]
+        pdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16, "u8": torch.uint8}[form]
         out = T.build_mpi(ctx, ds, cam, K, dtype=pdt, workspace=ws)
         img = torch.empty((V, cam.ny, cam.nx, 4), dtype=torch.float32, device=dev)
 
@@ -300,7 +300,7 @@ def main():
         info, st = T.build_stats(ctx, ws, check=True)
         ms = (t1 - t0) * 1e3 / args.steps
         phases = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}
-        pb = {"f32": 16, "f16": 8, "bf16": 8}[form]
+        pb = {"f32": 16, "f16": 8, "bf16": 8, "u8": 4}[form]
         comp_bytes = K * geo.plane_height * geo.plane_width * pb + V * cam.ny * cam.nx * 16
         comp_ms = phases["composite"]
         comp_roof = dict(bound="hbm", achieved=round(comp_bytes / (comp_ms * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS,

@@ -43,7 +43,10 @@ typedef enum {
   LF_ERR_HIP = 5            /* a HIP runtime call failed (also deferred async errors)  */
 } lf_status;
 
-typedef enum { LF_F32 = 0, LF_F16 = 1, LF_BF16 = 2 } lf_dtype;
+/* LF_U8 (planes only): UNORM8, the default plane format of Sec. 5.1 (8-bit C and T):    
+ * code = round-to-nearest-even(255 v) of the float32 value v clamped to [0, 1], read back
+ * as code / 255.                                                                          */
+typedef enum { LF_F32 = 0, LF_F16 = 1, LF_BF16 = 2, LF_U8 = 3 } lf_dtype;
 typedef enum { LF_NEAREST = 0, LF_BILINEAR = 1 } lf_interp;
 typedef enum { LF_BIN_QUANTILE = 0, LF_BIN_INV_DEPTH = 1 } lf_binning;
 typedef enum { LF_GAUSSIANS = 0, LF_VOXELS = 1 } lf_field_kind;
@@ -163,7 +166,7 @@ lf_status lf_build_mpi_workspace(const lf_field* field, const lf_camera* cam, in
  * Sec. 4.4 (Gaussians) / Sec. 4.5 (voxels, followed by the in-place plane low-pass).
  * binning: LF_BIN_QUANTILE (Sec. 4.4) or LF_BIN_INV_DEPTH with inv_depth_range = {z_lo,
  * z_hi} (host, z_lo > D_forward).  `mpi` describes caller-allocated outputs whose
- * n_chunk/width/height must match the camera; dtype may be F32, F16 or BF16.
+ * n_chunk/width/height must match the camera; dtype may be F32, F16, BF16 or U8.
  * Enqueued on `stream` with no host synchronisation; if the workspace's entry capacity
  * is exceeded the planes are invalid and lf_build_stats reports it.                    */
 lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
@@ -188,8 +191,9 @@ lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, con
  * sampling held fixed): given d_out = dL/d(Q_r, Q_g, Q_b, T) (device float32
  * [n_views][ny][nx][4]), writes d_planes = dL/d(C_r, C_g, C_b, A) (device float32
  * [n_chunk][height][width][4]; zero-filled by the callee, then accumulated).  The planes
- * of `mpi` are read in their own dtype; per-pixel transmittance is recomputed, not
- * stored.  Arguments as lf_composite.                                                     */
+ * of `mpi` are read in their own dtype (U8 planes: LF_ERR_UNSUPPORTED, the quantisation
+ * has no gradient); per-pixel transmittance is recomputed, not stored.  Arguments as
+ * lf_composite.                                                                           */
 lf_status lf_composite_backward(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
                                 int32_t n_views, int32_t interp, const float* d_out, float* d_planes,
                                 void* stream);

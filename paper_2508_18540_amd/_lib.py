@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LF_LIBRARY") or os.path.join(HERE, "liblf.so")   # LF_LIBRARY: another build
 
 LF_OK, LF_ERR_INVALID_ARG, LF_ERR_UNSUPPORTED, LF_ERR_CAPACITY, LF_ERR_OUT_OF_MEMORY, LF_ERR_HIP = range(6)
-LF_F32, LF_F16, LF_BF16 = 0, 1, 2
+LF_F32, LF_F16, LF_BF16, LF_U8 = 0, 1, 2, 3
 LF_NEAREST, LF_BILINEAR = 0, 1
 LF_BIN_QUANTILE, LF_BIN_INV_DEPTH = 0, 1
 LF_GAUSSIANS, LF_VOXELS = 0, 1

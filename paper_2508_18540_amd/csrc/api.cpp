@@ -8,11 +8,11 @@
 namespace lf {
 namespace {
 
-bool dtype_ok(int32_t d) { return d == LF_F32 || d == LF_F16 || d == LF_BF16; }
+bool dtype_ok(int32_t d) { return d == LF_F32 || d == LF_F16 || d == LF_BF16 || d == LF_U8; }
 
 lf_status check_mpi(const lf_mpi* mpi, const Geom& g) {
   if (!mpi) return fail(LF_ERR_INVALID_ARG, "mpi is NULL");
-  if (!dtype_ok(mpi->dtype)) return fail(LF_ERR_INVALID_ARG, "mpi dtype %d is not F32/F16/BF16", mpi->dtype);
+  if (!dtype_ok(mpi->dtype)) return fail(LF_ERR_INVALID_ARG, "mpi dtype %d is not F32/F16/BF16/U8", mpi->dtype);
   if (mpi->n_chunk < 1 || mpi->n_chunk > LF_MAX_CHUNKS)
     return fail(LF_ERR_INVALID_ARG, "n_chunk %d outside [1, %d]", mpi->n_chunk, LF_MAX_CHUNKS);
   if (mpi->width != g.wp || mpi->height != g.hp)
@@ -223,6 +223,8 @@ extern "C" lf_status lf_composite_backward(lf_ctx* ctx, const lf_mpi* mpi, const
   lf_status s = composite_args(mpi, cam, views, n_views, a);
   if (s == LF_OK && interp != LF_NEAREST && interp != LF_BILINEAR)
     s = fail(LF_ERR_INVALID_ARG, "interp %d is not NEAREST/BILINEAR", interp);
+  if (s == LF_OK && a->plane_dtype == LF_U8)
+    s = fail(LF_ERR_UNSUPPORTED, "UNORM8 planes have no composite backward (the quantisation has no gradient)");
   if (s == LF_OK && !d_out) s = fail(LF_ERR_INVALID_ARG, "d_out is NULL");
   if (s == LF_OK && !d_planes) s = fail(LF_ERR_INVALID_ARG, "d_planes is NULL");
   if (s == LF_OK) s = check_ctx(ctx);

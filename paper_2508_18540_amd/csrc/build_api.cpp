@@ -252,8 +252,8 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
       return fail(LF_ERR_INVALID_ARG, "inverse-depth range must satisfy D_forward < z_lo < z_hi < inf");
   }
   if (!mpi) return fail(LF_ERR_INVALID_ARG, "mpi is NULL");
-  if (mpi->dtype != LF_F32 && mpi->dtype != LF_F16 && mpi->dtype != LF_BF16)
-    return fail(LF_ERR_INVALID_ARG, "mpi dtype %d is not F32/F16/BF16", mpi->dtype);
+  if (mpi->dtype != LF_F32 && mpi->dtype != LF_F16 && mpi->dtype != LF_BF16 && mpi->dtype != LF_U8)
+    return fail(LF_ERR_INVALID_ARG, "mpi dtype %d is not F32/F16/BF16/U8", mpi->dtype);
   if (mpi->n_chunk != n_chunk) return fail(LF_ERR_INVALID_ARG, "mpi n_chunk %d != %d", mpi->n_chunk, n_chunk);
   if (mpi->width != g.wp || mpi->height != g.hp)
     return fail(LF_ERR_INVALID_ARG, "mpi is %dx%d but the camera's planes are %dx%d", mpi->width, mpi->height, g.wp,

@@ -76,7 +76,20 @@ __device__ __forceinline__ void store_rgba<__hip_bfloat16>(__hip_bfloat16* p, si
   reinterpret_cast<uint2*>(p)[i] = u;
 }
 
-// Texel load of a plane in its storage type, widened to float32 exactly.
+// UNORM8 code of a float32 value: round-to-nearest-even of 255 v, v clamped to [0, 1]
+// (NaN -> 0).
+__device__ __forceinline__ uint32_t unorm8_rn(float v) {
+  const float c = fminf(fmaxf(v, 0.0f), 1.0f);
+  return (uint32_t)__builtin_rintf(c * 255.0f);
+}
+
+template <>
+__device__ __forceinline__ void store_rgba<uint8_t>(uint8_t* p, size_t i, float r, float g, float b, float al) {
+  reinterpret_cast<uint32_t*>(p)[i] = unorm8_rn(r) | (unorm8_rn(g) << 8) | (unorm8_rn(b) << 16) | (unorm8_rn(al) << 24);
+}
+
+// Texel load of a plane in its storage type, widened to float32 (exactly; UNORM8 as
+// code / 255 to float32 rounding).
 template <typename T>
 __device__ __forceinline__ float4 load_rgba(const T* p, size_t i);
 
@@ -98,6 +111,14 @@ __device__ __forceinline__ float4 load_rgba<__hip_bfloat16>(const __hip_bfloat16
   const uint2 u = reinterpret_cast<const uint2*>(p)[i];
   return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
                      __uint_as_float(u.y & 0xffff0000u));
+}
+
+template <>
+__device__ __forceinline__ float4 load_rgba<uint8_t>(const uint8_t* p, size_t i) {
+  const uint32_t u = reinterpret_cast<const uint32_t*>(p)[i];
+  constexpr float s = 1.0f / 255.0f;
+  return make_float4((float)(u & 0xffu) * s, (float)((u >> 8) & 0xffu) * s, (float)((u >> 16) & 0xffu) * s,
+                     (float)(u >> 24) * s);
 }
 
 }  // namespace lf

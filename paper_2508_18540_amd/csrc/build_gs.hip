@@ -900,6 +900,7 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     } else switch (a.plane_dtype) {
       case LF_F16: hipLaunchKernelGGL((splat_gs<__half>), grid, dim3(256), 0, s, a, L.n_buckets); break;
       case LF_BF16: hipLaunchKernelGGL((splat_gs<__hip_bfloat16>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+      case LF_U8: hipLaunchKernelGGL((splat_gs<uint8_t>), grid, dim3(256), 0, s, a, L.n_buckets); break;
       default: hipLaunchKernelGGL((splat_gs<float>), grid, dim3(256), 0, s, a, L.n_buckets); break;
     }
   }
@@ -909,6 +910,7 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     switch (a.plane_dtype) {
       case LF_F16: hipLaunchKernelGGL((combine_segments<__half>), grid, dim3(256), 0, s, a, L.n_buckets); break;
       case LF_BF16: hipLaunchKernelGGL((combine_segments<__hip_bfloat16>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+      case LF_U8: hipLaunchKernelGGL((combine_segments<uint8_t>), grid, dim3(256), 0, s, a, L.n_buckets); break;
       default: hipLaunchKernelGGL((combine_segments<float>), grid, dim3(256), 0, s, a, L.n_buckets); break;
     }
   }

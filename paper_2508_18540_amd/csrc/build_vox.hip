@@ -261,6 +261,7 @@ hipError_t launch_splat_vox(const BuildArgs& a, const BuildLayout& L, hipStream_
   switch (a.plane_dtype) {
     case LF_F16: hipLaunchKernelGGL((splat_vox<__half>), grid, dim3(256), 0, s, a, L.n_buckets); break;
     case LF_BF16: hipLaunchKernelGGL((splat_vox<__hip_bfloat16>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+    case LF_U8: hipLaunchKernelGGL((splat_vox<uint8_t>), grid, dim3(256), 0, s, a, L.n_buckets); break;
     default: hipLaunchKernelGGL((splat_vox<float>), grid, dim3(256), 0, s, a, L.n_buckets); break;
   }
   return hipGetLastError();
@@ -271,6 +272,7 @@ hipError_t launch_lowpass(const BuildArgs& a, hipStream_t s) {
   switch (a.plane_dtype) {
     case LF_F16: return lowpass_typed<__half>(a, s);
     case LF_BF16: return lowpass_typed<__hip_bfloat16>(a, s);
+    case LF_U8: return lowpass_typed<uint8_t>(a, s);
     default: return lowpass_typed<float>(a, s);
   }
 }

@@ -71,6 +71,15 @@ __device__ __forceinline__ float4 load_texel<__hip_bfloat16>(const __hip_bfloat1
                      __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
 }
 
+template <>
+__device__ __forceinline__ float4 load_texel<uint8_t>(const uint8_t* p, size_t i) {
+  // UNORM8: code / 255 (to float32 rounding)
+  const uint32_t u = reinterpret_cast<const uint32_t*>(p)[i];
+  constexpr float s = 1.0f / 255.0f;
+  return make_float4((float)(u & 0xffu) * s, (float)((u >> 8) & 0xffu) * s, (float)((u >> 16) & 0xffu) * s,
+                     (float)(u >> 24) * s);
+}
+
 template <typename T>
 __device__ __forceinline__ void store_pixel(T* out, size_t i, float r, float g, float b, float t);
 
@@ -96,6 +105,15 @@ __device__ __forceinline__ float4 keep_if(bool ok, float4 a) {
 }
 
 __device__ __forceinline__ uint2 keep_if(bool ok, uint2 a) { return make_uint2(ok ? a.x : 0u, ok ? a.y : 0u); }
+
+__device__ __forceinline__ uint32_t keep_if(bool ok, uint32_t a) { return ok ? a : 0u; }
+
+// Four UNORM8 codes as four FP16 numbers 0..255 (exact).
+__device__ __forceinline__ uint2 codes_to_half4(uint32_t u) {
+  const __half2 lo = __floats2half2_rn((float)(u & 0xffu), (float)((u >> 8) & 0xffu));
+  const __half2 hi = __floats2half2_rn((float)((u >> 16) & 0xffu), (float)(u >> 24));
+  return make_uint2(*reinterpret_cast<const uint32_t*>(&lo), *reinterpret_cast<const uint32_t*>(&hi));
+}
 
 __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
   return make_float4(fmaf(w, b.x - a.x, a.x), fmaf(w, b.y - a.y, a.y), fmaf(w, b.z - a.z, a.z),
@@ -158,9 +176,12 @@ __device__ __forceinline__ int cvt_flr(float x) {
   return r;
 }
 
-// LDS texel of the nearest window: FP16 planes stay FP16 (8 bytes), others are float32.
+// LDS texel of the nearest window: FP16 planes stay FP16 (8 bytes), UNORM8 planes become
+// their codes as FP16 (exact: 0..255; the blend scales by 1/255), others are float32.  FP16
+// texels let the blend use mixed-precision FMAs (no conversion instructions).
 template <typename PT> struct LdsTexel { using type = float4; };
 template <> struct LdsTexel<__half> { using type = uint2; };
+template <> struct LdsTexel<uint8_t> { using type = uint2; };
 
 template <typename LT>
 __device__ __forceinline__ float4 lds_texel(const char* p);
@@ -204,7 +225,9 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
                                                               const float4* __restrict__ pt,
                                                               const float* __restrict__ ct) {
   using LT = typename std::conditional<BIL, float4, typename LdsTexel<PT>::type>::type;
-  constexpr bool RAW = std::is_same<LT, uint2>::value;     // FP16 texels copied unconverted
+  constexpr bool RAW = !std::is_same<LT, float4>::value;   // FP16 texels in LDS (FP16 / UNORM8 planes)
+  constexpr bool U8 = RAW && std::is_same<PT, uint8_t>::value;   // samples are codes: scale by 1/255
+  using RT = typename std::conditional<U8, uint32_t, uint2>::type;   // raw texel as fetched
   constexpr int PF = BIL ? kPrefetch / 2 : kPrefetch;
   extern __shared__ float4 win[];                          // 2 buffers of kWin float4
   __shared__ PlaneInfo pinfo[kBatch];
@@ -298,7 +321,7 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
     // clamped (always valid) addresses and no branches, so the loads stay in flight while the
     // current plane is sampled; store() masks the out-of-plane texels to zero and writes LDS.
     float4 ra[RAW ? 1 : PF], rb[BIL ? PF : 1], rc[BIL ? PF : 1], rd[BIL ? PF : 1];
-    uint2 praw[RAW ? PF : 1];
+    RT praw[RAW ? PF : 1];
     uint32_t valid = 0;                                    // bit (q * 4 + r): raw texel in the plane
     auto fetch = [&](int k) {
       const PlaneInfo pi = pinfo[k];
@@ -313,7 +336,7 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
         if constexpr (!BIL) {
           const bool ok = in && ix >= 0 && ix < wp;
           const size_t at = pbase + (size_t)pi.iy * wp + (size_t)min(max(ix, 0), wp - 1);
-          if constexpr (RAW) praw[q] = load_raw_half4(planes, at);
+          if constexpr (RAW) praw[q] = reinterpret_cast<const RT*>(planes)[at];
           else ra[q] = load_texel(planes, at);
           valid |= (ok ? 1u : 0u) << (q * 4);
         } else {
@@ -342,7 +365,8 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
         const int i = i0 < pi.len ? i0 : (BIL ? kWin / 2 : kWin);
         const uint32_t m = valid >> (q * 4);
         if constexpr (RAW) {
-          reinterpret_cast<uint2*>(w)[i] = keep_if((m & 1u) != 0u, praw[q]);
+          if constexpr (U8) reinterpret_cast<uint2*>(w)[i] = codes_to_half4(keep_if((m & 1u) != 0u, praw[q]));
+          else reinterpret_cast<uint2*>(w)[i] = keep_if((m & 1u) != 0u, praw[q]);
         } else if constexpr (!BIL) {
           w[i] = keep_if((m & 1u) != 0u, ra[q]);
         } else {
@@ -395,10 +419,11 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
 #pragma unroll
           for (int jj = 0; jj < kSub; ++jj) {
             const int j = j0 + jj;
-            Qr[j] = fmaf(Tr[j], sv[jj].x, Qr[j]);
-            Qg[j] = fmaf(Tr[j], sv[jj].y, Qg[j]);
-            Qb[j] = fmaf(Tr[j], sv[jj].z, Qb[j]);
-            Tr[j] = fmaf(-Tr[j], sv[jj].w, Tr[j]);
+            const float w = U8 ? Tr[j] * (1.0f / 255.0f) : Tr[j];
+            Qr[j] = fmaf(w, sv[jj].x, Qr[j]);
+            Qg[j] = fmaf(w, sv[jj].y, Qg[j]);
+            Qb[j] = fmaf(w, sv[jj].z, Qb[j]);
+            Tr[j] = fmaf(-w, sv[jj].w, Tr[j]);
           }
           // blend this sub-block before the next one's LDS reads are issued: bounds the
           // live sample registers (occupancy) instead of holding all G samples at once
@@ -1037,6 +1062,7 @@ hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, 
   switch (a.plane_dtype) {
     case LF_F16: return dispatch_out<__half>(a, rows, G, pt, ct, s);
     case LF_BF16: return dispatch_out<__hip_bfloat16>(a, rows, G, pt, ct, s);
+    case LF_U8: return dispatch_out<uint8_t>(a, rows, G, pt, ct, s);
     default: return dispatch_out<float>(a, rows, G, pt, ct, s);
   }
 }

@@ -6,7 +6,7 @@ import torch
 
 from . import _lib as L
 
-_DT = {torch.float32: L.LF_F32, torch.float16: L.LF_F16, torch.bfloat16: L.LF_BF16}
+_DT = {torch.float32: L.LF_F32, torch.float16: L.LF_F16, torch.bfloat16: L.LF_BF16, torch.uint8: L.LF_U8}
 _INTERP = {"nearest": L.LF_NEAREST, "bilinear": L.LF_BILINEAR}
 
 

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import scenegen
-from oracle import composite, geometry, partition, project, render, splat
+from oracle import composite, geometry, partition, project, quantize, render, splat
 from paper_2508_18540_amd import _lib as L
 from paper_2508_18540_amd import torch_api as T
 from tests.gpu_util import announce, ctx, host, psnr
@@ -100,6 +100,28 @@ def test_planes_uniform10k(pdt):
         tol = 2e-3 if pdt == "f16" else 4e-3      # one rounding of a value <= 1: 2^-11 / 2^-9
         e, frac = _masked_compare(got, mpi.planes, mpi.ambiguous, tol, 0.02)
         print(pdt, "unmasked max-abs", e)
+
+
+def test_planes_uniform10k_u8():
+    """UNORM8 planes (Sec. 5.1) of the 10k-Gaussian workload: every code equals the code of
+    the oracle's FP64 texel, except within 0.05 code units of a rounding tie (one code
+    either way) and at texels the 1/255 inclusion test makes ambiguous (within the jump of
+    one threshold Gaussian)."""
+    announce("planes uniform10k", "u8")
+    scene, cam, cfg = scenegen.config("uniform10k")
+    out, info, st = _gpu_build(scene, cam, 16, "inv_depth", (2.0, 6.0), dtype=torch.uint8)
+    assert st == L.LF_OK
+    mpi = render.build_mpi_gaussians(scene, cam, 16, "inv_depth", (2.0, 6.0))
+    _check_partition(out, mpi.part, 10_000)
+    got = out["rgba"].cpu().numpy().astype(np.int32)
+    ref = quantize.unorm8(mpi.planes).astype(np.int32)
+    d = np.abs(got - ref)
+    amb = np.broadcast_to(mpi.ambiguous[..., None], d.shape)
+    tie = quantize.near_tie(mpi.planes, 0.05)
+    assert d[~amb & ~tie].max(initial=0) == 0
+    assert d[~amb].max(initial=0) <= 1
+    assert d[amb].max(initial=0) <= 6                       # 0.02 * 255
+    print("u8 codes off by one near ties:", int((d[~amb] == 1).sum()), "of", int((~amb).sum()))
 
 
 @pytest.mark.parametrize("interp", ["nearest", "bilinear"])

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import scenegen
-from oracle import composite, decisions, geometry
+from oracle import composite, decisions, geometry, quantize
 from paper_2508_18540_amd import torch_api as T
 from tests.gpu_util import announce, ctx, dev, host, psnr
 
@@ -82,6 +82,22 @@ def test_composite_low_precision_planes(pdt, interp):
         assert err <= 2e-3
     else:
         assert err <= 8e-3      # 2^-9 relative per texel; reported, see design notes
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+@pytest.mark.parametrize("shape", [(256, 192, 24, 15, 1), (96, 80, 6, 4, 3)], ids=["rows", "general_vy3"])
+def test_composite_u8_planes(interp, shape):
+    """UNORM8 planes (Sec. 5.1), accumulated in FP32: 1e-4 against the oracle composite of
+    the same codes read back as code / 255 (row kernel and the per-pixel kernel)."""
+    nx, ny, K, vx, vy = shape
+    announce("composite u8", nx, ny, K, vx, vy, interp)
+    cam, g, p, dx, dy = _setup(nx, ny, K, vx, vy, 14, phi_y=12.0 if vy > 1 else 0.0)
+    codes = quantize.unorm8(p["rgba"])
+    ref, _ = composite.composite(quantize.dequant(codes), p["depth"], cam, g, dx, dy, interp)
+    out = T.composite(ctx(), dev(codes), dev(p["depth"]), cam, T.views_of(dx, dy), interp)
+    err = np.abs(host(out) - ref).max()
+    print("u8", interp, "max-abs", err)
+    assert err <= 1e-4
 
 
 def test_composite_fp16_output():

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import scenegen
-from oracle import composite, geometry, voxels
+from oracle import composite, geometry, quantize, voxels
 from paper_2508_18540_amd import _lib as L
 from paper_2508_18540_amd import torch_api as T
 from tests.gpu_util import announce, ctx, host, psnr
@@ -75,6 +75,25 @@ def test_voxel_planes_low_precision(pdt):
     err = np.abs(host(out["rgba"]) - mpi.planes).max()
     print(pdt, "planes max-abs", err)
     assert err <= (2e-3 if pdt == "f16" else 4e-3)
+
+
+def test_voxel_planes_u8():
+    """UNORM8 planes (Sec. 5.1): the splat's texels are stored as codes, then the in-place
+    low-pass reads them back and stores its output as codes again.  Against the oracle doing
+    the same two roundings on its FP64 values, every code is within one, and at least 99 %
+    are equal (a value within float32 error of a rounding tie may go either way, at either
+    rounding)."""
+    announce("voxel planes", "u8")
+    vox = _small()
+    cam = scenegen.camera(128, 128, 50.0, 4.0, math.radians(40.0))
+    out, info, st = _gpu_build(vox, cam, 8, dtype=torch.uint8)
+    assert st == L.LF_OK
+    raw = voxels.build_mpi_voxels(vox, cam, 8, filtered=False)
+    ref = np.stack([quantize.unorm8(voxels.lowpass(quantize.dequant(quantize.unorm8(pl)))) for pl in raw.planes])
+    torch.cuda.synchronize()
+    d = np.abs(out["rgba"].cpu().numpy().astype(np.int32) - ref.astype(np.int32))
+    print("u8 voxel codes: max diff", int(d.max()), "exact fraction", float((d == 0).mean()))
+    assert d.max() <= 1 and (d == 0).mean() >= 0.99
 
 
 @pytest.mark.parametrize("interp", ["nearest", "bilinear"])
