@@ -179,6 +179,21 @@ lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam,
 lf_status lf_build_stats(lf_ctx* ctx, const void* workspace, size_t workspace_bytes,
                          lf_build_info* out, void* stream);
 
+/* The conventional per-view render that the light field approximates (the baseline of
+ * Sec. 5.1, Table 1): every Gaussian of `field` in one depth-sorted chunk, splatted from
+ * the camera of view `view` (Eq. 5: at (dx, dy, 0) in base-camera coordinates, looking
+ * along +z, principal point shifted so its principal ray meets the focal-plane centre) at
+ * the view resolution with the constant 0.3 px^2 dilation of 3DGS.  Culled: depth <=
+ * z_near, or |x / z| > 1.3 tan(theta_x / 2) (view coordinates, about the view axis), or
+ * likewise in y.  `out` is a one-plane MPI of the view size (n_chunk = 1, height = ny,
+ * width = nx, any plane dtype): rgba = premultiplied (C, 1 - T), depth[0] = the median
+ * depth; chunk_of / chunk_count may be NULL.  `workspace`: lf_render_view_workspace bytes
+ * (reported by lf_build_stats like a build).  Gaussian fields only (voxels:
+ * LF_ERR_UNSUPPORTED).  Enqueued on `stream`.                                            */
+lf_status lf_render_view_workspace(const lf_field* field, const lf_camera* cam, size_t* bytes);
+lf_status lf_render_view(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, const lf_view* view,
+                         lf_mpi* out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Swizzle blending (Sec. 4.3, Eqs. 6-7, Alg. 1 steps 6-11): for each view v, pixel (x, y)
  * and plane k front to back, sample plane k at the texel coordinate of Eq. 6 (nearest or
  * bilinear; outside the plane is transparent) and over-composite with float32

@@ -28,7 +28,7 @@ EXPORTS = [
     "lf_version", "lf_last_error", "lf_create", "lf_destroy", "lf_geometry", "lf_quilt_views",
     "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_composite_backward",
     "lf_build_mpi_backward", "lf_plane_coeffs", "lf_batch_create", "lf_batch_run", "lf_batch_group",
-    "lf_batch_destroy", "lf_profile_enable", "lf_profile_read",
+    "lf_batch_destroy", "lf_profile_enable", "lf_profile_read", "lf_render_view_workspace", "lf_render_view",
 ]
 LF_BATCH_GRAPH, LF_BATCH_AUTOTUNE = 1, 2
 PHASES = ["preprocess", "sort", "bin", "splat", "merge", "filter", "coeff", "composite", "composite_bwd",
@@ -129,6 +129,9 @@ def load():
         "lf_batch_destroy": ([P], None),
         "lf_plane_coeffs": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
                              P, P, P, P, P, P, P], C.c_int),
+        "lf_render_view_workspace": ([C.POINTER(lf_field), C.POINTER(lf_camera), C.POINTER(C.c_size_t)], C.c_int),
+        "lf_render_view": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.POINTER(lf_view), C.POINTER(lf_mpi), P,
+                            C.c_size_t, P], C.c_int),
         "lf_profile_enable": ([P, C.c_int32], C.c_int),
         "lf_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32], C.c_int),
     }
@@ -228,6 +231,19 @@ def lf_build_mpi(ctx: int, field: lf_field, cam: lf_camera, n_chunk: int, binnin
         rng = (C.c_float * 2)(*[float(v) for v in inv_depth_range])
     _check(load().lf_build_mpi(ctx, C.byref(field), C.byref(cam), n_chunk, binning, rng, C.byref(mpi),
                                workspace, workspace_bytes, stream), "lf_build_mpi")
+
+
+def lf_render_view_workspace(field: lf_field, cam: lf_camera) -> int:
+    n = C.c_size_t()
+    _check(load().lf_render_view_workspace(C.byref(field), C.byref(cam), C.byref(n)), "lf_render_view_workspace")
+    return n.value
+
+
+def lf_render_view(ctx: int, field: lf_field, cam: lf_camera, dx: float, dy: float, out: lf_mpi, workspace: int,
+                   workspace_bytes: int, stream: int = 0) -> None:
+    v = lf_view(float(dx), float(dy))
+    _check(load().lf_render_view(ctx, C.byref(field), C.byref(cam), C.byref(v), C.byref(out), workspace,
+                                 workspace_bytes, stream), "lf_render_view")
 
 
 def lf_build_stats(ctx: int, workspace: int, workspace_bytes: int, stream: int = 0, check: bool = True):

@@ -290,6 +290,59 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   return LF_OK;
 }
 
+// The view camera of lf_render_view as a light-field camera with no baseline: D_forward = 0,
+// theta' = theta, one plane at the view resolution, f' = 0.3 texel^2.
+static lf_camera view_camera(const lf_camera* cam) {
+  lf_camera v = *cam;
+  v.phi_x = v.phi_y = 0.0f;
+  v.d_shift = 0.0f;
+  v.plane_scale = 1.0f;
+  return v;
+}
+
+extern "C" lf_status lf_render_view_workspace(const lf_field* field, const lf_camera* cam, size_t* bytes) {
+  if (!cam) return fail(LF_ERR_INVALID_ARG, "camera is NULL");
+  const lf_camera v = view_camera(cam);
+  return lf_build_mpi_workspace(field, &v, 1, 0, bytes);
+}
+
+extern "C" lf_status lf_render_view(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, const lf_view* view,
+                                    lf_mpi* out, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!cam) return fail(LF_ERR_INVALID_ARG, "camera is NULL");
+  if (!view) return fail(LF_ERR_INVALID_ARG, "view is NULL");
+  if (!(std::isfinite(view->dx) && std::isfinite(view->dy))) return fail(LF_ERR_INVALID_ARG, "view offset is not finite");
+  const lf_camera vc = view_camera(cam);
+  Geom g;
+  lf_status s = check_common(field, &vc, 1, &g);
+  if (s != LF_OK) return s;
+  if (field->kind != LF_GAUSSIANS) return fail(LF_ERR_UNSUPPORTED, "the per-view render covers Gaussian fields only");
+  if (!out) return fail(LF_ERR_INVALID_ARG, "out is NULL");
+  if (out->dtype != LF_F32 && out->dtype != LF_F16 && out->dtype != LF_BF16 && out->dtype != LF_U8)
+    return fail(LF_ERR_INVALID_ARG, "out dtype %d is not F32/F16/BF16/U8", out->dtype);
+  if (out->n_chunk != 1 || out->width != g.nx || out->height != g.ny)
+    return fail(LF_ERR_INVALID_ARG, "out must be one %dx%d plane", g.nx, g.ny);
+  if (!out->rgba || !out->depth) return fail(LF_ERR_INVALID_ARG, "out rgba/depth is NULL");
+  if (!workspace) return fail(LF_ERR_INVALID_ARG, "workspace is NULL");
+  const int64_t n = field->n;
+  const int64_t cap = capacity_of(field->kind, n, 1, g.wp, g.hp, workspace_bytes);
+  if (cap < 1) return fail(LF_ERR_CAPACITY, "workspace of %zu bytes is too small for this field", workspace_bytes);
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  // Eq. 5: the view camera at (dx, dy, 0), principal point c + p N / 2 with p = d / (D_focal tan(theta / 2))
+  const double px = (double)view->dx / ((double)cam->d_focal * g.tx);
+  const double py = (double)view->dy / ((double)cam->d_focal * g.ty);
+  g.c.t[0] = (float)((double)cam->t[0] - (double)view->dx);
+  g.c.t[1] = (float)((double)cam->t[1] - (double)view->dy);
+  g.c.cpx = (float)(g.cpx + px * g.nx / 2.0);
+  g.c.cpy = (float)(g.cpy + py * g.ny / 2.0);
+  const BuildLayout L = build_layout(field->kind, n, 1, g.wp, g.hp, cap);
+  BuildArgs a;
+  build_args(a, L, field, &vc, g, 1, LF_BIN_QUANTILE, out, workspace, cap);
+  if ((e = build_planes(a, L, (hipStream_t)stream, &ctx->prof)) != hipSuccess) return hip_fail(e, "render launch");
+  return LF_OK;
+}
+
 extern "C" lf_status lf_build_mpi_backward(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, const lf_mpi* mpi,
                                            const float* d_planes, const lf_gaussian_grads* grads, void* workspace,
                                            size_t workspace_bytes, void* stream) {

@@ -1,0 +1,120 @@
+"""Light-field quality against conventional per-view rendering, on seeded synthetic scenes.
+
+The paper measures how close the sweeping-plane light field comes to rendering every view
+on its own (Sec. 5.1: Table 1, and the N_chunk / P_s, uint8 and anti-aliasing curves).
+This harness does the same on the GPU: for a scene and a camera it renders the light field
+(lf_build_mpi + lf_composite, the hot path) and, for every view, the conventional render
+(lf_render_view), and reports the PSNR of the colour composited over black, per setting.
+
+    python -m paper_2508_18540_amd.quality --n 100000 --res 512 --views 45 \
+        --chunks 1,4,16,64,128,256 --scales 1,2 --interp nearest,bilinear
+
+prints one JSON line per (plane scale, interpolation, plane dtype, N_chunk).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import torch
+
+if __package__ in (None, ""):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_2508_18540_amd import _lib as L  # noqa: E402
+from paper_2508_18540_amd import torch_api as T  # noqa: E402
+
+_DTYPES = {"f32": torch.float32, "f16": torch.float16, "u8": torch.uint8}
+
+
+def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
+    """PSNR (dB, peak 1) of two images with values in [0, 1]."""
+    mse = float(torch.mean((a.double() - b.double()) ** 2))
+    return math.inf if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
+
+
+def reference_views(ctx: T.Context, scene: dict, cam, views) -> torch.Tensor:
+    """Conventional per-view renders [V, ny, nx, 3] (premultiplied colour over black)."""
+    out, ws = None, None
+    refs = []
+    for v in views:
+        out = T.render_view(ctx, scene, cam, v.dx, v.dy, workspace=ws, out=out)
+        ws = out["workspace"]
+        T.build_stats(ctx, ws, check=True)
+        refs.append(out["rgba"][0, ..., :3].float().clone())
+    return torch.stack(refs)
+
+
+def light_field_views(ctx: T.Context, scene: dict, cam, views, n_chunk: int, interp: str = "nearest",
+                      dtype=torch.float32) -> torch.Tensor:
+    """Composited light-field views [V, ny, nx, 3] (colour over black)."""
+    ws = T.workspace_for(scene, cam, n_chunk)
+    out = T.build_mpi(ctx, scene, cam, n_chunk, dtype=dtype, workspace=ws)
+    info, st = T.build_stats(ctx, ws, check=False)
+    if info.overflow:
+        ws = T.workspace_for(scene, cam, n_chunk, entry_capacity=int(info.entries_needed * 1.1) + 1024)
+        out = T.build_mpi(ctx, scene, cam, n_chunk, dtype=dtype, workspace=ws)
+        T.build_stats(ctx, ws, check=True)
+    img = T.composite(ctx, out["rgba"], out["depth"], cam, views, interp)
+    return img[..., :3].float()
+
+
+def sweep(ctx: T.Context, scene: dict, cam_of, vx: int, chunks, scales=(1.0,), interps=("nearest",),
+          dtypes=("f32",)):
+    """Yields one dict per (plane scale, interpolation, dtype, N_chunk): mean PSNR over the
+    views, the worst view's PSNR, and the settings.  cam_of(plane_scale) gives the camera."""
+    for ps in scales:
+        cam = cam_of(ps)
+        views = L.lf_quilt_views(L.make_camera(cam), vx, 1)
+        ref = reference_views(ctx, scene, cam, views)
+        for interp in interps:
+            for dt in dtypes:
+                for k in chunks:
+                    img = light_field_views(ctx, scene, cam, views, k, interp, _DTYPES[dt])
+                    per_view = [psnr(img[v], ref[v]) for v in range(len(views))]
+                    yield dict(plane_scale=ps, interp=interp, planes=dt, n_chunk=k,
+                               psnr_mean=round(float(np.mean(per_view)), 2),
+                               psnr_min=round(float(np.min(per_view)), 2), views=len(views))
+
+
+def main(argv=None) -> None:
+    import scenegen
+
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--scene", default="box", choices=["box", "cluster"],
+                   help="box: Gaussians uniform in a box around the focal plane (depth --zmin..--zmax); "
+                        "cluster: the clustered benchmark scene (depths 1.15..20, far beyond the focal plane)")
+    p.add_argument("--n", type=int, default=100_000, help="Gaussians")
+    p.add_argument("--zmin", type=float, default=1.6)
+    p.add_argument("--zmax", type=float, default=3.0)
+    p.add_argument("--seed", type=int, default=5)
+    p.add_argument("--res", type=int, default=512)
+    p.add_argument("--views", type=int, default=45)
+    p.add_argument("--phi", type=float, default=40.0, help="horizontal viewing angle (deg)")
+    p.add_argument("--fov", type=float, default=50.0)
+    p.add_argument("--chunks", default="1,4,16,64,128,256")
+    p.add_argument("--scales", default="1,2")
+    p.add_argument("--interp", default="nearest,bilinear")
+    p.add_argument("--planes", default="f32,u8")
+    a = p.parse_args(argv)
+    ctx = T.Context(0)
+    if a.scene == "cluster":
+        scene = scenegen.cluster_scene(a.n, seed=a.seed)
+    else:
+        scene = scenegen.small_scene(a.n, a.seed, xy=0.7, z=(a.zmin, a.zmax), log_scale=(-4.0, 0.4))
+    scene = T.to_device(scene)
+
+    def cam_of(ps):
+        return scenegen.camera(a.res, a.res, a.fov, 2.0, math.radians(a.phi), plane_scale=ps)
+
+    for row in sweep(ctx, scene, cam_of, a.views, [int(c) for c in a.chunks.split(",")],
+                     [float(s) for s in a.scales.split(",")], a.interp.split(","), a.planes.split(",")):
+        print(json.dumps(row), flush=True)
+
+
+if __name__ == "__main__":
+    main()

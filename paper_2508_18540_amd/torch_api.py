@@ -162,6 +162,25 @@ def build_mpi(ctx: Context, scene: dict, cam, n_chunk: int, binning: str = "quan
     return out
 
 
+def render_view(ctx: Context, scene: dict, cam, dx: float, dy: float = 0.0, dtype=torch.float32,
+                workspace: Workspace | None = None, out: dict | None = None) -> dict:
+    """lf_render_view: the conventional per-view render of view (dx, dy); returns dict(rgba
+    [1, ny, nx, 4] premultiplied (C, 1 - T), depth [1], workspace)."""
+    f = field_of(scene)
+    c = L.make_camera(cam)
+    dev = ctx.device
+    if workspace is None:
+        workspace = Workspace(L.lf_render_view_workspace(f, c), dev)
+    if out is None:
+        out = dict(rgba=torch.empty((1, cam.ny, cam.nx, 4), dtype=dtype, device=dev),
+                   depth=torch.empty(1, dtype=torch.float32, device=dev))
+    m = mpi_of(out["rgba"], out["depth"])
+    L.lf_render_view(ctx.handle, f, c, dx, dy, m, workspace.ptr, workspace.nbytes,
+                     torch.cuda.current_stream(dev).cuda_stream)
+    out["workspace"] = workspace
+    return out
+
+
 def build_stats(ctx: Context, workspace: Workspace, check: bool = True):
     """lf_build_stats (synchronises the current stream)."""
     info, status = L.lf_build_stats(ctx.handle, workspace.ptr, workspace.nbytes,

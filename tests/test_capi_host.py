@@ -202,3 +202,34 @@ def test_batch_rejects_invalid_items(lib):
         st = lib.lf_batch_create(dummy, (L.lf_batch_item * 1)(bad), 1, 0, ctypes.byref(h))
         assert st == L.LF_ERR_INVALID_ARG, field
         assert needle in L.lf_last_error(), (field, L.lf_last_error())
+
+
+def test_render_view_rejects_invalid_arguments(lib):
+    """The per-view render validates everything on the host before touching the device."""
+    cam = L.make_camera(CAMS["uniform10k"])
+    g = L.lf_geometry(cam)
+    f = _field(L.LF_GAUSSIANS, n=1000)
+    nbytes = ctypes.c_size_t(0)
+    assert lib.lf_render_view_workspace(ctypes.byref(f), ctypes.byref(cam), ctypes.byref(nbytes)) == L.LF_OK
+    one = ctypes.c_size_t(0)
+    assert lib.lf_build_mpi_workspace(ctypes.byref(f), ctypes.byref(cam), 1, 0, ctypes.byref(one)) == L.LF_OK
+    assert 0 < nbytes.value <= one.value              # one plane at the view size (P_s = 1)
+    v = L.lf_view(0.1, 0.0)
+    ok = L.make_mpi(L.LF_F32, 1, cam.ny, cam.nx, 0x6000, 0x7000)
+    cases = [
+        (dict(view=None), "view"),
+        (dict(view=L.lf_view(float("nan"), 0.0)), "not finite"),
+        (dict(out=L.make_mpi(L.LF_F32, 2, cam.ny, cam.nx, 0x6000, 0x7000)), "one"),
+        (dict(out=L.make_mpi(L.LF_F32, 1, g.plane_height + 8, g.plane_width, 0x6000, 0x7000)), "one"),
+        (dict(out=L.make_mpi(9, 1, cam.ny, cam.nx, 0x6000, 0x7000)), "dtype"),
+        (dict(nbytes=1024), "too small"),
+        (dict(field=_field(L.LF_VOXELS, n=1000)), "Gaussian fields only"),
+    ]
+    for kw, needle in cases:
+        fld = kw.get("field", f)
+        view = kw.get("view", v)
+        out = kw.get("out", ok)
+        st = lib.lf_render_view(None, ctypes.byref(fld), ctypes.byref(cam), ctypes.byref(view) if view else None,
+                                ctypes.byref(out), 0x8000, kw.get("nbytes", nbytes.value), None)
+        assert st != L.LF_OK, kw
+        assert needle in L.lf_last_error(), (kw, L.lf_last_error())

@@ -1,0 +1,84 @@
+"""The conventional per-view render (lf_render_view, the baseline of Sec. 5.1) against the
+FP64 oracle's, and the light-field quality harness built on it (quality.py).
+
+Per-view render: every texel within 1e-4 of the oracle's render_view, except where the
+1/255 inclusion test is ambiguous (within the jump one threshold Gaussian can cause)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from oracle import geometry, render
+from paper_2508_18540_amd import _lib as L
+from paper_2508_18540_amd import quality
+from paper_2508_18540_amd import torch_api as T
+from tests.gpu_util import announce, ctx, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _visible_about_view_axis(scene, cam, dx, dy):
+    """The cull lf_render_view applies: depth > z_near and |x/z|, |y/z| <= 1.3 tan(theta/2)
+    in the view camera's coordinates (about its axis, before the principal-point shift)."""
+    g = geometry.derive(cam)
+    R = np.asarray(cam.R, dtype=np.float64).reshape(3, 3)
+    pc = scene["means"].astype(np.float64) @ R.T + np.asarray(cam.t, dtype=np.float64)
+    x, y, z = pc[:, 0] - dx, pc[:, 1] - dy, pc[:, 2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return (z > cam.z_near) & (np.abs(x) <= 1.3 * g.tx * z) & (np.abs(y) <= 1.3 * g.ty * z)
+
+
+@pytest.mark.parametrize("dxy", [(0.0, 0.0), (0.35, 0.0), (-0.2, 0.15)], ids=["centre", "right", "left_up"])
+def test_render_view_matches_oracle(dxy):
+    dx, dy = dxy
+    announce("render_view", dx, dy)
+    scene = scenegen.small_scene(3000, 21, xy=2.0, z=(2.5, 8.0))
+    cam = scenegen.camera(96, 80, 50.0, 3.0, math.radians(30.0))
+    out = T.render_view(ctx(), T.to_device(scene), cam, dx, dy)
+    info, st = T.build_stats(ctx(), out["workspace"], check=False)
+    assert st == L.LF_OK
+    ref, amb = render.render_view(scene, cam, dx, dy, visible=_visible_about_view_axis(scene, cam, dx, dy))
+    got = host(out["rgba"][0])
+    err = np.abs(got - ref).max(axis=-1)
+    assert (ref[..., 3] > 0.05).mean() > 0.05                   # the view is not empty
+    assert err[~amb].max(initial=0.0) <= 1e-4, err[~amb].max()
+    assert err[amb].max(initial=0.0) <= 0.02
+    print("render_view max-abs", float(err[~amb].max()), "ambiguous", float(amb.mean()))
+
+
+def test_zero_baseline_light_field_is_the_per_view_render():
+    """phi = 0: the reference camera is the base camera, so every plane stack composites to the
+    conventional render of the base view, for any N_chunk (the over operator is associative)."""
+    announce("quality zero baseline")
+    scene = T.to_device(scenegen.cluster_scene(20_000, seed=4))
+    cam = scenegen.camera(128, 128, 50.0, 2.0, 0.0)
+    views = T.views_of([0.0])
+    ref = quality.reference_views(ctx(), scene, cam, views)
+    for k in (1, 8, 32):
+        img = quality.light_field_views(ctx(), scene, cam, views, k)
+        err = float((img - ref).abs().max())
+        print("N_chunk", k, "max-abs vs per-view", err)
+        assert err <= 1e-4
+
+
+def test_quality_grows_with_chunks():
+    """A box of Gaussians around the focal plane, 20 deg baseline: the light field approaches
+    the per-view renders as N_chunk grows (the trend of the paper's N_chunk curves), and 8-bit
+    planes give nearly the same PSNR as float32 ones (its uint8 comparison)."""
+    announce("quality sweep")
+    scene = T.to_device(scenegen.small_scene(50_000, 3, xy=0.7, z=(1.8, 2.4), log_scale=(-3.5, 0.4)))
+
+    def cam_of(ps):
+        return scenegen.camera(192, 192, 50.0, 2.0, math.radians(20.0), plane_scale=ps)
+
+    rows = list(quality.sweep(ctx(), scene, cam_of, 9, [1, 8, 64], scales=(2.0,), interps=("nearest",),
+                              dtypes=("f32", "u8")))
+    for r in rows:
+        print(r)
+    by = {(r["planes"], r["n_chunk"]): r["psnr_mean"] for r in rows}
+    assert by[("f32", 64)] > by[("f32", 1)] + 8.0
+    assert by[("f32", 64)] >= by[("f32", 8)] - 0.5
+    assert by[("f32", 64)] > 28.0
+    assert abs(by[("u8", 64)] - by[("f32", 64)]) < 1.0          # 8-bit planes: nearly the same PSNR
