@@ -222,7 +222,7 @@ __global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
 constexpr int kEmitRanks = 512;
 constexpr int64_t kCombineGroups = 8192;
 constexpr int kKeyDigitBits = 8;    // key sort: four passes over a grid wide enough to fill the CUs
-constexpr int kTileDigitBits = 6;   // tile sort: two narrow passes write more coalesced runs than one wide one
+constexpr int kTileDigitBits = 10;  // tile sort: one pass over up to 1024 tiles (writes are reordered in LDS)
 
 __device__ __forceinline__ int64_t last_le(const uint64_t* off, int64_t lo, int64_t hi, uint64_t v) {
   // last r in [lo, hi] with off[r] <= v (off is non-decreasing, off[lo] <= v)

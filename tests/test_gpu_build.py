@@ -225,7 +225,7 @@ def test_build_deterministic():
 @pytest.mark.parametrize("key_bits,tile_bits", [(4, 4), (11, 11), (7, 9)])
 def test_sort_digit_widths_agree(key_bits, tile_bits, monkeypatch):
     """The depth sort and the tile sort are stable sorts of unique (key, index) orders, so any
-    digit width gives the same planes, bit for bit, as the default (8 / 6 bits).  4 bits: 8
+    digit width gives the same planes, bit for bit, as the default (8 / 10 bits).  4 bits: 8
     depth passes of 16 digits and 3 tile passes (an odd count: result in the alternate
     arrays); 11 bits: 3 depth passes of 2048 digits (several digits per thread) and 1 tile
     pass of 1024 digits; 7 / 9 bits: a narrower last depth pass."""
