@@ -37,10 +37,10 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 COPY_FETCH_SCALE = 262144.0 / 131084.0
 COPY_WRITE_SCALE = 262144.0 / 262144.0
 MEASURED_TRAFFIC = {
-    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133421, write_kib=286992,
-                     digest="a2a5b3574439f74c"),
-    "composite_rows": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=349989, write_kib=184320,
-                           digest="f0e7b90ef0537f83"),
+    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133397, write_kib=286992,
+                     digest="11e3fa5c8720dcd9"),
+    "composite_rows": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=349987, write_kib=184320,
+                           digest="1a39884819a5ab64"),
 }
 
 
