@@ -167,9 +167,7 @@ __global__ __launch_bounds__(256) void rank_pass(BuildArgs a, const uint32_t* sk
 }
 
 // chunk_start[k] for k in [0, K]: first rank whose chunk is >= k
-__global__ void chunk_starts(BuildArgs a, const uint32_t* skeys) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > a.K) return;
+__device__ void chunk_start_of(const BuildArgs& a, const uint32_t* skeys, int k) {
   const int64_t nvis = a.hdr->n_vis;
   int64_t s;
   if (k == 0) s = 0;
@@ -188,9 +186,8 @@ __global__ void chunk_starts(BuildArgs a, const uint32_t* skeys) {
   a.chunk_start[k] = s;
 }
 
-__global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.K) return;
+// plane depth d_k and primitive count of chunk k (reads the starts of other chunks)
+__device__ void chunk_depth_of(const BuildArgs& a, const uint32_t* skeys, int k) {
   const int64_t s = a.chunk_start[k], cnt = a.chunk_start[k + 1] - s;
   if (a.chunk_count) a.chunk_count[k] = (int32_t)cnt;
   float d;
@@ -208,6 +205,13 @@ __global__ void chunk_depths(BuildArgs a, const uint32_t* skeys) {
     d = a.d_focal32;
   }
   a.depth[k] = d;
+}
+
+// Chunk starts, then depths and counts, in one work-group (the barrier orders the two).
+__global__ __launch_bounds__(1024) void chunk_table(BuildArgs a, const uint32_t* skeys) {
+  for (int k = threadIdx.x; k <= a.K; k += blockDim.x) chunk_start_of(a, skeys, k);
+  __syncthreads();
+  for (int k = threadIdx.x; k < a.K; k += blockDim.x) chunk_depth_of(a, skeys, k);
 }
 
 // One (tile, Gaussian) entry per covered tile, written in rank order.  Work is balanced by
@@ -844,8 +848,7 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
       // nothing to rasterise: transparent planes at D_focal (or the inverse-depth table)
       const size_t words = (size_t)a.K * a.c.hp * a.c.wp * (a.plane_dtype == LF_F32 ? 4 : 2);
       if ((e = fill(reinterpret_cast<uint32_t*>(a.planes), (int64_t)words, 0u, s)) != hipSuccess) return e;
-      hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, a.keys);
-      hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, a.keys);
+      hipLaunchKernelGGL(chunk_table, dim3(1), dim3(1024), 0, s, a, a.keys);
       return hipGetLastError();
     }
     if (a.kind == LF_VOXELS) {
@@ -868,8 +871,7 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     PhaseScope ps(prof, LF_PHASE_BIN, s);
     hipLaunchKernelGGL(find_nvis, dim3(gN), dim3(256), 0, s, a, skeys);
     hipLaunchKernelGGL(rank_pass, dim3(gN), dim3(256), 0, s, a, skeys, svals);
-    hipLaunchKernelGGL(chunk_starts, dim3((a.K + 1 + 255) / 256), dim3(256), 0, s, a, skeys);
-    hipLaunchKernelGGL(chunk_depths, dim3((a.K + 255) / 256), dim3(256), 0, s, a, skeys);
+    hipLaunchKernelGGL(chunk_table, dim3(1), dim3(1024), 0, s, a, skeys);
     if ((e = exclusive_scan_u64(a.ntiles_r, a.offsets, a.n, a.scan_state_offsets, &a.hdr->stalled, s, a.heads,
                                 a.n_heads, 8)) != hipSuccess)
       return e;
