@@ -199,11 +199,6 @@ __device__ __forceinline__ float4 lds_texel<uint2>(const char* p) {
   return make_float4(__low2float(lo), __high2float(lo), __low2float(hi), __high2float(hi));
 }
 
-template <typename PT>
-__device__ __forceinline__ uint2 load_raw_half4(const PT* p, size_t i) {
-  return reinterpret_cast<const uint2*>(p)[i];
-}
-
 // Bilinear window entry i of a plane: the vertically blended texel and its forward difference.
 template <typename PT>
 __device__ __forceinline__ void bilinear_entry(const PT* __restrict__ planes, size_t pbase, int wp, int hp,
