@@ -77,8 +77,9 @@ def parse():
     p.add_argument("--cpu-planes", type=int, default=48, help="planes the CPU oracle rasterises")
     p.add_argument("--cpu-views", type=int, default=6, help="views the CPU oracle composites")
     p.add_argument("--forms", default="f32,f16,u8", help="plane storage forms to time (first one is `value`)")
-    p.add_argument("--extra", default="voxel256,grad200k,batch8",
-                   help="further workloads timed into the same line (voxel256, grad200k, batch8; empty for none)")
+    p.add_argument("--extra", default="voxel256,grad200k,quilt2d,batch8",
+                   help="further workloads timed into the same line (voxel256, grad200k, quilt2d, batch8; "
+                        "empty for none)")
     p.add_argument("--extra-steps", type=int, default=5)
     p.add_argument("--only-extra", action="store_true",
                    help="time only the --extra workloads (for profiling them on their own)")
@@ -194,6 +195,50 @@ def extra_grad200k(ctx, steps, warmup):
                 ms_per_step=round(ms, 4), views_per_s=round(V / (ms * 1e-3), 1), phases_ms=ph)
 
 
+def extra_quilt2d(ctx, steps, warmup):
+    """2D parallax: the cluster500k scene, 512^2, 64 quantile planes, FP32, composited into a
+    9 x 5 quilt (five vertical offsets); build + composite per step.  Beside it, the composite
+    alone with the row kernel (views grouped by dy) and with the per-pixel kernel."""
+    import os
+
+    import torch
+
+    import scenegen
+    from paper_2508_18540_amd import _lib as L
+    from paper_2508_18540_amd import torch_api as T
+
+    scene, cam, cfg = scenegen.config("quilt2d")
+    K, V = cfg["n_chunk"], cfg["vx"] * cfg["vy"]
+    vlist = L.lf_quilt_views(L.make_camera(cam), cfg["vx"], cfg["vy"])
+    ds = T.to_device(scene)
+    ws = T.workspace_for(ds, cam, K)
+    out = T.build_mpi(ctx, ds, cam, K, workspace=ws)
+    info, st = T.build_stats(ctx, ws, check=False)
+    if st == L.LF_ERR_CAPACITY:
+        ws = T.workspace_for(ds, cam, K, entry_capacity=int(info.entries_needed * 1.25))
+        out = T.build_mpi(ctx, ds, cam, K, workspace=ws)
+    img = torch.empty((V, cam.ny, cam.nx, 4), dtype=torch.float32, device="cuda")
+
+    def step():
+        T.build_mpi(ctx, ds, cam, K, workspace=ws, out=out)
+        T.composite(ctx, out["rgba"], out["depth"], cam, vlist, "nearest", out=img)
+    ms, ph = _timed(step, warmup, steps, ctx, L)
+    T.build_stats(ctx, ws, check=True)
+    comp = {}
+    for kern in ("rows", "general"):
+        os.environ["LF_COMPOSITE_KERNEL"] = kern
+        try:
+            _, cph = _timed(lambda: T.composite(ctx, out["rgba"], out["depth"], cam, vlist, "nearest", out=img),
+                            warmup, steps, ctx, L)
+        finally:
+            del os.environ["LF_COMPOSITE_KERNEL"]
+        comp[kern] = cph.get("composite")
+    return dict(workload="quilt2d: 500k clustered Gaussians, 512x512, 64 quantile planes, 9x5 views "
+                         "(+-20 x +-10 deg), FP32",
+                views_per_s=round(V / (ms * 1e-3), 1), ms_per_step=round(ms, 4), phases_ms=ph,
+                composite_ms_row_kernel=comp["rows"], composite_ms_per_pixel_kernel=comp["general"])
+
+
 def extra_batch8(ctx, steps, warmup):
     """Eight clustered-Gaussian scenes of uneven size in one batch (seeds 30+i): (N, res,
     N_chunk, views) from 50k / 256^2 / 64 / 9 up to 2M / 768^2 / 128 / 45, FP16 planes and
@@ -254,7 +299,8 @@ def main():
     if args.only_extra:
         line = {"only_extra": True}
         for name in [x.strip() for x in args.extra.split(",") if x.strip()]:
-            fn = {"voxel256": extra_voxel256, "grad200k": extra_grad200k, "batch8": extra_batch8}[name]
+            fn = {"voxel256": extra_voxel256, "grad200k": extra_grad200k, "quilt2d": extra_quilt2d,
+                  "batch8": extra_batch8}[name]
             line[name] = fn(ctx, args.extra_steps, 2)
         print(json.dumps(line), flush=True)
         return
@@ -367,7 +413,8 @@ def main():
                                "composite_roofline": r["composite_roofline"],
                                "phases_ms": {k: round(v, 4) for k, v in r["phases_ms"].items()}}
     for name in [x.strip() for x in args.extra.split(",") if x.strip()]:
-        fn = {"voxel256": extra_voxel256, "grad200k": extra_grad200k, "batch8": extra_batch8}[name]
+        fn = {"voxel256": extra_voxel256, "grad200k": extra_grad200k, "quilt2d": extra_quilt2d,
+                  "batch8": extra_batch8}[name]
         line[name] = fn(ctx, args.extra_steps, 2)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, cam, dx, dy, K, args.cpu_planes, args.cpu_views, args.interp)

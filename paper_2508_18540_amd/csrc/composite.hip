@@ -9,23 +9,27 @@
 // -ffp-contract=off and fuses only where fmaf is written).  Nearest sampling takes the
 // texel floor(X); bilinear takes floor(X), floor(X)+1 with weight X - floor(X).
 //
-// A small table kernel evaluates these coefficients once per launch: per plane (bx, by,
-// the row offset Cy of the shared dy, a validity flag) and per (plane, view) Cx.
+// A small table kernel evaluates these coefficients once per launch: per (view group, plane)
+// (bx, by, the row offset Cy of the group's dy, a validity flag) and per (plane, view) Cx.
 //
-// Row kernel (all views share dy, e.g. a horizontal-parallax quilt).  Y depends only on
-// (k, y), so one work-group owns one output row y for a group of G views and every x of
-// a row segment; (Q, T) of the G views live in float32 registers.  Per plane it stages
+// Row kernel.  Views are grouped by their vertical offset dy: a horizontal-parallax quilt is
+// one class, a Vx x Vy quilt Vy classes, an arbitrary view list as many classes as distinct
+// dy.  Within a class Y depends only on (k, y), so one work-group owns one output row y for a
+// group of up to G views of one class and every x of a row segment; (Q, T) of the group's
+// views live in float32 registers.  Per plane it stages
 // into LDS the window of the plane row Y_k(y) (bilinear: the two rows blended
 // vertically) that holds every sample of the work-group, double-buffered so the next
 // plane's texels are in flight while the current one is sampled.  A sample is then one
 // LDS read plus four FMAs; the per-view offsets come through scalar loads.  Planes whose
 // row misses the plane are skipped.
-// General kernel (views with different dy): one thread per output pixel, texels read
-// straight from global memory.
+// General kernel (planes too wide for the row kernel's window buffer): one thread per output
+// pixel, texels read straight from global memory.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "lf_internal.h"
@@ -121,33 +125,36 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Table kernel: pt[k] = (bx, by, Cy, valid) for the shared dy, ct[k][v] = Cx with rows padded
-// to kViewPad views (the padding repeats the last view).  Nearest sampling folds the 1/2 of
-// floor(X + 1/2) into Cx and Cy.
+// Table kernel: pt[g][k] = (bx, by, Cy, valid) for view group g's dy, ct[k][p] = Cx of the
+// view at position p of the grouped order, rows padded by kViewPad positions (the padding
+// repeats the last position) so a group's G offsets can always be read.  Nearest sampling
+// folds the 1/2 of floor(X + 1/2) into Cx and Cy.
 // ---------------------------------------------------------------------------------------
 constexpr int kViewPad = 16;
 
-__host__ __device__ inline int padded_views(int V) { return (V + kViewPad - 1) / kViewPad * kViewPad; }
+__host__ __device__ inline int ct_stride(int V) { return V + kViewPad; }
 
 __global__ void coeff_table(CompositeArgs a, float4* __restrict__ pt, float* __restrict__ ct) {
-  const int vp = padded_views(a.n_views);
+  const int S = ct_stride(a.n_views);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.K * vp) return;
-  const int k = i / vp, v = min(i % vp, a.n_views - 1);
+  if (i >= a.K * S) return;
+  const int k = i / S, p = i % S;
+  const int v = a.perm[min(p, a.n_views - 1)];
   const float d = a.depth[k];
   const PlaneCo pc = plane_co(d, a.c);
   const float half = a.interp == LF_BILINEAR ? 0.0f : 0.5f;
   const float cx = a.c.cpx + pc.gx * a.dx[v];
   ct[i] = a.interp == LF_BILINEAR ? cx : cx + half;
-  if (i % vp == 0) {
-    const float cy = a.c.cpy + pc.gy * a.dy[0];
-    pt[k] = make_float4(pc.bx, pc.by, a.interp == LF_BILINEAR ? cy : cy + half, d - a.c.d_fwd > 0.0f ? 1.0f : 0.0f);
+  if (p < a.n_groups) {
+    const float cy = a.c.cpy + pc.gy * a.dy[a.perm[a.vgroup[p] & 0xffu]];
+    pt[(size_t)p * a.K + k] =
+        make_float4(pc.bx, pc.by, a.interp == LF_BILINEAR ? cy : cy + half, d - a.c.d_fwd > 0.0f ? 1.0f : 0.0f);
   }
 }
 
 // ---------------------------------------------------------------------------------------
 // Row kernel.  grid = (ny, view groups, x segments), block = up to kRowThreads threads, one
-// output pixel x per thread and G views per work-group.
+// output pixel x per thread and up to G views (one group) per work-group.
 //
 // Planes are processed in batches of kBatch.  A prologue (one thread per plane) derives
 // the plane row and the texel window [f0, f0 + len) that contains every sample of this
@@ -229,13 +236,15 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
   __shared__ int slist[kBatch];
   __shared__ int scount[2];                                // valid planes, any clamped window
   const int y = blockIdx.x;
-  const int v0 = blockIdx.y * G;
-  const int nv = min(G, a.n_views - v0);
+  const uint32_t gd = a.vgroup[blockIdx.y];
+  const int v0 = gd & 0xffu;                               // group's first position in perm
+  const int nv = gd >> 8;
+  pt += (size_t)blockIdx.y * a.K;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int xs0 = blockIdx.z * seg_len;
   const int x = xs0 + tid;
   const int xs1 = min(xs0 + seg_len, a.nx) - 1;
-  const int wp = a.wp, hp = a.hp, V = padded_views(a.n_views);
+  const int wp = a.wp, hp = a.hp, V = ct_stride(a.n_views);
   const PT* __restrict__ planes = static_cast<const PT*>(a.planes);
   const float xr = (float)x - a.c.cx;
   const float yr = (float)y - a.c.cy;
@@ -438,7 +447,7 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
     OT* out = static_cast<OT*>(a.out);
 #pragma unroll
     for (int j = 0; j < G; ++j)
-      if (j < nv) store_pixel(out, ((size_t)(v0 + j) * a.ny + y) * a.nx + x, Qr[j], Qg[j], Qb[j], Tr[j]);
+      if (j < nv) store_pixel(out, ((size_t)a.perm[v0 + j] * a.ny + y) * a.nx + x, Qr[j], Qg[j], Qb[j], Tr[j]);
   }
 }
 
@@ -513,137 +522,14 @@ __global__ void plane_coeffs_kernel(CompositeArgs a, float* bx, float* by, float
 }
 
 // ---------------------------------------------------------------------------------------
-// Backward of the composite (Eq. 7 over operator), one thread per output pixel.  With
-// Q = sum_k T_k c_k, T_{k+1} = T_k (1 - a_k) and cotangents g = dL/dQ, g_T = dL/dT_final:
+// Backward of the composite (Eq. 7 over operator).  With Q = sum_k T_k c_k,
+// T_{k+1} = T_k (1 - a_k) and cotangents g = dL/dQ, g_T = dL/dT_final:
 //   dL/dc_k = T_k g,   dL/da_k = -T_k (g . R_{k+1} + g_T S_{k+1}),
 //   R_k = c_k + (1 - a_k) R_{k+1},  S_k = (1 - a_k) S_{k+1},  R_K = 0, S_K = 1,
-// evaluated back to front.  T_k is recomputed, not stored: a forward sweep keeps T at the
-// start of every segment of ceil(K / 64) planes (LDS), and each segment is swept forward
-// again (T of its planes into LDS) before it is walked backwards.  Sampled texel values are
-// re-read per sweep; the cotangents of a sample go to its texels through the transposed
-// interpolation weights (float atomics into the FP32 plane gradient).
-// ---------------------------------------------------------------------------------------
-constexpr int kBwdThreads = 128;
-constexpr int kBwdCkpt = 64;
-
-struct Tap {
-  int ix, iy;      // nearest: the texel; bilinear: the lower corner
-  float wx, wy;    // bilinear weights of the upper neighbours
-};
-
-template <bool BIL>
-__device__ __forceinline__ Tap sample_tap(const CompositeArgs& a, int k, float xr, float yr, float dx, float dy) {
-  const PlaneCo pc = plane_co(a.depth[k], a.c);
-  const float cx = a.c.cpx + pc.gx * dx;
-  const float cy = a.c.cpy + pc.gy * dy;
-  Tap t;
-  if (!BIL) {
-    t.ix = __float2int_rd(pc.bx * xr + (cx + 0.5f));
-    t.iy = __float2int_rd(pc.by * yr + (cy + 0.5f));
-    t.wx = t.wy = 0.0f;
-  } else {
-    const float X = pc.bx * xr + cx, Y = pc.by * yr + cy;
-    const float fx0 = floorf(X), fy0 = floorf(Y);
-    t.wx = X - fx0;
-    t.wy = Y - fy0;
-    t.ix = __float2int_rd(fx0);
-    t.iy = __float2int_rd(fy0);
-  }
-  return t;
-}
-
-template <typename PT, bool BIL>
-__device__ __forceinline__ float4 sample_value(const CompositeArgs& a, const PT* planes, int k, const Tap& t) {
-  const size_t base = (size_t)k * a.hp * a.wp;
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (!BIL) {
-    return (t.ix >= 0 && t.ix < a.wp && t.iy >= 0 && t.iy < a.hp) ? load_texel(planes, base + (size_t)t.iy * a.wp + t.ix)
-                                                                    : z;
-  }
-  float4 q[2][2];
-#pragma unroll
-  for (int oy = 0; oy < 2; ++oy)
-#pragma unroll
-    for (int ox = 0; ox < 2; ++ox) {
-      const int xx = t.ix + ox, yy = t.iy + oy;
-      q[oy][ox] = (xx >= 0 && xx < a.wp && yy >= 0 && yy < a.hp) ? load_texel(planes, base + (size_t)yy * a.wp + xx) : z;
-    }
-  return lerp4(lerp4(q[0][0], q[0][1], t.wx), lerp4(q[1][0], q[1][1], t.wx), t.wy);
-}
-
-__device__ __forceinline__ void add_texel_grad(float* dp, const CompositeArgs& a, int k, int ix, int iy, float w,
-                                               float gr, float gg, float gb, float ga) {
-  if (ix < 0 || ix >= a.wp || iy < 0 || iy >= a.hp || w == 0.0f) return;
-  if (gr == 0.0f && gg == 0.0f && gb == 0.0f && ga == 0.0f) return;
-  float* q = dp + (((size_t)k * a.hp + iy) * a.wp + ix) * 4;
-  atomicAdd(q + 0, w * gr);
-  atomicAdd(q + 1, w * gg);
-  atomicAdd(q + 2, w * gb);
-  atomicAdd(q + 3, w * ga);
-}
-
-template <typename PT, bool BIL>
-__global__ __launch_bounds__(kBwdThreads) void composite_bwd(CompositeArgs a, const float* __restrict__ d_out,
-                                                             float* __restrict__ d_planes) {
-  __shared__ float ckpt[kBwdCkpt][kBwdThreads];
-  __shared__ float tseg[kBwdCkpt][kBwdThreads];
-  const int64_t n = (int64_t)a.n_views * a.ny * a.nx;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;                                       // no barriers below: LDS columns are per thread
-  const int tid = threadIdx.x;
-  const int x = (int)(i % a.nx);
-  const int y = (int)((i / a.nx) % a.ny);
-  const int v = (int)(i / ((int64_t)a.nx * a.ny));
-  const float4 g = reinterpret_cast<const float4*>(d_out)[i];
-  if (g.x == 0.0f && g.y == 0.0f && g.z == 0.0f && g.w == 0.0f) return;   // contributes nothing
-  const PT* planes = static_cast<const PT*>(a.planes);
-  const float xr = (float)x - a.c.cx, yr = (float)y - a.c.cy;
-  const float dx = a.dx[v], dy = a.dy[v];
-  const int S = (a.K + kBwdCkpt - 1) / kBwdCkpt;          // planes per segment
-  const int nseg = (a.K + S - 1) / S;
-  float T = 1.0f;
-  for (int k = 0; k < a.K; ++k) {
-    if (k % S == 0) ckpt[k / S][tid] = T;
-    const float4 s = sample_value<PT, BIL>(a, planes, k, sample_tap<BIL>(a, k, xr, yr, dx, dy));
-    T = fmaf(-T, s.w, T);
-  }
-  float Rr = 0.f, Rg = 0.f, Rb = 0.f, Sf = 1.0f;
-  for (int sg = nseg - 1; sg >= 0; --sg) {
-    const int k0 = sg * S, k1 = min(a.K, k0 + S);
-    float Tk = ckpt[sg][tid];
-    for (int k = k0; k < k1; ++k) {
-      tseg[k - k0][tid] = Tk;
-      const float4 s = sample_value<PT, BIL>(a, planes, k, sample_tap<BIL>(a, k, xr, yr, dx, dy));
-      Tk = fmaf(-Tk, s.w, Tk);
-    }
-    for (int k = k1 - 1; k >= k0; --k) {
-      const Tap t = sample_tap<BIL>(a, k, xr, yr, dx, dy);
-      const float4 s = sample_value<PT, BIL>(a, planes, k, t);
-      const float Tb = tseg[k - k0][tid];
-      const float gr = Tb * g.x, gg = Tb * g.y, gb = Tb * g.z;
-      const float ga = -Tb * ((g.x * Rr + g.y * Rg + g.z * Rb) + g.w * Sf);
-      if (!BIL) {
-        add_texel_grad(d_planes, a, k, t.ix, t.iy, 1.0f, gr, gg, gb, ga);
-      } else {
-        const float w00 = (1.0f - t.wx) * (1.0f - t.wy), w01 = t.wx * (1.0f - t.wy);
-        const float w10 = (1.0f - t.wx) * t.wy, w11 = t.wx * t.wy;
-        add_texel_grad(d_planes, a, k, t.ix, t.iy, w00, gr, gg, gb, ga);
-        add_texel_grad(d_planes, a, k, t.ix + 1, t.iy, w01, gr, gg, gb, ga);
-        add_texel_grad(d_planes, a, k, t.ix, t.iy + 1, w10, gr, gg, gb, ga);
-        add_texel_grad(d_planes, a, k, t.ix + 1, t.iy + 1, w11, gr, gg, gb, ga);
-      }
-      const float om = 1.0f - s.w;
-      Rr = fmaf(om, Rr, s.x);
-      Rg = fmaf(om, Rg, s.y);
-      Rb = fmaf(om, Rb, s.z);
-      Sf = om * Sf;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------------------
-// Row backward (all views share dy).  One work-group per (output row y, group of G views,
-// segment of 256 pixels); a thread owns pixel x for the G views.  T_k is not checkpointed:
+// evaluated back to front; a sample's cotangent goes to its texels through the transposed
+// interpolation weights.
+// One work-group per (output row y, view group of up to G views that share dy, segment of
+// 256 pixels); a thread owns pixel x for the group's views.  T_k is not checkpointed:
 // the forward sweep keeps, per view, the last plane m whose incoming transmittance T_m is
 // at least kTinyT, and the backward sweep recovers T_k = T_{k+1} / (1 - a_k) for k < m
 // (exact up to rounding: T_{k+1} > 0 there, so a_k < 1).  Planes behind m see T < kTinyT and
@@ -669,7 +555,7 @@ struct BwdPlane {
 
 template <bool BIL>
 __device__ __forceinline__ BwdPlane bwd_plane(const CompositeArgs& a, const float4* pt, const float* ct, int k, int v0,
-                                              int nv, float yr, float xr_lo, float xr_hi, int Vp) {
+                                              int nv, float yr, float xr_lo, float xr_hi, int S) {
   const float4 p = pt[k];                                  // (bx, by, Cy, valid)
   BwdPlane b;
   b.bx = p.x;
@@ -686,7 +572,7 @@ __device__ __forceinline__ BwdPlane bwd_plane(const CompositeArgs& a, const floa
     b.iy = __float2int_rd(fy0);
     b.ok = b.ok && b.iy >= -1 && b.iy < a.hp;
   }
-  const float* crow = ct + (size_t)k * Vp + v0;
+  const float* crow = ct + (size_t)k * S + v0;
   float cmin = crow[0], cmax = crow[0];
   for (int j = 1; j < nv; ++j) {
     cmin = fminf(cmin, crow[j]);
@@ -729,14 +615,16 @@ __global__ __launch_bounds__(kRowBwdThreads) void composite_rows_bwd(CompositeAr
   __shared__ float swx[BIL ? G : 1][kRowBwdThreads];       // its bilinear weight
   __shared__ short first[G][kRowBwdWin];                   // first x of each view's run per texel
   const int y = blockIdx.x;
-  const int v0 = blockIdx.y * G;
-  const int nv = min(G, a.n_views - v0);
+  const uint32_t gd = a.vgroup[blockIdx.y];
+  const int v0 = gd & 0xffu;                               // group's first position in perm
+  const int nv = gd >> 8;
+  pt += (size_t)blockIdx.y * a.K;
   const int tid = threadIdx.x;
   const int xs0 = blockIdx.z * kRowBwdThreads;
   const int x = xs0 + tid;
   const bool xin = x < a.nx;
   const int xs1 = min(xs0 + kRowBwdThreads, a.nx) - 1;
-  const int Vp = padded_views(a.n_views);
+  const int Vp = ct_stride(a.n_views);
   const PT* __restrict__ planes = static_cast<const PT*>(a.planes);
   const float xr = (float)x - a.c.cx, yr = (float)y - a.c.cy;
   const float xrp = (float)(x - 1) - a.c.cx;
@@ -747,7 +635,7 @@ __global__ __launch_bounds__(kRowBwdThreads) void composite_rows_bwd(CompositeAr
   int m[G];
 #pragma unroll
   for (int j = 0; j < G; ++j) {
-    g[j] = (xin && j < nv) ? d_out[((size_t)(v0 + j) * a.ny + y) * a.nx + x] : make_float4(0.f, 0.f, 0.f, 0.f);
+    g[j] = (xin && j < nv) ? d_out[((size_t)a.perm[v0 + j] * a.ny + y) * a.nx + x] : make_float4(0.f, 0.f, 0.f, 0.f);
     T[j] = 1.0f;
     Tm[j] = 1.0f;
     m[j] = -1;
@@ -958,17 +846,6 @@ __global__ void zero_f32(float* p, int64_t n) {
   if (i < n) p[i] = 0.0f;
 }
 
-template <typename PT>
-hipError_t launch_bwd(const CompositeArgs& a, const float* d_out, float* d_planes, hipStream_t s) {
-  const int64_t n = (int64_t)a.n_views * a.ny * a.nx;
-  const dim3 grid((unsigned)((n + kBwdThreads - 1) / kBwdThreads));
-  if (a.interp == LF_BILINEAR)
-    hipLaunchKernelGGL((composite_bwd<PT, true>), grid, dim3(kBwdThreads), 0, s, a, d_out, d_planes);
-  else
-    hipLaunchKernelGGL((composite_bwd<PT, false>), grid, dim3(kBwdThreads), 0, s, a, d_out, d_planes);
-  return hipGetLastError();
-}
-
 // threads of a row work-group, and whether the whole-row window fits its buffer and fetch
 int row_threads(int nx) {
   const int nseg = (nx + kRowThreads - 1) / kRowThreads;
@@ -983,8 +860,50 @@ bool rows_fit(const CompositeArgs& a) {
   return entries <= (bil ? kWin / 2 : kWin) && entries <= per_thread * row_threads(a.nx);
 }
 
-template <int G>
-int pick_cost(int V) { return ((V + G - 1) / G) * (G + 4); }
+// Views that share dy, as classes in the order of their first view, each class's views in
+// index order: perm lists them class by class, cls_end[c] is where class c ends in perm.
+int dy_classes(CompositeArgs& a, int* cls_end) {
+  bool placed[LF_MAX_VIEWS] = {};
+  int n = 0, nc = 0;
+  for (int v = 0; v < a.n_views; ++v) {
+    if (placed[v]) continue;
+    for (int u = v; u < a.n_views; ++u) {
+      if (!placed[u] && a.dy[u] == a.dy[v]) {
+        placed[u] = true;
+        a.perm[n++] = (uint8_t)u;
+      }
+    }
+    cls_end[nc++] = n;
+  }
+  return nc;
+}
+
+// Row-kernel cost of groups of G: work-groups per row times their per-view work plus a
+// fixed per-plane part worth about four views.
+int group_cost(const int* cls_end, int nc, int G) {
+  int cost = 0;
+  for (int c = 0, s = 0; c < nc; s = cls_end[c++]) cost += (cls_end[c] - s + G - 1) / G * (G + 4);
+  return cost;
+}
+
+// Cuts every class into runs of at most G views: a.vgroup / a.n_groups.
+void fill_groups(CompositeArgs& a, const int* cls_end, int nc, int G) {
+  int g = 0;
+  for (int c = 0, s = 0; c < nc; s = cls_end[c++])
+    for (int p = s; p < cls_end[c]; p += G) a.vgroup[g++] = (uint16_t)(p | (std::min(G, cls_end[c] - p) << 8));
+  a.n_groups = g;
+}
+
+// Table of composite coefficients: pt [groups][K] float4, then ct [K][ct_stride(V)] float.
+void table_parts(void* table, int K, int V, float4** pt, float** ct) {
+  *pt = static_cast<float4*>(table);
+  *ct = reinterpret_cast<float*>(static_cast<char*>(table) + (((size_t)K * V * 16 + 255) & ~(size_t)255));
+}
+
+void launch_table(const CompositeArgs& a, float4* pt, float* ct, hipStream_t s) {
+  const int n = a.K * ct_stride(a.n_views);
+  hipLaunchKernelGGL(coeff_table, dim3((n + 255) / 256), dim3(256), 0, s, a, pt, ct);
+}
 
 template <typename PT, typename OT, bool BIL>
 hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const float* ct, hipStream_t s) {
@@ -992,7 +911,7 @@ hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const fl
   const int seg = (a.nx + nseg - 1) / nseg;
   const int threads = ((seg + 63) / 64) * 64;
   const size_t lds = (size_t)2 * kWinStride * 16;
-  const dim3 grid(a.ny, (a.n_views + G - 1) / G, nseg);
+  const dim3 grid(a.ny, a.n_groups, nseg);
   switch (G) {
     case 4: hipLaunchKernelGGL((composite_rows<PT, OT, 4, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
     case 8: hipLaunchKernelGGL((composite_rows<PT, OT, 8, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
@@ -1023,57 +942,10 @@ hipError_t dispatch_out(const CompositeArgs& a, bool rows, int G, const float4* 
                                : dispatch_interp<PT, float>(a, rows, G, pt, ct, s);
 }
 
-}  // namespace
-
-size_t composite_table_bytes(int K, int n_views) {
-  return (size_t)K * 16 + (size_t)K * padded_views(n_views) * 4 + 256;
-}
-
-hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, Profiler* prof) {
-  float4* pt = static_cast<float4*>(table);
-  float* ct = reinterpret_cast<float*>(static_cast<char*>(table) + (((size_t)a.K * 16 + 255) & ~(size_t)255));
-  bool same_dy = true;
-  for (int v = 1; v < a.n_views; ++v) same_dy = same_dy && a.dy[v] == a.dy[0];
-  // the clamped whole-row fallback must fit the window buffer and the fetch of one
-  // work-group (kPrefetch entries per thread, half of them for bilinear)
-  const bool rows = same_dy && rows_fit(a);
-  int G = 16, best = pick_cost<16>(a.n_views);
-  if (pick_cost<12>(a.n_views) < best) { G = 12; best = pick_cost<12>(a.n_views); }
-  if (pick_cost<8>(a.n_views) < best) { G = 8; best = pick_cost<8>(a.n_views); }
-  if (pick_cost<4>(a.n_views) < best) { G = 4; best = pick_cost<4>(a.n_views); }
-  // an explicit group (autotuned) wins; else the LF_COMPOSITE_GROUP tuning override
-  if (a.group == 4 || a.group == 8 || a.group == 12 || a.group == 16) {
-    G = a.group;
-  } else if (const char* e = getenv("LF_COMPOSITE_GROUP")) {
-    const int g = atoi(e);
-    if (g == 4 || g == 8 || g == 12 || g == 16) G = g;
-  }
-  if (rows) {
-    PhaseScope ps(prof, LF_PHASE_COEFF, s);
-    const int n = a.K * padded_views(a.n_views);
-    hipLaunchKernelGGL(coeff_table, dim3((n + 255) / 256), dim3(256), 0, s, a, pt, ct);
-  }
-  PhaseScope ps(prof, LF_PHASE_COMPOSITE, s);
-  switch (a.plane_dtype) {
-    case LF_F16: return dispatch_out<__half>(a, rows, G, pt, ct, s);
-    case LF_BF16: return dispatch_out<__hip_bfloat16>(a, rows, G, pt, ct, s);
-    case LF_U8: return dispatch_out<uint8_t>(a, rows, G, pt, ct, s);
-    default: return dispatch_out<float>(a, rows, G, pt, ct, s);
-  }
-}
-
 template <typename PT>
-hipError_t launch_rows_bwd(const CompositeArgs& a, const float4* pt, const float* ct, const float* d_out,
+hipError_t launch_rows_bwd(const CompositeArgs& a, int G, const float4* pt, const float* ct, const float* d_out,
                            float* d_planes, hipStream_t s) {
-  // views per work-group (4: few enough registers and LDS for four or five work-groups
-  // per CU, which hides the latency of the per-plane staging); LF_BWD_GROUP overrides
-  int G = 4;
-  if (const char* e = getenv("LF_BWD_GROUP")) {
-    const int g = atoi(e);
-    if (g == 4 || g == 8 || g == 16) G = g;
-  }
-  const dim3 grid((unsigned)a.ny, (unsigned)((a.n_views + G - 1) / G),
-                  (unsigned)((a.nx + kRowBwdThreads - 1) / kRowBwdThreads));
+  const dim3 grid((unsigned)a.ny, (unsigned)a.n_groups, (unsigned)((a.nx + kRowBwdThreads - 1) / kRowBwdThreads));
   const float4* go = reinterpret_cast<const float4*>(d_out);
   const dim3 blk(kRowBwdThreads);
   if (G == 16) {
@@ -1089,31 +961,83 @@ hipError_t launch_rows_bwd(const CompositeArgs& a, const float4* pt, const float
   return hipGetLastError();
 }
 
-hipError_t composite_backward_launch(const CompositeArgs& a, void* table, const float* d_out, float* d_planes,
-                                    hipStream_t s, Profiler* prof) {
-  float4* pt = static_cast<float4*>(table);
-  float* ct = reinterpret_cast<float*>(static_cast<char*>(table) + (((size_t)a.K * 16 + 255) & ~(size_t)255));
-  bool same_dy = true;
-  for (int v = 1; v < a.n_views; ++v) same_dy = same_dy && a.dy[v] == a.dy[0];
-  if (same_dy) {
+}  // namespace
+
+size_t composite_table_bytes(int K, int n_views) {
+  // at most one view group per view
+  return (((size_t)K * n_views * 16 + 255) & ~(size_t)255) + (size_t)K * ct_stride(n_views) * 4 + 256;
+}
+
+hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profiler* prof) {
+  float4* pt;
+  float* ct;
+  table_parts(table, a.K, a.n_views, &pt, &ct);
+  int cls_end[LF_MAX_VIEWS];
+  const int nc = dy_classes(a, cls_end);
+  int G = 16, best = group_cost(cls_end, nc, 16);
+  for (int g : {12, 8, 4}) {
+    const int c = group_cost(cls_end, nc, g);
+    if (c < best) { G = g; best = c; }
+  }
+  // The row kernel needs the clamped whole-row fallback to fit the window buffer and the
+  // fetch of one work-group (kPrefetch entries per thread, half of them for bilinear).  It
+  // is taken while its cost stays below about four units per view: measured on MI355X
+  // (512 x 512 views, 64 planes, 45 views) a cost unit takes 0.006 ms nearest / 0.013 ms
+  // bilinear and the per-pixel kernel 0.025 / 0.05 ms per view, so quilts with several views
+  // per dy take the row kernel and lists of all-distinct dy the per-pixel one.
+  // LF_COMPOSITE_KERNEL=rows|general overrides the choice (tuning and tests).
+  const char* kern = getenv("LF_COMPOSITE_KERNEL");
+  bool rows = best <= 4 * a.n_views;
+  if (kern && std::strcmp(kern, "rows") == 0) rows = true;
+  if (kern && std::strcmp(kern, "general") == 0) rows = false;
+  rows = rows && rows_fit(a);
+  // an explicit group (autotuned) wins; else the LF_COMPOSITE_GROUP tuning override
+  if (a.group == 4 || a.group == 8 || a.group == 12 || a.group == 16) {
+    G = a.group;
+  } else if (const char* e = getenv("LF_COMPOSITE_GROUP")) {
+    const int g = atoi(e);
+    if (g == 4 || g == 8 || g == 12 || g == 16) G = g;
+  }
+  fill_groups(a, cls_end, nc, G);
+  if (rows) {
     PhaseScope ps(prof, LF_PHASE_COEFF, s);
-    const int n = a.K * padded_views(a.n_views);
-    hipLaunchKernelGGL(coeff_table, dim3((n + 255) / 256), dim3(256), 0, s, a, pt, ct);
+    launch_table(a, pt, ct, s);
+  }
+  PhaseScope ps(prof, LF_PHASE_COMPOSITE, s);
+  switch (a.plane_dtype) {
+    case LF_F16: return dispatch_out<__half>(a, rows, G, pt, ct, s);
+    case LF_BF16: return dispatch_out<__hip_bfloat16>(a, rows, G, pt, ct, s);
+    case LF_U8: return dispatch_out<uint8_t>(a, rows, G, pt, ct, s);
+    default: return dispatch_out<float>(a, rows, G, pt, ct, s);
+  }
+}
+
+hipError_t composite_backward_launch(CompositeArgs& a, void* table, const float* d_out, float* d_planes,
+                                    hipStream_t s, Profiler* prof) {
+  float4* pt;
+  float* ct;
+  table_parts(table, a.K, a.n_views, &pt, &ct);
+  // views per work-group (4: few enough registers and LDS for four or five work-groups
+  // per CU, which hides the latency of the per-plane staging); LF_BWD_GROUP overrides
+  int G = 4;
+  if (const char* e = getenv("LF_BWD_GROUP")) {
+    const int g = atoi(e);
+    if (g == 4 || g == 8 || g == 16) G = g;
+  }
+  int cls_end[LF_MAX_VIEWS];
+  const int nc = dy_classes(a, cls_end);
+  fill_groups(a, cls_end, nc, G);
+  {
+    PhaseScope ps(prof, LF_PHASE_COEFF, s);
+    launch_table(a, pt, ct, s);
   }
   PhaseScope ps(prof, LF_PHASE_COMPOSITE_BWD, s);
   const int64_t np = (int64_t)a.K * a.hp * a.wp * 4;
   if (np > 0) hipLaunchKernelGGL(zero_f32, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, d_planes, np);
-  if (same_dy) {
-    switch (a.plane_dtype) {
-      case LF_F16: return launch_rows_bwd<__half>(a, pt, ct, d_out, d_planes, s);
-      case LF_BF16: return launch_rows_bwd<__hip_bfloat16>(a, pt, ct, d_out, d_planes, s);
-      default: return launch_rows_bwd<float>(a, pt, ct, d_out, d_planes, s);
-    }
-  }
   switch (a.plane_dtype) {
-    case LF_F16: return launch_bwd<__half>(a, d_out, d_planes, s);
-    case LF_BF16: return launch_bwd<__hip_bfloat16>(a, d_out, d_planes, s);
-    default: return launch_bwd<float>(a, d_out, d_planes, s);
+    case LF_F16: return launch_rows_bwd<__half>(a, G, pt, ct, d_out, d_planes, s);
+    case LF_BF16: return launch_rows_bwd<__hip_bfloat16>(a, G, pt, ct, d_out, d_planes, s);
+    default: return launch_rows_bwd<float>(a, G, pt, ct, d_out, d_planes, s);
   }
 }
 

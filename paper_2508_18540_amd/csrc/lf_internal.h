@@ -95,11 +95,18 @@ struct CompositeArgs {
   Consts c;
   float dx[LF_MAX_VIEWS];
   float dy[LF_MAX_VIEWS];
+  // View groups of the row kernels, filled by the launch: views that share dy, listed class
+  // by class in perm (position -> view index); vgroup[g] = first position | count << 8.
+  int32_t n_groups;
+  uint16_t vgroup[LF_MAX_VIEWS];
+  uint8_t perm[LF_MAX_VIEWS];
 };
+static_assert(LF_MAX_VIEWS <= 256, "view positions and group starts are 8-bit");
 
 // Bytes of the coefficient table lf_composite keeps in its context for K planes, V views.
 size_t composite_table_bytes(int K, int n_views);
-hipError_t composite_launch(const CompositeArgs& a, void* table, hipStream_t s, Profiler* prof = nullptr);
+// Fills a's view groups, then launches the composite of a's views.
+hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profiler* prof = nullptr);
 // Validated composite arguments (host); shared by lf_composite and the batch entry points.
 lf_status composite_args(const lf_mpi* mpi, const lf_camera* cam, const lf_view* views, int32_t n_views,
                          CompositeArgs* a);
@@ -107,7 +114,7 @@ hipError_t plane_coeffs_launch(const CompositeArgs& a, float* bx, float* by, flo
                                float* cxn, float* cyn, hipStream_t s);
 // Zero-fills d_planes [K][hp][wp][4] and accumulates the composite's VJP of d_out into it
 // (table: composite_table_bytes(K, V) of device scratch for the sampling coefficients).
-hipError_t composite_backward_launch(const CompositeArgs& a, void* table, const float* d_out, float* d_planes,
+hipError_t composite_backward_launch(CompositeArgs& a, void* table, const float* d_out, float* d_planes,
                                     hipStream_t s, Profiler* prof = nullptr);
 
 }  // namespace lf

@@ -237,6 +237,10 @@ CONFIGS = {
     "cluster500k": dict(scene=("cluster", dict(n=500_000, seed=1)), res=512, n_chunk=64,
                         binning="quantile", vx=45, vy=1, d_focal=2.0, phi_x=math.radians(40.0),
                         fov_deg=50.0),
+    # 2D parallax: the cluster500k scene and planes seen by a 9 x 5 quilt over +-20 x +-10 deg
+    "quilt2d": dict(scene=("cluster", dict(n=500_000, seed=1)), res=512, n_chunk=64,
+                    binning="quantile", vx=9, vy=5, d_focal=2.0, phi_x=math.radians(40.0),
+                    phi_y=math.radians(20.0), fov_deg=50.0),
     # sparse voxels, 512^2, 64 quantile planes, 96 views
     "voxel256": dict(scene=("voxel", dict(seed=2)), res=512, n_chunk=64, binning="quantile",
                      vx=96, vy=1, d_focal=4.0, phi_x=math.radians(40.0), fov_deg=50.0),

@@ -88,7 +88,7 @@ def test_composite_low_precision_planes(pdt, interp):
 @pytest.mark.parametrize("shape", [(256, 192, 24, 15, 1), (96, 80, 6, 4, 3)], ids=["rows", "general_vy3"])
 def test_composite_u8_planes(interp, shape):
     """UNORM8 planes (Sec. 5.1), accumulated in FP32: 1e-4 against the oracle composite of
-    the same codes read back as code / 255 (row kernel and the per-pixel kernel)."""
+    the same codes read back as code / 255 (one and three dy classes)."""
     nx, ny, K, vx, vy = shape
     announce("composite u8", nx, ny, K, vx, vy, interp)
     cam, g, p, dx, dy = _setup(nx, ny, K, vx, vy, 14, phi_y=12.0 if vy > 1 else 0.0)
@@ -98,6 +98,52 @@ def test_composite_u8_planes(interp, shape):
     err = np.abs(host(out) - ref).max()
     print("u8", interp, "max-abs", err)
     assert err <= 1e-4
+
+
+def _view_list(kind, cam, seed):
+    """Offsets of the view-list shapes the row kernel groups by dy: a 5 x 3 quilt (2D
+    parallax), a list whose dy repeat in scattered order (classes of 1 to 9 views), and a
+    list of all-distinct dy (head-tracked viewers)."""
+    rng = np.random.default_rng(seed)
+    if kind == "quilt5x3":
+        dx, dy, _, _ = geometry.quilt_views(cam, 5, 3)
+    elif kind == "scattered":
+        ys = np.array([-0.06, 0.0, 0.02, 0.05])
+        dy = np.concatenate([np.repeat(ys, [9, 5, 3, 3]), rng.uniform(-0.08, 0.08, 3)])
+        dy = dy[rng.permutation(len(dy))]
+        dx = rng.uniform(-0.3, 0.3, len(dy))
+    else:
+        dy = rng.uniform(-0.08, 0.08, 12)
+        dx = rng.uniform(-0.3, 0.3, 12)
+    return np.asarray(dx, np.float32), np.asarray(dy, np.float32)
+
+
+@pytest.mark.parametrize("kernel", ["rows", "general"])
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+@pytest.mark.parametrize("kind", ["quilt5x3", "scattered", "distinct"])
+def test_composite_view_lists(kind, interp, kernel, monkeypatch):
+    """Views with different vertical offsets (2D parallax, arbitrary view lists): the row
+    kernel with views grouped by dy, and the per-pixel kernel, against the oracle."""
+    announce("composite view list", kind, interp, kernel)
+    monkeypatch.setenv("LF_COMPOSITE_KERNEL", kernel)
+    cam, g, p, _, _ = _setup(120, 72, 9, 1, 1, 15, phi_y=12.0)
+    dx, dy = _view_list(kind, cam, 4)
+    ref, _ = composite.composite(p["rgba"], p["depth"], cam, g, dx, dy, interp)
+    out = T.composite(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy), interp)
+    err = np.abs(host(out) - ref).max()
+    assert err <= 1e-4, err
+
+
+@pytest.mark.parametrize("group", ["4", "16"])
+def test_composite_view_groups_forced_size(group, monkeypatch):
+    """Every group size cuts the dy classes into runs that cover each view once."""
+    announce("composite view groups", group)
+    monkeypatch.setenv("LF_COMPOSITE_GROUP", group)
+    cam, g, p, _, _ = _setup(96, 64, 5, 1, 1, 16, phi_y=12.0)
+    dx, dy = _view_list("scattered", cam, 5)
+    ref, _ = composite.composite(p["rgba"], p["depth"], cam, g, dx, dy, "nearest")
+    out = T.composite(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy), "nearest")
+    assert np.abs(host(out) - ref).max() <= 1e-4
 
 
 def test_composite_fp16_output():

@@ -51,6 +51,31 @@ def test_composite_backward_matches_oracle(interp, pdt):
     _check(got, ref, f"d_planes {interp} {pdt}")
 
 
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+@pytest.mark.parametrize("kind", ["quilt3x2", "scattered"])
+def test_composite_backward_2d_views(kind, interp):
+    """Views with different vertical offsets: the row backward with views grouped by dy."""
+    announce("composite backward 2d", kind, interp)
+    cam = scenegen.camera(40, 36, 50.0, 3.0, math.radians(30.0), math.radians(10.0))
+    g = geometry.derive(cam)
+    K = 6
+    p = scenegen.random_planes(K, g.hp, g.wp, seed=12)
+    if kind == "quilt3x2":
+        dx, dy, _, _ = geometry.quilt_views(cam, 3, 2)
+    else:
+        rng = np.random.default_rng(7)
+        dy = np.array([0.03, -0.02, 0.03, 0.0, -0.02, 0.03, 0.05])
+        dx = rng.uniform(-0.25, 0.25, len(dy))
+    dx, dy = np.asarray(dx, np.float32), np.asarray(dy, np.float32)
+    d = grad.composite_decisions(cam, p["depth"], dx, dy, interp)
+    d_out = np.random.default_rng(3).normal(size=(len(dx), cam.ny, cam.nx, 4))
+    got = host(T.composite_backward(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy),
+                                    dev(d_out, torch.float32), interp))
+    ref = grad.composite_vjp(np.asarray(p["rgba"], np.float32).astype(np.float64), d, cam,
+                             d_out.astype(np.float32).astype(np.float64))
+    _check(got, ref, f"d_planes 2d {kind} {interp}")
+
+
 def _small_problem(seed=3, n=300, res=48, K=4, V=5, interp="nearest"):
     scene = scenegen.small_scene(n, seed)
     cam = scenegen.camera(res, res, 50.0, 3.0, math.radians(30.0))
