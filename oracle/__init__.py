@@ -16,9 +16,10 @@ This package is a plain, slow, obviously-correct restatement of what the paper
 * ``render``     conventional per-view rendering (the paper's ground-truth baseline)
 * ``grad``       gradients of a multi-view L2 loss (torch-CPU float64 autograd)
 * ``quantize``   UNORM8 plane storage (Sec. 5.1)
+* ``sh``         spherical-harmonic colour in the planes (the SH ablation, Fig. 6)
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import it.  It shares no code with the GPU path; the only common
 dependency is the seeded input generator ``scenegen``.
 """
-from . import geometry, decisions, partition, project, splat, composite, render, voxels, grad, quantize  # noqa: F401
+from . import geometry, decisions, partition, project, splat, composite, render, voxels, grad, quantize, sh  # noqa: F401

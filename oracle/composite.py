@@ -40,6 +40,35 @@ def _sample_mask(mask, iy, ix):
     return mask[np.clip(iy, 0, H - 1)][:, np.clip(ix, 0, W - 1)] & (vy[:, None] & vx[None, :])
 
 
+def sample_plane(plane, pc, c, k: int, v: int, xs, ys, interp: str, mask=None):
+    """Plane k [H,W,C] sampled at the pixels (xs x ys) of view v (Eq. 6): returns (s [Ny,Nx,C],
+    whether a sample touches a masked texel [Ny,Nx] or None without a mask)."""
+    if interp == "nearest":
+        X, Y = decisions.texel_coords32(pc, c, k, v, xs, ys, nearest=True)
+        ix = np.floor(X).astype(np.int64)
+        iy = np.floor(Y).astype(np.int64)
+        s = _sample_rows_cols(plane, iy, ix)
+        return s, (None if mask is None else _sample_mask(mask, iy, ix))
+    if interp != "bilinear":
+        raise ValueError(interp)
+    X, Y = decisions.texel_coords32(pc, c, k, v, xs, ys, nearest=False)
+    x0 = np.floor(X)
+    y0 = np.floor(Y)
+    wx = X.astype(np.float64) - x0
+    wy = Y.astype(np.float64) - y0
+    x0 = x0.astype(np.int64)
+    y0 = y0.astype(np.int64)
+    s = 0.0
+    pa = None if mask is None else np.zeros((len(ys), len(xs)), dtype=bool)
+    for oy, fy in ((0, 1.0 - wy), (1, wy)):
+        for ox, fx in ((0, 1.0 - wx), (1, wx)):
+            wgt = fy[:, None] * fx[None, :]
+            s = s + _sample_rows_cols(plane, y0 + oy, x0 + ox) * wgt[..., None]
+            if mask is not None:
+                pa |= _sample_mask(mask, y0 + oy, x0 + ox) & (wgt > 0)
+    return s, pa
+
+
 def composite(planes, depth32, cam, geom, dx32, dy32, interp: str = "nearest", amb=None, views=None):
     """Composite all pixels of the selected views.
 
@@ -60,30 +89,9 @@ def composite(planes, depth32, cam, geom, dx32, dy32, interp: str = "nearest", a
         T = np.ones((Ny, Nx))
         pa = np.zeros((Ny, Nx), dtype=bool)
         for k in range(K):
-            if interp == "nearest":
-                X, Y = decisions.texel_coords32(pc, c, k, v, xs, ys, nearest=True)
-                ix = np.floor(X).astype(np.int64)
-                iy = np.floor(Y).astype(np.int64)
-                s = _sample_rows_cols(planes[k], iy, ix)
-                if amb is not None:
-                    pa |= _sample_mask(amb[k], iy, ix)
-            elif interp == "bilinear":
-                X, Y = decisions.texel_coords32(pc, c, k, v, xs, ys, nearest=False)
-                x0 = np.floor(X)
-                y0 = np.floor(Y)
-                wx = X.astype(np.float64) - x0
-                wy = Y.astype(np.float64) - y0
-                x0 = x0.astype(np.int64)
-                y0 = y0.astype(np.int64)
-                s = 0.0
-                for oy, fy in ((0, 1.0 - wy), (1, wy)):
-                    for ox, fx in ((0, 1.0 - wx), (1, wx)):
-                        wgt = fy[:, None] * fx[None, :]
-                        s = s + _sample_rows_cols(planes[k], y0 + oy, x0 + ox) * wgt[..., None]
-                        if amb is not None:
-                            pa |= _sample_mask(amb[k], y0 + oy, x0 + ox) & (wgt > 0)
-            else:
-                raise ValueError(interp)
+            s, m = sample_plane(planes[k], pc, c, k, v, xs, ys, interp, None if amb is None else amb[k])
+            if m is not None:
+                pa |= m
             Q += T[..., None] * s[..., :3]
             T = T * (1.0 - s[..., 3])
         outs.append(np.concatenate([Q, T[..., None]], axis=-1))

@@ -45,9 +45,11 @@ def support_halfwidth(proj: Projected, eps: np.ndarray):
 def render_plane(proj: Projected, height: int, width: int, eps=None):
     """One plane from the Gaussians of one chunk, given in front-to-back order.
 
-    Returns (rgba [H,W,4] float64, ambiguous [H,W] bool).
+    Returns (rgba [H,W,4] float64, ambiguous [H,W] bool).  The colour may have any number
+    of channels c (proj.rgb [n,c]; the planes of spherical-harmonic coefficients blend the
+    coefficients the same way), and the result then has c + 1 channels, alpha last.
     """
-    C = np.zeros((height, width, 3))
+    C = np.zeros((height, width, proj.rgb.shape[1]))
     T = np.ones((height, width))
     amb = np.zeros((height, width), dtype=bool)
     n = proj.mean2d.shape[0]
@@ -84,11 +86,12 @@ def render_plane(proj: Projected, height: int, width: int, eps=None):
 def blend_texels(proj: Projected, px: np.ndarray, py: np.ndarray, eps=None):
     """Premultiplied RGBA of one chunk at arbitrary texel positions (vectorised over Gaussians).
 
-    Returns (rgba [n,4], ambiguous [n]).
+    Returns (rgba [n,4], ambiguous [n]); with c colour channels, [n, c + 1] (alpha last).
     """
     px = np.asarray(px, dtype=np.float64)
     py = np.asarray(py, dtype=np.float64)
-    out = np.zeros((px.size, 4))
+    nc = proj.rgb.shape[1]
+    out = np.zeros((px.size, nc + 1))
     amb = np.zeros(px.size, dtype=bool)
     ng = proj.mean2d.shape[0]
     if ng == 0:
@@ -108,7 +111,7 @@ def blend_texels(proj: Projected, px: np.ndarray, py: np.ndarray, eps=None):
         alpha = np.where(inc, np.minimum(ALPHA_MAX, np.exp(np.minimum(ln_a, 0.0))), 0.0)
         Tin = np.cumprod(np.concatenate([np.ones((1, alpha.shape[1])), 1.0 - alpha[:-1]], axis=0), axis=0)
         w = alpha * Tin
-        out[s:s + step, :3] = w.T @ proj.rgb
-        out[s:s + step, 3] = 1.0 - Tin[-1] * (1.0 - alpha[-1])
+        out[s:s + step, :nc] = w.T @ proj.rgb
+        out[s:s + step, nc] = 1.0 - Tin[-1] * (1.0 - alpha[-1])
         amb[s:s + step] = np.any(np.abs(ln_a - LN_ALPHA_MIN) <= eps[:, None], axis=0)
     return out, amb

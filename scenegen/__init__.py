@@ -202,6 +202,18 @@ def voxel_scene(res: int = 256, n_occupied: int = 335_544, seed: int = 2,
                 grid_res=res)
 
 
+def sh_coefficients(n: int, degree: int, seed: int, dc_range: float = 1.7, ac_scale: float = 0.4) -> np.ndarray:
+    """Spherical-harmonic colour coefficients [n, (degree+1)^2, 3] float32: the DC term
+    uniform in (-dc_range, dc_range), band l >= 1 normal with deviation ac_scale / l."""
+    rng = _rng(seed)
+    nc = (degree + 1) ** 2
+    c = np.empty((n, nc, 3))
+    c[:, 0] = rng.uniform(-dc_range, dc_range, size=(n, 3))
+    for l in range(1, degree + 1):
+        c[:, l * l:(l + 1) ** 2] = rng.normal(scale=ac_scale / l, size=(n, 2 * l + 1, 3))
+    return _f32(c)
+
+
 def random_planes(n_chunk: int, height: int, width: int, seed: int, depth_range=(1.5, 12.0),
                   p_empty: float = 0.3, p_opaque: float = 0.05) -> dict:
     """A premultiplied RGBA plane stack with sorted depths, for compositing tests.
