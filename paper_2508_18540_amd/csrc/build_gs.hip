@@ -846,7 +846,8 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     if ((e = fill(reinterpret_cast<uint32_t*>(a.hdr), a.clear_words, 0u, s)) != hipSuccess) return e;
     if (a.n == 0) {
       // nothing to rasterise: transparent planes at D_focal (or the inverse-depth table)
-      const size_t words = (size_t)a.K * a.c.hp * a.c.wp * (a.plane_dtype == LF_F32 ? 4 : 2);
+      const int texel_words = a.plane_dtype == LF_F32 ? 4 : a.plane_dtype == LF_U8 ? 1 : 2;
+      const size_t words = (size_t)a.K * a.c.hp * a.c.wp * texel_words;
       if ((e = fill(reinterpret_cast<uint32_t*>(a.planes), (int64_t)words, 0u, s)) != hipSuccess) return e;
       hipLaunchKernelGGL(chunk_table, dim3(1), dim3(1024), 0, s, a, a.keys);
       return hipGetLastError();

@@ -244,6 +244,22 @@ def test_sort_digit_widths_agree(key_bits, tile_bits, monkeypatch):
     assert torch.equal(ref["rgba"], got["rgba"])
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16, torch.uint8])
+def test_empty_field_fill_stays_in_planes(dtype):
+    """An empty field clears exactly its planes: a guard region behind them is untouched."""
+    scene = T.to_device({k: v[:0] for k, v in scenegen.small_scene(4, 0).items()})
+    cam = scenegen.camera(32, 32, 50.0, 2.0, math.radians(20))
+    info = L.lf_geometry(L.make_camera(cam))
+    K, n = 3, 3 * info.plane_height * info.plane_width * 4
+    buf = torch.full((n + 4096,), 7, dtype=dtype, device="cuda")
+    out = dict(rgba=buf[:n].view(K, info.plane_height, info.plane_width, 4),
+               depth=torch.empty(K, dtype=torch.float32, device="cuda"))
+    T.build_mpi(ctx(), scene, cam, K, dtype=dtype, out=out)
+    torch.cuda.synchronize()
+    assert float(buf[:n].float().abs().max()) == 0.0
+    assert bool((buf[n:] == 7).all())
+
+
 def test_empty_field():
     scene = {k: v[:0] for k, v in scenegen.small_scene(4, 0).items()}
     cam = scenegen.camera(32, 32, 50.0, 2.0, math.radians(20))
