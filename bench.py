@@ -77,9 +77,9 @@ def parse():
     p.add_argument("--cpu-planes", type=int, default=48, help="planes the CPU oracle rasterises")
     p.add_argument("--cpu-views", type=int, default=6, help="views the CPU oracle composites")
     p.add_argument("--forms", default="f32,f16,u8", help="plane storage forms to time (first one is `value`)")
-    p.add_argument("--extra", default="voxel256,grad200k,quilt2d,batch8",
-                   help="further workloads timed into the same line (voxel256, grad200k, quilt2d, batch8; "
-                        "empty for none)")
+    p.add_argument("--extra", default="voxel256,grad200k,quilt2d,sh500k,batch8",
+                   help="further workloads timed into the same line (voxel256, grad200k, quilt2d, sh500k, "
+                        "batch8; empty for none)")
     p.add_argument("--extra-steps", type=int, default=5)
     p.add_argument("--only-extra", action="store_true",
                    help="time only the --extra workloads (for profiling them on their own)")
@@ -239,6 +239,40 @@ def extra_quilt2d(ctx, steps, warmup):
                 composite_ms_row_kernel=comp["rows"], composite_ms_per_pixel_kernel=comp["general"])
 
 
+def extra_sh500k(ctx, steps, warmup):
+    """SH colour (the ablation of Fig. 6): the cluster500k scene with degree-3 spherical-
+    harmonic colour (seeded coefficients), 512^2, 64 quantile planes of 52 float32s per
+    texel, 45 views; build + composite per step, beside the RGB path's plane bytes."""
+    import torch
+
+    import scenegen
+    from paper_2508_18540_amd import _lib as L
+    from paper_2508_18540_amd import torch_api as T
+
+    scene, cam, cfg = scenegen.config("cluster500k")
+    K, V = cfg["n_chunk"], cfg["vx"]
+    vlist = L.lf_quilt_views(L.make_camera(cam), V, 1)
+    ds = T.to_device(scene)
+    coef = torch.from_numpy(scenegen.sh_coefficients(scene["means"].shape[0], 3, 7)).cuda()
+    ws = T.workspace_for(ds, cam, K)
+    out = T.build_mpi_sh(ctx, ds, coef, cam, K, workspace=ws)
+    info, st = T.build_stats(ctx, ws, check=False)
+    if st == L.LF_ERR_CAPACITY:
+        ws = T.workspace_for(ds, cam, K, entry_capacity=int(info.entries_needed * 1.25))
+        out = T.build_mpi_sh(ctx, ds, coef, cam, K, workspace=ws)
+    img = torch.empty((V, cam.ny, cam.nx, 4), dtype=torch.float32, device="cuda")
+
+    def step():
+        T.build_mpi_sh(ctx, ds, coef, cam, K, workspace=ws, out=out)
+        T.composite_sh(ctx, out["planes"], out["depth"], 3, cam, vlist, "nearest", out=img)
+    ms, ph = _timed(step, warmup, steps, ctx, L)
+    T.build_stats(ctx, ws, check=True)
+    return dict(workload="sh500k: cluster500k with degree-3 SH colour, 512x512, 64 quantile planes (52 float32 "
+                         "per texel), 45 views",
+                views_per_s=round(V / (ms * 1e-3), 1), ms_per_step=round(ms, 4), phases_ms=ph,
+                plane_bytes=int(out["planes"].numel() * 4), rgb_plane_bytes=int(out["planes"][..., :4].numel() * 4))
+
+
 def extra_batch8(ctx, steps, warmup):
     """Eight clustered-Gaussian scenes of uneven size in one batch (seeds 30+i): (N, res,
     N_chunk, views) from 50k / 256^2 / 64 / 9 up to 2M / 768^2 / 128 / 45, FP16 planes and
@@ -300,7 +334,7 @@ def main():
         line = {"only_extra": True}
         for name in [x.strip() for x in args.extra.split(",") if x.strip()]:
             fn = {"voxel256": extra_voxel256, "grad200k": extra_grad200k, "quilt2d": extra_quilt2d,
-                  "batch8": extra_batch8}[name]
+                  "sh500k": extra_sh500k, "batch8": extra_batch8}[name]
             line[name] = fn(ctx, args.extra_steps, 2)
         print(json.dumps(line), flush=True)
         return
@@ -414,7 +448,7 @@ def main():
                                "phases_ms": {k: round(v, 4) for k, v in r["phases_ms"].items()}}
     for name in [x.strip() for x in args.extra.split(",") if x.strip()]:
         fn = {"voxel256": extra_voxel256, "grad200k": extra_grad200k, "quilt2d": extra_quilt2d,
-                  "batch8": extra_batch8}[name]
+                  "sh500k": extra_sh500k, "batch8": extra_batch8}[name]
         line[name] = fn(ctx, args.extra_steps, 2)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, cam, dx, dy, K, args.cpu_planes, args.cpu_views, args.interp)

@@ -235,6 +235,54 @@ lf_status lf_plane_coeffs(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, 
                           float* cyn, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Spherical-harmonic colour (the SH ablation of Sec. 5, Fig. 6).  A Gaussian may carry
+ * real spherical-harmonic colour coefficients sh[n][(L+1)^2][3] (device float32, degree
+ * L <= LF_MAX_SH_DEGREE, basis index j = l^2 + l + m, Condon-Shortley phase in the sign
+ * convention of 3D Gaussian splatting); seen along the unit direction d its colour is
+ * max(sum_j sh_j Y_j(d) + 1/2, 0).  SH planes keep per texel the coefficients blended
+ * with the RGB planes' weights, q_j = sum_i alpha_i T_i sh_ij, and A = 1 - T, in
+ * lf_sh_texel_floats(L) float32s: q_0 (r, g, b), A, q_1 (r, g, b), ..., q_{n-1} (r, g, b),
+ * then zeros.
+ * ------------------------------------------------------------------------------------- */
+#define LF_MAX_SH_DEGREE 3
+
+typedef struct {
+  int32_t degree;         /* L, 0..LF_MAX_SH_DEGREE                                       */
+  int32_t n_chunk;        /* K                                                            */
+  int32_t height, width;  /* H_p, W_p as for lf_mpi                                       */
+  float* planes;          /* [n_chunk][height][width][lf_sh_texel_floats(degree)]         */
+  float* depth;           /* [n_chunk] plane depths d_k                                   */
+} lf_sh_mpi;
+
+/* Floats per SH-plane texel, 4 ceil((3 (L+1)^2 + 1) / 4) (4, 16, 28, 52); 0 for a degree
+ * outside [0, LF_MAX_SH_DEGREE].  Host only.                                              */
+int32_t lf_sh_texel_floats(int32_t degree);
+
+/* Alg. 1 steps 1-5 with SH colour: the partition, tile lists and rasterisation of
+ * lf_build_mpi for a Gaussian field, the planes blending `sh` (device [field->n][(L+1)^2]
+ * [3]) instead of rgb (field->rgb may be NULL; it is not used).  The workspace is that of
+ * lf_build_mpi (lf_build_mpi_workspace) and lf_build_stats reports on it.  Voxel fields:
+ * LF_ERR_UNSUPPORTED.  Enqueued on `stream`.                                              */
+lf_status lf_build_mpi_sh(lf_ctx* ctx, const lf_field* field, const float* sh, const lf_camera* cam,
+                          int32_t n_chunk, int32_t binning, const float* inv_depth_range, lf_sh_mpi* mpi,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Swizzle blending of SH planes (Eqs. 6-7): plane k is sampled by view v at pixel (x, y)
+ * as lf_composite samples it (nearest or bilinear, over all texel floats), and the sample
+ * adds the premultiplied colour max(sum_j q_j Y_j(d) + A / 2, 0), d the world direction of
+ * the pixel's ray in view v (Eq. 5 camera), the same for every plane.  out: device float32
+ * [n_views][ny][nx][4] of (Q_r, Q_g, Q_b, T).  Other arguments as lf_composite.          */
+lf_status lf_composite_sh(lf_ctx* ctx, const lf_sh_mpi* mpi, const lf_camera* cam, const lf_view* views,
+                          int32_t n_views, int32_t interp, float* out, void* stream);
+
+/* Colour of every Gaussian seen from view `view`: max(sum_j sh_j Y_j(d) + 1/2, 0), d the
+ * unit direction from the view camera's centre (Eq. 5: (dx, dy, 0) in base-camera axes) to
+ * the mean.  means [n][3], sh [n][(L+1)^2][3], rgb_out [n][3]: device float32.  With
+ * lf_render_view on the field with rgb = rgb_out this is the per-view render in SH colour. */
+lf_status lf_sh_colours(lf_ctx* ctx, const float* means, const float* sh, int32_t degree, int64_t n,
+                        const lf_camera* cam, const lf_view* view, float* rgb_out, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Batches.  Several scenes (fields, cameras, plane counts, view lists) rendered by one
  * call.  Each scene's build and composite go to a stream of their own, forked from and
  * joined back into the caller's stream, so small scenes run side by side on the GPU.

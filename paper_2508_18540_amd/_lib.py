@@ -29,7 +29,9 @@ EXPORTS = [
     "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_composite_backward",
     "lf_build_mpi_backward", "lf_plane_coeffs", "lf_batch_create", "lf_batch_run", "lf_batch_group",
     "lf_batch_destroy", "lf_profile_enable", "lf_profile_read", "lf_render_view_workspace", "lf_render_view",
+    "lf_sh_texel_floats", "lf_build_mpi_sh", "lf_composite_sh", "lf_sh_colours",
 ]
+LF_MAX_SH_DEGREE = 3
 LF_BATCH_GRAPH, LF_BATCH_AUTOTUNE = 1, 2
 PHASES = ["preprocess", "sort", "bin", "splat", "merge", "filter", "coeff", "composite", "composite_bwd",
           "build_bwd"]
@@ -62,6 +64,11 @@ class lf_mpi(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("n_chunk", C.c_int32), ("height", C.c_int32), ("width", C.c_int32),
                 ("rgba", C.c_void_p), ("depth", C.c_void_p), ("chunk_of", C.c_void_p),
                 ("chunk_count", C.c_void_p)]
+
+
+class lf_sh_mpi(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("n_chunk", C.c_int32), ("height", C.c_int32), ("width", C.c_int32),
+                ("planes", C.c_void_p), ("depth", C.c_void_p)]
 
 
 class lf_geometry_info(C.Structure):
@@ -133,6 +140,12 @@ def load():
         "lf_render_view": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.POINTER(lf_view), C.POINTER(lf_mpi), P,
                             C.c_size_t, P], C.c_int),
         "lf_profile_enable": ([P, C.c_int32], C.c_int),
+        "lf_sh_texel_floats": ([C.c_int32], C.c_int32),
+        "lf_build_mpi_sh": ([P, C.POINTER(lf_field), P, C.POINTER(lf_camera), C.c_int32, C.c_int32,
+                             C.POINTER(C.c_float), C.POINTER(lf_sh_mpi), P, C.c_size_t, P], C.c_int),
+        "lf_composite_sh": ([P, C.POINTER(lf_sh_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
+                             C.c_int32, P, P], C.c_int),
+        "lf_sh_colours": ([P, P, P, C.c_int32, C.c_int64, C.POINTER(lf_camera), C.POINTER(lf_view), P, P], C.c_int),
         "lf_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -231,6 +244,31 @@ def lf_build_mpi(ctx: int, field: lf_field, cam: lf_camera, n_chunk: int, binnin
         rng = (C.c_float * 2)(*[float(v) for v in inv_depth_range])
     _check(load().lf_build_mpi(ctx, C.byref(field), C.byref(cam), n_chunk, binning, rng, C.byref(mpi),
                                workspace, workspace_bytes, stream), "lf_build_mpi")
+
+
+def lf_sh_texel_floats(degree: int) -> int:
+    return int(load().lf_sh_texel_floats(degree))
+
+
+def lf_build_mpi_sh(ctx: int, field: lf_field, sh: int, cam: lf_camera, n_chunk: int, binning: int, inv_depth_range,
+                    mpi: lf_sh_mpi, workspace: int, workspace_bytes: int, stream: int = 0) -> None:
+    rng = None
+    if inv_depth_range is not None:
+        rng = (C.c_float * 2)(*[float(v) for v in inv_depth_range])
+    _check(load().lf_build_mpi_sh(ctx, C.byref(field), sh, C.byref(cam), n_chunk, binning, rng, C.byref(mpi),
+                                  workspace, workspace_bytes, stream), "lf_build_mpi_sh")
+
+
+def lf_composite_sh(ctx: int, mpi: lf_sh_mpi, cam: lf_camera, views, interp: int, out: int, stream: int = 0) -> None:
+    _check(load().lf_composite_sh(ctx, C.byref(mpi), C.byref(cam), views, len(views), interp, out, stream),
+           "lf_composite_sh")
+
+
+def lf_sh_colours(ctx: int, means: int, sh: int, degree: int, n: int, cam: lf_camera, dx: float, dy: float,
+                  rgb_out: int, stream: int = 0) -> None:
+    v = lf_view(float(dx), float(dy))
+    _check(load().lf_sh_colours(ctx, means, sh, degree, n, C.byref(cam), C.byref(v), rgb_out, stream),
+           "lf_sh_colours")
 
 
 def lf_render_view_workspace(field: lf_field, cam: lf_camera) -> int:

@@ -4,6 +4,7 @@
 #include <new>
 
 #include "lf_internal.h"
+#include "sh_basis.h"
 
 namespace lf {
 namespace {
@@ -236,6 +237,69 @@ extern "C" lf_status lf_composite_backward(lf_ctx* ctx, const lf_mpi* mpi, const
   }
   delete a;
   return s;
+}
+
+extern "C" int32_t lf_sh_texel_floats(int32_t degree) {
+  if (degree < 0 || degree > LF_MAX_SH_DEGREE) return 0;
+  return sh_texel_floats((degree + 1) * (degree + 1));
+}
+
+extern "C" lf_status lf_composite_sh(lf_ctx* ctx, const lf_sh_mpi* mpi, const lf_camera* cam, const lf_view* views,
+                                     int32_t n_views, int32_t interp, float* out, void* stream) {
+  if (!mpi) return fail(LF_ERR_INVALID_ARG, "mpi is NULL");
+  if (mpi->degree < 0 || mpi->degree > LF_MAX_SH_DEGREE)
+    return fail(LF_ERR_INVALID_ARG, "SH degree %d outside [0, %d]", mpi->degree, LF_MAX_SH_DEGREE);
+  if (interp != LF_NEAREST && interp != LF_BILINEAR)
+    return fail(LF_ERR_INVALID_ARG, "interp %d is not NEAREST/BILINEAR", interp);
+  if (!out) return fail(LF_ERR_INVALID_ARG, "out is NULL");
+  // the RGB composite's argument block over the SH texels (its dtype check sees F32)
+  const lf_mpi m{LF_F32, mpi->n_chunk, mpi->height, mpi->width, mpi->planes, mpi->depth, nullptr, nullptr};
+  CompositeArgs* a = new (std::nothrow) CompositeArgs;
+  if (!a) return fail(LF_ERR_OUT_OF_MEMORY, "argument block allocation failed");
+  lf_status s = composite_args(&m, cam, views, n_views, a);
+  Geom g;
+  if (s == LF_OK) s = derive_geometry(cam, &g);
+  if (s == LF_OK) s = check_ctx(ctx);
+  if (s == LF_OK) {
+    a->interp = interp;
+    a->out_dtype = LF_F32;
+    a->out = out;
+    // Eq. 5: principal point c + p N / 2 with p = d / (D_focal tan(theta / 2))
+    ShView sv;
+    sv.kx = (float)((double)g.nx / (2.0 * (double)cam->d_focal * g.tx));
+    sv.ky = (float)((double)g.ny / (2.0 * (double)cam->d_focal * g.ty));
+    sv.inv_fx = (float)(1.0 / g.fx);
+    sv.inv_fy = (float)(1.0 / g.fy);
+    const int nc = (mpi->degree + 1) * (mpi->degree + 1);
+    hipError_t e;
+    {
+      PhaseScope ps(&ctx->prof, LF_PHASE_COMPOSITE, (hipStream_t)stream);
+      e = composite_sh_launch(*a, nc, sv, (hipStream_t)stream);
+    }
+    if (e != hipSuccess) s = hip_fail(e, "SH composite launch");
+  }
+  delete a;
+  return s;
+}
+
+extern "C" lf_status lf_sh_colours(lf_ctx* ctx, const float* means, const float* sh, int32_t degree, int64_t n,
+                                   const lf_camera* cam, const lf_view* view, float* rgb_out, void* stream) {
+  if (degree < 0 || degree > LF_MAX_SH_DEGREE)
+    return fail(LF_ERR_INVALID_ARG, "SH degree %d outside [0, %d]", degree, LF_MAX_SH_DEGREE);
+  if (n < 0) return fail(LF_ERR_INVALID_ARG, "n is negative");
+  if (n > 0 && !(means && sh && rgb_out)) return fail(LF_ERR_INVALID_ARG, "means, sh or rgb_out is NULL");
+  if (!cam) return fail(LF_ERR_INVALID_ARG, "camera is NULL");
+  if (!view) return fail(LF_ERR_INVALID_ARG, "view is NULL");
+  if (!(std::isfinite(view->dx) && std::isfinite(view->dy))) return fail(LF_ERR_INVALID_ARG, "view offset is not finite");
+  lf_status s = check_ctx(ctx);
+  if (s != LF_OK) return s;
+  // centre = R^T ((dx, dy, 0) - t)
+  const double o[3] = {(double)view->dx - cam->t[0], (double)view->dy - cam->t[1], -(double)cam->t[2]};
+  float centre[3];
+  for (int i = 0; i < 3; ++i)
+    centre[i] = (float)((double)cam->R[i] * o[0] + (double)cam->R[3 + i] * o[1] + (double)cam->R[6 + i] * o[2]);
+  const hipError_t e = sh_colours_launch(means, sh, (degree + 1) * (degree + 1), n, centre, rgb_out, (hipStream_t)stream);
+  return e == hipSuccess ? LF_OK : hip_fail(e, "SH colour launch");
 }
 
 extern "C" lf_status lf_plane_coeffs(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,

@@ -235,9 +235,14 @@ extern "C" lf_status lf_build_mpi_workspace(const lf_field* field, const lf_came
   return LF_OK;
 }
 
-extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
-                                  int32_t binning, const float* inv_depth_range, lf_mpi* mpi, void* workspace,
-                                  size_t workspace_bytes, void* stream) {
+namespace lf {
+namespace {
+
+// lf_build_mpi, and with sh / sh_coef > 0 the SH planes of lf_build_mpi_sh (mpi then
+// describes float32 planes of sh_texel_floats(sh_coef) floats per texel).
+lf_status build_mpi_impl(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk, int32_t binning,
+                         const float* inv_depth_range, lf_mpi* mpi, const float* sh, int32_t sh_coef, void* workspace,
+                         size_t workspace_bytes, void* stream) {
   Geom g;
   lf_status s = check_common(field, cam, n_chunk, &g);
   if (s != LF_OK) return s;
@@ -258,7 +263,7 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   if (mpi->width != g.wp || mpi->height != g.hp)
     return fail(LF_ERR_INVALID_ARG, "mpi is %dx%d but the camera's planes are %dx%d", mpi->width, mpi->height, g.wp,
                 g.hp);
-  if (!mpi->rgba || !mpi->depth) return fail(LF_ERR_INVALID_ARG, "mpi rgba/depth is NULL");
+  if (!mpi->rgba || !mpi->depth) return fail(LF_ERR_INVALID_ARG, "mpi planes/depth is NULL");
   if (!workspace) return fail(LF_ERR_INVALID_ARG, "workspace is NULL");
   const int64_t n = field->n;
   const int64_t cap = capacity_of(field->kind, n, n_chunk, g.wp, g.hp, workspace_bytes);
@@ -277,6 +282,8 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
     return fail(LF_ERR_INVALID_ARG, "%d tiles x %d chunks do not fit a 32-bit (tile, chunk) key", L.n_tiles, n_chunk);
   BuildArgs a;
   build_args(a, L, field, cam, g, n_chunk, binning, mpi, workspace, cap);
+  a.sh = sh;
+  a.sh_coef = sh_coef;
   if (binning == LF_BIN_INV_DEPTH) {
     // K planes uniform in 1/z over [z_lo, z_hi]: interior edges E_i and plane depths at i = k + 1/2
     std::vector<float> edges((size_t)n_chunk, 0.0f), dtab((size_t)n_chunk);
@@ -290,7 +297,35 @@ extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_c
   return LF_OK;
 }
 
-// The view camera of lf_render_view as a light-field camera with no baseline: D_forward = 0,
+}  // namespace
+}  // namespace lf
+
+extern "C" lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                                  int32_t binning, const float* inv_depth_range, lf_mpi* mpi, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+  return build_mpi_impl(ctx, field, cam, n_chunk, binning, inv_depth_range, mpi, nullptr, 0, workspace,
+                        workspace_bytes, stream);
+}
+
+extern "C" lf_status lf_build_mpi_sh(lf_ctx* ctx, const lf_field* field, const float* sh, const lf_camera* cam,
+                                     int32_t n_chunk, int32_t binning, const float* inv_depth_range, lf_sh_mpi* mpi,
+                                     void* workspace, size_t workspace_bytes, void* stream) {
+  if (!field) return fail(LF_ERR_INVALID_ARG, "field is NULL");
+  if (field->kind != LF_GAUSSIANS) return fail(LF_ERR_UNSUPPORTED, "SH planes cover Gaussian fields only");
+  if (!mpi) return fail(LF_ERR_INVALID_ARG, "mpi is NULL");
+  if (mpi->degree < 0 || mpi->degree > LF_MAX_SH_DEGREE)
+    return fail(LF_ERR_INVALID_ARG, "SH degree %d outside [0, %d]", mpi->degree, LF_MAX_SH_DEGREE);
+  if (field->n > 0 && !sh) return fail(LF_ERR_INVALID_ARG, "sh is NULL");
+  // the RGB build over the SH planes: rgb is not read by the SH splat (preprocess copies
+  // three floats per Gaussian into its records, which sh always holds)
+  lf_field f = *field;
+  if (!f.rgb) f.rgb = sh;
+  lf_mpi m{LF_F32, mpi->n_chunk, mpi->height, mpi->width, mpi->planes, mpi->depth, nullptr, nullptr};
+  return build_mpi_impl(ctx, &f, cam, n_chunk, binning, inv_depth_range, &m, sh, (mpi->degree + 1) * (mpi->degree + 1),
+                        workspace, workspace_bytes, stream);
+}
+
+// The view camera of lf_render_view as a light-field camera with no baseline// The view camera of lf_render_view as a light-field camera with no baseline: D_forward = 0,
 // theta' = theta, one plane at the view resolution, f' = 0.3 texel^2.
 static lf_camera view_camera(const lf_camera* cam) {
   lf_camera v = *cam;

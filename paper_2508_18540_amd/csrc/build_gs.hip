@@ -18,6 +18,7 @@
 #include <cstdlib>
 
 #include "build_device.h"
+#include "sh_basis.h"
 #include "dfloat.h"
 #include "sort_internal.h"
 
@@ -503,6 +504,103 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// SH splat (the spherical-harmonic planes of Fig. 6): the texels blend the Gaussians'
+// NC x 3 colour coefficients with the weights alpha T of the RGB splat, in the same Taylor
+// form and with the same per-quadrant lists.  One work-group per (tile, chunk) bucket walks
+// the bucket's segments in order, so its transmittance carries over and no partial tiles
+// are needed (a texel's state is 3 NC + 1 floats).  Per segment, thread t stages entry t:
+// its quadratic form and its coefficients (LDS), then each wave walks its quadrant's list.
+// The texel is stored as q_0 (r, g, b), A, q_1 .. q_{NC-1} (r, g, b), zero padding.
+// ---------------------------------------------------------------------------------------
+template <int NC>
+__global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_buckets) {
+  constexpr int NF = 3 * NC;                     // coefficient floats per Gaussian
+  constexpr int TF = sh_texel_floats(NC);
+  __shared__ float4 s_p[kSegment];               // (ca, cb, cc, A)
+  __shared__ float2 s_q[kSegment];               // (B, C)
+  __shared__ float s_sh[kSegment][NF];
+  __shared__ uint16_t s_list[4][kSegment];
+  __shared__ int s_cnt[4][4];
+  const int64_t bidx = blockIdx.x;
+  if (bidx >= n_buckets) return;
+  const int tile = (int)(bidx / a.K), k = (int)(bidx % a.K);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
+  const int lxi = ((wave & 1) << 3) + (lane & 7), lyi = ((wave >> 1) << 3) + (lane >> 3);
+  const int px = ox + lxi, py = oy + lyi;
+  const float du = (float)lxi - 7.5f, dv = (float)lyi - 7.5f;
+  const float duu = du * du, duv = du * dv, dvv = dv * dv;
+  const bool ok = a.hdr->overflow == 0;
+  const uint32_t bb0 = a.bucket[bidx], bb1 = ok ? a.bucket[bidx + 1] : bb0;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  float acc[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) acc[j] = 0.0f;
+  float T = 1.0f;
+  for (uint32_t b0 = bb0; b0 < bb1; b0 += kSegment) {
+    const int n = (int)min(bb1 - b0, (uint32_t)kSegment);
+    __syncthreads();                             // the previous segment is consumed
+    uint32_t qm = 0;
+    if (tid < n) {
+      const uint32_t ent = a.evals[b0 + tid];
+      const uint32_t gi = min(ent & 0x0fffffffu, (uint32_t)a.n - 1u);
+      const GRec& g = a.rec[gi];
+      const TileTaylor tt = tile_taylor(g, ox, oy);
+      s_p[tid] = make_float4(g.ca, g.cb, g.cc, tt.A);
+      s_q[tid] = make_float2(tt.B, tt.C);
+      const float* src = a.sh + (size_t)gi * NF;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) s_sh[tid][j] = src[j];
+      qm = reached_quadrants(g, ent >> 28, tt.sx, tt.sy);
+    }
+    uint32_t rank[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t m = __ballot((qm >> q) & 1u);
+      rank[q] = __popcll(m & below);
+      if (lane == 0) s_cnt[q][wave] = __popcll(m);
+    }
+    __syncthreads();
+    int my_count = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int off = 0;
+      for (int w = 0; w < 4; ++w) off += w < wave ? s_cnt[q][w] : 0;
+      if ((qm >> q) & 1u) s_list[q][off + rank[q]] = (uint16_t)tid;
+      if (q == wave) my_count = s_cnt[q][0] + s_cnt[q][1] + s_cnt[q][2] + s_cnt[q][3];
+    }
+    __syncthreads();
+    const int cnt = __builtin_amdgcn_readfirstlane(my_count);
+    for (int i = 0; i < cnt; ++i) {
+      const int e = s_list[wave][i];
+      const float4 P = s_p[e];
+      const float2 Q = s_q[e];
+      const float q = taylor_q(P.x, P.y, P.z, P.w, Q.x, Q.y, du, dv, duu, duv, dvv);
+      const float alpha = q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f;
+      const float w = alpha * T;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) acc[j] = fmaf(w, s_sh[e][j], acc[j]);
+      T = T - w;
+    }
+  }
+  if (px < a.c.wp && py < a.c.hp) {
+    float t[TF];
+    t[0] = acc[0];
+    t[1] = acc[1];
+    t[2] = acc[2];
+    t[3] = 1.0f - T;
+#pragma unroll
+    for (int j = 3; j < NF; ++j) t[j + 1] = acc[j];
+#pragma unroll
+    for (int j = NF + 1; j < TF; ++j) t[j] = 0.0f;
+    float4* dst = reinterpret_cast<float4*>(static_cast<float*>(a.planes) + (((size_t)k * a.c.hp + py) * a.c.wp + px) * TF);
+#pragma unroll
+    for (int j = 0; j < TF / 4; ++j) dst[j] = make_float4(t[4 * j], t[4 * j + 1], t[4 * j + 2], t[4 * j + 3]);
+  }
+}
+
 template <typename PT>
 __device__ void combine_bucket(const BuildArgs& a, int64_t bidx) {
   const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
@@ -846,7 +944,8 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     if ((e = fill(reinterpret_cast<uint32_t*>(a.hdr), a.clear_words, 0u, s)) != hipSuccess) return e;
     if (a.n == 0) {
       // nothing to rasterise: transparent planes at D_focal (or the inverse-depth table)
-      const int texel_words = a.plane_dtype == LF_F32 ? 4 : a.plane_dtype == LF_U8 ? 1 : 2;
+      const int texel_words = a.sh_coef ? sh_texel_floats(a.sh_coef)
+                              : a.plane_dtype == LF_F32 ? 4 : a.plane_dtype == LF_U8 ? 1 : 2;
       const size_t words = (size_t)a.K * a.c.hp * a.c.wp * texel_words;
       if ((e = fill(reinterpret_cast<uint32_t*>(a.planes), (int64_t)words, 0u, s)) != hipSuccess) return e;
       hipLaunchKernelGGL(chunk_table, dim3(1), dim3(1024), 0, s, a, a.keys);
@@ -894,6 +993,18 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
                                      &a.hdr->stalled, s)) != hipSuccess)
       return e;
     hipLaunchKernelGGL(emit_items, dim3(gB), dim3(256), 0, s, a, L.n_buckets);
+  }
+  if (a.sh_coef) {
+    // SH planes: one work-group per bucket, no partial tiles to merge
+    PhaseScope ps(prof, LF_PHASE_SPLAT, s);
+    const dim3 grid((unsigned)L.n_buckets);
+    switch (a.sh_coef) {
+      case 1: hipLaunchKernelGGL((splat_sh_gs<1>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+      case 4: hipLaunchKernelGGL((splat_sh_gs<4>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+      case 9: hipLaunchKernelGGL((splat_sh_gs<9>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+      default: hipLaunchKernelGGL((splat_sh_gs<16>), grid, dim3(256), 0, s, a, L.n_buckets); break;
+    }
+    return hipGetLastError();
   }
   {
     PhaseScope ps(prof, LF_PHASE_SPLAT, s);

@@ -70,6 +70,9 @@ struct BuildArgs {
   Consts c;
   // field (Gaussians)
   const float *means, *log_scales, *quats, *opacity, *rgb;
+  // spherical-harmonic colour [n][sh_coef][3] (SH planes of float32 texels) or none (sh_coef 0)
+  const float* sh;
+  int32_t sh_coef;
   // field (voxels): cells, corner densities, grid origin and cell size; the reference camera
   // centre in world cell units, (R^T ((0, 0, D_fwd) - t) - origin) / h, as double-float
   const int32_t* ijk;

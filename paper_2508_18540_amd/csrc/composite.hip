@@ -40,17 +40,6 @@ namespace {
 
 constexpr int kRowThreads = 512;
 
-struct PlaneCo {
-  float bx, by, gx, gy;
-};
-
-__device__ __forceinline__ PlaneCo plane_co(float d, const Consts& c) {
-  const float z = d - c.d_fwd;
-  const float q = d / z;
-  const float w = (1.0f - d * c.inv_focal) / z;
-  return {c.ratio_x * q, c.ratio_y * q, c.fpx * w, c.fpy * w};
-}
-
 template <typename T>
 __device__ __forceinline__ float4 load_texel(const T* p, size_t i);
 

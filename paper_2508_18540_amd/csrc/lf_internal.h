@@ -85,6 +85,19 @@ lf_status derive_geometry(const lf_camera* cam, Geom* g);
 lf_status fail(lf_status s, const char* fmt, ...);
 lf_status hip_fail(hipError_t e, const char* what);
 
+// Eq. 6 in affine form for the plane at base depth d (see the composite kernels):
+// X = bx (x - c_x) + c'_x + gx dx, Y = by (y - c_y) + c'_y + gy dy, in float32.
+struct PlaneCo {
+  float bx, by, gx, gy;
+};
+
+__device__ __forceinline__ PlaneCo plane_co(float d, const Consts& c) {
+  const float z = d - c.d_fwd;
+  const float q = d / z;
+  const float w = (1.0f - d * c.inv_focal) / z;
+  return {c.ratio_x * q, c.ratio_y * q, c.fpx * w, c.fpy * w};
+}
+
 struct CompositeArgs {
   const void* planes;
   const float* depth;
@@ -112,6 +125,17 @@ lf_status composite_args(const lf_mpi* mpi, const lf_camera* cam, const lf_view*
                          CompositeArgs* a);
 hipError_t plane_coeffs_launch(const CompositeArgs& a, float* bx, float* by, float* cx, float* cy,
                                float* cxn, float* cyn, hipStream_t s);
+// Pixel rays of the views for SH colour: view v's principal point is (c_x + dx kx, c_y + dy ky)
+// (Eq. 5), its rays ((x - c_x,v) / f_x, (y - c_y,v) / f_y, 1) in base-camera axes.
+struct ShView {
+  float kx, ky, inv_fx, inv_fy;
+};
+// Composite of SH planes of n_coef coefficients (a.planes float32 texels of
+// sh_texel_floats(n_coef)) into a.out (float32 views).
+hipError_t composite_sh_launch(const CompositeArgs& a, int n_coef, const ShView& sv, hipStream_t s);
+// Colour of n Gaussians seen from the world point `centre`.
+hipError_t sh_colours_launch(const float* means, const float* sh, int n_coef, int64_t n, const float centre[3],
+                             float* rgb, hipStream_t s);
 // Zero-fills d_planes [K][hp][wp][4] and accumulates the composite's VJP of d_out into it
 // (table: composite_table_bytes(K, V) of device scratch for the sampling coefficients).
 hipError_t composite_backward_launch(CompositeArgs& a, void* table, const float* d_out, float* d_planes,

@@ -181,6 +181,82 @@ def render_view(ctx: Context, scene: dict, cam, dx: float, dy: float = 0.0, dtyp
     return out
 
 
+def _sh_degree(sh: torch.Tensor) -> int:
+    _need(sh, "sh", (torch.float32,), 3)
+    nc = sh.shape[1]
+    degree = int(round(nc ** 0.5)) - 1
+    if (degree + 1) ** 2 != nc or sh.shape[2] != 3 or not 0 <= degree <= L.LF_MAX_SH_DEGREE:
+        raise ValueError(f"sh must be [n, (L+1)^2, 3] with L <= {L.LF_MAX_SH_DEGREE}")
+    return degree
+
+
+def build_mpi_sh(ctx: Context, scene: dict, sh: torch.Tensor, cam, n_chunk: int, binning: str = "quantile",
+                 inv_depth_range=None, workspace: Workspace | None = None, out: dict | None = None) -> dict:
+    """lf_build_mpi_sh: SH planes of a Gaussian field; returns dict(planes [K,H,W,
+    lf_sh_texel_floats(L)] float32, depth [K], degree, workspace)."""
+    degree = _sh_degree(sh)
+    if sh.shape[0] != scene["means"].shape[0]:
+        raise ValueError("sh must have one row per Gaussian")
+    f = field_of(scene)
+    c = L.make_camera(cam)
+    info = L.lf_geometry(c)
+    dev = ctx.device
+    if workspace is None:
+        workspace = workspace_for(scene, cam, n_chunk, device=dev)
+    tf = L.lf_sh_texel_floats(degree)
+    if out is None:
+        out = dict(planes=torch.empty((n_chunk, info.plane_height, info.plane_width, tf), dtype=torch.float32,
+                                      device=dev),
+                   depth=torch.empty(n_chunk, dtype=torch.float32, device=dev))
+    _need(out["planes"], "planes", (torch.float32,), 4)
+    if out["planes"].shape[3] != tf:
+        raise ValueError(f"planes must have {tf} floats per texel for degree {degree}")
+    m = L.lf_sh_mpi(degree, n_chunk, out["planes"].shape[1], out["planes"].shape[2], out["planes"].data_ptr(),
+                    out["depth"].data_ptr())
+    L.lf_build_mpi_sh(ctx.handle, f, sh.data_ptr(), c, n_chunk, _BIN[binning], inv_depth_range, m, workspace.ptr,
+                      workspace.nbytes, torch.cuda.current_stream(dev).cuda_stream)
+    out["degree"] = degree
+    out["workspace"] = workspace
+    return out
+
+
+def composite_sh(ctx: Context, planes: torch.Tensor, depth: torch.Tensor, degree: int, cam, views,
+                 interp: str = "nearest", out: torch.Tensor | None = None) -> torch.Tensor:
+    """lf_composite_sh: views [V, ny, nx, 4] float32 of (Q_r, Q_g, Q_b, T) from SH planes."""
+    _need(planes, "planes", (torch.float32,), 4)
+    _need(depth, "depth", (torch.float32,), 1)
+    if planes.shape[3] != L.lf_sh_texel_floats(degree) or depth.shape[0] != planes.shape[0]:
+        raise ValueError("planes must be [K,H,W,lf_sh_texel_floats(degree)] and depth [K]")
+    V = len(views)
+    if out is None:
+        out = torch.empty((V, cam.ny, cam.nx, 4), dtype=torch.float32, device=planes.device)
+    _need(out, "out", (torch.float32,), 4)
+    if tuple(out.shape) != (V, cam.ny, cam.nx, 4):
+        raise ValueError(f"out must be [{V}, {cam.ny}, {cam.nx}, 4]")
+    m = L.lf_sh_mpi(degree, planes.shape[0], planes.shape[1], planes.shape[2], planes.data_ptr(), depth.data_ptr())
+    L.lf_composite_sh(ctx.handle, m, L.make_camera(cam), views, _INTERP[interp], out.data_ptr(), _stream(planes))
+    return out
+
+
+def sh_colours(ctx: Context, means: torch.Tensor, sh: torch.Tensor, cam, dx: float, dy: float = 0.0,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """lf_sh_colours: every Gaussian's colour [n, 3] seen from view (dx, dy)."""
+    degree = _sh_degree(sh)
+    _need(means, "means", (torch.float32,), 2)
+    if out is None:
+        out = torch.empty((means.shape[0], 3), dtype=torch.float32, device=means.device)
+    L.lf_sh_colours(ctx.handle, means.data_ptr(), sh.data_ptr(), degree, means.shape[0], L.make_camera(cam), dx, dy,
+                    out.data_ptr(), _stream(means))
+    return out
+
+
+def render_view_sh(ctx: Context, scene: dict, sh: torch.Tensor, cam, dx: float, dy: float = 0.0,
+                   workspace: Workspace | None = None, out: dict | None = None, rgb: torch.Tensor | None = None) -> dict:
+    """The per-view render in SH colour: lf_sh_colours for the view, then lf_render_view."""
+    rgb = sh_colours(ctx, scene["means"], sh, cam, dx, dy, out=rgb)
+    return render_view(ctx, dict(scene, rgb=rgb), cam, dx, dy, workspace=workspace, out=out)
+
+
 def build_stats(ctx: Context, workspace: Workspace, check: bool = True):
     """lf_build_stats (synchronises the current stream)."""
     info, status = L.lf_build_stats(ctx.handle, workspace.ptr, workspace.nbytes,

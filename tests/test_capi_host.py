@@ -233,3 +233,57 @@ def test_render_view_rejects_invalid_arguments(lib):
                                 ctypes.byref(out), 0x8000, kw.get("nbytes", nbytes.value), None)
         assert st != L.LF_OK, kw
         assert needle in L.lf_last_error(), (kw, L.lf_last_error())
+
+
+def test_sh_entry_points_reject_invalid_arguments(lib):
+    """The SH build, composite and colour entry points validate on the host first."""
+    assert [lib.lf_sh_texel_floats(d) for d in (-1, 0, 1, 2, 3, 4)] == [0, 4, 16, 28, 52, 0]
+    cam = L.make_camera(CAMS["uniform10k"])
+    g = L.lf_geometry(cam)
+    f = _field(L.LF_GAUSSIANS, n=1000)
+    nbytes = ctypes.c_size_t(0)
+    assert lib.lf_build_mpi_workspace(ctypes.byref(f), ctypes.byref(cam), 4, 0, ctypes.byref(nbytes)) == L.LF_OK
+
+    def sh_mpi(degree=2, K=4, h=g.plane_height, w=g.plane_width):
+        return L.lf_sh_mpi(degree, K, h, w, 0x6000, 0x7000)
+
+    build_cases = [
+        (dict(mpi=sh_mpi(degree=4)), "degree"),
+        (dict(mpi=sh_mpi(K=3)), "n_chunk"),
+        (dict(mpi=sh_mpi(h=g.plane_height + 2)), "planes are"),
+        (dict(sh=None), "sh is NULL"),
+        (dict(field=_field(L.LF_VOXELS, n=1000)), "Gaussian fields only"),
+        (dict(nbytes=1024), "too small"),
+    ]
+    for kw, needle in build_cases:
+        m = kw.get("mpi", sh_mpi())
+        st = lib.lf_build_mpi_sh(None, ctypes.byref(kw.get("field", f)), kw.get("sh", 0x9000), ctypes.byref(cam), 4,
+                                 L.LF_BIN_QUANTILE, None, ctypes.byref(m), 0x8000, kw.get("nbytes", nbytes.value), None)
+        assert st != L.LF_OK, kw
+        assert needle in L.lf_last_error(), (kw, L.lf_last_error())
+    views = L.make_views([0.0, 0.1], [0.0, 0.0])
+    comp_cases = [
+        (dict(mpi=sh_mpi(degree=-1)), "degree"),
+        (dict(interp=7), "interp"),
+        (dict(out=None), "out is NULL"),
+        (dict(mpi=sh_mpi(w=g.plane_width + 1)), "planes are"),
+        (dict(n_views=0), "n_views"),
+    ]
+    for kw, needle in comp_cases:
+        m = kw.get("mpi", sh_mpi())
+        st = lib.lf_composite_sh(None, ctypes.byref(m), ctypes.byref(cam), views, kw.get("n_views", 2),
+                                 kw.get("interp", L.LF_NEAREST), kw.get("out", 0xa000), None)
+        assert st != L.LF_OK, kw
+        assert needle in L.lf_last_error(), (kw, L.lf_last_error())
+    v = L.lf_view(0.0, 0.0)
+    colour_cases = [
+        (dict(degree=4), "degree"),
+        (dict(n=-1), "negative"),
+        (dict(means=None), "NULL"),
+        (dict(view=L.lf_view(float("inf"), 0.0)), "not finite"),
+    ]
+    for kw, needle in colour_cases:
+        st = lib.lf_sh_colours(None, kw.get("means", 0x1000), 0x2000, kw.get("degree", 1), kw.get("n", 10),
+                               ctypes.byref(cam), ctypes.byref(kw.get("view", v)), 0x3000, None)
+        assert st != L.LF_OK, kw
+        assert needle in L.lf_last_error(), (kw, L.lf_last_error())

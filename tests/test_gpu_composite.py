@@ -157,12 +157,15 @@ def test_composite_fp16_output():
 
 
 @pytest.mark.parametrize("interp", ["nearest", "bilinear"])
-def test_composite_full_size_cluster_shape(interp):
-    """512^2 views, 64 planes, 45 views (the headline shape), checked on three whole views."""
-    announce("composite 512x512 K64 V45", interp)
-    cam, g, p, dx, dy = _setup(512, 512, 64, 45, 1, 14)
+@pytest.mark.parametrize("quilt", [(45, 1), (9, 5)], ids=["45x1", "9x5"])
+def test_composite_full_size_cluster_shape(interp, quilt):
+    """512^2 views, 64 planes, 45 views (the headline shape, and the same views as a 9 x 5
+    quilt over +-10 deg vertically), checked on whole views from several rows of the quilt."""
+    vx, vy = quilt
+    announce("composite 512x512 K64", vx, vy, interp)
+    cam, g, p, dx, dy = _setup(512, 512, 64, vx, vy, 14, phi_y=20.0 if vy > 1 else 0.0)
     out = T.composite(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy), interp)
-    sel = [0, 22, 44]
+    sel = [0, 22, 44] if vy == 1 else [0, 13, 31, 44]
     ref, _ = composite.composite(p["rgba"], p["depth"], cam, g, dx, dy, interp, views=sel)
     got = host(out[sel])
     assert np.abs(got - ref).max() <= 1e-4

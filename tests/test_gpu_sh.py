@@ -1,0 +1,156 @@
+"""GPU parity of the spherical-harmonic path (the SH ablation of Fig. 6): lf_build_mpi_sh,
+lf_composite_sh and lf_sh_colours against the FP64 SH oracle on seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from oracle import geometry, render, sh
+from paper_2508_18540_amd import _lib as L
+from paper_2508_18540_amd import torch_api as T
+from tests.gpu_util import announce, ctx, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _unpack(planes, degree):
+    """Texel floats q_0 (rgb), A, q_1 .. q_{n-1} (rgb), zeros -> (q [..., n, 3], A, padding)."""
+    nc = sh.n_coef(degree)
+    q = np.concatenate([planes[..., None, 0:3], planes[..., 4:4 + 3 * (nc - 1)].reshape(*planes.shape[:-1], nc - 1, 3)],
+                       axis=-2)
+    return q, planes[..., 3], planes[..., 4 + 3 * (nc - 1):]
+
+
+def _rotation(seed):
+    m, _ = np.linalg.qr(np.random.default_rng(seed).normal(size=(3, 3)))
+    return m * np.sign(np.linalg.det(m))
+
+
+def _check_planes(got, degree, q, A, amb, tol=2e-4, jump=0.05):
+    gq, gA, pad = _unpack(got, degree)
+    assert not pad.any()
+    err = np.maximum(np.abs(gq - q).max(axis=(-1, -2)), np.abs(gA - A))
+    bad = (err > tol) & ~amb
+    assert not bad.any(), f"{bad.sum()} unmasked texels above {tol}: max {err[~amb].max()}"
+    if amb.any():
+        assert err[amb].max() <= jump, err[amb].max()
+    print("unmasked max-abs", float(err[~amb].max()), "ambiguous", float(amb.mean()))
+
+
+@pytest.mark.parametrize("degree", [0, 1, 2, 3])
+def test_sh_planes_match_oracle(degree):
+    announce("SH planes", degree)
+    n = 3000
+    scene = scenegen.small_scene(n, 21)
+    coef = scenegen.sh_coefficients(n, degree, 22)
+    cam = scenegen.camera(96, 80, 50.0, 3.0, math.radians(30))
+    K = 6
+    out = T.build_mpi_sh(ctx(), T.to_device(scene), dev(coef), cam, K)
+    info, st = T.build_stats(ctx(), out["workspace"])
+    q, A, amb, depth = sh.build_sh_planes(scene, coef, degree, cam, K)
+    assert np.array_equal(out["depth"].cpu().numpy().view(np.uint32), depth.view(np.uint32))
+    _check_planes(host(out["planes"]), degree, q, A, amb)
+
+
+def test_sh_planes_long_buckets():
+    """Buckets of many 256-entry segments: the work-group carries T across its segments."""
+    announce("SH planes long buckets")
+    n = 12000
+    scene = scenegen.small_scene(n, 23, xy=0.3, z=(2.6, 3.4), log_scale=(-3.5, 0.3))
+    coef = scenegen.sh_coefficients(n, 2, 24)
+    cam = scenegen.camera(64, 64, 50.0, 3.0, math.radians(20))
+    K = 2
+    out = T.build_mpi_sh(ctx(), T.to_device(scene), dev(coef), cam, K)
+    T.build_stats(ctx(), out["workspace"])
+    q, A, amb, _ = sh.build_sh_planes(scene, coef, 2, cam, K)
+    assert A.max() > 0.9                                    # dense enough to saturate
+    _check_planes(host(out["planes"]), 2, q, A, amb)
+
+
+def test_sh_planes_empty_field():
+    scene = T.to_device({k: v[:0] for k, v in scenegen.small_scene(4, 0).items()})
+    cam = scenegen.camera(32, 32, 50.0, 2.0, math.radians(20))
+    info = L.lf_geometry(L.make_camera(cam))
+    K, tf = 3, L.lf_sh_texel_floats(3)
+    n = K * info.plane_height * info.plane_width * tf
+    buf = torch.full((n + 1024,), 7.0, device="cuda")
+    out = dict(planes=buf[:n].view(K, info.plane_height, info.plane_width, tf),
+               depth=torch.empty(K, dtype=torch.float32, device="cuda"))
+    T.build_mpi_sh(ctx(), scene, torch.zeros((0, 16, 3), device="cuda"), cam, K, out=out)
+    torch.cuda.synchronize()
+    assert float(buf[:n].abs().max()) == 0.0 and bool((buf[n:] == 7.0).all())
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+@pytest.mark.parametrize("degree", [0, 1, 3])
+def test_sh_composite_matches_oracle(degree, interp):
+    announce("SH composite", degree, interp)
+    cam = scenegen.camera(72, 56, 50.0, 2.0, math.radians(30), math.radians(10), R=_rotation(4), t=[0.1, -0.2, 0.3])
+    g = geometry.derive(cam)
+    K, nc = 5, sh.n_coef(degree)
+    rng = np.random.default_rng(9)
+    A = np.where(rng.random((K, g.hp, g.wp)) < 0.3, 0.0, rng.uniform(0.0, 0.9, (K, g.hp, g.wp)))
+    q = rng.normal(scale=0.4, size=(K, g.hp, g.wp, nc, 3)) * A[..., None, None]
+    depth = np.sort(rng.uniform(g.d_forward + 0.3, 9.0, K)).astype(np.float32)
+    packed = np.zeros((K, g.hp, g.wp, L.lf_sh_texel_floats(degree)), np.float32)
+    packed[..., 0:3], packed[..., 3] = q[..., 0, :], A
+    packed[..., 4:4 + 3 * (nc - 1)] = q[..., 1:, :].reshape(K, g.hp, g.wp, -1)
+    q32, A32, _ = _unpack(packed.astype(np.float64), degree)
+    dx, dy, _, _ = geometry.quilt_views(cam, 5, 3)
+    dx, dy = dx.astype(np.float32), dy.astype(np.float32)
+    out = T.composite_sh(ctx(), dev(packed), dev(depth), degree, cam, T.views_of(dx, dy), interp)
+    ref = sh.composite_sh(q32, A32, degree, depth, cam, g, dx, dy, interp)
+    err = np.abs(host(out) - ref).max()
+    print("max-abs", err)
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+def test_sh_colours_match_oracle(degree):
+    announce("SH colours", degree)
+    n = 5000
+    rng = np.random.default_rng(3)
+    cam = scenegen.camera(64, 64, 50.0, 2.0, math.radians(30), R=_rotation(6), t=[0.3, 0.1, -0.2])
+    scene = {"means": rng.uniform(-2, 2, (n, 3)).astype(np.float32)}
+    coef = scenegen.sh_coefficients(n, degree, 8)
+    got = host(T.sh_colours(ctx(), dev(scene["means"]), dev(coef), cam, 0.2, -0.1))
+    ref = sh.view_colours(scene, coef, degree, cam, float(np.float32(0.2)), float(np.float32(-0.1)))
+    err = np.abs(got - ref).max()
+    print("max-abs", err)
+    assert err <= 2e-5
+
+
+def test_sh_degree0_equals_rgb_pipeline():
+    """Degree 0 on the GPU: the SH build and composite give the RGB build and composite of
+    rgb = sh_0 Y_0 + 1/2 (up to float32 rounding)."""
+    announce("SH degree 0 vs RGB")
+    n = 4000
+    scene = scenegen.small_scene(n, 31)
+    coef = scenegen.sh_coefficients(n, 0, 32)
+    scene["rgb"] = sh.gaussian_colour(coef, np.tile([0.0, 0.0, 1.0], (n, 1)), 0).astype(np.float32)
+    cam = scenegen.camera(96, 96, 50.0, 3.0, math.radians(30), math.radians(10))
+    K = 8
+    ds = T.to_device(scene)
+    o_sh = T.build_mpi_sh(ctx(), ds, dev(coef), cam, K)
+    o_rgb = T.build_mpi(ctx(), ds, cam, K)
+    vl = L.lf_quilt_views(L.make_camera(cam), 4, 2)
+    a = host(T.composite_sh(ctx(), o_sh["planes"], o_sh["depth"], 0, cam, vl, "bilinear"))
+    b = host(T.composite(ctx(), o_rgb["rgba"], o_rgb["depth"], cam, vl, "bilinear"))
+    err = np.abs(a - b).max()
+    print("max-abs", err)
+    assert err <= 2e-4
+
+
+def test_render_view_sh_matches_oracle():
+    announce("render_view SH")
+    n = 2000
+    scene = scenegen.small_scene(n, 41)
+    coef = scenegen.sh_coefficients(n, 3, 42)
+    cam = scenegen.camera(64, 48, 50.0, 3.0, math.radians(30))
+    out = T.render_view_sh(ctx(), T.to_device(scene), dev(coef), cam, 0.12, -0.05)
+    T.build_stats(ctx(), out["workspace"])
+    ref, amb = sh.render_view_sh(scene, coef, 3, cam, float(np.float32(0.12)), float(np.float32(-0.05)))
+    err = np.abs(host(out["rgba"][0]) - ref).max(axis=-1)
+    assert err[~amb].max() <= 1e-4, err[~amb].max()
