@@ -952,6 +952,13 @@ hipError_t launch_rows_bwd(const CompositeArgs& a, int G, const float4* pt, cons
 
 }  // namespace
 
+int view_groups(CompositeArgs& a, int G) {
+  int cls_end[LF_MAX_VIEWS];
+  const int nc = dy_classes(a, cls_end);
+  fill_groups(a, cls_end, nc, G);
+  return a.n_groups;
+}
+
 size_t composite_table_bytes(int K, int n_views) {
   // at most one view group per view
   return (((size_t)K * n_views * 16 + 255) & ~(size_t)255) + (size_t)K * ct_stride(n_views) * 4 + 256;

@@ -125,6 +125,9 @@ lf_status composite_args(const lf_mpi* mpi, const lf_camera* cam, const lf_view*
                          CompositeArgs* a);
 hipError_t plane_coeffs_launch(const CompositeArgs& a, float* bx, float* by, float* cx, float* cy,
                                float* cxn, float* cyn, hipStream_t s);
+// Groups the views of `a` for the row kernels (views that share dy, runs of at most G);
+// returns a.n_groups.
+int view_groups(CompositeArgs& a, int G);
 // Pixel rays of the views for SH colour: view v's principal point is (c_x + dx kx, c_y + dy ky)
 // (Eq. 5), its rays ((x - c_x,v) / f_x, (y - c_y,v) / f_y, 1) in base-camera axes.
 struct ShView {
@@ -132,7 +135,7 @@ struct ShView {
 };
 // Composite of SH planes of n_coef coefficients (a.planes float32 texels of
 // sh_texel_floats(n_coef)) into a.out (float32 views).
-hipError_t composite_sh_launch(const CompositeArgs& a, int n_coef, const ShView& sv, hipStream_t s);
+hipError_t composite_sh_launch(CompositeArgs& a, int n_coef, const ShView& sv, hipStream_t s);
 // Colour of n Gaussians seen from the world point `centre`.
 hipError_t sh_colours_launch(const float* means, const float* sh, int n_coef, int64_t n, const float centre[3],
                              float* rgb, hipStream_t s);

@@ -9,7 +9,9 @@ This harness does the same on the GPU: for a scene and a camera it renders the l
     python -m paper_2508_18540_amd.quality --n 100000 --res 512 --views 45 \
         --chunks 1,4,16,64,128,256 --scales 1,2 --interp nearest,bilinear
 
-prints one JSON line per (plane scale, interpolation, plane dtype, N_chunk).
+prints one JSON line per (plane scale, interpolation, plane dtype, N_chunk).  With
+--sh-degree L the Gaussians get seeded spherical-harmonic colour and the sweep compares RGB
+planes with SH planes (the ablation of Fig. 6).
 """
 from __future__ import annotations
 
@@ -81,6 +83,38 @@ def sweep(ctx: T.Context, scene: dict, cam_of, vx: int, chunks, scales=(1.0,), i
                                psnr_min=round(float(np.min(per_view)), 2), views=len(views))
 
 
+def sh_sweep(ctx: T.Context, scene: dict, sh: torch.Tensor, cam, vx: int, chunks, interp: str = "nearest"):
+    """The SH ablation (Fig. 6): against per-view renders in SH colour (every Gaussian
+    evaluated from its view), the light field of RGB planes (colours evaluated once, from the
+    base camera) and of SH planes (coefficients in the planes, evaluated per pixel ray).
+    Yields one dict per N_chunk with both mean PSNRs and both plane sizes."""
+    views = L.lf_quilt_views(L.make_camera(cam), vx, 1)
+    degree = T._sh_degree(sh)
+    ws, out, refs = None, None, []
+    for v in views:
+        out = T.render_view_sh(ctx, scene, sh, cam, v.dx, v.dy, workspace=ws, out=out)
+        ws = out["workspace"]
+        T.build_stats(ctx, ws, check=True)
+        refs.append(out["rgba"][0, ..., :3].float().clone())
+    ref = torch.stack(refs)
+    rgb_scene = dict(scene, rgb=T.sh_colours(ctx, scene["means"], sh, cam, 0.0, 0.0))
+    for k in chunks:
+        img = light_field_views(ctx, rgb_scene, cam, views, k, interp)
+        ws = T.workspace_for(scene, cam, k)
+        o = T.build_mpi_sh(ctx, scene, sh, cam, k, workspace=ws)
+        info, st = T.build_stats(ctx, ws, check=False)
+        if info.overflow:
+            ws = T.workspace_for(scene, cam, k, entry_capacity=int(info.entries_needed * 1.1) + 1024)
+            o = T.build_mpi_sh(ctx, scene, sh, cam, k, workspace=ws)
+            T.build_stats(ctx, ws, check=True)
+        img_sh = T.composite_sh(ctx, o["planes"], o["depth"], degree, cam, views, interp)[..., :3]
+        yield dict(n_chunk=k, sh_degree=degree, interp=interp,
+                   psnr_rgb_planes=round(float(np.mean([psnr(img[v], ref[v]) for v in range(len(views))])), 2),
+                   psnr_sh_planes=round(float(np.mean([psnr(img_sh[v], ref[v]) for v in range(len(views))])), 2),
+                   rgb_plane_bytes=int(k * o["planes"].shape[1] * o["planes"].shape[2] * 16),
+                   sh_plane_bytes=int(o["planes"].numel() * 4), views=len(views))
+
+
 def main(argv=None) -> None:
     import scenegen
 
@@ -100,6 +134,11 @@ def main(argv=None) -> None:
     p.add_argument("--scales", default="1,2")
     p.add_argument("--interp", default="nearest,bilinear")
     p.add_argument("--planes", default="f32,u8")
+    p.add_argument("--sh-degree", type=int, default=-1,
+                   help="0..3: give the Gaussians seeded SH colour of this degree and compare RGB planes with SH "
+                        "planes against per-view SH renders (the Fig. 6 ablation) instead of the sweep above")
+    p.add_argument("--sh-dc", type=float, default=1.0, help="SH DC coefficients uniform in (-sh_dc, sh_dc)")
+    p.add_argument("--sh-ac", type=float, default=0.4, help="SH band l >= 1 deviation sh_ac / l")
     a = p.parse_args(argv)
     ctx = T.Context(0)
     if a.scene == "cluster":
@@ -110,6 +149,14 @@ def main(argv=None) -> None:
 
     def cam_of(ps):
         return scenegen.camera(a.res, a.res, a.fov, 2.0, math.radians(a.phi), plane_scale=ps)
+
+    if a.sh_degree >= 0:
+        sh = torch.from_numpy(scenegen.sh_coefficients(a.n, a.sh_degree, a.seed + 1, dc_range=a.sh_dc,
+                                                       ac_scale=a.sh_ac)).cuda()
+        for row in sh_sweep(ctx, scene, sh, cam_of(float(a.scales.split(",")[0])), a.views,
+                            [int(c) for c in a.chunks.split(",")], a.interp.split(",")[0]):
+            print(json.dumps(row), flush=True)
+        return
 
     for row in sweep(ctx, scene, cam_of, a.views, [int(c) for c in a.chunks.split(",")],
                      [float(s) for s in a.scales.split(",")], a.interp.split(","), a.planes.split(",")):

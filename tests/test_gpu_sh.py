@@ -83,11 +83,18 @@ def test_sh_planes_empty_field():
     assert float(buf[:n].abs().max()) == 0.0 and bool((buf[n:] == 7.0).all())
 
 
+@pytest.mark.parametrize("shape", [(72, 56, 1.0), (200, 40, 3.0)], ids=["72x56", "200x40_ps3"])
+@pytest.mark.parametrize("kernel", ["rows", "general"])
 @pytest.mark.parametrize("interp", ["nearest", "bilinear"])
 @pytest.mark.parametrize("degree", [0, 1, 3])
-def test_sh_composite_matches_oracle(degree, interp):
-    announce("SH composite", degree, interp)
-    cam = scenegen.camera(72, 56, 50.0, 2.0, math.radians(30), math.radians(10), R=_rotation(4), t=[0.1, -0.2, 0.3])
+def test_sh_composite_matches_oracle(degree, interp, kernel, shape, monkeypatch):
+    """Both kernels; 200 x 40 at P_s = 3 spans two row segments and windows too wide for the
+    row kernel's LDS buffer at degree 3 (its global-read fallback)."""
+    announce("SH composite", degree, interp, kernel, shape)
+    monkeypatch.setenv("LF_COMPOSITE_KERNEL", kernel)
+    nx, ny, ps = shape
+    cam = scenegen.camera(nx, ny, 50.0, 2.0, math.radians(30), math.radians(10), R=_rotation(4), t=[0.1, -0.2, 0.3],
+                          plane_scale=ps)
     g = geometry.derive(cam)
     K, nc = 5, sh.n_coef(degree)
     rng = np.random.default_rng(9)
