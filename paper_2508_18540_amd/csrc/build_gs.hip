@@ -508,20 +508,25 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
 // SH splat (the spherical-harmonic planes of Fig. 6): the texels blend the Gaussians'
 // NC x 3 colour coefficients with the weights alpha T of the RGB splat, in the same Taylor
 // form and with the same per-quadrant lists.  One work-group per (tile, chunk) bucket walks
-// the bucket's segments in order, so its transmittance carries over and no partial tiles
-// are needed (a texel's state is 3 NC + 1 floats).  Per segment, thread t stages entry t:
-// its quadratic form and its coefficients (LDS), then each wave walks its quadrant's list.
-// The texel is stored as q_0 (r, g, b), A, q_1 .. q_{NC-1} (r, g, b), zero padding.
+// the bucket's entries in order, kShSplatSeg at a time, so its transmittance carries over
+// and no partial tiles are needed (a texel's state is 3 NC + 1 floats).  Per step, thread t
+// stages entry t's quadratic form, then all threads copy the entries' coefficients into LDS
+// with coalesced loads, and each wave walks its quadrant's list.  The short step keeps LDS
+// small enough for four work-groups per CU.  The texel is stored as q_0 (r, g, b), A,
+// q_1 .. q_{NC-1} (r, g, b), zero padding.
 // ---------------------------------------------------------------------------------------
+constexpr int kShSplatSeg = 64;
+
 template <int NC>
 __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_buckets) {
   constexpr int NF = 3 * NC;                     // coefficient floats per Gaussian
   constexpr int TF = sh_texel_floats(NC);
-  __shared__ float4 s_p[kSegment];               // (ca, cb, cc, A)
-  __shared__ float2 s_q[kSegment];               // (B, C)
-  __shared__ float s_sh[kSegment][NF];
-  __shared__ uint16_t s_list[4][kSegment];
-  __shared__ int s_cnt[4][4];
+  __shared__ float4 s_p[kShSplatSeg];            // (ca, cb, cc, A)
+  __shared__ float2 s_q[kShSplatSeg];            // (B, C)
+  __shared__ uint32_t s_gi[kShSplatSeg];
+  __shared__ float s_sh[kShSplatSeg * NF];
+  __shared__ uint8_t s_list[4][kShSplatSeg];
+  __shared__ int s_cnt[4];
   const int64_t bidx = blockIdx.x;
   if (bidx >= n_buckets) return;
   const int tile = (int)(bidx / a.K), k = (int)(bidx % a.K);
@@ -539,40 +544,32 @@ __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_bucket
 #pragma unroll
   for (int j = 0; j < NF; ++j) acc[j] = 0.0f;
   float T = 1.0f;
-  for (uint32_t b0 = bb0; b0 < bb1; b0 += kSegment) {
-    const int n = (int)min(bb1 - b0, (uint32_t)kSegment);
-    __syncthreads();                             // the previous segment is consumed
+  for (uint32_t b0 = bb0; b0 < bb1; b0 += kShSplatSeg) {
+    const int n = (int)min(bb1 - b0, (uint32_t)kShSplatSeg);
+    __syncthreads();                             // the previous step is consumed
     uint32_t qm = 0;
-    if (tid < n) {
+    if (tid < n) {                               // wave 0 holds the step's entries
       const uint32_t ent = a.evals[b0 + tid];
       const uint32_t gi = min(ent & 0x0fffffffu, (uint32_t)a.n - 1u);
       const GRec& g = a.rec[gi];
       const TileTaylor tt = tile_taylor(g, ox, oy);
       s_p[tid] = make_float4(g.ca, g.cb, g.cc, tt.A);
       s_q[tid] = make_float2(tt.B, tt.C);
-      const float* src = a.sh + (size_t)gi * NF;
-#pragma unroll
-      for (int j = 0; j < NF; ++j) s_sh[tid][j] = src[j];
+      s_gi[tid] = gi;
       qm = reached_quadrants(g, ent >> 28, tt.sx, tt.sy);
     }
-    uint32_t rank[4];
+    if (wave == 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint64_t m = __ballot((qm >> q) & 1u);
-      rank[q] = __popcll(m & below);
-      if (lane == 0) s_cnt[q][wave] = __popcll(m);
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t m = __ballot((qm >> q) & 1u);
+        if ((qm >> q) & 1u) s_list[q][__popcll(m & below)] = (uint8_t)tid;
+        if (lane == 0) s_cnt[q] = __popcll(m);
+      }
     }
     __syncthreads();
-    int my_count = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int off = 0;
-      for (int w = 0; w < 4; ++w) off += w < wave ? s_cnt[q][w] : 0;
-      if ((qm >> q) & 1u) s_list[q][off + rank[q]] = (uint16_t)tid;
-      if (q == wave) my_count = s_cnt[q][0] + s_cnt[q][1] + s_cnt[q][2] + s_cnt[q][3];
-    }
+    for (int f = tid; f < n * NF; f += 256) s_sh[f] = a.sh[(size_t)s_gi[f / NF] * NF + f % NF];
     __syncthreads();
-    const int cnt = __builtin_amdgcn_readfirstlane(my_count);
+    const int cnt = s_cnt[wave];
     for (int i = 0; i < cnt; ++i) {
       const int e = s_list[wave][i];
       const float4 P = s_p[e];
@@ -580,8 +577,9 @@ __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_bucket
       const float q = taylor_q(P.x, P.y, P.z, P.w, Q.x, Q.y, du, dv, duu, duv, dvv);
       const float alpha = q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f;
       const float w = alpha * T;
+      const float* c = s_sh + e * NF;
 #pragma unroll
-      for (int j = 0; j < NF; ++j) acc[j] = fmaf(w, s_sh[e][j], acc[j]);
+      for (int j = 0; j < NF; ++j) acc[j] = fmaf(w, c[j], acc[j]);
       T = T - w;
     }
   }
