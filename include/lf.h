@@ -69,6 +69,9 @@ typedef struct {
   float d_shift;       /* D_shift: moves the reference camera back (Sec. 4.2), >= 0          */
   float plane_scale;   /* P_s: plane resolution = round(P_s * N)                             */
   float z_near;        /* primitives with reference depth <= z_near are culled (> 0)         */
+  float dilation;      /* f' in reference texels^2: 0 = the adaptive value of Eq. 8; > 0 =
+                        * this constant (the constant filter of the adaptive-filter ablation,
+                        * Sec. 5)                                                             */
 } lf_camera;
 
 /* One quilt view: lateral offset of Eq. 4 in base-camera units.  The principal-point

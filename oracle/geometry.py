@@ -51,7 +51,9 @@ def derive(cam) -> Geometry:
     Eq. 2: tan(theta'_k/2) = D_focal * tan(theta_k/2) / (D_focal - D_forward).
     D_shift moves the reference camera back after theta' is fixed (Sec. 4.2); theta'
     uses the unshifted D_forward.
-    Eq. 8: f' = 0.3 * (D_focal tan(theta_x/2) / ((D_focal - D_forward) tan(theta'_x/2)) * P_s)^2.
+    Eq. 8: f' = 0.3 * (D_focal tan(theta_x/2) / ((D_focal - D_forward) tan(theta'_x/2)) * P_s)^2,
+    unless the camera sets a positive constant ``dilation`` (the constant filter of the
+    adaptive-filter ablation, Sec. 5).
     """
     Df = float(cam.d_focal)
     tx, ty = math.tan(0.5 * cam.fov_x), math.tan(0.5 * cam.fov_y)
@@ -62,7 +64,8 @@ def derive(cam) -> Geometry:
     dfwd = d0 - float(cam.d_shift)
     ps = float(cam.plane_scale)
     wp, hp = round_half_up(ps * cam.nx), round_half_up(ps * cam.ny)
-    fdil = 0.3 * (Df * tx / ((Df - dfwd) * tpx) * ps) ** 2
+    const = float(getattr(cam, "dilation", 0.0))
+    fdil = const if const > 0.0 else 0.3 * (Df * tx / ((Df - dfwd) * tpx) * ps) ** 2
     return Geometry(d_focal=Df, tx=tx, ty=ty, taux=taux, tauy=tauy, d_forward0=d0, d_forward=dfwd,
                     tpx=tpx, tpy=tpy, nx=int(cam.nx), ny=int(cam.ny), wp=wp, hp=hp,
                     fx=0.5 * cam.nx / tx, fy=0.5 * cam.ny / ty, cx=0.5 * (cam.nx - 1), cy=0.5 * (cam.ny - 1),

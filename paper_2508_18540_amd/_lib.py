@@ -46,7 +46,8 @@ class LFError(RuntimeError):
 class lf_camera(C.Structure):
     _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("fov_x", C.c_float), ("fov_y", C.c_float), ("d_focal", C.c_float), ("phi_x", C.c_float),
-                ("phi_y", C.c_float), ("d_shift", C.c_float), ("plane_scale", C.c_float), ("z_near", C.c_float)]
+                ("phi_y", C.c_float), ("d_shift", C.c_float), ("plane_scale", C.c_float), ("z_near", C.c_float),
+                ("dilation", C.c_float)]
 
 
 class lf_view(C.Structure):
@@ -175,6 +176,7 @@ def make_camera(cam) -> lf_camera:
     c.nx, c.ny = int(cam.nx), int(cam.ny)
     for f in ("fov_x", "fov_y", "d_focal", "phi_x", "phi_y", "d_shift", "plane_scale", "z_near"):
         setattr(c, f, float(getattr(cam, f)))
+    c.dilation = float(getattr(cam, "dilation", 0.0))
     return c
 
 

@@ -332,6 +332,7 @@ static lf_camera view_camera(const lf_camera* cam) {
   v.phi_x = v.phi_y = 0.0f;
   v.d_shift = 0.0f;
   v.plane_scale = 1.0f;
+  v.dilation = 0.0f;     // Eq. 8 with no baseline and P_s = 1: the 0.3 px^2 of 3DGS
   return v;
 }
 

@@ -52,6 +52,8 @@ lf_status derive_geometry(const lf_camera* cam, Geom* g) {
     return fail(LF_ERR_INVALID_ARG, "z_near must be positive and finite");
   if (!(cam->plane_scale > 0.0f) || !std::isfinite(cam->plane_scale))
     return fail(LF_ERR_INVALID_ARG, "plane_scale must be positive and finite");
+  if (!(cam->dilation >= 0.0f) || !std::isfinite(cam->dilation))
+    return fail(LF_ERR_INVALID_ARG, "dilation must be >= 0 and finite");
 
   const double Df = cam->d_focal;
   g->tx = std::tan(0.5 * (double)cam->fov_x);
@@ -80,9 +82,10 @@ lf_status derive_geometry(const lf_camera* cam, Geom* g) {
   g->fpy = 0.5 * g->hp / g->tpy;
   g->cpx = 0.5 * (g->wp - 1);
   g->cpy = 0.5 * (g->hp - 1);
-  // Eq. 8: dilation aligned with the base camera's pixel size on the focal plane.
+  // Eq. 8: dilation aligned with the base camera's pixel size on the focal plane, unless
+  // the camera asks for a constant one
   const double r = Df * g->tx / ((Df - g->d_forward) * g->tpx) * ps;
-  g->f_dil = 0.3 * (r * r);
+  g->f_dil = cam->dilation > 0.0f ? (double)cam->dilation : 0.3 * (r * r);
 
   Consts& c = g->c;
   split(g->d_forward, &c.d_fwd, &c.d_fwd_lo);

@@ -9,7 +9,7 @@ This harness does the same on the GPU: for a scene and a camera it renders the l
     python -m paper_2508_18540_amd.quality --n 100000 --res 512 --views 45 \
         --chunks 1,4,16,64,128,256 --scales 1,2 --interp nearest,bilinear
 
-prints one JSON line per (plane scale, interpolation, plane dtype, N_chunk).  With
+prints one JSON line per (filter, plane scale, interpolation, plane dtype, N_chunk).  With
 --sh-degree L the Gaussians get seeded spherical-harmonic colour and the sweep compares RGB
 planes with SH planes (the ablation of Fig. 6).
 """
@@ -134,6 +134,9 @@ def main(argv=None) -> None:
     p.add_argument("--scales", default="1,2")
     p.add_argument("--interp", default="nearest,bilinear")
     p.add_argument("--planes", default="f32,u8")
+    p.add_argument("--filters", default="adaptive",
+                   help="adaptive (Eq. 8) and/or constant (f' = 0.3 reference texels^2 whatever P_s): the "
+                        "adaptive-filter ablation")
     p.add_argument("--sh-degree", type=int, default=-1,
                    help="0..3: give the Gaussians seeded SH colour of this degree and compare RGB planes with SH "
                         "planes against per-view SH renders (the Fig. 6 ablation) instead of the sweep above")
@@ -147,8 +150,9 @@ def main(argv=None) -> None:
         scene = scenegen.small_scene(a.n, a.seed, xy=0.7, z=(a.zmin, a.zmax), log_scale=(-4.0, 0.4))
     scene = T.to_device(scene)
 
-    def cam_of(ps):
-        return scenegen.camera(a.res, a.res, a.fov, 2.0, math.radians(a.phi), plane_scale=ps)
+    def cam_of(ps, filt="adaptive"):
+        return scenegen.camera(a.res, a.res, a.fov, 2.0, math.radians(a.phi), plane_scale=ps,
+                               dilation=0.3 if filt == "constant" else 0.0)
 
     if a.sh_degree >= 0:
         sh = torch.from_numpy(scenegen.sh_coefficients(a.n, a.sh_degree, a.seed + 1, dc_range=a.sh_dc,
@@ -158,9 +162,10 @@ def main(argv=None) -> None:
             print(json.dumps(row), flush=True)
         return
 
-    for row in sweep(ctx, scene, cam_of, a.views, [int(c) for c in a.chunks.split(",")],
-                     [float(s) for s in a.scales.split(",")], a.interp.split(","), a.planes.split(",")):
-        print(json.dumps(row), flush=True)
+    for filt in a.filters.split(","):
+        for row in sweep(ctx, scene, lambda ps: cam_of(ps, filt), a.views, [int(c) for c in a.chunks.split(",")],
+                         [float(s) for s in a.scales.split(",")], a.interp.split(","), a.planes.split(",")):
+            print(json.dumps(dict(row, filter=filt)), flush=True)
 
 
 if __name__ == "__main__":

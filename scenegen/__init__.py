@@ -61,6 +61,7 @@ class Camera:
     d_shift: float = 0.0
     plane_scale: float = 1.0
     z_near: float = 0.2
+    dilation: float = 0.0     # f' in reference texels^2; 0 = the adaptive value of Eq. 8
 
     def with_(self, **kw) -> "Camera":
         kw = {k: (float(np.float32(v)) if isinstance(v, float) else v) for k, v in kw.items()}
@@ -69,7 +70,7 @@ class Camera:
 
 def camera(nx: int, ny: int, fov_deg: float, d_focal: float, phi_x: float, phi_y: float = 0.0,
            plane_scale: float = 1.0, d_shift: float = 0.0, z_near: float = 0.2,
-           R=None, t=None, fov_y_deg: float | None = None) -> Camera:
+           R=None, t=None, fov_y_deg: float | None = None, dilation: float = 0.0) -> Camera:
     """Build a :class:`Camera`; ``phi_*`` are display viewing angles in radians."""
     R = np.eye(3) if R is None else np.asarray(R, dtype=np.float64).reshape(3, 3)
     t = np.zeros(3) if t is None else np.asarray(t, dtype=np.float64).reshape(3)
@@ -78,7 +79,7 @@ def camera(nx: int, ny: int, fov_deg: float, d_focal: float, phi_x: float, phi_y
     return Camera(R=tuple(f(v) for v in R.reshape(-1)), t=tuple(f(v) for v in t),
                   nx=int(nx), ny=int(ny), fov_x=f(math.radians(fov_deg)), fov_y=f(math.radians(fy)),
                   d_focal=f(d_focal), phi_x=f(phi_x), phi_y=f(phi_y), d_shift=f(d_shift),
-                  plane_scale=f(plane_scale), z_near=f(z_near))
+                  plane_scale=f(plane_scale), z_near=f(z_near), dilation=f(dilation))
 
 
 def _gaussian_attributes(rng: np.random.Generator, n: int, means: np.ndarray) -> dict:

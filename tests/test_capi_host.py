@@ -47,6 +47,7 @@ CAMS = {
                                d_shift=0.2, z_near=0.1),
     "rotated": scenegen.camera(128, 96, 45.0, 3.0, math.radians(35.0), R=[[0, 0, 1], [0, 1, 0], [-1, 0, 0]],
                                t=[0.5, -0.25, 4.0]),
+    "constant_filter": scenegen.camera(160, 120, 50.0, 2.0, math.radians(30.0), plane_scale=2.0, dilation=0.3),
 }
 
 
@@ -98,6 +99,8 @@ def _valid_call(lib, **kw):
     (dict(cam=dict(phi_x=-0.1)), "viewing angles"),
     (dict(cam=dict(z_near=0.0)), "z_near"),
     (dict(cam=dict(plane_scale=float("nan"))), "plane_scale"),
+    (dict(cam=dict(dilation=-0.1)), "dilation"),
+    (dict(cam=dict(dilation=float("inf"))), "dilation"),
     (dict(dtype=7), "dtype"),
     (dict(n_chunk=0), "n_chunk"),
     (dict(w=64), "planes are"),

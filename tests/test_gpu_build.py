@@ -244,6 +244,26 @@ def test_sort_digit_widths_agree(key_bits, tile_bits, monkeypatch):
     assert torch.equal(ref["rgba"], got["rgba"])
 
 
+def test_constant_filter_planes():
+    """The camera's constant dilation (adaptive-filter ablation) reaches the splat: planes at
+    P_s = 2 against the oracle's with the same constant, and a constant equal to the Eq. 8
+    value gives the adaptive planes bit for bit."""
+    announce("planes constant filter")
+    scene = scenegen.small_scene(2000, 12)
+    cam = scenegen.camera(64, 48, 50.0, 3.0, math.radians(20), plane_scale=2.0, dilation=0.3)
+    out, info, st = _gpu_build(scene, cam, 4)
+    assert st == L.LF_OK
+    mpi = render.build_mpi_gaussians(scene, cam, 4)
+    _masked_compare(host(out["rgba"]), mpi.planes, mpi.ambiguous, 1e-4, 0.02)
+    adaptive = cam.with_(dilation=0.0)
+    same = cam.with_(dilation=float(np.float32(geometry.derive(adaptive).f_dilation)))
+    a, _, _ = _gpu_build(scene, adaptive, 4)
+    b, _, _ = _gpu_build(scene, same, 4)
+    torch.cuda.synchronize()
+    if np.float32(geometry.derive(adaptive).f_dilation) == np.float32(geometry.derive(same).f_dilation):
+        assert torch.equal(a["rgba"], b["rgba"])
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float16, torch.uint8])
 def test_empty_field_fill_stays_in_planes(dtype):
     """An empty field clears exactly its planes: a guard region behind them is untouched."""

@@ -75,6 +75,16 @@ def test_adaptive_dilation_closed_form(shift, ps):
     assert g.f_dilation == pytest.approx(0.3 * (ratio * ps) ** 2, rel=1e-12)
 
 
+@pytest.mark.parametrize("ps", [1.0, 2.0, 3.0])
+def test_constant_dilation_overrides_eq8(ps):
+    """A camera's constant dilation (the adaptive-filter ablation) replaces Eq. 8 whatever P_s;
+    with no baseline and P_s = 1, Eq. 8 itself is the constant 0.3 of 3DGS."""
+    g = geometry.derive(_cam(plane_scale=ps, dilation=float(np.float32(0.45))))
+    assert g.f_dilation == float(np.float32(0.45))
+    flat = scenegen.camera(64, 48, 50.0, 2.0, 0.0)
+    assert geometry.derive(flat).f_dilation == pytest.approx(0.3, rel=1e-15)
+
+
 def test_view_grid():
     cam = scenegen.config("uniform10k")[1]
     dx, dy, px, py = geometry.quilt_views(cam, 9, 1)
