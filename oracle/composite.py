@@ -99,11 +99,12 @@ def composite(planes, depth32, cam, geom, dx32, dy32, interp: str = "nearest", a
     return np.stack(outs), np.stack(ambs)
 
 
-def composite_at(texel_fn, depth32, cam, geom, dx32, dy32, interp: str, pix):
+def composite_at(texel_fn, depth32, cam, geom, dx32, dy32, interp: str, pix, colour=None):
     """Composite individual pixels; ``pix`` is an int array [n,3] of (view, y, x).
 
     ``texel_fn(k, iy, ix)`` returns (rgba [m,4], ambiguous [m]) of plane k at in-range
-    integer texels.  Returns (out [n,4], ambiguous [n]).
+    integer texels.  Returns (out [n,4], ambiguous [n]).  For texels of other channels,
+    ``colour(s)`` maps the samples s [n, C] to (premultiplied colour [n,3], alpha [n]).
     """
     pix = np.asarray(pix, dtype=np.int64).reshape(-1, 3)
     K = len(depth32)
@@ -132,13 +133,16 @@ def composite_at(texel_fn, depth32, cam, geom, dx32, dy32, interp: str, pix):
             y0 = y0.astype(np.int64)
             taps = [(y0 + oy, x0 + ox, fy * fx) for oy, fy in ((0, 1 - wy), (1, wy))
                     for ox, fx in ((0, 1 - wx), (1, wx))]
-        s = np.zeros((n, 4))
+        s = None
         for iy, ix, w in taps:
             ok = (iy >= 0) & (iy < H) & (ix >= 0) & (ix < W)
+            val, am = texel_fn(k, iy[ok], ix[ok])
+            if s is None:
+                s = np.zeros((n, val.shape[1]))
             if np.any(ok):
-                val, am = texel_fn(k, iy[ok], ix[ok])
                 s[ok] += val * w[ok, None]
                 pa[np.nonzero(ok)[0][am & (w[ok] > 0)]] = True
-        Q += T[:, None] * s[:, :3]
-        T = T * (1.0 - s[:, 3])
+        col, alpha = (s[:, :3], s[:, 3]) if colour is None else colour(s)
+        Q += T[:, None] * col
+        T = T * (1.0 - alpha)
     return np.concatenate([Q, T[:, None]], axis=1), pa

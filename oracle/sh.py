@@ -101,6 +101,24 @@ def pixel_directions(cam, g: geometry.Geometry, dx: float, dy: float, xs, ys) ->
     return w / np.linalg.norm(w, axis=-1, keepdims=True)
 
 
+def composite_sh_at(texel_fn, degree: int, depth32, cam, g: geometry.Geometry, dx32, dy32, interp: str, pix):
+    """The SH composite at individual pixels pix [n,3] of (view, y, x).  texel_fn(k, iy, ix)
+    returns (texels [m, 3 n_coef + 1], ambiguous [m]) in the channel order of the planes that
+    build_sh_planes blends (the coefficients (j, rgb) flattened, then A)."""
+    nc = n_coef(degree)
+    pix = np.asarray(pix, dtype=np.int64).reshape(-1, 3)
+    Y = np.empty((pix.shape[0], nc))
+    for i, (v, y, x) in enumerate(pix):
+        Y[i] = basis(pixel_directions(cam, g, float(dx32[v]), float(dy32[v]), [x], [y])[0, 0], degree)
+
+    def colour(s):
+        a = s[:, 3 * nc]
+        c = np.einsum("nj,njc->nc", Y, s[:, :3 * nc].reshape(-1, nc, 3)) + 0.5 * a[:, None]
+        return np.maximum(c, 0.0), a
+
+    return composite.composite_at(texel_fn, depth32, cam, g, dx32, dy32, interp, pix, colour=colour)
+
+
 def build_sh_planes(scene: dict, sh, degree: int, cam, n_chunk: int, binning="quantile", inv_depth_range=None,
                     chunks=None):
     """SH planes of a Gaussian field: (q [K,H,W,n_coef,3], A [K,H,W], ambiguous [K,H,W], depth [K]).

@@ -161,3 +161,44 @@ def test_render_view_sh_matches_oracle():
     ref, amb = sh.render_view_sh(scene, coef, 3, cam, float(np.float32(0.12)), float(np.float32(-0.05)))
     err = np.abs(host(out["rgba"][0]) - ref).max(axis=-1)
     assert err[~amb].max() <= 1e-4, err[~amb].max()
+
+
+def test_sh500k_full_size():
+    """The sh500k workload (cluster500k with degree-3 SH colour, 64 SH planes, 45 views):
+    partition as the RGB build; texels and pixels on seeded samples against the oracle."""
+    from oracle import partition, splat
+    announce("sh500k full size")
+    scene, cam, cfg = scenegen.config("cluster500k")
+    n = scene["means"].shape[0]
+    coef = scenegen.sh_coefficients(n, 3, 7)
+    out = T.build_mpi_sh(ctx(), T.to_device(scene), dev(coef), cam, 64)
+    info, st = T.build_stats(ctx(), out["workspace"])
+    g = geometry.derive(cam)
+    part = partition.partition(scene["means"], cam, g, 64)
+    assert np.array_equal(out["depth"].cpu().numpy().view(np.uint32), part.depth.view(np.uint32))
+    coloured = dict(scene, rgb=coef.reshape(n, 48).astype(np.float64))
+    cache = {}
+
+    def texels(k, iy, ix):
+        if k not in cache:
+            cache[k] = render.chunk_projection(coloured, cam, g, part, k)
+        return splat.blend_texels(cache[k], ix, iy)
+
+    rng = np.random.default_rng(1)
+    planes = out["planes"]
+    for k in rng.choice(64, 4, replace=False):
+        iy, ix = rng.integers(0, g.hp, 300), rng.integers(0, g.wp, 300)
+        ref, amb = texels(int(k), iy, ix)
+        got = host(planes[int(k)][torch.from_numpy(iy).cuda(), torch.from_numpy(ix).cuda()])
+        gq, gA, _ = _unpack(got, 3)
+        err = np.maximum(np.abs(gq.reshape(-1, 48) - ref[:, :48]).max(axis=1), np.abs(gA - ref[:, 48]))
+        assert err[~amb].max() <= 2e-4, err[~amb].max()
+    dx, dy, _, _ = geometry.quilt_views(cam, 45, 1)
+    dx, dy = dx.astype(np.float32), dy.astype(np.float32)
+    views = T.composite_sh(ctx(), planes, out["depth"], 3, cam, T.views_of(dx, dy), "nearest")
+    pix = np.stack([rng.integers(0, 45, 150), rng.integers(0, 512, 150), rng.integers(0, 512, 150)], 1)
+    ref, amb = sh.composite_sh_at(texels, 3, out["depth"].cpu().numpy(), cam, g, dx, dy, "nearest", pix)
+    sel = torch.from_numpy(pix).cuda()
+    got = host(views[sel[:, 0], sel[:, 1], sel[:, 2]])
+    err = np.abs(got - ref).max(axis=1)
+    assert err[~amb].max() <= 2e-4, err[~amb].max()

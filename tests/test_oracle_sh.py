@@ -196,3 +196,24 @@ def test_view_colours_use_the_view_centre():
 def test_basis_degree_prefix(degree):
     d = _unit(np.random.default_rng(7), 9)
     np.testing.assert_array_equal(sh.basis(d, degree), sh.basis(d, 3)[:, :sh.n_coef(degree)])
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+def test_composite_sh_at_matches_whole_views(interp):
+    """The per-pixel SH composite (used at full size) equals the whole-view one."""
+    R = np.asarray(_rotation(8))
+    cam = scenegen.camera(40, 30, 50.0, 2.0, math.radians(30), math.radians(10), R=R)
+    g = geometry.derive(cam)
+    rng = np.random.default_rng(2)
+    K, nc = 3, 9
+    A = rng.uniform(0, 0.8, (K, g.hp, g.wp))
+    q = rng.normal(scale=0.3, size=(K, g.hp, g.wp, nc, 3)) * A[..., None, None]
+    depth = np.sort(rng.uniform(g.d_forward + 0.3, 8.0, K)).astype(np.float32)
+    dx, dy, _, _ = geometry.quilt_views(cam, 3, 2)
+    dx, dy = dx.astype(np.float32), dy.astype(np.float32)
+    full = sh.composite_sh(q, A, 2, depth, cam, g, dx, dy, interp)
+    stacked = np.concatenate([q.reshape(K, g.hp, g.wp, 3 * nc), A[..., None]], axis=-1)
+    f = lambda k, iy, ix: (stacked[k, iy, ix], np.zeros(iy.size, bool))
+    pix = np.stack([rng.integers(0, 6, 150), rng.integers(0, g.ny, 150), rng.integers(0, g.nx, 150)], 1)
+    at, _ = sh.composite_sh_at(f, 2, depth, cam, g, dx, dy, interp, pix)
+    np.testing.assert_allclose(at, full[pix[:, 0], pix[:, 1], pix[:, 2]], atol=1e-13)
