@@ -510,12 +510,14 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
 // form and with the same per-quadrant lists.  One work-group per (tile, chunk) bucket walks
 // the bucket's entries in order, kShSplatSeg at a time, so its transmittance carries over
 // and no partial tiles are needed (a texel's state is 3 NC + 1 floats).  Per step, thread t
-// stages entry t's quadratic form, then all threads copy the entries' coefficients into LDS
-// with coalesced loads, and each wave walks its quadrant's list.  The short step keeps LDS
-// small enough for four work-groups per CU.  The texel is stored as q_0 (r, g, b), A,
-// q_1 .. q_{NC-1} (r, g, b), zero padding.
+// stages entry t's quadratic form and Gaussian index in LDS, and each wave walks its
+// quadrant's list.  A wave's entry is uniform, so its coefficients come through scalar
+// loads (read-only data, constant address space) and feed the blend FMAs as scalar
+// operands: no LDS traffic and no vector registers for them.  The texel is stored as q_0
+// (r, g, b), A, q_1 .. q_{NC-1} (r, g, b), zero padding.
 // ---------------------------------------------------------------------------------------
 constexpr int kShSplatSeg = 64;
+typedef const float __attribute__((address_space(4))) ConstF32;
 
 template <int NC>
 __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_buckets) {
@@ -524,7 +526,6 @@ __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_bucket
   __shared__ float4 s_p[kShSplatSeg];            // (ca, cb, cc, A)
   __shared__ float2 s_q[kShSplatSeg];            // (B, C)
   __shared__ uint32_t s_gi[kShSplatSeg];
-  __shared__ float s_sh[kShSplatSeg * NF];
   __shared__ uint8_t s_list[4][kShSplatSeg];
   __shared__ int s_cnt[4];
   const int64_t bidx = blockIdx.x;
@@ -540,6 +541,7 @@ __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_bucket
   const bool ok = a.hdr->overflow == 0;
   const uint32_t bb0 = a.bucket[bidx], bb1 = ok ? a.bucket[bidx + 1] : bb0;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  ConstF32* sh = (ConstF32*)a.sh;
   float acc[NF];
 #pragma unroll
   for (int j = 0; j < NF; ++j) acc[j] = 0.0f;
@@ -567,17 +569,16 @@ __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_bucket
       }
     }
     __syncthreads();
-    for (int f = tid; f < n * NF; f += 256) s_sh[f] = a.sh[(size_t)s_gi[f / NF] * NF + f % NF];
-    __syncthreads();
-    const int cnt = s_cnt[wave];
+    const int cnt = __builtin_amdgcn_readfirstlane(s_cnt[wave]);
     for (int i = 0; i < cnt; ++i) {
-      const int e = s_list[wave][i];
+      const int e = __builtin_amdgcn_readfirstlane(s_list[wave][i]);
+      const uint32_t gi = __builtin_amdgcn_readfirstlane(s_gi[e]);
+      ConstF32* c = sh + (size_t)gi * NF;
       const float4 P = s_p[e];
       const float2 Q = s_q[e];
       const float q = taylor_q(P.x, P.y, P.z, P.w, Q.x, Q.y, du, dv, duu, duv, dvv);
       const float alpha = q >= kLog2AlphaMin ? fminf(kAlphaMax, __builtin_amdgcn_exp2f(q)) : 0.0f;
       const float w = alpha * T;
-      const float* c = s_sh + e * NF;
 #pragma unroll
       for (int j = 0; j < NF; ++j) acc[j] = fmaf(w, c[j], acc[j]);
       T = T - w;
