@@ -37,7 +37,7 @@ extern "C" {
 typedef enum {
   LF_OK = 0,
   LF_ERR_INVALID_ARG = 1,   /* a null pointer, a size or an enum out of range         */
-  LF_ERR_UNSUPPORTED = 2,   /* a valid request this build does not implement          */
+  LF_ERR_UNSUPPORTED = 2,   /* a valid request the library does not implement         */
   LF_ERR_CAPACITY = 3,      /* a workspace too small; the needed size is reported      */
   LF_ERR_OUT_OF_MEMORY = 4, /* a library-owned allocation failed                       */
   LF_ERR_HIP = 5            /* a HIP runtime call failed (also deferred async errors)  */

@@ -34,7 +34,7 @@ def test_torch_forward_is_the_oracle_forward(interp):
 
 @pytest.mark.parametrize("interp", ["nearest", "bilinear"])
 def test_autograd_matches_central_differences(interp):
-    """Central differences (h from the survey's FD protocol, scaled for float64) of the
+    """Central differences (a step scaled for float64) of the
     loss with frozen decisions against the autograd gradient on 40 random parameters."""
     scene, cam, K, dx, dy, _ = _setup(interp=interp)
     target = scenegen.perturbed_target(scene, 9)
