@@ -510,13 +510,13 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
 // form and with the same per-quadrant lists.  One work-group per (tile, chunk) bucket walks
 // the bucket's entries in order, kShSplatSeg at a time, so its transmittance carries over
 // and no partial tiles are needed (a texel's state is 3 NC + 1 floats).  Per step, thread t
-// stages entry t's quadratic form and Gaussian index in LDS, and each wave walks its
-// quadrant's list.  A wave's entry is uniform, so its coefficients come through scalar
+// stages entry t's quadratic form and Gaussian index in LDS, the work-group compacts the
+// entries reaching each quadrant (stable), and each wave walks its quadrant's list.  A wave's entry is uniform, so its coefficients come through scalar
 // loads (read-only data, constant address space) and feed the blend FMAs as scalar
 // operands: no LDS traffic and no vector registers for them.  The texel is stored as q_0
 // (r, g, b), A, q_1 .. q_{NC-1} (r, g, b), zero padding.
 // ---------------------------------------------------------------------------------------
-constexpr int kShSplatSeg = 64;
+constexpr int kShSplatSeg = 256;
 typedef const float __attribute__((address_space(4))) ConstF32;
 
 template <int NC>
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_bucket
   __shared__ float2 s_q[kShSplatSeg];            // (B, C)
   __shared__ uint32_t s_gi[kShSplatSeg];
   __shared__ uint8_t s_list[4][kShSplatSeg];
-  __shared__ int s_cnt[4];
+  __shared__ int s_cnt[4][4];                    // [quadrant][loading wave]
   const int64_t bidx = blockIdx.x;
   if (bidx >= n_buckets) return;
   const int tile = (int)(bidx / a.K), k = (int)(bidx % a.K);
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_bucket
     const int n = (int)min(bb1 - b0, (uint32_t)kShSplatSeg);
     __syncthreads();                             // the previous step is consumed
     uint32_t qm = 0;
-    if (tid < n) {                               // wave 0 holds the step's entries
+    if (tid < n) {
       const uint32_t ent = a.evals[b0 + tid];
       const uint32_t gi = min(ent & 0x0fffffffu, (uint32_t)a.n - 1u);
       const GRec& g = a.rec[gi];
@@ -560,16 +560,24 @@ __global__ __launch_bounds__(256) void splat_sh_gs(BuildArgs a, int64_t n_bucket
       s_gi[tid] = gi;
       qm = reached_quadrants(g, ent >> 28, tt.sx, tt.sy);
     }
-    if (wave == 0) {
+    uint32_t rank[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint64_t m = __ballot((qm >> q) & 1u);
-        if ((qm >> q) & 1u) s_list[q][__popcll(m & below)] = (uint8_t)tid;
-        if (lane == 0) s_cnt[q] = __popcll(m);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t m = __ballot((qm >> q) & 1u);
+      rank[q] = __popcll(m & below);
+      if (lane == 0) s_cnt[q][wave] = __popcll(m);
     }
     __syncthreads();
-    const int cnt = __builtin_amdgcn_readfirstlane(s_cnt[wave]);
+    int my_count = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int off = 0;
+      for (int w = 0; w < 4; ++w) off += w < wave ? s_cnt[q][w] : 0;
+      if ((qm >> q) & 1u) s_list[q][off + rank[q]] = (uint8_t)tid;
+      if (q == wave) my_count = s_cnt[q][0] + s_cnt[q][1] + s_cnt[q][2] + s_cnt[q][3];
+    }
+    __syncthreads();
+    const int cnt = __builtin_amdgcn_readfirstlane(my_count);
     for (int i = 0; i < cnt; ++i) {
       const int e = __builtin_amdgcn_readfirstlane(s_list[wave][i]);
       const uint32_t gi = __builtin_amdgcn_readfirstlane(s_gi[e]);
