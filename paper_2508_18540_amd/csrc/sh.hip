@@ -11,6 +11,7 @@
 // output pixel, texels read from global memory) is kept as the plain form.
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "lf_internal.h"
 #include "sh_basis.h"
@@ -219,12 +220,9 @@ __global__ __launch_bounds__(kShSeg * kShWaves) void composite_sh_rows(Composite
     if (fits)
       for (int i = tid; i < len * T4; i += NT) win[i] = fetch(f0 + i / T4, i % T4);
     __syncthreads();
-    auto texel = [&](int ix, int c) -> float4 {
-      return fits ? win[min(max(ix - f0, 0), len - 1) * T4 + c] : fetch(ix, c);
-    };
-#pragma unroll
-    for (int jj = 0; jj < VW; ++jj) {
-      if (wave + kShWaves * jj >= nv) continue;
+    // one view's sample: texels from the LDS window (FROM_LDS) or from global memory
+    auto blend_view = [&](int jj, auto from_lds_tag) {
+      constexpr bool FROM_LDS = decltype(from_lds_tag)::value;
       const float cx = a.c.cpx + pc.gx * dxv[jj];
       const float X = pc.bx * xr + (BIL ? cx : cx + 0.5f);
       int ix;
@@ -236,10 +234,13 @@ __global__ __launch_bounds__(kShSeg * kShWaves) void composite_sh_rows(Composite
         ax = X - fx0;
         ix = __float2int_rd(fx0);
       }
+      // window slots of the sample's texels, computed once (clamped: lanes past the row end)
+      const int w0 = FROM_LDS ? min(max(ix - f0, 0), len - 1) * T4 : 0;
+      const int w1 = FROM_LDS && BIL ? min(max(ix + 1 - f0, 0), len - 1) * T4 : 0;
       auto sample = [&](int c) -> float4 {
-        const float4 t0 = texel(ix, c);
+        const float4 t0 = FROM_LDS ? win[w0 + c] : fetch(ix, c);
         if (!BIL) return t0;
-        const float4 t1 = texel(ix + 1, c);
+        const float4 t1 = FROM_LDS ? win[w1 + c] : fetch(ix + 1, c);
         return make_float4(fmaf(ax, t1.x - t0.x, t0.x), fmaf(ax, t1.y - t0.y, t0.y), fmaf(ax, t1.z - t0.z, t0.z),
                            fmaf(ax, t1.w - t0.w, t0.w));
       };
@@ -259,6 +260,15 @@ __global__ __launch_bounds__(kShSeg * kShWaves) void composite_sh_rows(Composite
       Qg[jj] = fmaf(Tr[jj], fmaxf(cg, 0.0f), Qg[jj]);
       Qb[jj] = fmaf(Tr[jj], fmaxf(cb, 0.0f), Qb[jj]);
       Tr[jj] = fmaf(-Tr[jj], A, Tr[jj]);
+    };
+    if (fits) {                                            // uniform: one straight path each
+#pragma unroll
+      for (int jj = 0; jj < VW; ++jj)
+        if (wave + kShWaves * jj < nv) blend_view(jj, std::true_type{});
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < VW; ++jj)
+        if (wave + kShWaves * jj < nv) blend_view(jj, std::false_type{});
     }
   }
   if (x < a.nx) {
