@@ -836,17 +836,23 @@ __global__ void zero_f32(float* p, int64_t n) {
 }
 
 // threads of a row work-group, and whether the whole-row window fits its buffer and fetch
-int row_threads(int nx) {
-  const int nseg = (nx + kRowThreads - 1) / kRowThreads;
-  const int seg = (nx + nseg - 1) / nseg;
-  return ((seg + 63) / 64) * 64;
+// Threads of a row work-group for its segment of seg pixels: one per pixel, and enough
+// (up to kRowThreads) for the fetch of the whole-row fallback, wp + 4 entries at kPrefetch
+// per thread (half for bilinear); the threads past the segment only fetch.
+int row_threads(const CompositeArgs& a, int* seg_out) {
+  const int nseg = (a.nx + kRowThreads - 1) / kRowThreads;
+  const int seg = (a.nx + nseg - 1) / nseg;
+  const int per_thread = a.interp == LF_BILINEAR ? kPrefetch / 2 : kPrefetch;
+  const int need = std::min((a.wp + 4 + per_thread - 1) / per_thread, kRowThreads);
+  if (seg_out) *seg_out = seg;
+  return (std::max(seg, need) + 63) / 64 * 64;
 }
 
 bool rows_fit(const CompositeArgs& a) {
   const bool bil = a.interp == LF_BILINEAR;
   const int entries = a.wp + 4;
   const int per_thread = bil ? kPrefetch / 2 : kPrefetch;
-  return entries <= (bil ? kWin / 2 : kWin) && entries <= per_thread * row_threads(a.nx);
+  return entries <= (bil ? kWin / 2 : kWin) && entries <= per_thread * row_threads(a, nullptr);
 }
 
 // Views that share dy, as classes in the order of their first view, each class's views in
@@ -896,9 +902,9 @@ void launch_table(const CompositeArgs& a, float4* pt, float* ct, hipStream_t s) 
 
 template <typename PT, typename OT, bool BIL>
 hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const float* ct, hipStream_t s) {
-  const int nseg = (a.nx + kRowThreads - 1) / kRowThreads;
-  const int seg = (a.nx + nseg - 1) / nseg;
-  const int threads = ((seg + 63) / 64) * 64;
+  int seg;
+  const int threads = row_threads(a, &seg);
+  const int nseg = (a.nx + seg - 1) / seg;
   const size_t lds = (size_t)2 * kWinStride * 16;
   const dim3 grid(a.ny, a.n_groups, nseg);
   switch (G) {

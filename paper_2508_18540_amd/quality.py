@@ -39,14 +39,28 @@ def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
     return math.inf if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
 
 
+def _render_checked(ctx: T.Context, render, scene: dict, cam, ws):
+    """render(workspace) -> out, re-run once with a larger workspace if its tile lists overflowed
+    (the per-view render builds one plane at the view size with the view camera's settings)."""
+    out = render(ws)
+    info, st = T.build_stats(ctx, out["workspace"], check=False)
+    if info.overflow:
+        view_cam = cam.with_(phi_x=0.0, phi_y=0.0, d_shift=0.0, plane_scale=1.0, dilation=0.0)
+        ws = T.workspace_for(scene, view_cam, 1, entry_capacity=int(info.entries_needed * 1.1) + 1024)
+        out = render(ws)
+        T.build_stats(ctx, out["workspace"], check=True)
+    elif st != L.LF_OK:
+        T.build_stats(ctx, out["workspace"], check=True)
+    return out
+
+
 def reference_views(ctx: T.Context, scene: dict, cam, views) -> torch.Tensor:
     """Conventional per-view renders [V, ny, nx, 3] (premultiplied colour over black)."""
     out, ws = None, None
     refs = []
     for v in views:
-        out = T.render_view(ctx, scene, cam, v.dx, v.dy, workspace=ws, out=out)
+        out = _render_checked(ctx, lambda w: T.render_view(ctx, scene, cam, v.dx, v.dy, workspace=w), scene, cam, ws)
         ws = out["workspace"]
-        T.build_stats(ctx, ws, check=True)
         refs.append(out["rgba"][0, ..., :3].float().clone())
     return torch.stack(refs)
 
@@ -65,10 +79,37 @@ def light_field_views(ctx: T.Context, scene: dict, cam, views, n_chunk: int, int
     return img[..., :3].float()
 
 
+def frame_ms(ctx: T.Context, scene: dict, cam, views, n_chunk: int, interp: str = "nearest", dtype=torch.float32,
+             reps: int = 3) -> dict:
+    """GPU time of one light-field frame (build + composite), from the library's HIP-event
+    phase timers: warm-up, then the mean over reps frames, and the plane bytes."""
+    ws = T.workspace_for(scene, cam, n_chunk)
+    out = T.build_mpi(ctx, scene, cam, n_chunk, dtype=dtype, workspace=ws)
+    info, st = T.build_stats(ctx, ws, check=False)
+    if info.overflow:
+        ws = T.workspace_for(scene, cam, n_chunk, entry_capacity=int(info.entries_needed * 1.1) + 1024)
+        out = T.build_mpi(ctx, scene, cam, n_chunk, dtype=dtype, workspace=ws)
+    img = T.composite(ctx, out["rgba"], out["depth"], cam, views, interp)
+    torch.cuda.synchronize()
+    L.lf_profile_read(ctx.handle, reset=True)
+    L.lf_profile_enable(ctx.handle, True)
+    for _ in range(reps):
+        T.build_mpi(ctx, scene, cam, n_chunk, dtype=dtype, workspace=ws, out=out)
+        T.composite(ctx, out["rgba"], out["depth"], cam, views, interp, out=img)
+    torch.cuda.synchronize()
+    L.lf_profile_enable(ctx.handle, False)
+    prof = L.lf_profile_read(ctx.handle, reset=True)
+    T.build_stats(ctx, ws, check=True)
+    comp = prof["composite"][0] + prof["coeff"][0]
+    return dict(build_ms=round((sum(v[0] for v in prof.values()) - comp) / reps, 3), composite_ms=round(comp / reps, 3),
+                plane_bytes=int(out["rgba"].numel() * out["rgba"].element_size()))
+
+
 def sweep(ctx: T.Context, scene: dict, cam_of, vx: int, chunks, scales=(1.0,), interps=("nearest",),
-          dtypes=("f32",)):
+          dtypes=("f32",), timed: bool = False):
     """Yields one dict per (plane scale, interpolation, dtype, N_chunk): mean PSNR over the
-    views, the worst view's PSNR, and the settings.  cam_of(plane_scale) gives the camera."""
+    views, the worst view's PSNR, and the settings (with timed, also the frame's GPU time and
+    plane bytes).  cam_of(plane_scale) gives the camera."""
     for ps in scales:
         cam = cam_of(ps)
         views = L.lf_quilt_views(L.make_camera(cam), vx, 1)
@@ -78,9 +119,12 @@ def sweep(ctx: T.Context, scene: dict, cam_of, vx: int, chunks, scales=(1.0,), i
                 for k in chunks:
                     img = light_field_views(ctx, scene, cam, views, k, interp, _DTYPES[dt])
                     per_view = [psnr(img[v], ref[v]) for v in range(len(views))]
-                    yield dict(plane_scale=ps, interp=interp, planes=dt, n_chunk=k,
+                    row = dict(plane_scale=ps, interp=interp, planes=dt, n_chunk=k,
                                psnr_mean=round(float(np.mean(per_view)), 2),
                                psnr_min=round(float(np.min(per_view)), 2), views=len(views))
+                    if timed:
+                        row.update(frame_ms(ctx, scene, cam, views, k, interp, _DTYPES[dt]))
+                    yield row
 
 
 def sh_sweep(ctx: T.Context, scene: dict, sh: torch.Tensor, cam, vx: int, chunks, interp: str = "nearest"):
@@ -90,11 +134,11 @@ def sh_sweep(ctx: T.Context, scene: dict, sh: torch.Tensor, cam, vx: int, chunks
     Yields one dict per N_chunk with both mean PSNRs and both plane sizes."""
     views = L.lf_quilt_views(L.make_camera(cam), vx, 1)
     degree = T._sh_degree(sh)
-    ws, out, refs = None, None, []
+    ws, refs = None, []
     for v in views:
-        out = T.render_view_sh(ctx, scene, sh, cam, v.dx, v.dy, workspace=ws, out=out)
+        out = _render_checked(ctx, lambda w: T.render_view_sh(ctx, scene, sh, cam, v.dx, v.dy, workspace=w), scene,
+                              cam, ws)
         ws = out["workspace"]
-        T.build_stats(ctx, ws, check=True)
         refs.append(out["rgba"][0, ..., :3].float().clone())
     ref = torch.stack(refs)
     rgb_scene = dict(scene, rgb=T.sh_colours(ctx, scene["means"], sh, cam, 0.0, 0.0))
@@ -134,6 +178,7 @@ def main(argv=None) -> None:
     p.add_argument("--scales", default="1,2")
     p.add_argument("--interp", default="nearest,bilinear")
     p.add_argument("--planes", default="f32,u8")
+    p.add_argument("--time", action="store_true", help="also report the frame's GPU time and plane bytes")
     p.add_argument("--filters", default="adaptive",
                    help="adaptive (Eq. 8) and/or constant (f' = 0.3 reference texels^2 whatever P_s): the "
                         "adaptive-filter ablation")
@@ -164,8 +209,9 @@ def main(argv=None) -> None:
 
     for filt in a.filters.split(","):
         for row in sweep(ctx, scene, lambda ps: cam_of(ps, filt), a.views, [int(c) for c in a.chunks.split(",")],
-                         [float(s) for s in a.scales.split(",")], a.interp.split(","), a.planes.split(",")):
-            print(json.dumps(dict(row, filter=filt)), flush=True)
+                         [float(s) for s in a.scales.split(",")], a.interp.split(","), a.planes.split(","),
+                         timed=a.time):
+            print(json.dumps(dict(row, filter=filt, res=a.res, phi=a.phi)), flush=True)
 
 
 if __name__ == "__main__":

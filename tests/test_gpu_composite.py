@@ -47,6 +47,7 @@ CASES = [
     ("single_view_single_plane", 64, 48, 1, 1, 1, 1.0, 0.0),
     ("general_vy3", 96, 80, 6, 4, 3, 1.0, 12.0),
     ("wide700", 700, 40, 4, 3, 1, 1.0, 0.0),
+    ("wide_planes_768_ps2", 768, 40, 4, 3, 1, 2.0, 0.0),
 ]
 
 
