@@ -16,20 +16,22 @@ from tests.gpu_util import announce, ctx
 
 pytestmark = pytest.mark.gpu
 
-# (Gaussians, resolution, N_chunk, views, binning, plane dtype, interp)
+# (Gaussians, resolution, N_chunk, views (vx, vy), binning, plane dtype, interp); the last
+# scene is a 2D quilt (three vertical offsets) with UNORM8 planes
 SCENES = [
-    (20_000, 128, 16, 5, "quantile", torch.float32, "nearest"),
-    (40_000, 192, 32, 9, "inv_depth", torch.float16, "bilinear"),
-    (60_000, 256, 64, 16, "quantile", torch.bfloat16, "nearest"),
-    (30_000, 160, 8, 24, "quantile", torch.float16, "nearest"),
+    (20_000, 128, 16, (5, 1), "quantile", torch.float32, "nearest"),
+    (40_000, 192, 32, (9, 1), "inv_depth", torch.float16, "bilinear"),
+    (60_000, 256, 64, (16, 1), "quantile", torch.bfloat16, "nearest"),
+    (30_000, 160, 8, (24, 1), "quantile", torch.float16, "nearest"),
+    (25_000, 144, 12, (4, 3), "quantile", torch.uint8, "nearest"),
 ]
 
 
 def _scenes():
     out = []
-    for i, (n, res, K, V, binning, pdt, interp) in enumerate(SCENES):
-        cam = scenegen.camera(res, res, 50.0, 2.0, math.radians(40.0))
-        dx, dy, _, _ = geometry.quilt_views(cam, V, 1)
+    for i, (n, res, K, (vx, vy), binning, pdt, interp) in enumerate(SCENES):
+        cam = scenegen.camera(res, res, 50.0, 2.0, math.radians(40.0), math.radians(12.0) if vy > 1 else 0.0)
+        dx, dy, _, _ = geometry.quilt_views(cam, vx, vy)
         out.append(dict(scene=T.to_device(scenegen.cluster_scene(n, seed=40 + i)), cam=cam, n_chunk=K,
                         views=T.views_of(dx.astype(np.float32), dy.astype(np.float32)), binning=binning,
                         inv_depth_range=(1.0, 20.0) if binning == "inv_depth" else None, plane_dtype=pdt,
