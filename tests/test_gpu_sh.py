@@ -54,6 +54,21 @@ def test_sh_planes_match_oracle(degree):
     _check_planes(host(out["planes"]), degree, q, A, amb)
 
 
+def test_sh_planes_inverse_depth_binning():
+    """SH planes over inverse-depth chunks (the binning of the uniform workload)."""
+    announce("SH planes inv_depth")
+    n = 3000
+    scene = scenegen.small_scene(n, 25)
+    coef = scenegen.sh_coefficients(n, 1, 26)
+    cam = scenegen.camera(80, 64, 50.0, 3.0, math.radians(30))
+    out = T.build_mpi_sh(ctx(), T.to_device(scene), dev(coef), cam, 5, binning="inv_depth",
+                         inv_depth_range=(2.0, 4.0))
+    T.build_stats(ctx(), out["workspace"])
+    q, A, amb, depth = sh.build_sh_planes(scene, coef, 1, cam, 5, "inv_depth", (2.0, 4.0))
+    assert np.array_equal(out["depth"].cpu().numpy().view(np.uint32), depth.view(np.uint32))
+    _check_planes(host(out["planes"]), 1, q, A, amb)
+
+
 def test_sh_planes_long_buckets():
     """Buckets of many 256-entry segments: the work-group carries T across its segments."""
     announce("SH planes long buckets")
