@@ -397,9 +397,16 @@ def main():
                           frac=round(evals * 16 / (splat_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
                           traffic=measured_traffic("splat_gs") if form == "f32" else None, kernel="splat_gs",
                           flops_per_launch=evals * 16, avg_ms=round(splat_ms, 4))
+        # the composite's instruction-issue view: its nearest-sampling loop issues 8 VALU per
+        # sample (coordinate add, clamp, floor, LDS address, 4 blend FMA) in the compiled kernel
+        samples = V * cam.ny * cam.nx * K
+        comp_valu = dict(bound="alu", achieved=round(samples * 8 / (comp_ms * 1e-3) / 1e12, 3),
+                         peak=round(VALU_LANE_OPS / 1e12, 1), unit="T VALU lane-instructions/s",
+                         frac=round(samples * 8 / (comp_ms * 1e-3) / VALU_LANE_OPS, 4), kernel="composite_rows",
+                         samples_per_launch=samples, valu_per_sample=8)
         return dict(form=form, ms_per_step=ms, views_per_s=V / (ms * 1e-3), phases_ms=phases,
-                    composite_roofline=comp_roof, splat_roofline=splat_roof, entries=int(info.entries_needed),
-                    n_visible=int(info.n_visible))
+                    composite_roofline=comp_roof, splat_roofline=splat_roof, composite_valu=comp_valu,
+                    entries=int(info.entries_needed), n_visible=int(info.n_visible))
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     res = {f: one_form(f) for f in forms}
@@ -434,6 +441,8 @@ def main():
                    "views": V, "resolution": [cam.nx, cam.ny]},
         "roofline": roof,
         "composite_roofline": main_r["composite_roofline"],
+        "splat_roofline": main_r["splat_roofline"],
+        "composite_valu": main_r["composite_valu"] if args.interp == "nearest" else None,
         "phases_ms": {k: round(v, 4) for k, v in ph.items()},
         "entries": main_r["entries"],
         "n_visible": main_r["n_visible"],
