@@ -245,7 +245,9 @@ lf_status lf_plane_coeffs(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, 
  * max(sum_j sh_j Y_j(d) + 1/2, 0).  SH planes keep per texel the coefficients blended
  * with the RGB planes' weights, q_j = sum_i alpha_i T_i sh_ij, and A = 1 - T, in
  * lf_sh_texel_floats(L) float32s: q_0 (r, g, b), A, q_1 (r, g, b), ..., q_{n-1} (r, g, b),
- * then zeros.
+ * then zeros.  As everywhere in this header, the caller owns every buffer, and arguments
+ * are validated on the host (LF_ERR_INVALID_ARG, with lf_last_error) before anything is
+ * enqueued.
  * ------------------------------------------------------------------------------------- */
 #define LF_MAX_SH_DEGREE 3
 
