@@ -188,6 +188,18 @@ def test_composite_many_planes_many_views():
     assert np.abs(got - ref).max() <= 1e-4
 
 
+@pytest.mark.parametrize("quilt", [(256, 1), (16, 16)], ids=["256x1", "16x16"])
+def test_composite_maximum_view_count(quilt):
+    """LF_MAX_VIEWS views (one dy class, and 16 classes of 16): the view groups' 8-bit
+    positions and starts reach their limit."""
+    vx, vy = quilt
+    announce("composite max views", vx, vy)
+    cam, g, p, dx, dy = _setup(64, 48, 3, vx, vy, 17, phi_y=16.0 if vy > 1 else 0.0)
+    ref, _ = composite.composite(p["rgba"], p["depth"], cam, g, dx, dy, "nearest")
+    out = T.composite(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy), "nearest")
+    assert np.abs(host(out) - ref).max() <= 1e-4
+
+
 def test_composite_deterministic():
     cam, g, p, dx, dy = _setup(256, 256, 32, 45, 1, 16)
     a = T.composite(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy), "bilinear")
