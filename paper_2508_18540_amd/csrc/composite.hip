@@ -142,8 +142,12 @@ __global__ void coeff_table(CompositeArgs a, float4* __restrict__ pt, float* __r
 }
 
 // ---------------------------------------------------------------------------------------
-// Row kernel.  grid = (ny, view groups, x segments), block = up to kRowThreads threads, one
-// output pixel x per thread and up to G views (one group) per work-group.
+// Row kernel.  One work-group per (view group, x segment, output row), block = up to
+// kRowThreads threads, one output pixel x per thread and up to G views (one group) per
+// work-group.  The groups and segments of a row stage the same plane rows, so the logical
+// tiles (group fastest, then segment, then row) are dealt to the 8 XCDs in contiguous runs
+// (work-group w runs on XCD w mod 8): the work-groups that share plane rows run at about
+// the same time and meet in one L2.
 //
 // Planes are processed in batches of kBatch.  A prologue (one thread per plane) derives
 // the plane row and the texel window [f0, f0 + len) that contains every sample of this
@@ -213,6 +217,7 @@ __device__ __forceinline__ void bilinear_entry(const PT* __restrict__ planes, si
 
 template <typename PT, typename OT, int G, bool BIL>
 __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, int seg_len,
+                                                              int nseg, int total,
                                                               const float4* __restrict__ pt,
                                                               const float* __restrict__ ct) {
   using LT = typename std::conditional<BIL, float4, typename LdsTexel<PT>::type>::type;
@@ -223,14 +228,19 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
   extern __shared__ float4 win[];                          // 2 buffers of kWin float4
   __shared__ PlaneInfo pinfo[kBatch];
   __shared__ int slist[kBatch];
-  __shared__ int scount[2];                                // valid planes, any clamped window
-  const int y = blockIdx.x;
-  const uint32_t gd = a.vgroup[blockIdx.y];
+  __shared__ int scount;                                   // valid planes of the batch
+  const int wg = blockIdx.x;
+  const int per = (total + 7) / 8;
+  const int lg = (wg % 8) * per + wg / 8;
+  if (lg >= total) return;                                 // whole work-group: grid padded to 8 per
+  const int gi = lg % a.n_groups, rest = lg / a.n_groups;
+  const int y = rest / nseg;
+  const uint32_t gd = a.vgroup[gi];
   const int v0 = gd & 0xffu;                               // group's first position in perm
   const int nv = gd >> 8;
-  pt += (size_t)blockIdx.y * a.K;
+  pt += (size_t)gi * a.K;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int xs0 = blockIdx.z * seg_len;
+  const int xs0 = (rest % nseg) * seg_len;
   const int x = xs0 + tid;
   const int xs1 = min(xs0 + seg_len, a.nx) - 1;
   const int wp = a.wp, hp = a.hp, V = ct_stride(a.n_views);
@@ -250,7 +260,7 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
   for (int kb = 0; kb < a.K; kb += kBatch) {
     const int nk = min(kBatch, a.K - kb);
     __syncthreads();                                       // previous batch fully consumed
-    if (tid < 2) scount[tid] = 0;
+    if (tid == 0) scount = 0;
     __syncthreads();
     if (tid < nk) {
       const int k = kb + tid;
@@ -278,24 +288,18 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
       const float hi = floorf(p.x * xr_hi + cmax) + (BIL ? 1.0f : 0.0f);
       // a window must fit the buffer and be covered by the fetch (PF entries per thread)
       const int cap = min(BIL ? kWin / 2 : kWin, PF * nt);
-      bool clamp = false;
       if (lo >= -1.0e9f && hi <= 1.0e9f && hi - lo + 1.0f <= (float)cap) {
         pi.f0 = (int)lo;
         pi.len = (int)(hi - lo) + 1;
       } else {
         pi.f0 = -2;                                        // whole row [-2, wp + 1], clamped
         pi.len = wp + 4;
-        clamp = true;
       }
       pinfo[tid] = pi;
-      if (ok) {
-        slist[atomicAdd(&scount[0], 1)] = tid;             // order restored below
-        if (clamp) atomicOr(&scount[1], 1);
-      }
+      if (ok) slist[atomicAdd(&scount, 1)] = tid;          // order restored below
     }
     __syncthreads();
-    const int nvalid = __builtin_amdgcn_readfirstlane(scount[0]);
-    const bool any_clamp = __builtin_amdgcn_readfirstlane(scount[1]) != 0;
+    const int nvalid = __builtin_amdgcn_readfirstlane(scount);
     if (nvalid == 0) continue;
     if (tid == 0) {                                        // front-to-back order of the valid planes
       for (int i = 1; i < nvalid; ++i) {
@@ -370,8 +374,7 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
         }
       }
     };
-    auto run = [&](auto clamp_tag) {
-      constexpr bool CLAMP = decltype(clamp_tag)::value;
+    {
       fetch(slist[0]);
       store(0, slist[0]);
       __syncthreads();
@@ -396,8 +399,9 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
 #pragma unroll
           for (int jj = 0; jj < kSub; ++jj) {
             const int j = j0 + jj;
-            float X = bxr + Cv[j];
-            if (CLAMP) X = __builtin_amdgcn_fmed3f(X, xmin, xmax);
+            // the clamp is a no-op for fitting windows and holds a whole-row window's
+            // samples on its zero guards
+            const float X = __builtin_amdgcn_fmed3f(bxr + Cv[j], xmin, xmax);
             const int ix = cvt_flr(X);
             if (!BIL) {
               sv[jj] = lds_texel<LT>(wbytes + (ptrdiff_t)ix * (ptrdiff_t)sizeof(LT));
@@ -428,9 +432,7 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
         if (more) store((n + 1) & 1, slist[n + 1]);
         __syncthreads();
       }
-    };
-    (void)any_clamp;
-    run(std::true_type{});                                 // the clamp is a no-op for fitting windows
+    }
   }
   if (tid < seg_len && x < a.nx) {
     OT* out = static_cast<OT*>(a.out);
@@ -906,12 +908,13 @@ hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const fl
   const int threads = row_threads(a, &seg);
   const int nseg = (a.nx + seg - 1) / seg;
   const size_t lds = (size_t)2 * kWinStride * 16;
-  const dim3 grid(a.ny, a.n_groups, nseg);
+  const int total = a.n_groups * nseg * a.ny;
+  const dim3 grid((unsigned)(((total + 7) / 8) * 8)), block(threads);
   switch (G) {
-    case 4: hipLaunchKernelGGL((composite_rows<PT, OT, 4, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
-    case 8: hipLaunchKernelGGL((composite_rows<PT, OT, 8, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
-    case 12: hipLaunchKernelGGL((composite_rows<PT, OT, 12, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
-    default: hipLaunchKernelGGL((composite_rows<PT, OT, 16, BIL>), grid, dim3(threads), lds, s, a, seg, pt, ct); break;
+    case 4: hipLaunchKernelGGL((composite_rows<PT, OT, 4, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
+    case 8: hipLaunchKernelGGL((composite_rows<PT, OT, 8, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
+    case 12: hipLaunchKernelGGL((composite_rows<PT, OT, 12, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
+    default: hipLaunchKernelGGL((composite_rows<PT, OT, 16, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
   }
   return hipGetLastError();
 }
