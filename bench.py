@@ -39,8 +39,8 @@ COPY_WRITE_SCALE = 262144.0 / 262144.0
 MEASURED_TRAFFIC = {
     "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133397, write_kib=286992,
                      digest="11e3fa5c8720dcd9"),
-    "composite_rows": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=89907, write_kib=184320,
-                           digest="321689a4af5e8692"),
+    "composite_rows": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=89674, write_kib=184320,
+                           digest="d974ba25813192f3"),
 }
 
 

@@ -224,6 +224,10 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
   constexpr bool RAW = !std::is_same<LT, float4>::value;   // FP16 texels in LDS (FP16 / UNORM8 planes)
   constexpr bool U8 = RAW && std::is_same<PT, uint8_t>::value;   // samples are codes: scale by 1/255
   using RT = typename std::conditional<U8, uint32_t, uint2>::type;   // raw texel as fetched
+  // nearest FP32 / FP16 / UNORM8 windows are fetched with buffer loads over the plane row:
+  // the hardware's range check returns zero outside the row, so no clamp or mask is needed
+  constexpr bool BUF = !BIL && (RAW || std::is_same<PT, float>::value);
+  constexpr int kTexelBytes = RAW ? (int)sizeof(RT) : 16;
   constexpr int PF = BIL ? kPrefetch / 2 : kPrefetch;
   extern __shared__ float4 win[];                          // 2 buffers of kWin float4
   __shared__ PlaneInfo pinfo[kBatch];
@@ -291,6 +295,10 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
       if (lo >= -1.0e9f && hi <= 1.0e9f && hi - lo + 1.0f <= (float)cap) {
         pi.f0 = (int)lo;
         pi.len = (int)(hi - lo) + 1;
+        // a window wholly outside the row samples only transparent texels, which leave
+        // (Q, T) unchanged exactly; skipping it also keeps every fetched column within
+        // (-cap, wp + cap), where a buffer offset cannot wrap
+        if (!BIL) ok = ok && hi >= 0.0f && lo <= (float)(wp - 1);
       } else {
         pi.f0 = -2;                                        // whole row [-2, wp + 1], clamped
         pi.len = wp + 4;
@@ -315,8 +323,10 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
     __syncthreads();
 
     // Window fetch, split in two: fetch() issues every load of the next plane's window with
-    // clamped (always valid) addresses and no branches, so the loads stay in flight while the
-    // current plane is sampled; store() masks the out-of-plane texels to zero and writes LDS.
+    // no branches, so the loads stay in flight while the current plane is sampled; store()
+    // writes them to LDS.  Nearest FP32 / FP16 / UNORM8 rows use buffer loads, which return
+    // zero outside the row; the other forms clamp their addresses (always valid) and store()
+    // masks the out-of-plane texels to zero.
     float4 ra[RAW ? 1 : PF], rb[BIL ? PF : 1], rc[BIL ? PF : 1], rd[BIL ? PF : 1];
     RT praw[RAW ? PF : 1];
     uint32_t valid = 0;                                    // bit (q * 4 + r): raw texel in the plane
@@ -324,13 +334,22 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
       const PlaneInfo pi = pinfo[k];
       const size_t pbase = (size_t)(kb + k) * plane_elems;
       valid = 0;
+      // (the row of a fetched plane lies in the plane: planes with iy outside it are not valid)
+      const char* rowp = reinterpret_cast<const char*>(planes) + (BUF ? (pbase + (size_t)pi.iy * wp) * kTexelBytes : 0);
+      const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(rowp), (short)0, wp * kTexelBytes, 0x00020000);
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
         if (q * nt >= pi.len) break;                       // uniform: the window is shorter
         const int i = tid + q * nt;
         const int ix = pi.f0 + i;
         const bool in = i < pi.len;
-        if constexpr (!BIL) {
+        if constexpr (BUF) {
+          (void)in;
+          const uint32_t off = (uint32_t)ix * (uint32_t)kTexelBytes;   // ix < 0 wraps past the row
+          if constexpr (U8) praw[q] = (RT)__builtin_amdgcn_raw_buffer_load_b32(rsrc, off, 0, 0);
+          else if constexpr (RAW) praw[q] = __builtin_bit_cast(RT, __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0));
+          else ra[q] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
+        } else if constexpr (!BIL) {
           const bool ok = in && ix >= 0 && ix < wp;
           const size_t at = pbase + (size_t)pi.iy * wp + (size_t)min(max(ix, 0), wp - 1);
           if constexpr (RAW) praw[q] = reinterpret_cast<const RT*>(planes)[at];
@@ -361,7 +380,12 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
         const int i0 = tid + q * nt;
         const int i = i0 < pi.len ? i0 : (BIL ? kWin / 2 : kWin);
         const uint32_t m = valid >> (q * 4);
-        if constexpr (RAW) {
+        if constexpr (BUF) {
+          (void)m;
+          if constexpr (U8) reinterpret_cast<uint2*>(w)[i] = codes_to_half4(praw[q]);
+          else if constexpr (RAW) reinterpret_cast<uint2*>(w)[i] = praw[q];
+          else w[i] = ra[q];
+        } else if constexpr (RAW) {
           if constexpr (U8) reinterpret_cast<uint2*>(w)[i] = codes_to_half4(keep_if((m & 1u) != 0u, praw[q]));
           else reinterpret_cast<uint2*>(w)[i] = keep_if((m & 1u) != 0u, praw[q]);
         } else if constexpr (!BIL) {
