@@ -149,7 +149,12 @@ const char* lf_version(void);
 /* Message of the last failing call on this thread ("" if none).                          */
 const char* lf_last_error(void);
 
-/* Create a context on HIP device `device`; fails with LF_ERR_HIP if it is absent.        */
+/* Create a context on HIP device `device`; fails with LF_ERR_HIP if it is absent.  The
+ * context allocates (once, about 21 MB of device memory) the table of sampling
+ * coefficients lf_composite and lf_composite_backward fill on their stream before they
+ * composite, so those calls never allocate, free or synchronise and may be captured into
+ * a graph.  Calls on one context share that table: calls that overlap on different
+ * streams race (one context per stream).                                                 */
 lf_status lf_create(lf_ctx** out, int device);
 void lf_destroy(lf_ctx* ctx);
 

@@ -87,6 +87,15 @@ extern "C" lf_status lf_create(lf_ctx** out, int device) {
   lf_ctx* c = new (std::nothrow) lf_ctx;
   if (!c) return fail(LF_ERR_OUT_OF_MEMORY, "context allocation failed");
   c->device = device;
+  // The composite's coefficient table, sized once for the largest call (LF_MAX_CHUNKS planes,
+  // LF_MAX_VIEWS views, about 21 MB): lf_composite and lf_composite_backward then never
+  // allocate, free or synchronise, so they can be captured into a graph, and a captured
+  // graph's table stays valid until lf_destroy.
+  c->table_bytes = composite_table_bytes(LF_MAX_CHUNKS, LF_MAX_VIEWS);
+  if ((e = hipMalloc(&c->table, c->table_bytes)) != hipSuccess) {
+    delete c;
+    return hip_fail(e, "composite coefficient table");
+  }
   *out = c;
   return LF_OK;
 }
@@ -176,23 +185,6 @@ extern "C" lf_status lf_profile_read(lf_ctx* ctx, double* ms, int64_t* count, in
   return LF_OK;
 }
 
-// The context's coefficient table, grown on demand (a call under stream capture needs an
-// earlier call of at least this size).  The old table may still be in use by enqueued work,
-// so the device is synchronised before it is freed.
-static hipError_t grow_table(lf_ctx* ctx, size_t need) {
-  if (ctx->table_bytes >= need) return hipSuccess;
-  if (ctx->table) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return e;
-    hipFree(ctx->table);
-  }
-  ctx->table = nullptr;
-  ctx->table_bytes = 0;
-  hipError_t e = hipMalloc(&ctx->table, need);
-  if (e == hipSuccess) ctx->table_bytes = need;
-  return e;
-}
-
 extern "C" lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
                                   int32_t n_views, int32_t interp, int32_t out_dtype, void* out, void* stream) {
   CompositeArgs* a = new (std::nothrow) CompositeArgs;
@@ -208,8 +200,7 @@ extern "C" lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camer
     a->interp = interp;
     a->out_dtype = out_dtype;
     a->out = out;
-    hipError_t e = grow_table(ctx, composite_table_bytes(a->K, a->n_views));
-    if (e == hipSuccess) e = composite_launch(*a, ctx->table, (hipStream_t)stream, &ctx->prof);
+    const hipError_t e = composite_launch(*a, ctx->table, (hipStream_t)stream, &ctx->prof);
     if (e != hipSuccess) s = hip_fail(e, "composite launch");
   }
   delete a;
@@ -231,8 +222,7 @@ extern "C" lf_status lf_composite_backward(lf_ctx* ctx, const lf_mpi* mpi, const
   if (s == LF_OK) s = check_ctx(ctx);
   if (s == LF_OK) {
     a->interp = interp;
-    hipError_t e = grow_table(ctx, composite_table_bytes(a->K, a->n_views));
-    if (e == hipSuccess) e = composite_backward_launch(*a, ctx->table, d_out, d_planes, (hipStream_t)stream, &ctx->prof);
+    const hipError_t e = composite_backward_launch(*a, ctx->table, d_out, d_planes, (hipStream_t)stream, &ctx->prof);
     if (e != hipSuccess) s = hip_fail(e, "composite backward launch");
   }
   delete a;

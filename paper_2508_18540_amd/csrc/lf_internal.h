@@ -48,8 +48,8 @@ struct PhaseScope {
 struct lf_ctx {
   int device;
   lf::Profiler prof;
-  void* table = nullptr;         // device scratch of the composite's coefficient table
-  size_t table_bytes = 0;
+  void* table = nullptr;         // device table of the composite's sampling coefficients,
+  size_t table_bytes = 0;        // allocated by lf_create for the largest call
 };
 
 namespace lf {

@@ -223,3 +223,37 @@ def test_composite_magnified_near_planes_narrow_rows(interp, nx):
     for got in outs:
         err = np.abs(got - ref).max()
         assert err <= 1e-4, err
+
+
+def test_composite_captured_after_larger_call():
+    """lf_composite under stream capture: a larger call before the capture and another one
+    after it leave the captured graph valid (the coefficient table is the context's, sized
+    for the largest call, and never reallocated); every replay equals the eager result and
+    the oracle."""
+    announce("composite graph capture after a larger call")
+    c = ctx()
+    cam_b, g_b, p_b, dx_b, dy_b = _setup(160, 96, 48, 45, 1, 21)
+    big_planes, big_depth = dev(p_b["rgba"]), dev(p_b["depth"])
+    big = T.composite(c, big_planes, big_depth, cam_b, T.views_of(dx_b, dy_b))
+    cam, g, p, dx, dy = _setup(96, 64, 6, 9, 1, 22)
+    planes, depth = dev(p["rgba"]), dev(p["depth"])
+    views = T.views_of(dx, dy)
+    eager = T.composite(c, planes, depth, cam, views)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):                       # warm-up on the capture stream
+        T.composite(c, planes, depth, cam, views)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        captured = T.composite(c, planes, depth, cam, views)
+    ref, _ = composite.composite(p["rgba"], p["depth"], cam, g, dx, dy, "nearest")
+    for r in range(3):
+        captured.zero_()
+        T.composite(c, big_planes, big_depth, cam_b, T.views_of(dx_b, dy_b), out=big)   # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(captured, eager), r
+        assert np.abs(host(captured) - ref).max() <= 1e-4
