@@ -24,7 +24,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import decisions, geometry, partition, project, splat
+from . import composite, decisions, geometry, partition, project, splat
 
 KEYS = ("means", "log_scales", "quats", "opacity", "rgb")
 TD = torch.float64
@@ -354,3 +354,116 @@ def pixel_vjp_sparse(texel_fn, depth32, cam, dx32, dy32, interp: str, pix: np.nd
         R = s[:, :3] + (1.0 - s[:, 3])[:, None] * R
         S = (1.0 - s[:, 3]) * S
     return out
+
+
+def footprint_fd(scene: dict, cam, part: partition.Partition, planes: np.ndarray, dx32, dy32, target: np.ndarray,
+                 i: int, key: str, j, h: float, interp: str = "nearest"):
+    """Central difference (L(theta + h e) - L(theta - h e)) / 2h of the frozen-decision loss
+    L = sum (Q - Q*)^2 (views, pixels, RGB) for parameter ``key``[i, j] (j None for opacity),
+    evaluated only where it can change: Gaussian i's frozen support in its plane k (the texels
+    where o G >= 1/255 at theta) and the view pixels whose samples reach those texels.  Every
+    other texel comes from ``planes`` [K,H,W,4] (the oracle's planes at theta), so a
+    full-size workload costs a footprint, not a frame.  Within the footprint the chunk's
+    Gaussians blend front to back with their inclusion and 0.99-clamp decisions frozen at
+    theta, as ``frozen_loss`` does.  Returns (fd, ambiguous): ambiguous is True when some
+    Gaussian's inclusion or clamp decision at a footprint texel lies within float32
+    rounding of its threshold (a float32 forward may then take the other piece)."""
+    g = geometry.derive(cam)
+    k = int(part.chunk_of[i])
+    if k < 0:
+        return 0.0, False
+    idx = part.order[part.chunk_start[k]:part.chunk_start[k + 1]]
+    pr = project.project_reference(scene, np.array([i]), cam, g)
+    hx, hy, ok = splat.support_halfwidth(pr, np.zeros(1))
+    if not ok[0]:
+        return 0.0, False
+    mx, my = pr.mean2d[0]
+    x0, x1 = max(0, math.ceil(mx - hx[0])), min(g.wp - 1, math.floor(mx + hx[0]))
+    y0, y1 = max(0, math.ceil(my - hy[0])), min(g.hp - 1, math.floor(my + hy[0]))
+    if x0 > x1 or y0 > y1:
+        return 0.0, False
+    yy, xx = np.meshgrid(np.arange(y0, y1 + 1), np.arange(x0, x1 + 1), indexing="ij")
+    ty, tx = yy.reshape(-1), xx.reshape(-1)
+    # the chunk's Gaussians whose support box meets the footprint box (the others add
+    # nothing there), in (key, index) order
+    pa = project.project_reference(scene, idx, cam, g)
+    ax, ay, aok = splat.support_halfwidth(pa, np.zeros(idx.size))
+    near = aok & (pa.mean2d[:, 0] + ax >= x0) & (pa.mean2d[:, 0] - ax <= x1) & \
+        (pa.mean2d[:, 1] + ay >= y0) & (pa.mean2d[:, 1] - ay <= y1)
+    sub_idx = idx[near]
+    pos = int(np.nonzero(sub_idx == i)[0][0])
+    sub = {kk: np.asarray(scene[kk], np.float64)[sub_idx] for kk in KEYS}
+
+    def ln_alpha(p):
+        mean2d, conic = project_reference(p, cam, g)
+        ddx = torch.from_numpy(tx.astype(np.float64))[:, None] - mean2d[None, :, 0]
+        ddy = torch.from_numpy(ty.astype(np.float64))[:, None] - mean2d[None, :, 1]
+        quad = conic[None, :, 0, 0] * ddx * ddx + (conic[None, :, 0, 1] + conic[None, :, 1, 0]) * ddx * ddy + \
+            conic[None, :, 1, 1] * ddy * ddy
+        return torch.log(p["opacity"])[None, :] - 0.5 * quad, conic
+
+    with torch.no_grad():
+        p0 = params_of(sub, requires_grad=False)
+        ln0, conic0 = ln_alpha(p0)
+        inc = ln0 >= splat.LN_ALPHA_MIN
+        clamped = ln0 >= math.log(project.ALPHA_MAX)
+        eps = torch.from_numpy(splat.ambiguity_eps(np.linalg.inv(conic0.numpy())))[None, :]
+        amb = bool((((ln0 - splat.LN_ALPHA_MIN).abs() <= eps) |
+                    ((ln0 - math.log(project.ALPHA_MAX)).abs() <= eps)).any())
+        foot = inc[:, pos].numpy()                       # the frozen support of Gaussian i
+        if not foot.any():
+            return 0.0, amb
+
+        def texels(sign):
+            p = params_of(sub, requires_grad=False)
+            if j is None:
+                p[key][pos] += sign * h
+            else:
+                p[key][pos, j] += sign * h
+            ln, _ = ln_alpha(p)
+            a = torch.exp(torch.clamp(ln, max=0.0))
+            alpha = torch.where(inc, torch.where(clamped, torch.full_like(a, project.ALPHA_MAX), a), torch.zeros_like(a))
+            Tin = torch.cumprod(torch.cat([torch.ones_like(alpha[:, :1]), 1.0 - alpha[:, :-1]], 1), 1)
+            C = (Tin * alpha) @ p["rgb"]
+            A = 1.0 - Tin[:, -1] * (1.0 - alpha[:, -1])
+            return torch.cat([C, A[:, None]], 1).numpy()
+
+        vals = {s: texels(s) for s in (1, -1)}
+    ty, tx = ty[foot], tx[foot]
+    # the view pixels whose taps reach the footprint: X depends on x only and Y on y only
+    c = decisions.constants(g, cam)
+    depth32 = np.asarray(part.depth, np.float32)
+    dx32, dy32 = np.asarray(dx32, np.float32), np.asarray(dy32, np.float32)
+    pc = decisions.plane_coeffs32(c, depth32, dx32, dy32)
+    nearest = interp == "nearest"
+    fx0, fx1, fy0, fy1 = tx.min(), tx.max(), ty.min(), ty.max()
+    xs_all, ys_all = np.arange(cam.nx), np.arange(cam.ny)
+    pix = []
+    for v in range(len(dx32)):
+        X, _ = decisions.texel_coords32(pc, c, k, v, xs_all, np.zeros(cam.nx, np.int64), nearest)
+        _, Y = decisions.texel_coords32(pc, c, k, v, np.zeros(cam.ny, np.int64), ys_all, nearest)
+        ix, iy = np.floor(X).astype(np.int64), np.floor(Y).astype(np.int64)
+        reach = 0 if nearest else 1                      # bilinear also reads the next texel
+        xs = xs_all[(ix + reach >= fx0) & (ix <= fx1)]
+        ys = ys_all[(iy + reach >= fy0) & (iy <= fy1)]
+        if xs.size and ys.size:
+            gy, gx = np.meshgrid(ys, xs, indexing="ij")
+            pix.append(np.stack([np.full(gx.size, v), gy.reshape(-1), gx.reshape(-1)], 1))
+    if not pix:
+        return 0.0, amb
+    pix = np.concatenate(pix)
+    tgt = np.asarray(target, np.float64)[pix[:, 0], pix[:, 1], pix[:, 2], :3]
+
+    def loss(sign):
+        plane_k = np.array(planes[k], np.float64)
+        plane_k[ty, tx] = vals[sign][foot]
+        no = np.zeros(0, bool)
+
+        def texel_fn(kk, iy, ix):
+            src = plane_k if kk == k else planes[kk]
+            return np.asarray(src[iy, ix], np.float64), np.zeros(iy.shape, bool) if iy.size else no
+
+        Q, _ = composite.composite_at(texel_fn, depth32, cam, g, dx32, dy32, interp, pix)
+        return float(((Q[:, :3] - tgt) ** 2).sum())
+
+    return (loss(1) - loss(-1)) / (2.0 * h), amb

@@ -149,3 +149,41 @@ def test_local_vjps_match_the_dense_oracle():
         for (k, y, x), v in sp.items():
             dsp[k, y, x] = v
         np.testing.assert_allclose(dsp, dref, rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+def test_footprint_fd_equals_whole_frame_fd(interp):
+    """The footprint-local central difference (the Gaussian's frozen support in its plane and
+    the pixels that reach it) equals the central difference of the whole frozen-decision
+    loss over every pixel of every view, on 30 random (Gaussian, parameter) pairs with the
+    full-size steps (1e-4 means / log-scales / quaternions, 1e-5 opacity, 1e-3 colour)."""
+    scene, cam, K, dx, dy, _ = _setup(n=60, seed=4, res=32, K=3, views=4, interp=interp)
+    target = composite.composite(render.build_mpi_gaussians(scenegen.perturbed_target(scene, 2), cam, K).planes,
+                                 render.build_mpi_gaussians(scene, cam, K).depth, cam, geometry.derive(cam), dx, dy,
+                                 interp)[0]
+    d = grad.decide(scene, cam, K, dx, dy, interp)
+    mpi = render.build_mpi_gaussians(scene, cam, K)
+    tt = torch.as_tensor(target)
+    rng = np.random.default_rng(5)
+    vis = np.unique(d.gauss)
+    steps = {"means": 1e-4, "log_scales": 1e-4, "quats": 1e-4, "opacity": 1e-5, "rgb": 1e-3}
+    checked = 0
+    for _ in range(30):
+        key = grad.KEYS[rng.integers(0, 5)]
+        i = int(rng.choice(vis))
+        j = int(rng.integers(0, scene[key].shape[1])) if scene[key].ndim == 2 else None
+        h = steps[key]
+        local, amb = grad.footprint_fd(scene, cam, d.part, mpi.planes, dx, dy, target, i, key, j, h, interp)
+        vals = []
+        for sgn in (1, -1):
+            p = grad.params_of(scene, requires_grad=False)
+            with torch.no_grad():
+                if j is None:
+                    p[key][i] += sgn * h
+                else:
+                    p[key][i, j] += sgn * h
+            vals.append(float(grad.frozen_loss(p, cam, d, K, tt)[0]))
+        whole = (vals[0] - vals[1]) / (2 * h)
+        assert abs(local - whole) <= 1e-7 * max(abs(whole), 1e-3), (key, i, j, local, whole)
+        checked += abs(whole) > 1e-6
+    assert checked >= 20
