@@ -187,6 +187,20 @@ lf_status lf_build_mpi(lf_ctx* ctx, const lf_field* field, const lf_camera* cam,
 lf_status lf_build_stats(lf_ctx* ctx, const void* workspace, size_t workspace_bytes,
                          lf_build_info* out, void* stream);
 
+/* The (tile, chunk) lists of the last lf_build_mpi on `workspace` (Sec. 4.4 and Alg. 1
+ * "Rasterize": every chunk's primitives binned to the square tiles of the plane their
+ * support box covers, each list in (depth key, index) order).  Diagnostic entry point for
+ * tests.  field, cam, n_chunk: those of that build.  Host outputs: *tile (texels per tile
+ * side), *tiles_x, *tiles_y.  Device outputs, each skipped when NULL (both NULL: only the
+ * host outputs, no GPU work): bucket_start [tiles_x * tiles_y * n_chunk + 1] int64, the
+ * list of chunk k in tile t = ty * tiles_x + tx being entries[bucket_start[t * n_chunk +
+ * k] .. bucket_start[t * n_chunk + k + 1]) and bucket_start[last] the number of entries;
+ * entries [entries_needed of lf_build_stats] int32 primitive indices.  A build that
+ * overflowed its capacity has no lists (every start 0).  Enqueued on `stream`.            */
+lf_status lf_build_tile_lists(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                              const void* workspace, size_t workspace_bytes, int32_t* tile, int32_t* tiles_x,
+                              int32_t* tiles_y, int64_t* bucket_start, int32_t* entries, void* stream);
+
 /* The conventional per-view render that the light field approximates (the baseline of
  * Sec. 5.1, Table 1): every Gaussian of `field` in one depth-sorted chunk, splatted from
  * the camera of view `view` (Eq. 5: at (dx, dy, 0) in base-camera coordinates, looking

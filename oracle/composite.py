@@ -116,12 +116,14 @@ def composite_at(texel_fn, depth32, cam, geom, dx32, dy32, interp: str, pix, col
     pa = np.zeros(n, dtype=bool)
     W, H = geom.wp, geom.hp
     nearest = interp == "nearest"
+    by_view = np.argsort(pix[:, 0], kind="stable")          # the pixels of each view, found once
+    views, starts = np.unique(pix[by_view, 0], return_index=True)
+    groups = [(int(v), by_view[s:e]) for v, s, e in zip(views, starts, list(starts[1:]) + [n])]
     for k in range(K):
         X = np.empty(n, dtype=np.float32)
         Y = np.empty(n, dtype=np.float32)
-        for v in np.unique(pix[:, 0]):
-            sel = pix[:, 0] == v
-            X[sel], Y[sel] = decisions.texel_coords32(pc, c, k, int(v), pix[sel, 2], pix[sel, 1], nearest)
+        for v, sel in groups:
+            X[sel], Y[sel] = decisions.texel_coords32(pc, c, k, v, pix[sel, 2], pix[sel, 1], nearest)
         if nearest:
             taps = [(np.floor(Y).astype(np.int64), np.floor(X).astype(np.int64), np.ones(n))]
         else:

@@ -367,21 +367,23 @@ def footprint_fd(scene: dict, cam, part: partition.Partition, planes: np.ndarray
     Gaussians blend front to back with their inclusion and 0.99-clamp decisions frozen at
     theta, as ``frozen_loss`` does.  Returns (fd, ambiguous): ambiguous is True when some
     Gaussian's inclusion or clamp decision at a footprint texel lies within float32
-    rounding of its threshold (a float32 forward may then take the other piece)."""
+    rounding of its threshold (a float32 forward may then take the other piece).  Returns
+    (fd, ambiguous, support): support is False, and fd 0, when Gaussian i is culled or
+    includes no texel (o G < 1/255 everywhere)."""
     g = geometry.derive(cam)
     k = int(part.chunk_of[i])
     if k < 0:
-        return 0.0, False
+        return 0.0, False, False
     idx = part.order[part.chunk_start[k]:part.chunk_start[k + 1]]
     pr = project.project_reference(scene, np.array([i]), cam, g)
     hx, hy, ok = splat.support_halfwidth(pr, np.zeros(1))
     if not ok[0]:
-        return 0.0, False
+        return 0.0, False, False
     mx, my = pr.mean2d[0]
     x0, x1 = max(0, math.ceil(mx - hx[0])), min(g.wp - 1, math.floor(mx + hx[0]))
     y0, y1 = max(0, math.ceil(my - hy[0])), min(g.hp - 1, math.floor(my + hy[0]))
     if x0 > x1 or y0 > y1:
-        return 0.0, False
+        return 0.0, False, False
     yy, xx = np.meshgrid(np.arange(y0, y1 + 1), np.arange(x0, x1 + 1), indexing="ij")
     ty, tx = yy.reshape(-1), xx.reshape(-1)
     # the chunk's Gaussians whose support box meets the footprint box (the others add
@@ -412,7 +414,7 @@ def footprint_fd(scene: dict, cam, part: partition.Partition, planes: np.ndarray
                     ((ln0 - math.log(project.ALPHA_MAX)).abs() <= eps)).any())
         foot = inc[:, pos].numpy()                       # the frozen support of Gaussian i
         if not foot.any():
-            return 0.0, amb
+            return 0.0, amb, False
 
         def texels(sign):
             p = params_of(sub, requires_grad=False)
@@ -450,7 +452,7 @@ def footprint_fd(scene: dict, cam, part: partition.Partition, planes: np.ndarray
             gy, gx = np.meshgrid(ys, xs, indexing="ij")
             pix.append(np.stack([np.full(gx.size, v), gy.reshape(-1), gx.reshape(-1)], 1))
     if not pix:
-        return 0.0, amb
+        return 0.0, amb, True
     pix = np.concatenate(pix)
     tgt = np.asarray(target, np.float64)[pix[:, 0], pix[:, 1], pix[:, 2], :3]
 
@@ -466,4 +468,4 @@ def footprint_fd(scene: dict, cam, part: partition.Partition, planes: np.ndarray
         Q, _ = composite.composite_at(texel_fn, depth32, cam, g, dx32, dy32, interp, pix)
         return float(((Q[:, :3] - tgt) ** 2).sum())
 
-    return (loss(1) - loss(-1)) / (2.0 * h), amb
+    return (loss(1) - loss(-1)) / (2.0 * h), amb, True

@@ -29,7 +29,7 @@ EXPORTS = [
     "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_composite_backward",
     "lf_build_mpi_backward", "lf_plane_coeffs", "lf_batch_create", "lf_batch_run", "lf_batch_group",
     "lf_batch_destroy", "lf_profile_enable", "lf_profile_read", "lf_render_view_workspace", "lf_render_view",
-    "lf_sh_texel_floats", "lf_build_mpi_sh", "lf_composite_sh", "lf_sh_colours",
+    "lf_sh_texel_floats", "lf_build_mpi_sh", "lf_composite_sh", "lf_sh_colours", "lf_build_tile_lists",
 ]
 LF_MAX_SH_DEGREE = 3
 LF_BATCH_GRAPH, LF_BATCH_AUTOTUNE = 1, 2
@@ -125,6 +125,8 @@ def load():
         "lf_build_mpi": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.c_int32, C.c_int32,
                           C.POINTER(C.c_float), C.POINTER(lf_mpi), P, C.c_size_t, P], C.c_int),
         "lf_build_stats": ([P, P, C.c_size_t, C.POINTER(lf_build_info), P], C.c_int),
+        "lf_build_tile_lists": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.c_int32, P, C.c_size_t,
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), P, P, P], C.c_int),
         "lf_composite": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32, C.c_int32,
                           C.c_int32, P, P], C.c_int),
         "lf_composite_backward": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
@@ -292,6 +294,16 @@ def lf_build_stats(ctx: int, workspace: int, workspace_bytes: int, stream: int =
     if check:
         _check(st, "lf_build_stats")
     return out, st
+
+
+def lf_build_tile_lists(ctx: int, field: lf_field, cam: lf_camera, n_chunk: int, workspace: int, workspace_bytes: int,
+                        bucket_start: int = 0, entries: int = 0, stream: int = 0):
+    """Returns (tile, tiles_x, tiles_y); fills the device arrays when given."""
+    t, tx, ty = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().lf_build_tile_lists(ctx, C.byref(field), C.byref(cam), n_chunk, workspace, workspace_bytes,
+                                      C.byref(t), C.byref(tx), C.byref(ty), bucket_start or None, entries or None,
+                                      stream), "lf_build_tile_lists")
+    return t.value, tx.value, ty.value
 
 
 def lf_composite(ctx: int, mpi: lf_mpi, cam: lf_camera, views, interp: int, out_dtype: int, out: int,

@@ -73,8 +73,7 @@ BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t
   L.o_items = take((size_t)L.max_items * 8);
   L.o_partial = take((size_t)L.max_partial * kTile * kTile * 16);
   L.o_split = take((size_t)L.max_partial * 4);
-  L.o_halo_rows = take((size_t)K * L.filt_bands * 2 * wp * 16);
-  L.o_halo_cols = take((size_t)K * L.filt_segs * 2 * hp * 16);
+  L.o_stage = take(kind == LF_VOXELS ? (size_t)K * hp * wp * 16 : 0);
   L.o_ggrad = take(kind == LF_VOXELS ? 0 : un * kGradSlots * 4);
   L.clear_words = (int64_t)(L.o_keys - L.o_hdr) / 4;   // header and sync region
   L.total = o;
@@ -194,8 +193,7 @@ void build_args(BuildArgs& a, const BuildLayout& L, const lf_field* field, const
   a.items = reinterpret_cast<uint2*>(w + L.o_items);
   a.partial = reinterpret_cast<float4*>(w + L.o_partial);
   a.max_items = L.max_items;
-  a.halo_rows = reinterpret_cast<float4*>(w + L.o_halo_rows);
-  a.halo_cols = reinterpret_cast<float4*>(w + L.o_halo_cols);
+  a.stage = reinterpret_cast<float4*>(w + L.o_stage);
   if (field->kind == LF_VOXELS) {
     a.ijk = field->ijk;
     a.density = field->density;
@@ -411,6 +409,34 @@ extern "C" lf_status lf_build_mpi_backward(lf_ctx* ctx, const lf_field* field, c
   a.d_planes = d_planes;
   a.grads = *grads;
   if ((e = build_backward(a, L, (hipStream_t)stream, &ctx->prof)) != hipSuccess) return hip_fail(e, "build backward launch");
+  return LF_OK;
+}
+
+extern "C" lf_status lf_build_tile_lists(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                                         const void* workspace, size_t workspace_bytes, int32_t* tile, int32_t* tiles_x,
+                                         int32_t* tiles_y, int64_t* bucket_start, int32_t* entries, void* stream) {
+  Geom g;
+  lf_status s = check_common(field, cam, n_chunk, &g);
+  if (s != LF_OK) return s;
+  if (!tile || !tiles_x || !tiles_y) return fail(LF_ERR_INVALID_ARG, "tile, tiles_x or tiles_y is NULL");
+  if (!workspace) return fail(LF_ERR_INVALID_ARG, "workspace is NULL");
+  const int64_t cap = capacity_of(field->kind, field->n, n_chunk, g.wp, g.hp, workspace_bytes);
+  if (cap < 1) return fail(LF_ERR_CAPACITY, "workspace of %zu bytes is too small for this field", workspace_bytes);
+  const BuildLayout L = build_layout(field->kind, field->n, n_chunk, g.wp, g.hp, cap);
+  *tile = kTile;
+  *tiles_x = L.ntx;
+  *tiles_y = L.nty;
+  if (!bucket_start && !entries) return LF_OK;
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  if (field->n == 0) return fail(LF_ERR_UNSUPPORTED, "an empty field has no tile lists");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  BuildArgs a;
+  lf_mpi none{LF_F32, n_chunk, g.hp, g.wp, nullptr, nullptr, nullptr, nullptr};
+  build_args(a, L, field, cam, g, n_chunk, LF_BIN_QUANTILE, &none, const_cast<void*>(workspace), cap);
+  if (radix_passes(L.tile_bits, tile_digit_bits()) & 1) a.evals = a.evals_alt;
+  if ((e = tile_lists_launch(a, L, bucket_start, entries, (hipStream_t)stream)) != hipSuccess)
+    return hip_fail(e, "tile list copy");
   return LF_OK;
 }
 

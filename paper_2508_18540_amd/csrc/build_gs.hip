@@ -15,6 +15,7 @@
 //  splat       one work-group per (tile, chunk): front-to-back blending of the bucket into
 //              premultiplied RGBA (C, 1 - T) with alpha = min(0.99, o G), only where
 //              o G >= 1/255, no early termination
+#include <algorithm>
 #include <cstdlib>
 
 #include "build_device.h"
@@ -906,6 +907,15 @@ __global__ __launch_bounds__(256) void preprocess_bwd_gs(BuildArgs a) {
   a.grads.opacity[i] = go;
 }
 
+// Copy of the tile lists for inspection: bucket starts widened to int64, entries reduced to
+// their primitive index (the quadrant mask of bits 28..31 dropped).
+__global__ __launch_bounds__(256) void copy_tile_lists(const uint32_t* bucket, const uint32_t* evals, int64_t n_buckets,
+                                                      int64_t* bucket_out, int32_t* entries_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bucket_out && i <= n_buckets) bucket_out[i] = bucket[i];
+  if (entries_out && i < (int64_t)bucket[n_buckets]) entries_out[i] = (int32_t)(evals[i] & 0x0fffffffu);
+}
+
 __global__ void write_table(float* dst, TableChunk t) {
   const int i = threadIdx.x;
   if (i < t.count) dst[t.offset + i] = t.v[i];
@@ -921,6 +931,14 @@ hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s) {
     for (int i = 0; i < t.count; ++i) t.v[i] = host[off + i];
     hipLaunchKernelGGL(write_table, dim3(1), dim3(kTableChunk), 0, s, dst, t);
   }
+  return hipGetLastError();
+}
+
+hipError_t tile_lists_launch(const BuildArgs& a, const BuildLayout& L, int64_t* bucket_start, int32_t* entries,
+                             hipStream_t s) {
+  const int64_t n = std::max<int64_t>(L.n_buckets + 1, L.cap);
+  hipLaunchKernelGGL(copy_tile_lists, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.bucket, a.evals,
+                     L.n_buckets, bucket_start, entries);
   return hipGetLastError();
 }
 
@@ -1013,6 +1031,14 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     }
     return hipGetLastError();
   }
+  // voxel planes are splatted in float32 into the workspace's stage; the low-pass then
+  // stores each plane once in its own dtype (one rounding of the filtered value)
+  void* const planes_out = a.planes;
+  const int32_t dtype_out = a.plane_dtype;
+  if (a.kind == LF_VOXELS) {
+    a.planes = a.stage;
+    a.plane_dtype = LF_F32;
+  }
   {
     PhaseScope ps(prof, LF_PHASE_SPLAT, s);
     const dim3 grid((unsigned)L.max_items);
@@ -1036,6 +1062,8 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
     }
   }
   if (a.kind == LF_VOXELS) {
+    a.planes = planes_out;
+    a.plane_dtype = dtype_out;
     PhaseScope ps(prof, LF_PHASE_FILTER, s);
     if ((e = launch_lowpass(a, s)) != hipSuccess) return e;
   }

@@ -37,8 +37,8 @@ struct VRec {
   float pad1;
 };
 
-// Low-pass filter (voxel planes): regions of kFiltRows x kFiltCols texels; the original
-// texels around every region are saved first so the filter can run in place.
+// Low-pass filter (voxel planes): regions of kFiltRows x kFiltCols texels, read from the
+// float32 stage the voxel splat writes and stored into the planes in their dtype.
 constexpr int kFiltRows = 16;
 constexpr int kFiltCols = 64;
 
@@ -51,7 +51,7 @@ struct BuildLayout {
   int32_t filt_bands, filt_segs;      // voxel low-pass regions (0 for Gaussians)
   size_t o_hdr, o_keys, o_vals, o_keys_alt, o_vals_alt, o_rec, o_ntiles_i, o_ntiles_r, o_chunk_r, o_offsets,
       o_sync, o_chunk_start, o_edges, o_dtab, o_nseg, o_bucket, o_radix, o_ekeys, o_evals, o_ekeys_alt, o_heads,
-      o_evals_alt, o_pcnt, o_item_start, o_pslot, o_split, o_items, o_partial, o_halo_rows, o_halo_cols, o_ggrad;
+      o_evals_alt, o_pcnt, o_item_start, o_pslot, o_split, o_items, o_partial, o_stage, o_ggrad;
   int64_t max_items, max_partial;
   // zero-initialised synchronisation words after the header (digit totals of both sorts,
   // scan states); the build clears [o_hdr, o_hdr + 4 clear_words) first
@@ -108,8 +108,8 @@ struct BuildArgs {
   uint2* items;
   float4* partial;
   int64_t max_items;
-  // voxel low-pass: saved original rows [K][bands][2][wp] and columns [K][segs][2][hp]
-  float4 *halo_rows, *halo_cols;
+  // voxel planes: float32 stage [K][hp][wp] of the splat, filtered into the planes
+  float4* stage;
   int32_t filt_bands, filt_segs;
   // backward: plane cotangents, per-Gaussian accumulators [n][kGradSlots], outputs
   const float* d_planes;
@@ -129,6 +129,10 @@ struct TableChunk {
 hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s);
 // The whole build of one field (either kind) on stream s.
 hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof);
+// Copies the (tile, chunk) bucket starts and the entries' primitive indices of the last build
+// (a.evals must name the array the tile sort ended in); either output may be null.
+hipError_t tile_lists_launch(const BuildArgs& a, const BuildLayout& L, int64_t* bucket_start, int32_t* entries,
+                             hipStream_t s);
 // Digit width the tile sort of the entries uses (its pass count decides where they end up).
 int tile_digit_bits();
 

@@ -168,60 +168,26 @@ __global__ __launch_bounds__(256) void splat_vox(BuildArgs a, int64_t n_buckets)
 }
 
 // ---------------------------------------------------------------------------------------
-// Low-pass.  Region (k, band, seg) covers rows [band R, band R + R) and columns
-// [seg S, seg S + S).  Saved first: the original rows band R - 1 and band R + R (whole
-// width) and the original columns seg S - 1 and seg S + S (whole height), zero outside the
-// plane.  Each region then reads only its own texels from the plane and its border from
-// the saved copies, so regions can be overwritten in any order.
+// Low-pass: the separable [1, 2, 1] / 4 filter of every premultiplied channel, zero outside
+// the plane, from the float32 stage into the planes (stored once, in their dtype).  One
+// work-group per kFiltRows x kFiltCols region of one plane stages the region and its
+// one-texel border in LDS.
 // ---------------------------------------------------------------------------------------
 template <typename PT>
-__global__ __launch_bounds__(256) void lowpass_save(BuildArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int W = a.c.wp, H = a.c.hp;
-  const int64_t nrow = (int64_t)a.K * a.filt_bands * 2 * W;
-  const int64_t ncol = (int64_t)a.K * a.filt_segs * 2 * H;
-  const PT* planes = static_cast<const PT*>(a.planes);
-  if (t < nrow) {
-    const int x = (int)(t % W);
-    const int64_t r = t / W;                                  // (k, band, side)
-    const int side = (int)(r & 1), band = (int)((r >> 1) % a.filt_bands), k = (int)((r >> 1) / a.filt_bands);
-    const int y = side ? band * kFiltRows + kFiltRows : band * kFiltRows - 1;
-    a.halo_rows[t] = (y >= 0 && y < H) ? load_rgba(planes, ((size_t)k * H + y) * W + x) : make_float4(0.f, 0.f, 0.f, 0.f);
-  } else if (t < nrow + ncol) {
-    const int64_t u = t - nrow;
-    const int y = (int)(u % H);
-    const int64_t r = u / H;                                  // (k, seg, side)
-    const int side = (int)(r & 1), seg = (int)((r >> 1) % a.filt_segs), k = (int)((r >> 1) / a.filt_segs);
-    const int x = side ? seg * kFiltCols + kFiltCols : seg * kFiltCols - 1;
-    a.halo_cols[u] = (x >= 0 && x < W) ? load_rgba(planes, ((size_t)k * H + y) * W + x) : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-}
-
-template <typename PT>
-__global__ __launch_bounds__(256) void lowpass_apply(BuildArgs a) {
+__global__ __launch_bounds__(256) void lowpass(BuildArgs a) {
   constexpr int LR = kFiltRows + 2, LC = kFiltCols + 2;
   __shared__ float4 tile[LR][LC];
   const int seg = blockIdx.x, band = blockIdx.y, k = blockIdx.z;
   const int W = a.c.wp, H = a.c.hp;
   const int x0 = seg * kFiltCols, y0 = band * kFiltRows;
-  PT* planes = static_cast<PT*>(a.planes);
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4* hrow = a.halo_rows + ((size_t)(k * a.filt_bands + band) * 2) * W;
-  const float4* hcol = a.halo_cols + ((size_t)(k * a.filt_segs + seg) * 2) * H;
+  const float4* __restrict__ src = a.stage + (size_t)k * H * W;
   for (int i = threadIdx.x; i < LR * LC; i += blockDim.x) {
     const int ly = i / LC, lx = i % LC;
     const int y = y0 - 1 + ly, x = x0 - 1 + lx;
-    float4 v = zero;
-    if (x >= 0 && x < W && y >= 0 && y < H) {
-      if (ly == 0) v = hrow[x];
-      else if (ly == LR - 1) v = hrow[W + x];
-      else if (lx == 0) v = hcol[y];
-      else if (lx == LC - 1) v = hcol[H + y];
-      else v = load_rgba(planes, ((size_t)k * H + y) * W + x);
-    }
-    tile[ly][lx] = v;
+    tile[ly][lx] = (x >= 0 && x < W && y >= 0 && y < H) ? src[(size_t)y * W + x] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   __syncthreads();
+  PT* planes = static_cast<PT*>(a.planes);
   for (int i = threadIdx.x; i < kFiltRows * kFiltCols; i += blockDim.x) {
     const int ly = i / kFiltCols + 1, lx = i % kFiltCols + 1;
     const int y = y0 + ly - 1, x = x0 + lx - 1;
@@ -243,9 +209,7 @@ __global__ __launch_bounds__(256) void lowpass_apply(BuildArgs a) {
 
 template <typename PT>
 hipError_t lowpass_typed(const BuildArgs& a, hipStream_t s) {
-  const int64_t n = (int64_t)a.K * a.filt_bands * 2 * a.c.wp + (int64_t)a.K * a.filt_segs * 2 * a.c.hp;
-  hipLaunchKernelGGL((lowpass_save<PT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL((lowpass_apply<PT>), dim3(a.filt_segs, a.filt_bands, a.K), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((lowpass<PT>), dim3(a.filt_segs, a.filt_bands, a.K), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -264,6 +264,20 @@ def build_stats(ctx: Context, workspace: Workspace, check: bool = True):
     return info, status
 
 
+def tile_lists(ctx: Context, scene: dict, cam, n_chunk: int, workspace: Workspace):
+    """lf_build_tile_lists after a build_mpi on ``workspace``: (tile, tiles_x, tiles_y,
+    bucket_start [tiles * n_chunk + 1] int64, entries [n] int32)."""
+    f, c = field_of(scene), L.make_camera(cam)
+    tile, tx, ty = L.lf_build_tile_lists(ctx.handle, f, c, n_chunk, workspace.ptr, workspace.nbytes)
+    info, _ = build_stats(ctx, workspace)
+    dev = ctx.device
+    starts = torch.empty(tx * ty * n_chunk + 1, dtype=torch.int64, device=dev)
+    entries = torch.empty(max(int(info.entries_needed), 1), dtype=torch.int32, device=dev)
+    L.lf_build_tile_lists(ctx.handle, f, c, n_chunk, workspace.ptr, workspace.nbytes, starts.data_ptr(),
+                          entries.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
+    return tile, tx, ty, starts, entries[:int(info.entries_needed)]
+
+
 def composite_backward(ctx: Context, rgba: torch.Tensor, depth: torch.Tensor, cam, views, d_out: torch.Tensor,
                        interp: str = "nearest", d_planes: torch.Tensor | None = None) -> torch.Tensor:
     """lf_composite_backward: dL/d(planes) [K, H, W, 4] float32 from dL/d(views) [V, ny, nx, 4]."""
@@ -332,7 +346,8 @@ class Batch:
     """lf_batch over torch tensors: ``scenes`` is a list of dicts with keys scene (device
     field dict), cam, n_chunk, views (lf_view array), and optionally binning,
     inv_depth_range, interp, plane_dtype, out_dtype.  Allocates every scene's planes, views
-    and workspace; ``run()`` renders them all (``outs[i]`` = dict(rgba, depth, views))."""
+    and workspace; ``run()`` renders them all (``outs[i]`` = dict(rgba, depth, chunk_of,
+    chunk_count, views, workspace))."""
 
     def __init__(self, ctx: Context, scenes: list, graph: bool = True, autotune: bool = False, probe: bool = True):
         self.ctx = ctx
@@ -354,6 +369,8 @@ class Batch:
             o = dict(rgba=torch.empty((K, info.plane_height, info.plane_width, 4), dtype=sc.get("plane_dtype", torch.float16),
                                       device=dev),
                      depth=torch.empty(K, dtype=torch.float32, device=dev),
+                     chunk_of=torch.empty(max(int(sc["scene"]["means"].shape[0]), 1), dtype=torch.int32, device=dev),
+                     chunk_count=torch.empty(K, dtype=torch.int32, device=dev),
                      views=torch.empty((len(views), cam.ny, cam.nx, 4), dtype=sc.get("out_dtype", torch.float32), device=dev),
                      workspace=ws)
             it = L.lf_batch_item()
@@ -367,7 +384,7 @@ class Batch:
             it.n_views = len(views)
             it.interp = _INTERP[sc.get("interp", "nearest")]
             it.out_dtype = _DT[o["views"].dtype]
-            it.mpi = mpi_of(o["rgba"], o["depth"])
+            it.mpi = mpi_of(o["rgba"], o["depth"], o["chunk_of"], o["chunk_count"])
             it.out = o["views"].data_ptr()
             it.workspace = ws.ptr
             it.workspace_bytes = ws.nbytes

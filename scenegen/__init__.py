@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "Camera", "camera", "uniform_scene", "cluster_scene", "voxel_scene",
     "random_planes", "perturbed_target", "small_scene", "CONFIGS", "config", "config_camera",
-    "BATCH_SCENES",
+    "BATCH_SCENES", "batch_scene",
 ]
 
 
@@ -269,6 +269,14 @@ BATCH_SCENES = [
     (700_000, 256, 512, 100), (1_000_000, 384, 64, 48), (1_500_000, 512, 512, 96),
     (2_000_000, 768, 128, 45),
 ]
+
+
+def batch_scene(i: int):
+    """Scene i of the batched workload: (scene, camera, N_chunk, views per row); clustered
+    Gaussians as cluster500k (seed 30 + i), D_focal = 2, 40 deg of horizontal parallax."""
+    n, res, K, V = BATCH_SCENES[i]
+    cam = camera(res, res, 50.0, 2.0, math.radians(40.0))
+    return cluster_scene(n, seed=30 + i), cam, K, V
 
 
 def config_camera(name: str, **override):

@@ -97,9 +97,10 @@ def test_planes_uniform10k(pdt):
         e, frac = _masked_compare(got, mpi.planes, mpi.ambiguous, 1e-4, 0.02)
         print("unmasked max-abs", e, "ambiguous texel fraction", frac)
     else:
-        tol = 2e-3 if pdt == "f16" else 4e-3      # one rounding of a value <= 1: 2^-11 / 2^-9
-        e, frac = _masked_compare(got, mpi.planes, mpi.ambiguous, tol, 0.02)
-        print(pdt, "unmasked max-abs", e)
+        e, frac = _masked_compare(got, mpi.planes, mpi.ambiguous, 2e-3, 0.02)
+        q = psnr(got[..., :3], mpi.planes[..., :3])
+        print(pdt, "unmasked max-abs", e, "PSNR", q)
+        assert q >= 50.0
 
 
 def test_planes_uniform10k_u8():
@@ -154,52 +155,6 @@ def test_zero_baseline_identity_on_gpu():
         got = host(v)
         for j in range(2):
             _masked_compare(got[j], ref, amb, 1e-4, 0.03)
-
-
-class _OracleTexels:
-    """Oracle plane texels on demand for a big scene (chunk projections cached)."""
-
-    def __init__(self, scene, cam, K, binning="quantile", rng=None):
-        self.g = geometry.derive(cam)
-        self.part = partition.partition(scene["means"], cam, self.g, K, binning, rng)
-        self.scene, self.cam, self.cache = scene, cam, {}
-
-    def proj(self, k):
-        if k not in self.cache:
-            self.cache[k] = render.chunk_projection(self.scene, self.cam, self.g, self.part, k)
-        return self.cache[k]
-
-    def __call__(self, k, iy, ix):
-        return splat.blend_texels(self.proj(k), ix, iy)
-
-
-@pytest.mark.parametrize("pdt", ["f32", "f16"])
-def test_cluster500k_full_size(pdt):
-    """The headline workload: 500k clustered Gaussians, 512^2, 64 quantile planes, 45 views.
-    Partition bit-exact on all Gaussians; texels and pixels checked on seeded samples."""
-    announce("cluster500k full size", pdt)
-    scene, cam, cfg = scenegen.config("cluster500k")
-    out, info, st = _gpu_build(scene, cam, 64, dtype=TDT[pdt])
-    assert st == L.LF_OK, L.lf_last_error()
-    orc = _OracleTexels(scene, cam, 64)
-    _check_partition(out, orc.part, 500_000)
-    print("visible", info.n_visible, "entries", info.entries_needed, "capacity", info.entry_capacity)
-    rng = np.random.default_rng(0)
-    tol = 1e-4 if pdt == "f32" else 2e-3
-    for k in rng.choice(64, 8, replace=False):
-        iy = rng.integers(0, 512, 400)
-        ix = rng.integers(0, 512, 400)
-        ref, amb = orc(int(k), iy, ix)
-        plane = host(out["rgba"][int(k)])
-        _masked_compare(plane[iy, ix], ref, amb, tol, 0.02)
-    dx, dy, _, _ = geometry.quilt_views(cam, 45, 1)
-    dx, dy = dx.astype(np.float32), dy.astype(np.float32)
-    views = T.composite(ctx(), out["rgba"], out["depth"], cam, T.views_of(dx, dy), "nearest")
-    pix = np.stack([rng.integers(0, 45, 300), rng.integers(0, 512, 300), rng.integers(0, 512, 300)], 1)
-    ref, amb = composite.composite_at(orc, out["depth"].cpu().numpy(), cam, orc.g, dx, dy, "nearest", pix)
-    sel = torch.from_numpy(pix).cuda()
-    got = host(views[sel[:, 0], sel[:, 1], sel[:, 2]])
-    _masked_compare(got, ref, amb, tol if pdt == "f32" else 2e-3, 0.03)
 
 
 def test_capacity_overflow_is_reported():
@@ -288,3 +243,34 @@ def test_empty_field():
     torch.cuda.synchronize()
     assert float(out["rgba"].abs().max()) == 0.0
     assert np.all(out["depth"].cpu().numpy() == np.float32(cam.d_focal))
+
+
+BIN_CASES = [
+    ("uniform10k_invdepth", lambda: (scenegen.uniform_scene(10_000, 0), scenegen.config_camera("uniform10k")[0], 16,
+                                     "inv_depth", (2.0, 6.0))),
+    ("cluster50k_q64_ragged", lambda: (scenegen.cluster_scene(50_000, seed=3),
+                                       scenegen.camera(250, 200, 50.0, 2.0, math.radians(40)), 64, "quantile", None)),
+    ("rotated_camera", lambda: (scenegen.small_scene(3000, 2, xy=2.0, z=(-1.0, 6.0)), _rotated_camera(), 24, "quantile",
+                                None)),
+]
+
+
+@pytest.mark.parametrize("case", BIN_CASES, ids=[c[0] for c in BIN_CASES])
+def test_tile_lists_against_oracle(case):
+    """The (tile, chunk) lists (Sec. 4.4, Alg. 1 "Rasterize"): every list holds each Gaussian
+    of its chunk whose support box meets the tile, in (key, index) order, and nothing beyond
+    that box widened by 3e-3 relative and 3e-3 texel (the kernel's float32 margin)."""
+    from oracle import bins
+    name, make = case
+    scene, cam, K, binning, rng = make()
+    announce("tile lists", name)
+    ds = T.to_device(scene)
+    ws = T.workspace_for(ds, cam, K)
+    T.build_mpi(ctx(), ds, cam, K, binning, rng, workspace=ws)
+    tile, tx, ty, starts, entries = T.tile_lists(ctx(), ds, cam, K, ws)
+    g = geometry.derive(cam)
+    part = partition.partition(scene["means"], cam, g, K, binning, rng)
+    must, may = bins.tile_lists(scene, cam, g, part, tile=tile)
+    torch.cuda.synchronize()
+    stats = bins.check_lists(starts.cpu().numpy(), entries.cpu().numpy(), must, may, part, tx * ty * K, K)
+    print(name, stats)

@@ -3,7 +3,7 @@ field) and of its composited light field against the FP64 oracle.
 
 Partition results must match bit for bit.  The voxel path has no threshold decision (alpha
 is continuous in the chord length), so every texel and pixel is compared: 1e-4 max-abs for
-FP32 planes, 2e-3 (FP16) / 4e-3 (BF16) per plane texel, and PSNR >= 50 dB for the views."""
+FP32 planes, 2e-3 and PSNR >= 50 dB for FP16 and BF16 planes."""
 import math
 
 import numpy as np
@@ -72,28 +72,28 @@ def test_voxel_planes_low_precision(pdt):
     out, info, st = _gpu_build(vox, cam, 8, dtype=TDT[pdt])
     assert st == L.LF_OK
     mpi = voxels.build_mpi_voxels(vox, cam, 8)
-    err = np.abs(host(out["rgba"]) - mpi.planes).max()
-    print(pdt, "planes max-abs", err)
-    assert err <= (2e-3 if pdt == "f16" else 4e-3)
+    got = host(out["rgba"])
+    err = np.abs(got - mpi.planes).max()
+    q = psnr(got[..., :3], mpi.planes[..., :3])
+    print(pdt, "planes max-abs", err, "PSNR", q)
+    assert err <= 2e-3 and q >= 50.0
 
 
 def test_voxel_planes_u8():
-    """UNORM8 planes (Sec. 5.1): the splat's texels are stored as codes, then the in-place
-    low-pass reads them back and stores its output as codes again.  Against the oracle doing
-    the same two roundings on its FP64 values, every code is within one, and at least 99 %
-    are equal (a value within float32 error of a rounding tie may go either way, at either
-    rounding)."""
+    """UNORM8 planes (Sec. 5.1): the splat works in float32 and the low-pass stores each
+    filtered texel once as a code, so every code equals the code of the oracle's FP64 texel
+    except within 0.05 code units of a rounding tie (one code either way)."""
     announce("voxel planes", "u8")
     vox = _small()
     cam = scenegen.camera(128, 128, 50.0, 4.0, math.radians(40.0))
     out, info, st = _gpu_build(vox, cam, 8, dtype=torch.uint8)
     assert st == L.LF_OK
-    raw = voxels.build_mpi_voxels(vox, cam, 8, filtered=False)
-    ref = np.stack([quantize.unorm8(voxels.lowpass(quantize.dequant(quantize.unorm8(pl)))) for pl in raw.planes])
+    mpi = voxels.build_mpi_voxels(vox, cam, 8)
     torch.cuda.synchronize()
-    d = np.abs(out["rgba"].cpu().numpy().astype(np.int32) - ref.astype(np.int32))
-    print("u8 voxel codes: max diff", int(d.max()), "exact fraction", float((d == 0).mean()))
-    assert d.max() <= 1 and (d == 0).mean() >= 0.99
+    d = np.abs(out["rgba"].cpu().numpy().astype(np.int32) - quantize.unorm8(mpi.planes).astype(np.int32))
+    tie = quantize.near_tie(mpi.planes, 0.05)
+    print("u8 voxel codes: max diff", int(d.max()), "off by one near ties", int((d == 1).sum()))
+    assert d[~tie].max(initial=0) == 0 and d.max() <= 1
 
 
 @pytest.mark.parametrize("interp", ["nearest", "bilinear"])
@@ -110,39 +110,6 @@ def test_voxel_frame_f32(interp):
     ref, _ = composite.composite(mpi.planes, mpi.depth, cam, mpi.geom, dx, dy, interp)
     err = np.abs(host(views) - ref).max()
     print("frame max-abs", err)
-    assert err <= 1e-4
-
-
-def test_voxel256_full_size_sampled_planes():
-    """The 256^3 / 2 % voxel workload at full size (335,544 voxels, 512^2, 64 planes, FP16
-    planes): the partition bit for bit, three whole planes against the oracle, and the 96-view
-    light field composited from these planes on 3000 sampled pixels against the oracle's
-    per-pixel composite of the same planes."""
-    announce("voxel256 full size")
-    vox, cam, cfg = scenegen.config("voxel256")
-    K = cfg["n_chunk"]
-    out, info, st = _gpu_build(vox, cam, K, dtype=torch.float16)
-    assert st == L.LF_OK, L.lf_last_error()
-    g = geometry.derive(cam)
-    part = voxels.partition_voxels(vox, cam, g, K)
-    _check_partition(out, part, vox["ijk"].shape[0])
-    got = host(out["rgba"])
-    for k in (0, K // 2, K - 1):
-        idx = part.order[part.chunk_start[k]:part.chunk_start[k + 1]]
-        ref = voxels.lowpass(voxels.render_plane(vox, idx, cam, g))
-        err = np.abs(got[k] - ref).max()
-        print("plane", k, "voxels", idx.size, "max-abs", err, "psnr", psnr(got[k][..., :3], ref[..., :3]))
-        assert err <= 2e-3
-        assert (ref[..., 3] > 1e-3).mean() > 0.005
-    dx, dy, _, _ = geometry.quilt_views(cam, cfg["vx"], 1)
-    dx, dy = dx.astype(np.float32), dy.astype(np.float32)
-    views = host(T.composite(ctx(), out["rgba"], out["depth"], cam, T.views_of(dx, dy), "nearest"))
-    rng = np.random.default_rng(0)
-    pix = np.stack([rng.integers(0, len(dx), 3000), rng.integers(0, cam.ny, 3000), rng.integers(0, cam.nx, 3000)], 1)
-    ref, _ = composite.composite_at(lambda k, iy, ix: (got[k, iy, ix], np.zeros(iy.shape, bool)),
-                                    out["depth"].cpu().numpy(), cam, g, dx, dy, "nearest", pix)
-    err = np.abs(views[pix[:, 0], pix[:, 1], pix[:, 2]] - ref).max()
-    print("96-view composite max-abs on sampled pixels", err)
     assert err <= 1e-4
 
 

@@ -173,7 +173,7 @@ def test_footprint_fd_equals_whole_frame_fd(interp):
         i = int(rng.choice(vis))
         j = int(rng.integers(0, scene[key].shape[1])) if scene[key].ndim == 2 else None
         h = steps[key]
-        local, amb = grad.footprint_fd(scene, cam, d.part, mpi.planes, dx, dy, target, i, key, j, h, interp)
+        local, amb, support = grad.footprint_fd(scene, cam, d.part, mpi.planes, dx, dy, target, i, key, j, h, interp)
         vals = []
         for sgn in (1, -1):
             p = grad.params_of(scene, requires_grad=False)
@@ -186,4 +186,5 @@ def test_footprint_fd_equals_whole_frame_fd(interp):
         whole = (vals[0] - vals[1]) / (2 * h)
         assert abs(local - whole) <= 1e-7 * max(abs(whole), 1e-3), (key, i, j, local, whole)
         checked += abs(whole) > 1e-6
+        assert support or whole == 0.0
     assert checked >= 20
