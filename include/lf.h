@@ -224,6 +224,20 @@ lf_status lf_render_view(lf_ctx* ctx, const lf_field* field, const lf_camera* ca
 lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
                        int32_t n_views, int32_t interp, int32_t out_dtype, void* out, void* stream);
 
+/* lf_composite for callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and results, with
+ * the coefficient table in a static device array of LF_COMPOSITE_SCRATCH_BYTES that each
+ * GPU holds until the process ends (its address is resolved by lf_create).  The call
+ * allocates nothing, host or device.  The table needs
+ * 16 K V rounded up to 256, plus 4 K (V + 16) + 256 bytes for K = mpi->n_chunk planes and
+ * V = n_views views; a call beyond LF_COMPOSITE_SCRATCH_BYTES returns LF_ERR_CAPACITY
+ * before anything is enqueued.  Every call on one GPU shares that one array (each call
+ * rewrites it before compositing): calls that overlap on one GPU, on any streams or
+ * contexts, race.  Arguments and outputs as lf_composite.                                */
+#define LF_COMPOSITE_SCRATCH_BYTES (4u << 20)
+lf_status lf_composite_noalloc(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,
+                               int32_t n_views, int32_t interp, int32_t out_dtype, void* out, void* stream);
+
 /* Vector-Jacobian product of lf_composite (the over operator of Eq. 7 with the Eq. 6
  * sampling held fixed): given d_out = dL/d(Q_r, Q_g, Q_b, T) (device float32
  * [n_views][ny][nx][4]), writes d_planes = dL/d(C_r, C_g, C_b, A) (device float32

@@ -30,7 +30,9 @@ EXPORTS = [
     "lf_build_mpi_backward", "lf_plane_coeffs", "lf_batch_create", "lf_batch_run", "lf_batch_group",
     "lf_batch_destroy", "lf_profile_enable", "lf_profile_read", "lf_render_view_workspace", "lf_render_view",
     "lf_sh_texel_floats", "lf_build_mpi_sh", "lf_composite_sh", "lf_sh_colours", "lf_build_tile_lists",
+    "lf_composite_noalloc",
 ]
+LF_COMPOSITE_SCRATCH_BYTES = 4 << 20
 LF_MAX_SH_DEGREE = 3
 LF_BATCH_GRAPH, LF_BATCH_AUTOTUNE = 1, 2
 PHASES = ["preprocess", "sort", "bin", "splat", "merge", "filter", "coeff", "composite", "composite_bwd",
@@ -129,6 +131,8 @@ def load():
                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), P, P, P], C.c_int),
         "lf_composite": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32, C.c_int32,
                           C.c_int32, P, P], C.c_int),
+        "lf_composite_noalloc": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
+                                  C.c_int32, C.c_int32, P, P], C.c_int),
         "lf_composite_backward": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
                                    C.c_int32, P, P, P], C.c_int),
         "lf_build_mpi_backward": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.POINTER(lf_mpi), P,
@@ -310,6 +314,12 @@ def lf_composite(ctx: int, mpi: lf_mpi, cam: lf_camera, views, interp: int, out_
                  stream: int = 0) -> None:
     _check(load().lf_composite(ctx, C.byref(mpi), C.byref(cam), views, len(views), interp, out_dtype, out, stream),
            "lf_composite")
+
+
+def lf_composite_noalloc(ctx: int, mpi: lf_mpi, cam: lf_camera, views, interp: int, out_dtype: int, out: int,
+                         stream: int = 0) -> None:
+    _check(load().lf_composite_noalloc(ctx, C.byref(mpi), C.byref(cam), views, len(views), interp, out_dtype, out,
+                                       stream), "lf_composite_noalloc")
 
 
 def lf_composite_backward(ctx: int, mpi: lf_mpi, cam: lf_camera, views, interp: int, d_out: int, d_planes: int,

@@ -1,6 +1,7 @@
 // C ABI entry points: argument validation on the host, then kernel launches.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "lf_internal.h"
@@ -74,6 +75,31 @@ lf_status check_ctx(lf_ctx* ctx) {
 
 using namespace lf;
 
+// Device memory of lf_composite_noalloc's coefficient table: a file-scope array every GPU
+// the library runs on holds until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol); it uses the device
+// address lf_create resolves once per device with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[LF_COMPOSITE_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+void* scratch_ptr[kMaxDevices] = {};
+
+// Resolves this device's address of `scratch` (the device must be current); once per device.
+hipError_t resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) scratch_ptr[device] = p;
+  return e;
+}
+
+}  // namespace
+
 extern "C" const char* lf_version(void) { return "lf-mi355x 0.1 (gfx950)"; }
 
 extern "C" lf_status lf_create(lf_ctx** out, int device) {
@@ -95,6 +121,11 @@ extern "C" lf_status lf_create(lf_ctx** out, int device) {
   if ((e = hipMalloc(&c->table, c->table_bytes)) != hipSuccess) {
     delete c;
     return hip_fail(e, "composite coefficient table");
+  }
+  if ((e = resolve_scratch(device)) != hipSuccess) {
+    hipFree(c->table);
+    delete c;
+    return hip_fail(e, "hipGetSymbolAddress of the composite scratch table");
   }
   *out = c;
   return LF_OK;
@@ -205,6 +236,32 @@ extern "C" lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camer
   }
   delete a;
   return s;
+}
+
+extern "C" lf_status lf_composite_noalloc(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam,
+                                          const lf_view* views, int32_t n_views, int32_t interp,
+                                          int32_t out_dtype, void* out, void* stream) {
+  // lf_composite with its table in the device's `scratch` array: no allocation of any kind
+  // (the argument block lives on the stack, profiling is not used)
+  CompositeArgs a;
+  lf_status s = composite_args(mpi, cam, views, n_views, &a);
+  if (s != LF_OK) return s;
+  if (interp != LF_NEAREST && interp != LF_BILINEAR)
+    return fail(LF_ERR_INVALID_ARG, "interp %d is not NEAREST/BILINEAR", interp);
+  if (out_dtype != LF_F32 && out_dtype != LF_F16) return fail(LF_ERR_INVALID_ARG, "out_dtype %d is not F32/F16", out_dtype);
+  if (!out) return fail(LF_ERR_INVALID_ARG, "out is NULL");
+  const size_t need = composite_table_bytes(a.K, a.n_views);
+  if (need > (size_t)LF_COMPOSITE_SCRATCH_BYTES)
+    return fail(LF_ERR_CAPACITY, "%d planes x %d views need a %zu-byte coefficient table; the static scratch holds %zu",
+                a.K, a.n_views, need, (size_t)LF_COMPOSITE_SCRATCH_BYTES);
+  if ((s = check_ctx(ctx)) != LF_OK) return s;
+  void* table = (ctx->device >= 0 && ctx->device < kMaxDevices) ? scratch_ptr[ctx->device] : nullptr;
+  if (!table) return fail(LF_ERR_HIP, "the composite scratch table of device %d was not resolved", ctx->device);
+  a.interp = interp;
+  a.out_dtype = out_dtype;
+  a.out = out;
+  const hipError_t e = composite_launch(a, table, (hipStream_t)stream, nullptr);
+  return e == hipSuccess ? LF_OK : hip_fail(e, "composite launch");
 }
 
 extern "C" lf_status lf_composite_backward(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, const lf_view* views,

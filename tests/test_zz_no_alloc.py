@@ -1,0 +1,66 @@
+"""lf_composite_noalloc (the composite with its coefficient table in a static device array,
+for callers that cannot allocate) against lf_composite through the C ABI: bit-equal views
+on two calls in a row, the second smaller, and a clear capacity error beyond the array."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from oracle import composite, geometry
+from paper_2508_18540_amd import _lib as L
+from tests.gpu_util import announce, ctx, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(nx, ny, K, V, seed, interp, out_dtype):
+    cam = scenegen.camera(nx, ny, 50.0, 2.0, math.radians(40.0))
+    g = geometry.derive(cam)
+    p = scenegen.random_planes(K, g.hp, g.wp, seed, depth_range=(g.d_forward + 0.25, 20.0))
+    dx, dy, _, _ = geometry.quilt_views(cam, V, 1)
+    dx, dy = dx.astype(np.float32), dy.astype(np.float32)
+    return cam, g, p, dx, dy
+
+
+def _run(entry, cam, planes, depth, dx, dy, interp, out_dtype):
+    K, H, W, _ = planes.shape
+    m = L.make_mpi(L.LF_F32, K, H, W, planes.data_ptr(), depth.data_ptr())
+    views = L.make_views(dx, dy)
+    tdt = torch.float32 if out_dtype == L.LF_F32 else torch.float16
+    out = torch.full((len(dx), cam.ny, cam.nx, 4), float("nan"), dtype=tdt, device="cuda")
+    interp_id = L.LF_NEAREST if interp == "nearest" else L.LF_BILINEAR
+    entry(ctx().handle, m, L.make_camera(cam), views, interp_id, out_dtype, out.data_ptr(),
+          torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+def test_noalloc_matches_composite_two_calls(interp):
+    shapes = [(512, 256, 64, 45, 31, L.LF_F32), (200, 150, 9, 7, 32, L.LF_F16)]   # the second call is smaller
+    for nx, ny, K, V, seed, odt in shapes:
+        announce("composite_noalloc", nx, ny, K, V, interp, odt)
+        cam, g, p, dx, dy = _case(nx, ny, K, V, seed, interp, odt)
+        planes, depth = dev(p["rgba"]), dev(p["depth"])
+        got = _run(L.lf_composite_noalloc, cam, planes, depth, dx, dy, interp, odt)
+        exp = _run(L.lf_composite, cam, planes, depth, dx, dy, interp, odt)
+        assert torch.equal(got, exp)
+        if K <= 9:
+            ref, _ = composite.composite(p["rgba"], p["depth"], cam, g, dx, dy, interp)
+            tol = 1e-4 if odt == L.LF_F32 else 2e-3
+            assert np.abs(host(got) - ref).max() <= tol
+
+
+def test_noalloc_rejects_tables_beyond_scratch():
+    announce("composite_noalloc capacity")
+    cam = scenegen.camera(16, 8, 50.0, 2.0, math.radians(40.0))
+    g = geometry.derive(cam)
+    K, V = 1024, 256                                  # 16 K V + 4 K (V + 16) > 4 MiB
+    planes = torch.zeros((K, g.hp, g.wp, 4), device="cuda")
+    depth = torch.linspace(g.d_forward + 0.5, 10.0, K, device="cuda")
+    dx = np.linspace(-0.1, 0.1, V).astype(np.float32)
+    with pytest.raises(L.LFError) as e:
+        _run(L.lf_composite_noalloc, cam, planes, depth, dx, np.zeros(V, np.float32), "nearest", L.LF_F32)
+    assert e.value.status == L.LF_ERR_CAPACITY and "static scratch" in str(e.value)
