@@ -114,16 +114,24 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Table kernel: pt[g][k] = (bx, by, Cy, valid) for view group g's dy, ct[k][p] = Cx of the
+// Table kernel: pt[g][k] = (bx, by, Cy, L) for view group g's dy (L: 0 for an invalid plane,
+// else the lane count of the backward's accumulation phases), ct[k][p] = Cx of the
 // view at position p of the grouped order, rows padded by kViewPad positions (the padding
-// repeats the last position) so a group's G offsets can always be read.  Nearest sampling
-// folds the 1/2 of floor(X + 1/2) into Cx and Cy.
+// repeats the last position) so a group's G offsets can always be read, and pm[g][k] = the
+// least and greatest Cx of group g's views.  Nearest sampling folds the 1/2 of
+// floor(X + 1/2) into Cx and Cy.
 // ---------------------------------------------------------------------------------------
 constexpr int kViewPad = 16;
 
 __host__ __device__ inline int ct_stride(int V) { return V + kViewPad; }
 
-__global__ void coeff_table(CompositeArgs a, float4* __restrict__ pt, float* __restrict__ ct) {
+__device__ __forceinline__ float view_cx(const CompositeArgs& a, const PlaneCo& pc, int p) {
+  const float cx = a.c.cpx + pc.gx * a.dx[a.perm[min(p, a.n_views - 1)]];
+  return a.interp == LF_BILINEAR ? cx : cx + 0.5f;
+}
+
+__global__ void coeff_table(CompositeArgs a, float4* __restrict__ pt, float* __restrict__ ct, float2* __restrict__ pm,
+                            int slots) {
   const int S = ct_stride(a.n_views);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.K * S) return;
@@ -135,9 +143,25 @@ __global__ void coeff_table(CompositeArgs a, float4* __restrict__ pt, float* __r
   const float cx = a.c.cpx + pc.gx * a.dx[v];
   ct[i] = a.interp == LF_BILINEAR ? cx : cx + half;
   if (p < a.n_groups) {
-    const float cy = a.c.cpy + pc.gy * a.dy[a.perm[a.vgroup[p] & 0xffu]];
-    pt[(size_t)p * a.K + k] =
-        make_float4(pc.bx, pc.by, a.interp == LF_BILINEAR ? cy : cy + half, d - a.c.d_fwd > 0.0f ? 1.0f : 0.0f);
+    const int q0 = a.vgroup[p] & 0xffu, nq = a.vgroup[p] >> 8;
+    const float cy = a.c.cpy + pc.gy * a.dy[a.perm[q0]];
+    // w: 0 for a plane at or behind the reference camera, else the lane count L the
+    // backward's updates need: lanes L apart never share a texel floor(X) when their
+    // coordinates differ by at least 1.  They differ by L bx up to the two roundings of each
+    // X, under 4e-3 in all for |X|, |bx xr| < 2^14, so L bx must exceed 1 by 1e-2.
+    const float L = pc.bx > 0.0f ? fminf(floorf(1.01f / pc.bx) + 1.0f, 64.0f) : 64.0f;
+    pt[(size_t)p * a.K + k] = make_float4(pc.bx, pc.by, a.interp == LF_BILINEAR ? cy : cy + half,
+                                          d - a.c.d_fwd > 0.0f ? L : 0.0f);
+    // least and greatest Cx over the group's positions, padded to `slots` (a kernel that
+    // samples a fixed number of views reads the positions after a short group's end)
+    const int qe = min(q0 + max(nq, slots), S);
+    float cmin = view_cx(a, pc, q0), cmax = cmin;
+    for (int q = q0 + 1; q < qe; ++q) {
+      const float c = view_cx(a, pc, q);
+      cmin = fminf(cmin, c);
+      cmax = fmaxf(cmax, c);
+    }
+    pm[(size_t)p * a.K + k] = make_float2(cmin, cmax);
   }
 }
 
@@ -539,319 +563,522 @@ __global__ void plane_coeffs_kernel(CompositeArgs a, float* bx, float* by, float
 // ---------------------------------------------------------------------------------------
 // Backward of the composite (Eq. 7 over operator).  With Q = sum_k T_k c_k,
 // T_{k+1} = T_k (1 - a_k) and cotangents g = dL/dQ, g_T = dL/dT_final:
-//   dL/dc_k = T_k g,   dL/da_k = -T_k (g . R_{k+1} + g_T S_{k+1}),
-//   R_k = c_k + (1 - a_k) R_{k+1},  S_k = (1 - a_k) S_{k+1},  R_K = 0, S_K = 1,
-// evaluated back to front; a sample's cotangent goes to its texels through the transposed
-// interpolation weights.
-// One work-group per (output row y, view group of up to G views that share dy, segment of
-// 256 pixels); a thread owns pixel x for the group's views.  T_k is not checkpointed:
-// the forward sweep keeps, per view, the last plane m whose incoming transmittance T_m is
-// at least kTinyT, and the backward sweep recovers T_k = T_{k+1} / (1 - a_k) for k < m
-// (exact up to rounding: T_{k+1} > 0 there, so a_k < 1).  Planes behind m see T < kTinyT and
-// get no gradient (it would be below 1e-30 |g|).
-// Per plane the work-group stages the window of the plane row its samples fall in (as the
-// forward row kernel does).  The samples' cotangents are then summed per texel without
-// atomics: pixel threads store them (with their texel index) in LDS and mark where each
-// view's run of equal texels starts (x -> texel is monotone), and texel threads add the runs
-// of all views, in a fixed order, before one global atomic per texel channel adds the
-// window into the plane gradient (windows of other rows and view groups overlap it); the
-// atomics go one channel word per lane, so each instruction covers whole cache lines.
+//   dL/dc_k = T_k g,   dL/da_k = -T_k U_{k+1},   U_k = g . c_k + (1 - a_k) U_{k+1},  U_K = g_T
+// (U_k = g . R_k + g_T S_k folds the colour R and transmittance S behind plane k into one
+// scalar), evaluated back to front; a sample's cotangent goes to its texels through the
+// transposed interpolation weights.
+//
+// One work-group is one wave: a segment of 64 output pixels of row y for a group of up to
+// G views that share dy (lane = pixel, the G views in registers), tiles dealt to the XCDs as
+// in the forward.  A single wave needs no barrier: its LDS operations complete in order.
+// Transmittance is recomputed, not stored: sweep 1 (front to back, alpha only) finds per
+// (pixel, view) the last plane m whose incoming transmittance T_m is at least kTinyT and
+// keeps T_m; sweep 2 (back to front) recovers T_k = T_{k+1} / (1 - a_k) for k < m (exact up
+// to rounding: T_{k+1} >= kTinyT there, a normal number, and 1 - a_k > 0) and gives planes
+// behind m no gradient (below kTinyT |g|), while U keeps the colour behind them.
+// Per plane the wave stages the window of the plane row its samples fall in (bilinear: the
+// two rows blended vertically): sweep 1 its alpha, sweep 2 its texels, beside two LDS
+// accumulators of the window.  A sample adds its cotangent (bilinear: its two weighted
+// parts, one after the other) to an accumulator with a plain read-modify-write: x -> texel
+// is monotone with slope bx, so lanes L or more apart never share a texel when L bx > 1.
+// For L <= 2 (bx > 0.505, the usual case) even lanes update one accumulator and odd lanes
+// the other, all in one instruction; otherwise the lanes update the first in L phases of
+// lanes L apart.  The window is then added to the plane gradient with one global atomic
+// per texel channel (windows of other rows, segments and view groups overlap it).
 // ---------------------------------------------------------------------------------------
-constexpr int kRowBwdThreads = 256;
-constexpr int kRowBwdWin = 512;
+constexpr int kBwdWin = 128;          // texels of an LDS window chunk
+constexpr int kBwdPf = kBwdWin / 64;  // window entries each lane fetches
 constexpr float kTinyT = 1e-30f;
-constexpr int kNoTexel = -(1 << 30);
+constexpr int kBufFlags = 0x00020000; // buffer resource: raw dword access, range checked
 
-struct BwdPlane {
-  bool ok, direct;
-  int iy, f0, len;
-  float wy, bx, by;
+struct BwdInfo {
+  float bx, wy;
+  int32_t iy, f0, len;                // len 0: the plane is skipped (invalid, or wholly outside)
+  int32_t phases;                     // L: lanes L apart never share a texel
 };
 
-template <bool BIL>
-__device__ __forceinline__ BwdPlane bwd_plane(const CompositeArgs& a, const float4* pt, const float* ct, int k, int v0,
-                                              int nv, float yr, float xr_lo, float xr_hi, int S) {
-  const float4 p = pt[k];                                  // (bx, by, Cy, valid)
-  BwdPlane b;
-  b.bx = p.x;
-  b.by = p.y;
-  b.wy = 0.0f;
-  b.ok = p.w != 0.0f;
-  if (!BIL) {
-    b.iy = __float2int_rd(p.y * yr + p.z);
-    b.ok = b.ok && b.iy >= 0 && b.iy < a.hp;
-  } else {
-    const float Y = p.y * yr + p.z;
-    const float fy0 = floorf(Y);
-    b.wy = Y - fy0;
-    b.iy = __float2int_rd(fy0);
-    b.ok = b.ok && b.iy >= -1 && b.iy < a.hp;
-  }
-  const float* crow = ct + (size_t)k * S + v0;
-  float cmin = crow[0], cmax = crow[0];
-  for (int j = 1; j < nv; ++j) {
-    cmin = fminf(cmin, crow[j]);
-    cmax = fmaxf(cmax, crow[j]);
-  }
-  const float lo = floorf(p.x * xr_lo + cmin);
-  const float hi = floorf(p.x * xr_hi + cmax) + (BIL ? 1.0f : 0.0f);
-  b.direct = !(lo >= -1.0e9f && hi <= 1.0e9f && hi - lo + 1.0f <= (float)kRowBwdWin);
-  b.f0 = b.direct ? 0 : (int)lo;
-  b.len = b.direct ? 0 : (int)(hi - lo) + 1;
-  return b;
+// texel ix of a plane row through a buffer resource over that row: zero outside the row
+// (the hardware's range check, also for ix < 0, whose offset wraps far past the row)
+template <typename T>
+__device__ __forceinline__ float4 buf_texel(__amdgpu_buffer_rsrc_t r, int ix);
+template <>
+__device__ __forceinline__ float4 buf_texel<float>(__amdgpu_buffer_rsrc_t r, int ix) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)ix * 16u, 0, 0));
+}
+template <>
+__device__ __forceinline__ float4 buf_texel<__half>(__amdgpu_buffer_rsrc_t r, int ix) {
+  const uint2 u = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, (uint32_t)ix * 8u, 0, 0));
+  const __half2 lo = *reinterpret_cast<const __half2*>(&u.x), hi = *reinterpret_cast<const __half2*>(&u.y);
+  const float2 f = __half22float2(lo), h = __half22float2(hi);
+  return make_float4(f.x, f.y, h.x, h.y);
+}
+template <>
+__device__ __forceinline__ float4 buf_texel<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, int ix) {
+  const uint2 u = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, (uint32_t)ix * 8u, 0, 0));
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+                     __uint_as_float(u.y & 0xffff0000u));
 }
 
-// texel of the (bilinear: vertically blended) plane row at column ix, zero outside the plane
-template <typename PT, bool BIL>
-__device__ __forceinline__ float4 row_texel(const PT* planes, const CompositeArgs& a, size_t pbase, const BwdPlane& b,
-                                            int ix) {
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (ix < 0 || ix >= a.wp) return z;
-  if (!BIL) return load_texel(planes, pbase + (size_t)b.iy * a.wp + ix);
-  const float4 r0 = b.iy >= 0 ? load_texel(planes, pbase + (size_t)b.iy * a.wp + ix) : z;
-  const float4 r1 = b.iy + 1 < a.hp ? load_texel(planes, pbase + (size_t)(b.iy + 1) * a.wp + ix) : z;
-  return lerp4(r0, r1, b.wy);
+// alpha (A = 1 - T) of texel ix of a plane row, likewise
+template <typename T>
+__device__ __forceinline__ float buf_alpha(__amdgpu_buffer_rsrc_t r, int ix);
+template <>
+__device__ __forceinline__ float buf_alpha<float>(__amdgpu_buffer_rsrc_t r, int ix) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)ix * 16u + 12u, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_alpha<__half>(__amdgpu_buffer_rsrc_t r, int ix) {
+  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)ix * 8u + 4u, 0, 0);
+  return __half2float(__ushort_as_half((unsigned short)(u >> 16)));
+}
+template <>
+__device__ __forceinline__ float buf_alpha<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, int ix) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)ix * 8u + 4u, 0, 0) & 0xffff0000u);
 }
 
-__device__ __forceinline__ void add_row_grad(float* d_planes, const CompositeArgs& a, int k, int iy, int ix, int c,
-                                             float v) {
-  if (iy < 0 || iy >= a.hp || ix < 0 || ix >= a.wp || v == 0.0f) return;
-  atomicAdd(d_planes + (((size_t)k * a.hp + iy) * a.wp + ix) * 4 + c, v);
-}
-
-template <typename PT, int G, bool BIL>
-__global__ __launch_bounds__(kRowBwdThreads) void composite_rows_bwd(CompositeArgs a, const float4* __restrict__ pt,
-                                                                     const float* __restrict__ ct,
-                                                                     const float4* __restrict__ d_out,
-                                                                     float* __restrict__ d_planes) {
-  __shared__ float4 val[kRowBwdWin];
-  __shared__ float4 slot[G][kRowBwdThreads];               // cotangent of sample (view, x)
-  __shared__ int sx[G][kRowBwdThreads];                    // its texel (lower texel for bilinear)
-  __shared__ float swx[BIL ? G : 1][kRowBwdThreads];       // its bilinear weight
-  __shared__ short first[G][kRowBwdWin];                   // first x of each view's run per texel
-  const int y = blockIdx.x;
-  const uint32_t gd = a.vgroup[blockIdx.y];
+// FAST: the form for work-groups whose every window fits one chunk and whose planes all
+// have L <= 2 (bx > 0.505); the general form takes the other work-groups.  Both are
+// launched over every work-group, and each returns at once from the work-groups of the other.
+template <typename PT, int G, bool BIL, bool FAST>
+__global__ __launch_bounds__(64) void composite_rows_bwd(CompositeArgs a, int nseg, int total,
+                                                         const float4* __restrict__ pt, const float* __restrict__ ct,
+                                                         const float2* __restrict__ pm,
+                                                         const float4* __restrict__ d_out, float* __restrict__ d_planes) {
+  __shared__ float4 win[kBwdWin];                          // sweep 1: alpha (as floats); sweep 2: texels
+  // sweep 2: cotangent accumulators (fast form: two, the second kBwdWin texels on)
+  constexpr int kAcc = FAST ? 2 : 1;
+  __shared__ float4 acc[kAcc * kBwdWin];
+  __shared__ float tmL[G * 64];                            // T_m of view slot j at [j][lane]
+  float* winA = reinterpret_cast<float*>(win);
+  const int wg = blockIdx.x;
+  const int per = (total + 7) / 8;
+  const int lg = (wg % 8) * per + wg / 8;
+  if (lg >= total) return;                                 // whole work-group: grid padded to 8 per
+  const int gi = lg % a.n_groups, rest = lg / a.n_groups;
+  const int y = rest / nseg, seg = rest % nseg;
+  const uint32_t gd = a.vgroup[gi];
   const int v0 = gd & 0xffu;                               // group's first position in perm
   const int nv = gd >> 8;
-  pt += (size_t)blockIdx.y * a.K;
-  const int tid = threadIdx.x;
-  const int xs0 = blockIdx.z * kRowBwdThreads;
-  const int x = xs0 + tid;
+  pt += (size_t)gi * a.K;
+  pm += (size_t)gi * a.K;
+  const int lane = threadIdx.x;
+  const int xs0 = seg * 64;
+  const int x = xs0 + lane;
   const bool xin = x < a.nx;
-  const int xs1 = min(xs0 + kRowBwdThreads, a.nx) - 1;
-  const int Vp = ct_stride(a.n_views);
-  const PT* __restrict__ planes = static_cast<const PT*>(a.planes);
+  // Every lane samples at its own x, also past the row's end (a pixel with a zero cotangent,
+  // so its updates add zero), and every view slot of the group is sampled: the slots past a
+  // short group's end read the table's padded positions (within the window the table's
+  // per-group extents cover) with zero cotangents.  So the per-view code has no branches.
   const float xr = (float)x - a.c.cx, yr = (float)y - a.c.cy;
-  const float xrp = (float)(x - 1) - a.c.cx;
-  const float xr_lo = (float)xs0 - a.c.cx, xr_hi = (float)xs1 - a.c.cx;
+  const float xr_lo = (float)xs0 - a.c.cx, xr_hi = (float)(xs0 + 63) - a.c.cx;
+  const int S = ct_stride(a.n_views);
   const size_t plane_elems = (size_t)a.hp * a.wp;
-  float4 g[G];
+  constexpr int kTB = sizeof(PT) * 4;                      // bytes per texel
+  const char* planes = static_cast<const char*>(a.planes);
+  // a window wider than the LDS buffer is processed in chunks of kBwdWin texels (bilinear:
+  // overlapping by one, so each sample's two texels lie in the chunk that owns its first)
+  constexpr int kStride = BIL ? kBwdWin - 1 : kBwdWin;
+
+  // Plane windows, 64 planes at a time: lane i derives the window of plane kb + i (the
+  // texels every sample of the wave falls in), its row and weight; a plane's fields are read
+  // out of its lane (wave uniform) when it is processed.  The planes with a window are the
+  // set bits of the batch mask.
+  int my_f0 = 0, my_len = 0, my_iy = 0;
+  float my_wy = 0.0f;
+  bool my_slow = false;                                    // needs the general form
+  auto batch = [&](int kb) -> uint64_t {
+    const int k = kb + lane;
+    int f0 = 0, len = 0, iy = 0;
+    float wy = 0.0f;
+    bool slow = false;
+    if (k < a.K) {
+      const float4 p = pt[k];                              // (bx, by, Cy, L)
+      const float2 cr = pm[k];                             // least and greatest Cx of the group
+      bool ok = p.w != 0.0f;
+      if (!BIL) {
+        iy = (int)floorf(p.y * yr + p.z);
+        ok = ok && iy >= 0 && iy < a.hp;
+      } else {
+        const float Y = p.y * yr + p.z;
+        const float fy0 = floorf(Y);
+        wy = Y - fy0;
+        iy = (int)fy0;
+        ok = ok && iy >= -1 && iy < a.hp;
+      }
+      // X = bx xr + C is monotone in xr and C (each rounding is monotone), so the samples
+      // of the wave lie in [floor(X(xr_lo, cmin)), floor(X(xr_hi, cmax))] (+1 bilinear)
+      const float lo = floorf(p.x * xr_lo + cr.x);
+      const float hi = floorf(p.x * xr_hi + cr.y) + (BIL ? 1.0f : 0.0f);
+      // a window wholly outside the row samples only transparent texels: a = 0 leaves T
+      // and U unchanged and texels outside the plane get no gradient, so the plane is
+      // skipped; the window is clipped to the columns [-kBwdWin, wp + kBwdWin) (samples
+      // outside the plane read zero texels there) so its length stays an int
+      ok = ok && hi >= 0.0f && lo <= (float)(a.wp - 1);
+      const float lc = fmaxf(lo, (float)-kBwdWin), hc = fminf(hi, (float)(a.wp + kBwdWin - 1));
+      f0 = ok ? (int)lc : 0;
+      len = ok ? (int)(hc - lc) + 1 : 0;
+      slow = ok && (len > kBwdWin || p.w > 2.0f);
+    }
+    my_f0 = f0;
+    my_len = len;
+    my_iy = iy;
+    my_wy = wy;
+    my_slow = slow;
+    return __builtin_amdgcn_ballot_w64(len > 0);
+  };
+  // the form this work-group takes: the fast one when no plane needs the general one
+  {
+    bool slow = false;
+    for (int kb = 0; kb < a.K; kb += 64) {
+      batch(kb);
+      slow = slow || __builtin_amdgcn_ballot_w64(my_slow) != 0;
+    }
+    if (slow == FAST) return;
+  }
+  auto plane_at = [&](int i, int k) {
+    BwdInfo b;
+    b.f0 = __builtin_amdgcn_readlane(my_f0, i);
+    b.len = __builtin_amdgcn_readlane(my_len, i);
+    b.iy = __builtin_amdgcn_readlane(my_iy, i);
+    b.wy = BIL ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_wy), i)) : 0.0f;
+    const float4 p = pt[k];
+    b.bx = p.x;
+    b.phases = (int)p.w;
+    return b;
+  };
+  int kb = 0;
+  uint64_t mask = 0;
+  // the next plane with a window front to back (sweep 1) or back to front (sweep 2)
+  auto next_fwd = [&](int& k, BwdInfo& b) {
+    while (mask == 0) {
+      kb += 64;
+      if (kb >= a.K) return false;
+      mask = batch(kb);
+    }
+    const int i = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    k = kb + i;
+    b = plane_at(i, k);
+    return true;
+  };
+  auto next_bwd = [&](int& k, BwdInfo& b) {
+    while (mask == 0) {
+      kb -= 64;
+      if (kb < 0) return false;
+      mask = batch(kb);
+    }
+    const int i = 63 - __builtin_clzll(mask);
+    mask &= ~(1ull << i);
+    k = kb + i;
+    b = plane_at(i, k);
+    return true;
+  };
+  // buffer resources over rows iy and iy + 1 of plane k (a row outside the plane: zero
+  // records, so every read returns zero)
+  auto row_rsrc = [&](int k, int iy, int width_bytes) {
+    const bool in = iy >= 0 && iy < a.hp;
+    const char* base = planes + ((size_t)k * plane_elems + (size_t)(in ? iy : 0) * a.wp) * kTB;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, in ? width_bytes : 0, kBufFlags);
+  };
+  // Chunks of a window (the fast form: one).  Of a window of several chunks, chunk
+  // [c0, c0 + clen) owns the samples whose texel (bilinear: first texel) lies in
+  // [c0, c0 + clen) ([c0, c0 + clen - 1)); the others read a safe texel and update nothing.
+  auto chunks = [&](const BwdInfo& b) {
+    return FAST || b.len <= kBwdWin ? 1 : 1 + (b.len - kBwdWin + kStride - 1) / kStride;
+  };
+  auto owned = [&](int& ix, int c0, uint32_t lim) {
+    if (FAST) return true;
+    const bool own = (uint32_t)(ix - c0) < lim;
+    ix = own ? ix : c0;
+    return own;
+  };
+  float cv[G];                                             // the plane's Cx of each view slot
+  auto load_cx = [&](int k) {
+    const float* crow = ct + (size_t)k * S + v0;
+#pragma unroll
+    for (int j = 0; j < G; ++j) cv[j] = crow[j];
+  };
+
   float T[G], Tm[G];
   int m[G];
 #pragma unroll
   for (int j = 0; j < G; ++j) {
-    g[j] = (xin && j < nv) ? d_out[((size_t)a.perm[v0 + j] * a.ny + y) * a.nx + x] : make_float4(0.f, 0.f, 0.f, 0.f);
     T[j] = 1.0f;
     Tm[j] = 1.0f;
     m[j] = -1;
   }
-  // sample of view j (slot) at plane k: value, texel (bilinear: lower texel) and weight
-  auto sample = [&](const BwdPlane& b, size_t pbase, float c, int& ix, float& wx) -> float4 {
-    const float X = b.bx * xr + c;
-    if (!BIL) {
-      ix = __float2int_rd(X);
-      wx = 0.0f;
-      if (b.direct) return row_texel<PT, false>(planes, a, pbase, b, ix);
-      return val[min(max(ix - b.f0, 0), b.len - 1)];
-    }
-    const float fx0 = floorf(X);
-    wx = X - fx0;
-    ix = __float2int_rd(fx0);
-    if (b.direct)
-      return lerp4(row_texel<PT, true>(planes, a, pbase, b, ix), row_texel<PT, true>(planes, a, pbase, b, ix + 1), wx);
-    const int i0 = min(max(ix - b.f0, 0), b.len - 1), i1 = min(max(ix + 1 - b.f0, 0), b.len - 1);
-    return lerp4(val[i0], val[i1], wx);
-  };
-  // window texels are fetched one plane ahead into registers (kPre per thread), so the
-  // global loads of plane k+1 are in flight while plane k is sampled
-  constexpr int kPre = kRowBwdWin / kRowBwdThreads;
-  float4 pre0[kPre], pre1[kPre];
-  auto fetch = [&](const BwdPlane& b, int k) {
-    if (!b.ok || b.direct) return;
-    const size_t pbase = (size_t)k * plane_elems;
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  // ---- sweep 1: front to back over alpha, last plane with incoming T >= kTinyT ----------
+  // The next plane's first alpha chunk is fetched into registers while this one is sampled.
+  float pa0[kBwdPf], pa1[BIL ? kBwdPf : 1];
+  auto fetch_alpha = [&](const BwdInfo& b, int k, int c0) {
+    const auto r0 = row_rsrc(k, b.iy, a.wp * kTB);
+    const auto r1 = row_rsrc(k, b.iy + 1, a.wp * kTB);
 #pragma unroll
-    for (int q = 0; q < kPre; ++q) {
-      const int i = tid + q * kRowBwdThreads;
-      const int ix = b.f0 + i;
-      pre0[q] = pre1[q] = z;
-      if (i < b.len && ix >= 0 && ix < a.wp) {
-        if (!BIL) {
-          pre0[q] = load_texel(planes, pbase + (size_t)b.iy * a.wp + ix);
-        } else {
-          if (b.iy >= 0) pre0[q] = load_texel(planes, pbase + (size_t)b.iy * a.wp + ix);
-          if (b.iy + 1 < a.hp) pre1[q] = load_texel(planes, pbase + (size_t)(b.iy + 1) * a.wp + ix);
-        }
-      }
+    for (int q = 0; q < kBwdPf; ++q) {
+      pa0[q] = buf_alpha<PT>(r0, c0 + lane + q * 64);
+      if (BIL) pa1[BIL ? q : 0] = buf_alpha<PT>(r1, c0 + lane + q * 64);
     }
   };
-  auto commit = [&](const BwdPlane& b) {
+  auto store_alpha = [&](const BwdInfo& b, int clen) {
 #pragma unroll
-    for (int q = 0; q < kPre; ++q) {
-      const int i = tid + q * kRowBwdThreads;
-      if (i < b.len) val[i] = BIL ? lerp4(pre0[q], pre1[q], b.wy) : pre0[q];
+    for (int q = 0; q < kBwdPf; ++q) {
+      const int i = lane + q * 64;
+      const float v = BIL ? fmaf(b.wy, pa1[BIL ? q : 0] - pa0[q], pa0[q]) : pa0[q];
+      if (i < clen) winA[i] = v;
     }
   };
-  auto plane_at = [&](int k) { return bwd_plane<BIL>(a, pt, ct, k, v0, nv, yr, xr_lo, xr_hi, Vp); };
-  // forward sweep: transmittance per view, last plane with T >= kTinyT
-  {
-    BwdPlane b = a.K > 0 ? plane_at(0) : BwdPlane{};
-    fetch(b, 0);
-    for (int k = 0; k < a.K; ++k) {
-      const BwdPlane bn = k + 1 < a.K ? plane_at(k + 1) : BwdPlane{};
-      if (b.ok) {
-        const size_t pbase = (size_t)k * plane_elems;
-        if (!b.direct) {
-          lds_barrier();
-          commit(b);
-          lds_barrier();
-        }
-        fetch(bn, k + 1);
-        if (xin) {
+  auto pass1 = [&](int k, float bxr, int c0, int clen) {
+    const float* wa = winA - c0;
+    const uint32_t lim = (uint32_t)(clen - (BIL ? 1 : 0));
 #pragma unroll
-          for (int j = 0; j < G; ++j) {
-            if (j >= nv) continue;
-            int ix;
-            float wx;
-            const float4 s = sample(b, pbase, ct[(size_t)k * Vp + v0 + j], ix, wx);
-            if (T[j] >= kTinyT) {
-              m[j] = k;
-              Tm[j] = T[j];
-            }
-            T[j] = fmaf(-T[j], s.w, T[j]);
-          }
-        }
+    for (int j = 0; j < G; ++j) {
+      const float X = bxr + cv[j];
+      float al;
+      bool own;
+      if (!BIL) {
+        int ix = cvt_flr(X);
+        own = owned(ix, c0, lim);
+        al = wa[ix];
       } else {
-        fetch(bn, k + 1);
+        const float fx = floorf(X), wx = X - fx;
+        int ix = cvt_flr(fx);
+        own = owned(ix, c0, lim);
+        al = fmaf(wx, wa[ix + 1] - wa[ix], wa[ix]);
       }
+      const bool live = own && T[j] >= kTinyT;
+      m[j] = live ? k : m[j];
+      Tm[j] = live ? T[j] : Tm[j];
+      const float Tn = fmaf(-T[j], al, T[j]);
+      T[j] = own ? Tn : T[j];
+    }
+  };
+  {
+    kb = 0;
+    mask = batch(0);
+    int k = 0;
+    BwdInfo b{};
+    bool have = next_fwd(k, b);
+    if (have) fetch_alpha(b, k, b.f0);
+    while (have) {
+      const float bxr = b.bx * xr;
+      load_cx(k);
+      const int nch = chunks(b);
+      int kn = 0;
+      BwdInfo bn{};
+      bool have_n = false;
+      for (int c = 0; c < nch; ++c) {
+        const int c0 = b.f0 + c * kStride, clen = min(kBwdWin, b.len - c * kStride);
+        if (c > 0) fetch_alpha(b, k, c0);
+        store_alpha(b, clen);                              // chunk 0: the prefetched one
+        if (c == nch - 1) {
+          have_n = next_fwd(kn, bn);
+          if (have_n) fetch_alpha(bn, kn, bn.f0);
+        }
+        pass1(k, bxr, c0, clen);
+      }
+      k = kn;
       b = bn;
+      have = have_n;
     }
   }
-  // backward sweep
-  float Rr[G], Rg[G], Rb[G], S[G], Tc[G];
+
+  // ---- sweep 2: back to front, gradients of the planes at or before m -------------------
+  // T_m goes to LDS (read at plane m only) and m + 1 to 16-bit halves, two views a register.
+  uint32_t mp[(G + 1) / 2];
 #pragma unroll
   for (int j = 0; j < G; ++j) {
-    Rr[j] = Rg[j] = Rb[j] = 0.0f;
-    S[j] = 1.0f;
-    Tc[j] = Tm[j];
+    tmL[j * 64 + lane] = Tm[j];
+    const uint32_t h = (uint32_t)(m[j] + 1);
+    mp[j / 2] = (j & 1) ? (mp[j / 2] | (h << 16)) : h;
   }
-  BwdPlane bnext = a.K > 0 ? plane_at(a.K - 1) : BwdPlane{};
-  fetch(bnext, a.K - 1);
-  for (int k = a.K - 1; k >= 0; --k) {
-    const BwdPlane b = bnext;
-    bnext = k > 0 ? plane_at(k - 1) : BwdPlane{};
-    if (!b.ok) {
-      fetch(bnext, k - 1);
-      continue;
-    }
-    const size_t pbase = (size_t)k * plane_elems;
-    if (!b.direct) {
-      lds_barrier();                                     // previous plane's gather is done
-      commit(b);
-      for (int i = tid; i < G * b.len; i += kRowBwdThreads) first[i / b.len][i % b.len] = -1;
-      lds_barrier();
-    }
-    fetch(bnext, k - 1);
-    #pragma unroll
-    for (int j = 0; j < G; ++j) {
-      float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
-      int ix = kNoTexel;
-      float wx = 0.0f;
-      if (xin && j < nv) {
-        const float c = ct[(size_t)k * Vp + v0 + j];
-        const float4 s = sample(b, pbase, c, ix, wx);
-        const float om = 1.0f - s.w;
-        // T_k = T_{k+1} / (1 - a_k) below m (reciprocal to ~1 ulp); no gradient behind m.
-        // Branch free: om may be 0 behind m, where the quotient is discarded.
-        const bool live = k <= m[j];
-        const float Tk = live ? (k == m[j] ? Tm[j] : Tc[j] * __builtin_amdgcn_rcpf(om)) : 0.0f;
-        Tc[j] = live ? Tk : Tc[j];
-        d = make_float4(Tk * g[j].x, Tk * g[j].y, Tk * g[j].z,
-                        -Tk * ((g[j].x * Rr[j] + g[j].y * Rg[j] + g[j].z * Rb[j]) + g[j].w * S[j]));
-        Rr[j] = fmaf(om, Rr[j], s.x);
-        Rg[j] = fmaf(om, Rg[j], s.y);
-        Rb[j] = fmaf(om, Rb[j], s.z);
-        S[j] = om * S[j];
-        if (!b.direct) {
-          // x -> texel is monotone: a run of equal texels starts where the left neighbour differs
-          const float Xp = b.bx * xrp + c;
-          const int ixp = BIL ? __float2int_rd(floorf(Xp)) : __float2int_rd(Xp);
-          if (tid == 0 || ixp != ix) first[j][ix - b.f0] = (short)tid;
-        }
-      }
-      if (!b.direct) {
-        slot[j][tid] = d;
-        sx[j][tid] = ix;
-        if (BIL) swx[BIL ? j : 0][tid] = wx;
-      } else if (ix != kNoTexel) {
-        const float d4[4] = {d.x, d.y, d.z, d.w};
+  float4 g[G];
+  float Tc[G], U[G];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (!BIL) {
-            add_row_grad(d_planes, a, k, b.iy, ix, c, d4[c]);
-          } else {
-            add_row_grad(d_planes, a, k, b.iy, ix, c, (1.0f - b.wy) * (1.0f - wx) * d4[c]);
-            add_row_grad(d_planes, a, k, b.iy + 1, ix, c, b.wy * (1.0f - wx) * d4[c]);
-            add_row_grad(d_planes, a, k, b.iy, ix + 1, c, (1.0f - b.wy) * wx * d4[c]);
-            add_row_grad(d_planes, a, k, b.iy + 1, ix + 1, c, b.wy * wx * d4[c]);
-          }
-        }
-      }
-    }
-    if (!b.direct) {
-      lds_barrier();
-      // texel threads: sum every view's runs (fixed order), then add the window to the plane
-      for (int t = tid; t < b.len; t += kRowBwdThreads) {
-        const int X = b.f0 + t;
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int j = 0; j < G; ++j) {
+    g[j] = (xin && j < nv) ? d_out[((size_t)a.perm[v0 + j] * a.ny + y) * a.nx + x] : make_float4(0.f, 0.f, 0.f, 0.f);
+    Tc[j] = 0.0f;                                          // stays 0 behind m
+    U[j] = g[j].w;                                         // U_K = g_T
+  }
+  for (int i = lane; i < kAcc * kBwdWin; i += 64) acc[i] = make_float4(0.f, 0.f, 0.f, 0.f);   // flushes re-zero
+  float4 pr0[kBwdPf], pr1[BIL ? kBwdPf : 1];
+  auto fetch = [&](const BwdInfo& b, int k, int c0) {
+    const auto r0 = row_rsrc(k, b.iy, a.wp * kTB);
+    const auto r1 = row_rsrc(k, b.iy + 1, a.wp * kTB);
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
-          if (j >= nv) continue;
-          for (int q = first[j][t]; q >= 0 && q < kRowBwdThreads && sx[j][q] == X; ++q) {
-            const float w = BIL ? 1.0f - swx[BIL ? j : 0][q] : 1.0f;
-            const float4 d = slot[j][q];
-            acc.x = fmaf(w, d.x, acc.x);
-            acc.y = fmaf(w, d.y, acc.y);
-            acc.z = fmaf(w, d.z, acc.z);
-            acc.w = fmaf(w, d.w, acc.w);
-          }
-          if (BIL && t > 0) {
-            for (int q = first[j][t - 1]; q >= 0 && q < kRowBwdThreads && sx[j][q] == X - 1; ++q) {
-              const float w = swx[BIL ? j : 0][q];
-              const float4 d = slot[j][q];
-              acc.x = fmaf(w, d.x, acc.x);
-              acc.y = fmaf(w, d.y, acc.y);
-              acc.z = fmaf(w, d.z, acc.z);
-              acc.w = fmaf(w, d.w, acc.w);
-            }
-          }
-        }
-        val[t] = acc;                                      // (the samples have read val)
-      }
-      lds_barrier();
-      // add the window to the plane gradient one channel word per lane: consecutive lanes
-      // hit consecutive words, so an atomic instruction covers whole cache lines
-      const float* vw = reinterpret_cast<const float*>(val);
-      for (int w = tid; w < 4 * b.len; w += kRowBwdThreads) {
-        const int X = b.f0 + (w >> 2), c = w & 3;
-        const float v = vw[w];
+    for (int q = 0; q < kBwdPf; ++q) {
+      pr0[q] = buf_texel<PT>(r0, c0 + lane + q * 64);
+      if (BIL) pr1[BIL ? q : 0] = buf_texel<PT>(r1, c0 + lane + q * 64);
+    }
+  };
+  auto store = [&](const BwdInfo& b, int clen) {
+#pragma unroll
+    for (int q = 0; q < kBwdPf; ++q) {
+      const int i = lane + q * 64;
+      const float4 v = BIL ? lerp4(pr0[q], pr1[BIL ? q : 0], b.wy) : pr0[q];
+      if (i < clen) win[i] = v;
+    }
+  };
+  // the accumulators' sum added to the plane gradient (rows iy, iy + 1 split by wy for
+  // bilinear) through buffer atomics over the row: columns outside the plane are dropped by
+  // the range check.  One channel word per lane: consecutive lanes add consecutive words, so
+  // an atomic instruction covers whole cache lines.  The accumulators are re-zeroed.
+  auto flush = [&](const BwdInfo& b, int k, int c0, int clen) {
+    const bool in0 = b.iy >= 0 && b.iy < a.hp, in1 = BIL && b.iy + 1 < a.hp;   // iy >= -1
+    char* gp = reinterpret_cast<char*>(d_planes) + (size_t)k * a.hp * a.wp * 16;
+    const auto g0 = __builtin_amdgcn_make_buffer_rsrc(gp + (size_t)(in0 ? b.iy : 0) * a.wp * 16, (short)0,
+                                                      in0 ? a.wp * 16 : 0, kBufFlags);
+    const auto g1 = __builtin_amdgcn_make_buffer_rsrc(gp + (size_t)(in1 ? b.iy + 1 : 0) * a.wp * 16, (short)0,
+                                                      in1 ? a.wp * 16 : 0, kBufFlags);
+    // word i = 4 t + c of the window (channel c of texel t) at lane i mod 64, summed over the
+    // accumulators.  The whole buffers are read, then cleared (past the window they hold
+    // zeros), so that no read waits on another.
+    float* af = reinterpret_cast<float*>(acc) + lane;
+    constexpr int kIt = kBwdWin * 4 / 64;
+    float v[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      v[it] = af[64 * it];
+      if (kAcc == 2) v[it] += af[64 * it + 4 * kBwdWin];
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      af[64 * it] = 0.0f;
+      if (kAcc == 2) af[64 * it + 4 * kBwdWin] = 0.0f;
+    }
+    const uint32_t off = (uint32_t)c0 * 16u + (uint32_t)lane * 4u;
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      if (v[it] != 0.0f) {                                 // (zero past the window)
         if (!BIL) {
-          add_row_grad(d_planes, a, k, b.iy, X, c, v);
+          __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(v[it], g0, off + 256u * it, 0, 0);
         } else {
-          add_row_grad(d_planes, a, k, b.iy, X, c, (1.0f - b.wy) * v);
-          add_row_grad(d_planes, a, k, b.iy + 1, X, c, b.wy * v);
+          __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32((1.0f - b.wy) * v[it], g0, off + 256u * it, 0, 0);
+          __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(b.wy * v[it], g1, off + 256u * it, 0, 0);
         }
       }
+    }
+  };
+  // Sample pass of sweep 2 over a window chunk.
+  // Fast form: x -> texel is monotone and lanes 2 apart never share a texel, so even lanes
+  // update the first accumulator and odd lanes the second, all in one read-modify-write.
+  // General form: samples owned by the chunk update the first in L phases (phase of lane l:
+  // ph).
+  float4* const acc_lane = acc + (FAST && (lane & 1) ? kBwdWin : 0);
+  auto pass2 = [&](int k, float bxr, int c0, int clen, int L, int ph) {
+    const float4* wt = win - c0;
+    float4* ac = acc_lane - c0;
+    const uint32_t lim = (uint32_t)(clen - (BIL ? 1 : 0));
+    // Lanes update texels other lanes read and write next, which the compiler cannot see:
+    // an empty asm with a memory clobber after every update keeps the LDS operations in
+    // program order (one wave executes them in order, so no wait is needed).
+    auto scatter = [&](int i, const float4& e, bool own) {
+      auto rmw = [&]() {
+        float4 v = ac[i];
+        v.x += e.x;
+        v.y += e.y;
+        v.z += e.z;
+        v.w += e.w;
+        ac[i] = v;
+      };
+      if (FAST) {
+        rmw();
+        asm volatile("" ::: "memory");
+      } else {
+        for (int p = 0; p < L; ++p) {
+          if (own && ph == p) rmw();
+          asm volatile("" ::: "memory");
+        }
+      }
+    };
+    // the texel (bilinear: the blend) of view slot j, its column ix, weight wx, ownership
+    auto sample = [&](int j, int& ix, float& wx, bool& own) {
+      const float X = bxr + cv[j];
+      wx = 0.0f;
+      if (!BIL) {
+        ix = cvt_flr(X);
+        own = owned(ix, c0, lim);
+        return wt[ix];
+      }
+      const float fx = floorf(X);
+      wx = X - fx;
+      ix = cvt_flr(fx);
+      own = owned(ix, c0, lim);
+      return lerp4(wt[ix], wt[ix + 1], wx);
+    };
+    int ixn;
+    float wxn;
+    bool ownn;
+    float4 sn = sample(0, ixn, wxn, ownn);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int ix = ixn;
+      const float wx = wxn;
+      const bool own = ownn;
+      const float4 s = sn;
+      if (j + 1 < G) sn = sample(j + 1, ixn, wxn, ownn);   // read ahead of this view's updates
+      const float om = 1.0f - s.w;
+      const float gc = fmaf(g[j].z, s.z, fmaf(g[j].y, s.y, g[j].x * s.x));
+      // T_k: kept at m, recovered from T_{k+1} before it (reciprocal to ~1 ulp; 1 - a > 0
+      // there), 0 behind it (Tc = 0; the clamp keeps 0 / (1 - a) finite)
+      float Tk = Tc[j] * __builtin_amdgcn_rcpf(fmaxf(om, kTinyT));
+      const uint32_t mj = (j & 1) ? (mp[j / 2] >> 16) : (mp[j / 2] & 0xffffu);
+      const bool at_m = mj == (uint32_t)(k + 1);
+      if (__builtin_amdgcn_ballot_w64(at_m) != 0) {        // wave uniform
+        const float tm = tmL[j * 64 + lane];
+        Tk = at_m ? tm : Tk;
+      }
+      const float4 d = make_float4(Tk * g[j].x, Tk * g[j].y, Tk * g[j].z, -Tk * U[j]);
+      float Un = fmaf(om, U[j], gc);
+      // (an empty asm pins the update here: sunk below the scatters, it would keep every
+      // view's texel live across them)
+      asm volatile("" : "+v"(Un));
+      Tc[j] = own ? Tk : Tc[j];
+      U[j] = own ? Un : U[j];
+      if (!BIL) {
+        scatter(ix, d, own);
+      } else {
+        const float w0 = 1.0f - wx;
+        scatter(ix, make_float4(w0 * d.x, w0 * d.y, w0 * d.z, w0 * d.w), own);
+        scatter(ix + 1, make_float4(wx * d.x, wx * d.y, wx * d.z, wx * d.w), own);
+      }
+    }
+  };
+  {
+    kb = ((a.K - 1) / 64) * 64;
+    mask = batch(kb);
+    int k = 0;
+    BwdInfo b{};
+    bool have = next_bwd(k, b);
+    if (have) fetch(b, k, b.f0);
+    while (have) {
+      const float bxr = b.bx * xr;
+      load_cx(k);
+      const int L = b.phases;
+      // lane l updates in phase l mod L (general form): lane / L = (lane mul) >> 16 for lanes < 64
+      int ph = 0;
+      if (!FAST) {
+        const uint32_t mul = (uint32_t)ceilf(65536.0f * __builtin_amdgcn_rcpf((float)L));
+        ph = lane - L * (int)(((uint32_t)lane * mul) >> 16);
+      }
+      const int nch = chunks(b);
+      int kn = 0;
+      BwdInfo bn{};
+      bool have_n = false;
+      for (int c = 0; c < nch; ++c) {
+        const int c0 = b.f0 + c * kStride, clen = min(kBwdWin, b.len - c * kStride);
+        if (c > 0) fetch(b, k, c0);
+        store(b, clen);                                    // chunk 0: the prefetched one
+        if (c == nch - 1) {
+          have_n = next_bwd(kn, bn);
+          if (have_n) fetch(bn, kn, bn.f0);
+        }
+        pass2(k, bxr, c0, clen, L, ph);
+        flush(b, k, c0, clen);
+      }
+      k = kn;
+      b = bn;
+      have = have_n;
     }
   }
 }
@@ -915,15 +1142,21 @@ void fill_groups(CompositeArgs& a, const int* cls_end, int nc, int G) {
   a.n_groups = g;
 }
 
-// Table of composite coefficients: pt [groups][K] float4, then ct [K][ct_stride(V)] float.
-void table_parts(void* table, int K, int V, float4** pt, float** ct) {
-  *pt = static_cast<float4*>(table);
-  *ct = reinterpret_cast<float*>(static_cast<char*>(table) + (((size_t)K * V * 16 + 255) & ~(size_t)255));
+// Table of composite coefficients: pt [groups][K] float4, ct [K][ct_stride(V)] float, then
+// pm [groups][K] float2 (at most one view group per view).
+size_t align_256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void table_parts(void* table, int K, int V, float4** pt, float** ct, float2** pm) {
+  char* t = static_cast<char*>(table);
+  const size_t o_ct = align_256((size_t)K * V * 16), o_pm = o_ct + align_256((size_t)K * ct_stride(V) * 4);
+  *pt = reinterpret_cast<float4*>(t);
+  *ct = reinterpret_cast<float*>(t + o_ct);
+  *pm = reinterpret_cast<float2*>(t + o_pm);
 }
 
-void launch_table(const CompositeArgs& a, float4* pt, float* ct, hipStream_t s) {
+void launch_table(const CompositeArgs& a, float4* pt, float* ct, float2* pm, hipStream_t s, int slots = 0) {
   const int n = a.K * ct_stride(a.n_views);
-  hipLaunchKernelGGL(coeff_table, dim3((n + 255) / 256), dim3(256), 0, s, a, pt, ct);
+  hipLaunchKernelGGL(coeff_table, dim3((n + 255) / 256), dim3(256), 0, s, a, pt, ct, pm, slots);
 }
 
 template <typename PT, typename OT, bool BIL>
@@ -938,6 +1171,7 @@ hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const fl
     case 4: hipLaunchKernelGGL((composite_rows<PT, OT, 4, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
     case 8: hipLaunchKernelGGL((composite_rows<PT, OT, 8, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
     case 12: hipLaunchKernelGGL((composite_rows<PT, OT, 12, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
+    case 24: hipLaunchKernelGGL((composite_rows<PT, OT, 24, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
     default: hipLaunchKernelGGL((composite_rows<PT, OT, 16, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
   }
   return hipGetLastError();
@@ -964,22 +1198,29 @@ hipError_t dispatch_out(const CompositeArgs& a, bool rows, int G, const float4* 
                                : dispatch_interp<PT, float>(a, rows, G, pt, ct, s);
 }
 
-template <typename PT>
-hipError_t launch_rows_bwd(const CompositeArgs& a, int G, const float4* pt, const float* ct, const float* d_out,
-                           float* d_planes, hipStream_t s) {
-  const dim3 grid((unsigned)a.ny, (unsigned)a.n_groups, (unsigned)((a.nx + kRowBwdThreads - 1) / kRowBwdThreads));
-  const float4* go = reinterpret_cast<const float4*>(d_out);
-  const dim3 blk(kRowBwdThreads);
-  if (G == 16) {
-    if (a.interp == LF_BILINEAR) hipLaunchKernelGGL((composite_rows_bwd<PT, 16, true>), grid, blk, 0, s, a, pt, ct, go, d_planes);
-    else hipLaunchKernelGGL((composite_rows_bwd<PT, 16, false>), grid, blk, 0, s, a, pt, ct, go, d_planes);
-  } else if (G == 4) {
-    if (a.interp == LF_BILINEAR) hipLaunchKernelGGL((composite_rows_bwd<PT, 4, true>), grid, blk, 0, s, a, pt, ct, go, d_planes);
-    else hipLaunchKernelGGL((composite_rows_bwd<PT, 4, false>), grid, blk, 0, s, a, pt, ct, go, d_planes);
+template <typename PT, int G>
+void launch_rows_bwd_g(const CompositeArgs& a, int nseg, int total, const float4* pt, const float* ct,
+                       const float2* pm, const float4* go, float* d_planes, hipStream_t s) {
+  const dim3 grid((unsigned)(((total + 7) / 8) * 8)), blk(64);
+  // both forms over every work-group: each takes the work-groups that are its own
+  if (a.interp == LF_BILINEAR) {
+    hipLaunchKernelGGL((composite_rows_bwd<PT, G, true, true>), grid, blk, 0, s, a, nseg, total, pt, ct, pm, go, d_planes);
+    hipLaunchKernelGGL((composite_rows_bwd<PT, G, true, false>), grid, blk, 0, s, a, nseg, total, pt, ct, pm, go, d_planes);
   } else {
-    if (a.interp == LF_BILINEAR) hipLaunchKernelGGL((composite_rows_bwd<PT, 8, true>), grid, blk, 0, s, a, pt, ct, go, d_planes);
-    else hipLaunchKernelGGL((composite_rows_bwd<PT, 8, false>), grid, blk, 0, s, a, pt, ct, go, d_planes);
+    hipLaunchKernelGGL((composite_rows_bwd<PT, G, false, true>), grid, blk, 0, s, a, nseg, total, pt, ct, pm, go, d_planes);
+    hipLaunchKernelGGL((composite_rows_bwd<PT, G, false, false>), grid, blk, 0, s, a, nseg, total, pt, ct, pm, go, d_planes);
   }
+}
+
+template <typename PT>
+hipError_t launch_rows_bwd(const CompositeArgs& a, int G, const float4* pt, const float* ct, const float2* pm,
+                           const float* d_out, float* d_planes, hipStream_t s) {
+  const int nseg = (a.nx + 63) / 64;
+  const int total = a.n_groups * nseg * a.ny;
+  const float4* go = reinterpret_cast<const float4*>(d_out);
+  if (G == 16) launch_rows_bwd_g<PT, 16>(a, nseg, total, pt, ct, pm, go, d_planes, s);
+  else if (G == 12) launch_rows_bwd_g<PT, 12>(a, nseg, total, pt, ct, pm, go, d_planes, s);
+  else launch_rows_bwd_g<PT, 8>(a, nseg, total, pt, ct, pm, go, d_planes, s);
   return hipGetLastError();
 }
 
@@ -994,13 +1235,15 @@ int view_groups(CompositeArgs& a, int G) {
 
 size_t composite_table_bytes(int K, int n_views) {
   // at most one view group per view
-  return (((size_t)K * n_views * 16 + 255) & ~(size_t)255) + (size_t)K * ct_stride(n_views) * 4 + 256;
+  return align_256((size_t)K * n_views * 16) + align_256((size_t)K * ct_stride(n_views) * 4) +
+         align_256((size_t)K * n_views * 8);
 }
 
 hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profiler* prof) {
   float4* pt;
   float* ct;
-  table_parts(table, a.K, a.n_views, &pt, &ct);
+  float2* pm;
+  table_parts(table, a.K, a.n_views, &pt, &ct, &pm);
   int cls_end[LF_MAX_VIEWS];
   const int nc = dy_classes(a, cls_end);
   int G = 16, best = group_cost(cls_end, nc, 16);
@@ -1021,16 +1264,16 @@ hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profil
   if (kern && std::strcmp(kern, "general") == 0) rows = false;
   rows = rows && rows_fit(a);
   // an explicit group (autotuned) wins; else the LF_COMPOSITE_GROUP tuning override
-  if (a.group == 4 || a.group == 8 || a.group == 12 || a.group == 16) {
+  if (a.group == 4 || a.group == 8 || a.group == 12 || a.group == 16 || a.group == 24) {
     G = a.group;
   } else if (const char* e = getenv("LF_COMPOSITE_GROUP")) {
     const int g = atoi(e);
-    if (g == 4 || g == 8 || g == 12 || g == 16) G = g;
+    if (g == 4 || g == 8 || g == 12 || g == 16 || g == 24) G = g;
   }
   fill_groups(a, cls_end, nc, G);
   if (rows) {
     PhaseScope ps(prof, LF_PHASE_COEFF, s);
-    launch_table(a, pt, ct, s);
+    launch_table(a, pt, ct, pm, s);
   }
   PhaseScope ps(prof, LF_PHASE_COMPOSITE, s);
   switch (a.plane_dtype) {
@@ -1045,28 +1288,27 @@ hipError_t composite_backward_launch(CompositeArgs& a, void* table, const float*
                                     hipStream_t s, Profiler* prof) {
   float4* pt;
   float* ct;
-  table_parts(table, a.K, a.n_views, &pt, &ct);
-  // views per work-group (4: few enough registers and LDS for four or five work-groups
-  // per CU, which hides the latency of the per-plane staging); LF_BWD_GROUP overrides
-  int G = 4;
-  if (const char* e = getenv("LF_BWD_GROUP")) {
-    const int g = atoi(e);
-    if (g == 4 || g == 8 || g == 16) G = g;
-  }
+  float2* pm;
+  table_parts(table, a.K, a.n_views, &pt, &ct, &pm);
+  // views per work-group (one wave, the views in registers): 16, or 8 / 12 (LF_BWD_GROUP);
+  // 16 does the per-plane work (window staging, gradient atomics) for the most views
+  int G = 16;
+  if (const char* e = getenv("LF_BWD_GROUP"))
+    if (atoi(e) == 8 || atoi(e) == 12) G = atoi(e);
   int cls_end[LF_MAX_VIEWS];
   const int nc = dy_classes(a, cls_end);
   fill_groups(a, cls_end, nc, G);
   {
     PhaseScope ps(prof, LF_PHASE_COEFF, s);
-    launch_table(a, pt, ct, s);
+    launch_table(a, pt, ct, pm, s, G);
   }
   PhaseScope ps(prof, LF_PHASE_COMPOSITE_BWD, s);
   const int64_t np = (int64_t)a.K * a.hp * a.wp * 4;
   if (np > 0) hipLaunchKernelGGL(zero_f32, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, d_planes, np);
   switch (a.plane_dtype) {
-    case LF_F16: return launch_rows_bwd<__half>(a, G, pt, ct, d_out, d_planes, s);
-    case LF_BF16: return launch_rows_bwd<__hip_bfloat16>(a, G, pt, ct, d_out, d_planes, s);
-    default: return launch_rows_bwd<float>(a, G, pt, ct, d_out, d_planes, s);
+    case LF_F16: return launch_rows_bwd<__half>(a, G, pt, ct, pm, d_out, d_planes, s);
+    case LF_BF16: return launch_rows_bwd<__hip_bfloat16>(a, G, pt, ct, pm, d_out, d_planes, s);
+    default: return launch_rows_bwd<float>(a, G, pt, ct, pm, d_out, d_planes, s);
   }
 }
 

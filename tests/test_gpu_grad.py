@@ -226,3 +226,47 @@ def test_grad200k_full_size_sparse_cotangents():
     assert touched.sum() >= 40
     for k in grad.KEYS:
         _check(host(gg[k])[keep], rg[k][keep], k + " (full size)")
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+def test_composite_backward_wide_windows(interp):
+    """Planes just behind the reference camera magnify by 5-20 texels per pixel, so a
+    work-group's window spans several LDS chunks; the chunked backward against the oracle."""
+    announce("composite backward wide windows", interp)
+    cam = scenegen.camera(200, 40, 50.0, 2.0, math.radians(40.0))
+    g = geometry.derive(cam)
+    K = 5
+    p = scenegen.random_planes(K, g.hp, g.wp, seed=13, depth_range=(g.d_forward + 0.02, g.d_forward + 0.15))
+    dx, dy = _views(cam, 12)
+    d = grad.composite_decisions(cam, p["depth"], dx, dy, interp)
+    d_out = np.random.default_rng(4).normal(size=(len(dx), cam.ny, cam.nx, 4))
+    got = host(T.composite_backward(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy),
+                                    dev(d_out, torch.float32), interp))
+    ref = grad.composite_vjp(np.asarray(p["rgba"], np.float32).astype(np.float64), d, cam,
+                             d_out.astype(np.float32).astype(np.float64))
+    _check(got, ref, f"d_planes wide windows {interp}")
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+@pytest.mark.parametrize("group", [8, 12, 16])
+@pytest.mark.parametrize("plane_scale", [1.0, 0.4])
+def test_composite_backward_view_groups(plane_scale, group, interp, monkeypatch):
+    """Every view-group size of the backward (LF_BWD_GROUP) with 20 views in two dy classes
+    (groups cut short at each class end), for planes at the views' resolution (x -> texel
+    slope about 0.6-1: lanes two apart never share a texel) and at 0.4 of it (slope about
+    0.3: the phased update form)."""
+    announce("composite backward view groups", plane_scale, group, interp)
+    monkeypatch.setenv("LF_BWD_GROUP", str(group))
+    cam = scenegen.camera(70, 20, 50.0, 3.0, math.radians(30.0), math.radians(8.0), plane_scale=plane_scale)
+    g = geometry.derive(cam)
+    K = 6
+    p = scenegen.random_planes(K, g.hp, g.wp, seed=14)
+    dx, dy, _, _ = geometry.quilt_views(cam, 10, 2)
+    dx, dy = np.asarray(dx, np.float32), np.asarray(dy, np.float32)
+    d = grad.composite_decisions(cam, p["depth"], dx, dy, interp)
+    d_out = np.random.default_rng(5).normal(size=(len(dx), cam.ny, cam.nx, 4))
+    got = host(T.composite_backward(ctx(), dev(p["rgba"]), dev(p["depth"]), cam, T.views_of(dx, dy),
+                                    dev(d_out, torch.float32), interp))
+    ref = grad.composite_vjp(np.asarray(p["rgba"], np.float32).astype(np.float64), d, cam,
+                             d_out.astype(np.float32).astype(np.float64))
+    _check(got, ref, f"d_planes groups of {group}, plane scale {plane_scale}, {interp}")
