@@ -8,10 +8,12 @@ lf_build_mpi (cull, key, depth sort, chunking, tile binning, splat into planes) 
 by lf_composite (swizzle blending of all 45 views).  Inputs are seeded synthetic scenes
 (scenegen) resident in HBM before timing starts.
 
-The JSON line reports views/s of the FP32-plane form as ``value`` and the FP16- and
-UNORM8-plane forms beside it, the roofline of the dominant kernel and of the composite, per-phase kernel
-times measured with HIP events on the launch stream, and the FP64 CPU oracle's rate on
-a bounded sample of the same frame.
+The JSON line reports views/s of the FP32-plane form (FP32 views) as ``value`` and beside
+it the FP16-, BF16- and UNORM8-plane forms (FP16 views), the FP32 form with bilinear
+sampling, the roofline of the dominant kernel and of the composite against the 8 TB/s HBM
+peak and against a measured device-copy rate, per-phase kernel times measured with HIP
+events on the launch stream, and the FP64 CPU oracle's rate on the whole frame computed
+by a pool of worker processes over the host's cores.
 """
 from __future__ import annotations
 
@@ -74,9 +76,11 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--interp", default="nearest", choices=["nearest", "bilinear"])
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-planes", type=int, default=48, help="planes the CPU oracle rasterises")
-    p.add_argument("--cpu-views", type=int, default=6, help="views the CPU oracle composites")
-    p.add_argument("--forms", default="f32,f16,u8", help="plane storage forms to time (first one is `value`)")
+    p.add_argument("--cpu-processes", type=int, default=0, help="oracle worker processes (0: the host's cores, "
+                   "at most 16)")
+    p.add_argument("--forms", default="f32,f16,bf16,u8",
+                   help="plane storage forms to time (first one is `value`; f32 writes FP32 views, the others FP16)")
+    p.add_argument("--no-bilinear", action="store_true", help="skip the bilinear-sampling row")
     p.add_argument("--extra", default="voxel256,grad200k,quilt2d,sh500k,batch8",
                    help="further workloads timed into the same line (voxel256, grad200k, quilt2d, sh500k, "
                         "batch8; empty for none)")
@@ -88,35 +92,68 @@ def parse():
     return p.parse_args()
 
 
-def cpu_baseline(scene, cam, views_dx, views_dy, n_chunk, n_planes, n_views, interp):
-    """Time the FP64 oracle on a bounded sample and scale it to one full frame."""
-    import numpy as np
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
-    from oracle import composite, geometry, partition, project, splat
 
-    g = geometry.derive(cam)
-    t0 = time.perf_counter()
-    part = partition.partition(scene["means"], cam, g, n_chunk, "quantile")
-    t_part = time.perf_counter() - t0
-    ks = np.linspace(0, n_chunk - 1, n_planes).round().astype(int)
-    planes = np.zeros((n_planes, g.hp, g.wp, 4))
-    t0 = time.perf_counter()
-    for j, k in enumerate(ks):
-        idx = part.order[part.chunk_start[k]:part.chunk_start[k + 1]]
-        pr = project.project_reference(scene, idx, cam, g)
-        planes[j], _ = splat.render_plane(pr, g.hp, g.wp)
-    t_planes = time.perf_counter() - t0
-    vsel = list(np.linspace(0, len(views_dx) - 1, n_views).round().astype(int))
-    t0 = time.perf_counter()
-    composite.composite(planes, part.depth[ks], cam, g, views_dx, views_dy, interp, views=vsel)
-    t_comp = time.perf_counter() - t0
-    frame_s = t_part + t_planes * n_chunk / n_planes + t_comp * (n_chunk / n_planes) * (len(views_dx) / n_views)
-    return dict(value=len(views_dx) / frame_s, unit="views/s", cores=1, kind="oracle",
-                sample=(f"partition of all {scene['means'].shape[0]} Gaussians ({t_part:.2f} s), "
-                        f"{n_planes} of {n_chunk} planes rasterised ({t_planes:.2f} s), {n_views} of "
-                        f"{len(views_dx)} views composited over them ({t_comp:.2f} s); scaled to one frame "
-                        f"= {frame_s:.1f} s"),
-                measured_s=round(t_part + t_planes + t_comp, 2))
+def cpu_baseline(config, n_views, interp, processes):
+    """The FP64 oracle on the whole frame (every plane, every view), its per-plane and
+    per-view work spread over worker processes.  The pool forks, so it runs as a child
+    program (this process has used the GPU)."""
+    import subprocess
+    import tempfile
+
+    with tempfile.TemporaryDirectory(prefix="lf_cpu_") as d:
+        cmd = [sys.executable, "-m", "oracle.pool", "frame", "--config", config, "--out", d, "--no-save",
+               "--interp", interp]
+        if processes:
+            cmd += ["--processes", str(processes)]
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+        r = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+        if r.returncode != 0:
+            return dict(error=r.stderr[-2000:])
+        t = json.load(open(os.path.join(d, "timing.json")))
+    frame_s = t["partition_s"] + t["planes_s"] + t["views_s"]
+    return dict(value=round(n_views / frame_s, 3), unit="views/s", cores=t["processes"], kind="oracle",
+                cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+                sample=(f"the whole {config} frame: partition of every Gaussian ({t['partition_s']:.2f} s, one "
+                        f"process), every plane rasterised ({t['planes_s']:.2f} s) and every view composited "
+                        f"({t['views_s']:.2f} s) on {t['processes']} worker processes; {frame_s:.1f} s wall"),
+                measured_s=round(frame_s, 2))
+
+
+def copy_rate(dev, nbytes=1 << 30, reps=5):
+    """Best device-to-device copy rate (bytes read + written per second, GB/s) of a plain
+    torch copy of nbytes, timed with HIP events: the achievable HBM bandwidth."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2 * nbytes / (best * 1e-3) / 1e9
 
 
 def _timed(fn, warmup, steps, ctx, L):
@@ -355,14 +392,15 @@ def main():
     if st == L.LF_ERR_CAPACITY:
         ws = T.workspace_for(ds, cam, K, entry_capacity=int(info.entries_needed * 1.25), device=dev)
 
-    def one_form(form):
+    def one_form(form, interp):
         pdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16, "u8": torch.uint8}[form]
+        vdt = torch.float32 if form == "f32" else torch.float16
         out = T.build_mpi(ctx, ds, cam, K, dtype=pdt, workspace=ws)
-        img = torch.empty((V, cam.ny, cam.nx, 4), dtype=torch.float32, device=dev)
+        img = torch.empty((V, cam.ny, cam.nx, 4), dtype=vdt, device=dev)
 
         def step():
             T.build_mpi(ctx, ds, cam, K, dtype=pdt, workspace=ws, out=out)
-            T.composite(ctx, out["rgba"], out["depth"], cam, vlist, args.interp, out=img)
+            T.composite(ctx, out["rgba"], out["depth"], cam, vlist, interp, out=img, out_dtype=vdt)
 
         for _ in range(args.warmup):
             step()
@@ -381,11 +419,13 @@ def main():
         ms = (t1 - t0) * 1e3 / args.steps
         phases = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}
         pb = {"f32": 16, "f16": 8, "bf16": 8, "u8": 4}[form]
-        comp_bytes = K * geo.plane_height * geo.plane_width * pb + V * cam.ny * cam.nx * 16
+        comp_bytes = K * geo.plane_height * geo.plane_width * pb + V * cam.ny * cam.nx * (16 if form == "f32" else 8)
         comp_ms = phases["composite"]
-        comp_roof = dict(bound="hbm", achieved=round(comp_bytes / (comp_ms * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS,
-                         unit="GB/s", frac=round(comp_bytes / (comp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                         traffic=measured_traffic("composite_rows") if form == "f32" else None,
+        gbs = comp_bytes / (comp_ms * 1e-3) / 1e9
+        comp_roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
+                         unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), copy_peak=round(copy_gbs, 1),
+                         frac_of_copy=round(gbs / copy_gbs, 4),
+                         traffic=measured_traffic("composite_rows") if form == "f32" and interp == "nearest" else None,
                          kernel="composite_rows", bytes_per_launch=comp_bytes,
                          avg_ms=round(comp_ms, 4))
         # splat: algorithmic work = (entry, texel) evaluations of the tile lists; one evaluation is
@@ -404,12 +444,15 @@ def main():
                          peak=round(VALU_LANE_OPS / 1e12, 1), unit="T VALU lane-instructions/s",
                          frac=round(samples * 8 / (comp_ms * 1e-3) / VALU_LANE_OPS, 4), kernel="composite_rows",
                          samples_per_launch=samples, valu_per_sample=8)
-        return dict(form=form, ms_per_step=ms, views_per_s=V / (ms * 1e-3), phases_ms=phases,
+        return dict(form=form, views="f32" if form == "f32" else "f16", interp=interp, ms_per_step=ms,
+                    views_per_s=V / (ms * 1e-3), phases_ms=phases,
                     composite_roofline=comp_roof, splat_roofline=splat_roof, composite_valu=comp_valu,
                     entries=int(info.entries_needed), n_visible=int(info.n_visible))
 
+    copy_gbs = copy_rate(dev)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    res = {f: one_form(f) for f in forms}
+    res = {f: one_form(f, args.interp) for f in forms}
+    bil = one_form(forms[0], "bilinear") if args.interp == "nearest" and not args.no_bilinear else None
     main_r = res[forms[0]]
     ph = main_r["phases_ms"]
     dominant = max(("splat", "composite"), key=lambda k: ph.get(k, 0.0))
@@ -440,6 +483,7 @@ def main():
                    "planes": forms[0], "interp": args.interp, "n_gaussians": 500_000, "n_chunk": K,
                    "views": V, "resolution": [cam.nx, cam.ny]},
         "roofline": roof,
+        "copy_gbs": round(copy_gbs, 1),
         "composite_roofline": main_r["composite_roofline"],
         "splat_roofline": main_r["splat_roofline"],
         "composite_valu": main_r["composite_valu"] if args.interp == "nearest" else None,
@@ -449,18 +493,25 @@ def main():
     }
     for f in forms[1:]:
         r = res[f]
-        line[f"{f}_planes"] = {"value": round(r["views_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+        line[f"{f}_planes"] = {"value": round(r["views_per_s"], 1), "views": r["views"],
+                               "ms_per_step": round(r["ms_per_step"], 4),
                                "speedup_vs_" + forms[0]: round(main_r["ms_per_step"] / r["ms_per_step"], 3),
                                "composite_speedup_vs_" + forms[0]:
                                    round(ph["composite"] / r["phases_ms"]["composite"], 3),
                                "composite_roofline": r["composite_roofline"],
                                "phases_ms": {k: round(v, 4) for k, v in r["phases_ms"].items()}}
+    if bil is not None:
+        line["bilinear"] = {"value": round(bil["views_per_s"], 1), "planes": forms[0], "views": bil["views"],
+                            "ms_per_step": round(bil["ms_per_step"], 4),
+                            "slowdown_vs_nearest": round(bil["ms_per_step"] / main_r["ms_per_step"], 3),
+                            "composite_roofline": bil["composite_roofline"],
+                            "phases_ms": {k: round(v, 4) for k, v in bil["phases_ms"].items()}}
     for name in [x.strip() for x in args.extra.split(",") if x.strip()]:
         fn = {"voxel256": extra_voxel256, "grad200k": extra_grad200k, "quilt2d": extra_quilt2d,
                   "sh500k": extra_sh500k, "batch8": extra_batch8}[name]
         line[name] = fn(ctx, args.extra_steps, 2)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(scene, cam, dx, dy, K, args.cpu_planes, args.cpu_views, args.interp)
+        line["cpu_baseline"] = cpu_baseline("cluster500k", V, args.interp, args.cpu_processes)
     print(json.dumps(line), flush=True)
 
 

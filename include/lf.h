@@ -166,7 +166,7 @@ lf_status lf_geometry(const lf_camera* cam, lf_geometry_info* out);
 lf_status lf_quilt_views(const lf_camera* cam, int32_t vx, int32_t vy, lf_view* out);
 
 /* Bytes of workspace lf_build_mpi needs for `field` with room for `entry_capacity`
- * (tile, chunk) list entries (entry_capacity <= 0 picks 32 entries per primitive).       */
+ * (tile, chunk) list entries (entry_capacity <= 0 picks 16 per primitive, at least 65536). */
 lf_status lf_build_mpi_workspace(const lf_field* field, const lf_camera* cam, int32_t n_chunk,
                                  int64_t entry_capacity, size_t* bytes);
 
@@ -356,9 +356,18 @@ typedef struct lf_batch lf_batch;
 lf_status lf_batch_create(lf_ctx* ctx, const lf_batch_item* items, int32_t n_items, int32_t flags,
                           lf_batch** out);
 
-/* Renders every scene (build then composite) on `stream`.  Asynchronous; capacity
- * overflows are reported per scene by lf_build_stats on its workspace.                   */
+/* Renders every scene (build then composite) on `stream`.  Asynchronous; lf_batch_stats
+ * reports the builds' capacity overflows and timed-out waits after it.                   */
 lf_status lf_batch_run(lf_batch* batch, void* stream);
+
+/* Build counters of every scene of the batch's last run, as lf_build_stats gives them for
+ * one build: out, if not NULL, a host array of the batch's n_items entries; *n_failed, if
+ * not NULL, the number of scenes whose build overflowed its entry capacity or gave up a
+ * bounded device-wide wait (their planes and views are invalid).  SYNCHRONISES `stream`
+ * (the stream of the run).  Returns LF_ERR_HIP if a scene's wait gave up, else
+ * LF_ERR_CAPACITY if a scene overflowed (the message names the first such scene), else
+ * LF_OK; out and n_failed are filled in every case.                                      */
+lf_status lf_batch_stats(lf_batch* batch, lf_build_info* out, int32_t* n_failed, void* stream);
 
 /* The view-group size the composite of scene `item` uses (autotuned, or 0 for default). */
 lf_status lf_batch_group(const lf_batch* batch, int32_t item, int32_t* group);

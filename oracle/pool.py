@@ -18,6 +18,7 @@ runs inside a process that has used the GPU.  The frame written to DIR:
     views.npy    [V,Ny,Nx,4] float64 (Q_r, Q_g, Q_b, T) of the quilt's views
     vamb.npy     [V,Ny,Nx] bool, pixels that sample an ambiguous texel
     timing.json  wall seconds of the partition, planes and views and the process count
+                 (with ``--no-save`` the only file: the benchmark's CPU baseline)
 
 ``--target`` renders the workload's perturbed copy instead (the gradient workload's target
 views).  ``python -m oracle.pool batch --index i --out DIR`` writes, for scene i of the
@@ -208,6 +209,7 @@ def _main(argv=None):
     ap.add_argument("--processes", type=int, default=0)
     ap.add_argument("--interp", default="nearest")
     ap.add_argument("--no-views", action="store_true")
+    ap.add_argument("--no-save", action="store_true", help="frame: time only, write timing.json alone")
     a = ap.parse_args(argv)
     import scenegen        # seeded inputs only
 
@@ -248,7 +250,7 @@ def _main(argv=None):
     res, t = frame(scene, cam, cfg["n_chunk"], kind, cfg["binning"], cfg.get("inv_depth_range"), dx, dy, a.interp,
                    a.processes or None)
     os.makedirs(a.out, exist_ok=True)
-    for name, arr in res.items():
+    for name, arr in ({} if a.no_save else res).items():
         np.save(os.path.join(a.out, name + ".npy"), arr)
     with open(os.path.join(a.out, "timing.json"), "w") as f:
         json.dump(t, f)

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "LF_OK", 1: "LF_ERR_INVALID_ARG", 2: "LF_ERR_UNSUPPORTED", 3:
 EXPORTS = [
     "lf_version", "lf_last_error", "lf_create", "lf_destroy", "lf_geometry", "lf_quilt_views",
     "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_composite_backward",
-    "lf_build_mpi_backward", "lf_plane_coeffs", "lf_batch_create", "lf_batch_run", "lf_batch_group",
+    "lf_build_mpi_backward", "lf_plane_coeffs", "lf_batch_create", "lf_batch_run", "lf_batch_stats", "lf_batch_group",
     "lf_batch_destroy", "lf_profile_enable", "lf_profile_read", "lf_render_view_workspace", "lf_render_view",
     "lf_sh_texel_floats", "lf_build_mpi_sh", "lf_composite_sh", "lf_sh_colours", "lf_build_tile_lists",
     "lf_composite_noalloc",
@@ -139,6 +139,7 @@ def load():
                                    C.POINTER(lf_gaussian_grads), P, C.c_size_t, P], C.c_int),
         "lf_batch_create": ([P, C.POINTER(lf_batch_item), C.c_int32, C.c_int32, C.POINTER(P)], C.c_int),
         "lf_batch_run": ([P, P], C.c_int),
+        "lf_batch_stats": ([P, C.POINTER(lf_build_info), C.POINTER(C.c_int32), P], C.c_int),
         "lf_batch_group": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
         "lf_batch_destroy": ([P], None),
         "lf_plane_coeffs": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
@@ -349,6 +350,16 @@ def lf_batch_create(ctx: int, items, flags: int = 0) -> int:
 
 def lf_batch_run(batch: int, stream: int = 0) -> None:
     _check(load().lf_batch_run(batch, stream), "lf_batch_run")
+
+
+def lf_batch_stats(batch: int, n_items: int, stream: int = 0, check: bool = True):
+    """(list of lf_build_info per scene, number of failed scenes, status)."""
+    out = (lf_build_info * n_items)()
+    nf = C.c_int32()
+    st = load().lf_batch_stats(batch, out, C.byref(nf), stream)
+    if check:
+        _check(st, "lf_batch_stats")
+    return list(out), nf.value, st
 
 
 def lf_batch_group(batch: int, item: int) -> int:

@@ -7,6 +7,7 @@
 #include <new>
 #include <vector>
 
+#include "build_internal.h"
 #include "lf_internal.h"
 
 namespace {
@@ -272,6 +273,44 @@ extern "C" lf_status lf_batch_group(const lf_batch* b, int32_t item, int32_t* gr
   if (!b || !group) return fail(LF_ERR_INVALID_ARG, "batch or group is NULL");
   if (item < 0 || item >= (int32_t)b->items.size()) return fail(LF_ERR_INVALID_ARG, "item %d out of range", item);
   *group = b->group[(size_t)item];
+  return LF_OK;
+}
+
+extern "C" lf_status lf_batch_stats(lf_batch* b, lf_build_info* out, int32_t* n_failed, void* stream) {
+  if (!b) return fail(LF_ERR_INVALID_ARG, "batch is NULL");
+  hipError_t e = hipSetDevice(b->ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const size_t n = b->items.size();
+  std::vector<BuildHeader> h(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (b->items[i].workspace_bytes < sizeof(BuildHeader))
+      return fail(LF_ERR_INVALID_ARG, "scene %zu: workspace too small", i);
+    if ((e = hipMemcpyAsync(&h[i], b->items[i].workspace, sizeof(BuildHeader), hipMemcpyDeviceToHost,
+                            (hipStream_t)stream)) != hipSuccess)
+      return hip_fail(e, "hipMemcpyAsync");
+  }
+  if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  int failed = 0, first_stall = -1, first_over = -1;
+  for (size_t i = 0; i < n; ++i) {
+    if (out) {
+      out[i].n_visible = h[i].n_vis;
+      out[i].entries_needed = h[i].entries;
+      out[i].entry_capacity = h[i].capacity;
+      out[i].overflow = h[i].overflow;
+      out[i].stalled = h[i].stalled ? 1 : 0;
+    }
+    if (h[i].stalled && first_stall < 0) first_stall = (int)i;
+    if (h[i].overflow && first_over < 0) first_over = (int)i;
+    failed += (h[i].stalled || h[i].overflow) ? 1 : 0;
+  }
+  if (n_failed) *n_failed = failed;
+  if (first_stall >= 0)
+    return fail(LF_ERR_HIP, "scene %d: a device-wide wait of its build timed out (its planes are invalid); %d "
+                "scene(s) failed", first_stall, failed);
+  if (first_over >= 0)
+    return fail(LF_ERR_CAPACITY, "scene %d: the build needed %lld entries but the workspace holds %lld; %d scene(s) "
+                "failed", first_over, (long long)h[(size_t)first_over].entries,
+                (long long)h[(size_t)first_over].capacity, failed);
   return LF_OK;
 }
 

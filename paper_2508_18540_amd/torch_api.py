@@ -347,7 +347,9 @@ class Batch:
     field dict), cam, n_chunk, views (lf_view array), and optionally binning,
     inv_depth_range, interp, plane_dtype, out_dtype.  Allocates every scene's planes, views
     and workspace; ``run()`` renders them all (``outs[i]`` = dict(rgba, depth, chunk_of,
-    chunk_count, views, workspace))."""
+    chunk_count, views, workspace)), ``stats()`` reports every scene's build.  A scene's
+    tile-list capacity is sized by one probe build unless ``probe`` (or the scene's own
+    "probe" key) is false."""
 
     def __init__(self, ctx: Context, scenes: list, graph: bool = True, autotune: bool = False, probe: bool = True):
         self.ctx = ctx
@@ -357,7 +359,7 @@ class Batch:
             info = L.lf_geometry(L.make_camera(cam))
             dev = ctx.device
             ws = workspace_for(sc["scene"], cam, K, device=dev)
-            if probe:
+            if sc.get("probe", probe):
                 # one build sizes the tile-list capacity (re-allocated once if the default is short)
                 tmp = build_mpi(ctx, sc["scene"], cam, K, sc.get("binning", "quantile"), sc.get("inv_depth_range"),
                                 dtype=sc.get("plane_dtype", torch.float16), workspace=ws)
@@ -397,6 +399,12 @@ class Batch:
     def run(self):
         L.lf_batch_run(self.handle, torch.cuda.current_stream(self.ctx.device).cuda_stream)
         return self.outs
+
+    def stats(self, check: bool = True):
+        """lf_batch_stats after the last run: (per-scene lf_build_info list, failed scenes,
+        status); raises on a failed scene when ``check``."""
+        return L.lf_batch_stats(self.handle, len(self.outs), torch.cuda.current_stream(self.ctx.device).cuda_stream,
+                                check)
 
     def groups(self):
         return [L.lf_batch_group(self.handle, i) for i in range(len(self.outs))]

@@ -84,3 +84,35 @@ def test_batch_autotuned_groups():
     b.run()
     _same(b, refs)
     b.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_stats_reports_each_scene(graph):
+    """lf_batch_stats after a run: every scene's counters, and a scene whose build overflows
+    its tile-list capacity (large footprints, the default capacity of 65536 entries, no
+    probe) named in the LF_ERR_CAPACITY it returns, the other scenes unaffected."""
+    from paper_2508_18540_amd import _lib as L
+    announce("batch stats", "graph" if graph else "streams")
+    scenes = _scenes()[:2]
+    cam = scenegen.camera(256, 256, 50.0, 2.0, math.radians(40.0))
+    dx, dy, _, _ = geometry.quilt_views(cam, 5, 1)
+    big = scenegen.small_scene(1500, 7, xy=1.0, z=(2.5, 4.0), log_scale=(-0.6, 0.2))
+    scenes.insert(1, dict(scene=T.to_device(big), cam=cam, n_chunk=8, probe=False,
+                          views=T.views_of(dx.astype(np.float32), dy.astype(np.float32))))
+    b = T.Batch(ctx(), scenes, graph=graph)
+    b.run()
+    info, n_failed, st = b.stats(check=False)
+    assert st == L.LF_ERR_CAPACITY and n_failed == 1, (st, n_failed)
+    assert [i.overflow for i in info] == [0, 1, 0]
+    assert info[1].entries_needed > info[1].entry_capacity
+    for i in (0, 2):
+        assert 0 < info[i].entries_needed <= info[i].entry_capacity and info[i].stalled == 0
+        assert info[i].n_visible > 0
+    with pytest.raises(L.LFError, match="scene 1"):
+        b.stats()
+    b.close()
+    ok = T.Batch(ctx(), _scenes()[:2], graph=graph)
+    ok.run()
+    info, n_failed, st = ok.stats()
+    assert st == L.LF_OK and n_failed == 0 and len(info) == 2
+    ok.close()
