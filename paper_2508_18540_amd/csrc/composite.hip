@@ -38,7 +38,7 @@
 namespace lf {
 namespace {
 
-constexpr int kRowThreads = 512;
+constexpr int kRowThreads = 256;
 
 template <typename T>
 __device__ __forceinline__ float4 load_texel(const T* p, size_t i);
@@ -118,10 +118,11 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
 // else the lane count of the backward's accumulation phases), ct[k][p] = Cx of the
 // view at position p of the grouped order, rows padded by kViewPad positions (the padding
 // repeats the last position) so a group's G offsets can always be read, and pm[g][k] = the
-// least and greatest Cx of group g's views.  Nearest sampling folds the 1/2 of
-// floor(X + 1/2) into Cx and Cy.
+// least and greatest Cx of group g's view slots (its views, and with `slots` the positions
+// after a short group's end up to `slots` in all: kernels that sample every slot read them).
+// Nearest sampling folds the 1/2 of floor(X + 1/2) into Cx and Cy.
 // ---------------------------------------------------------------------------------------
-constexpr int kViewPad = 16;
+constexpr int kViewPad = 24;                  // >= the largest view group - 1
 
 __host__ __device__ inline int ct_stride(int V) { return V + kViewPad; }
 
@@ -177,8 +178,10 @@ __global__ void coeff_table(CompositeArgs a, float4* __restrict__ pt, float* __r
 // the plane row and the texel window [f0, f0 + len) that contains every sample of this
 // work-group: X is monotone in x and in Cx, so its extremes are the samples at the segment
 // ends with the extreme offsets.  Windows are staged into LDS with zeros outside the
-// plane, and a sample is floor(X) - f0 without a clamp.  A window longer than the buffer
-// falls back to the whole row [-2, wp + 1] with samples clamped onto its zero guards.
+// plane, and a sample is floor(X) - f0 without a clamp.
+// The row kernel takes the 64-pixel segments the one-wave kernel (below) leaves: those with
+// a window longer than that kernel's buffer.  A window longer than its own buffer (kWin)
+// falls back to the whole row [-2, wp + 1], with samples clamped onto its zero guards.
 //   nearest  : win[i] = texel f0 + i (FP16 planes keep FP16 texels, others float32)
 //   bilinear : win[2i] = t(f0 + i), win[2i+1] = t(f0 + i + 1) - t(f0 + i), float32, with t
 //              the row pair blended vertically by the plane's weight wy
@@ -187,6 +190,39 @@ constexpr int kBatch = 64;
 constexpr int kWin = 2048;                    // float4 entries per window buffer
 constexpr int kWinStride = kWin + 2;          // plus a trash slot for inactive stores
 constexpr int kPrefetch = kWin / kRowThreads; // window entries prefetched per thread (nearest)
+constexpr int kWaveWin = 256;                 // window entries of the one-wave kernel's buffers
+
+// Whether every plane that view group `pt`/`pm` (the group's table rows) samples has, for
+// the 64 pixels [xs0, xs0 + 64) of row y, a window of at most kWaveWin entries (the
+// one-wave kernel's); wave uniform.  A plane is sampled unless it is invalid, its row lies
+// outside the plane, or its window lies wholly outside the row (transparent texels only).
+// The one-wave kernel and the row kernel decide each segment with this same function.
+template <bool BIL>
+__device__ bool wave_fits(const CompositeArgs& a, const float4* __restrict__ pt, const float2* __restrict__ pm,
+                          int xs0, int y) {
+  const int lane = threadIdx.x & 63;
+  const float yr = (float)y - a.c.cy;
+  const float xr_lo = (float)xs0 - a.c.cx, xr_hi = (float)(xs0 + 63) - a.c.cx;
+  const int cap = BIL ? kWaveWin / 2 : kWaveWin;
+  bool slow = false;
+  for (int kb = 0; kb < a.K; kb += 64) {
+    const int k = kb + lane;
+    bool s = false;
+    if (k < a.K) {
+      const float4 p = pt[k];
+      const float2 cr = pm[k];
+      const float Y = p.y * yr + p.z;
+      const int iy = (int)floorf(Y);
+      const bool ok = p.w != 0.0f && iy >= (BIL ? -1 : 0) && iy < a.hp;
+      const float lo = floorf(p.x * xr_lo + cr.x);
+      const float hi = floorf(p.x * xr_hi + cr.y) + (BIL ? 1.0f : 0.0f);
+      const bool outside = hi < 0.0f || lo > (float)(a.wp - 1);
+      s = ok && !outside && !(hi - lo + 1.0f <= (float)cap);
+    }
+    slow = slow || __builtin_amdgcn_ballot_w64(s) != 0;
+  }
+  return !slow;
+}
 constexpr int kSub = 4;                       // views sampled per scheduling block
 
 struct PlaneInfo {
@@ -243,7 +279,8 @@ template <typename PT, typename OT, int G, bool BIL>
 __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, int seg_len,
                                                               int nseg, int total,
                                                               const float4* __restrict__ pt,
-                                                              const float* __restrict__ ct) {
+                                                              const float* __restrict__ ct,
+                                                              const float2* __restrict__ pm) {
   using LT = typename std::conditional<BIL, float4, typename LdsTexel<PT>::type>::type;
   constexpr bool RAW = !std::is_same<LT, float4>::value;   // FP16 texels in LDS (FP16 / UNORM8 planes)
   constexpr bool U8 = RAW && std::is_same<PT, uint8_t>::value;   // samples are codes: scale by 1/255
@@ -252,8 +289,9 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
   // the hardware's range check returns zero outside the row, so no clamp or mask is needed
   constexpr bool BUF = !BIL && (RAW || std::is_same<PT, float>::value);
   constexpr int kTexelBytes = RAW ? (int)sizeof(RT) : 16;
-  constexpr int PF = BIL ? kPrefetch / 2 : kPrefetch;
-  extern __shared__ float4 win[];                          // 2 buffers of kWin float4
+  constexpr int W = kWin, WS = kWinStride;
+  constexpr int PF = (W / kRowThreads) / (BIL ? 2 : 1);    // window entries each thread fetches
+  extern __shared__ float4 win[];                          // 2 buffers of W float4
   __shared__ PlaneInfo pinfo[kBatch];
   __shared__ int slist[kBatch];
   __shared__ int scount;                                   // valid planes of the batch
@@ -267,6 +305,7 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
   const int v0 = gd & 0xffu;                               // group's first position in perm
   const int nv = gd >> 8;
   pt += (size_t)gi * a.K;
+  pm += (size_t)gi * a.K;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int xs0 = (rest % nseg) * seg_len;
   const int x = xs0 + tid;
@@ -278,6 +317,37 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
   const float xr_lo = (float)xs0 - a.c.cx, xr_hi = (float)xs1 - a.c.cx;
   const size_t plane_elems = (size_t)hp * wp;
 
+  // the window of plane k for this work-group: row iy (bilinear: first of two, weight wy),
+  // [lo, hi] as floats, and whether the plane is sampled at all (ok)
+  auto window = [&](int k, float& lo, float& hi, int& iy, float& wy) {
+    const float4 p = pt[k];                                // (bx, by, Cy, valid)
+    wy = 0.0f;
+    bool ok = p.w != 0.0f;
+    if (!BIL) {
+      iy = __float2int_rd(p.y * yr + p.z);
+      ok = ok && iy >= 0 && iy < hp;
+    } else {
+      const float Y = p.y * yr + p.z;
+      const float fy0 = floorf(Y);
+      wy = Y - fy0;
+      iy = __float2int_rd(fy0);
+      ok = ok && iy >= -1 && iy < hp;
+    }
+    // the least and greatest Cx over the group's G slots (the table's padded extents: the
+    // slots past a short group's end are sampled too, their results dropped)
+    const float2 cr = pm[k];
+    lo = floorf(p.x * xr_lo + cr.x);
+    hi = floorf(p.x * xr_hi + cr.y) + (BIL ? 1.0f : 0.0f);
+    return ok;
+  };
+  // a window fits a buffer of `cap` entries (and the fetch of PF entries per thread)
+  auto fits = [&](float lo, float hi, int cap) { return lo >= -1.0e9f && hi <= 1.0e9f && hi - lo + 1.0f <= (float)cap; };
+  // this wave's 64-pixel segment is the one-wave kernel's when its windows fit that
+  // kernel's buffer (segments start at multiples of 64: seg_len is); the work-group
+  // returns when all its waves' are
+  const int wx0 = xs0 + (tid & ~63);
+  const bool wave_done = wx0 >= a.nx || wave_fits<BIL>(a, pt, pm, wx0, y);
+  if (__syncthreads_and(wave_done)) return;
   float Qr[G], Qg[G], Qb[G], Tr[G];
 #pragma unroll
   for (int j = 0; j < G; ++j) {
@@ -292,31 +362,12 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
     __syncthreads();
     if (tid < nk) {
       const int k = kb + tid;
-      const float4 p = pt[k];                              // (bx, by, Cy, valid)
       PlaneInfo pi;
-      pi.wy = 0.0f;
-      bool ok = p.w != 0.0f;
-      if (!BIL) {
-        pi.iy = __float2int_rd(p.y * yr + p.z);
-        ok = ok && pi.iy >= 0 && pi.iy < hp;
-      } else {
-        const float Y = p.y * yr + p.z;
-        const float fy0 = floorf(Y);
-        pi.wy = Y - fy0;
-        pi.iy = __float2int_rd(fy0);
-        ok = ok && pi.iy >= -1 && pi.iy < hp;
-      }
-      const float* crow = ct + (size_t)k * V + v0;
-      float cmin = crow[0], cmax = crow[0];
-      for (int j = 1; j < nv; ++j) {
-        cmin = fminf(cmin, crow[j]);
-        cmax = fmaxf(cmax, crow[j]);
-      }
-      const float lo = floorf(p.x * xr_lo + cmin);
-      const float hi = floorf(p.x * xr_hi + cmax) + (BIL ? 1.0f : 0.0f);
+      float lo, hi;
+      bool ok = window(k, lo, hi, pi.iy, pi.wy);
       // a window must fit the buffer and be covered by the fetch (PF entries per thread)
-      const int cap = min(BIL ? kWin / 2 : kWin, PF * nt);
-      if (lo >= -1.0e9f && hi <= 1.0e9f && hi - lo + 1.0f <= (float)cap) {
+      const int cap = min(BIL ? W / 2 : W, PF * nt);
+      if (fits(lo, hi, cap)) {
         pi.f0 = (int)lo;
         pi.len = (int)(hi - lo) + 1;
         // a window wholly outside the row samples only transparent texels, which leave
@@ -397,12 +448,12 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
     // here would split the loop into blocks the compiler then schedules across)
     auto store = [&](int buf, int k) {
       const PlaneInfo pi = pinfo[k];
-      float4* w = win + buf * kWinStride;
+      float4* w = win + buf * WS;
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
         if (q * nt >= pi.len) break;                       // uniform: the window is shorter
         const int i0 = tid + q * nt;
-        const int i = i0 < pi.len ? i0 : (BIL ? kWin / 2 : kWin);
+        const int i = i0 < pi.len ? i0 : (BIL ? W / 2 : W);
         const uint32_t m = valid >> (q * 4);
         if constexpr (BUF) {
           (void)m;
@@ -438,7 +489,7 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
         for (int j = 0; j < G; ++j) Cv[j] = crow[j];          // scalar loads, one wait
         const float bxr = pt[kb + k].x * xr;
         const float xmin = (float)f0, xmax = (float)(f0 + len) - 0.5f;
-        const char* wbytes = reinterpret_cast<const char*>(win) + (n & 1) * (kWinStride * 16) -
+        const char* wbytes = reinterpret_cast<const char*>(win) + (n & 1) * (WS * 16) -
                              (ptrdiff_t)f0 * (ptrdiff_t)(BIL ? 32 : (int)sizeof(LT));
 #pragma unroll
         for (int j0 = 0; j0 < G; j0 += kSub) {
@@ -482,7 +533,230 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
       }
     }
   }
-  if (tid < seg_len && x < a.nx) {
+  if (tid < seg_len && x < a.nx && !wave_done) {
+    OT* out = static_cast<OT*>(a.out);
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (j < nv) store_pixel(out, ((size_t)a.perm[v0 + j] * a.ny + y) * a.nx + x, Qr[j], Qg[j], Qb[j], Tr[j]);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// One-wave kernel: a work-group is one wave, 64 output pixels of row y (lane = pixel) for a
+// group of G views that share dy, the G views' (Q, T) in registers; tiles dealt to the XCDs
+// as in the row kernel.  It takes the segments whose every window fits kWaveWin entries
+// (wave_fits; the row kernel takes the others).  A single wave needs no barrier: its LDS
+// operations complete in order.  Plane windows are derived 64 at a time across the lanes
+// and read out (readlane) when a plane is processed; the next plane's window is in flight
+// in registers (buffer loads over the plane row: zero outside it) while this one is
+// sampled, and the window buffers alternate, so a sample is floor(X) - f0 with no clamp.
+//   nearest  : win[i] = texel f0 + i (FP16 and UNORM8 planes as FP16, others float32)
+//   bilinear : win[2i] = t(f0 + i), win[2i+1] = t(f0 + i + 1) - t(f0 + i), t the row pair
+//              blended vertically by the plane's weight wy
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ float4 wave_texel(__amdgpu_buffer_rsrc_t r, int ix);
+template <>
+__device__ __forceinline__ float4 wave_texel<float>(__amdgpu_buffer_rsrc_t r, int ix) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)ix * 16u, 0, 0));
+}
+template <>
+__device__ __forceinline__ float4 wave_texel<__half>(__amdgpu_buffer_rsrc_t r, int ix) {
+  const uint2 u = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, (uint32_t)ix * 8u, 0, 0));
+  const float2 f = __half22float2(*reinterpret_cast<const __half2*>(&u.x));
+  const float2 h = __half22float2(*reinterpret_cast<const __half2*>(&u.y));
+  return make_float4(f.x, f.y, h.x, h.y);
+}
+template <>
+__device__ __forceinline__ float4 wave_texel<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, int ix) {
+  const uint2 u = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, (uint32_t)ix * 8u, 0, 0));
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+                     __uint_as_float(u.y & 0xffff0000u));
+}
+template <>
+__device__ __forceinline__ float4 wave_texel<uint8_t>(__amdgpu_buffer_rsrc_t r, int ix) {
+  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)ix * 4u, 0, 0);
+  constexpr float s = 1.0f / 255.0f;
+  return make_float4((float)(u & 0xffu) * s, (float)((u >> 8) & 0xffu) * s, (float)((u >> 16) & 0xffu) * s,
+                     (float)(u >> 24) * s);
+}
+
+template <typename PT, typename OT, int G, bool BIL>
+__global__ __launch_bounds__(64) void composite_wave(CompositeArgs a, int nseg, int total,
+                                                     const float4* __restrict__ pt, const float* __restrict__ ct,
+                                                     const float2* __restrict__ pm) {
+  // LDS texels: FP16 for FP16 / UNORM8 nearest windows (UNORM8 as codes 0..255), else float32
+  using LT = typename std::conditional<BIL, float4, typename LdsTexel<PT>::type>::type;
+  constexpr bool RAW = !std::is_same<LT, float4>::value;
+  constexpr bool U8 = RAW && std::is_same<PT, uint8_t>::value;
+  using RT = typename std::conditional<U8, uint32_t, typename std::conditional<RAW, uint2, float4>::type>::type;
+  constexpr int E = BIL ? kWaveWin / 2 : kWaveWin;          // window entries
+  constexpr int PF = E / 64;                                 // entries each lane fetches
+  constexpr int kTB = std::is_same<PT, float>::value ? 16 : (std::is_same<PT, uint8_t>::value ? 4 : 8);
+  __shared__ LT win[2][(BIL ? 2 : 1) * E + 2];              // plus a trash slot (entries past the window)
+  const int wg = blockIdx.x;
+  const int per = (total + 7) / 8;
+  const int lg = (wg % 8) * per + wg / 8;
+  if (lg >= total) return;                                 // whole work-group: grid padded to 8 per
+  const int gi = lg % a.n_groups, rest = lg / a.n_groups;
+  const int y = rest / nseg, xs0 = (rest % nseg) * 64;
+  const uint32_t gd = a.vgroup[gi];
+  const int v0 = gd & 0xffu;
+  const int nv = gd >> 8;
+  pt += (size_t)gi * a.K;
+  pm += (size_t)gi * a.K;
+  if (!wave_fits<BIL>(a, pt, pm, xs0, y)) return;          // the row kernel's segment
+  const int lane = threadIdx.x;
+  const int x = xs0 + lane;
+  // lanes past the row's end sample at their own x (results dropped)
+  const float xr = (float)x - a.c.cx, yr = (float)y - a.c.cy;
+  const float xr_lo = (float)xs0 - a.c.cx, xr_hi = (float)(xs0 + 63) - a.c.cx;
+  const int S = ct_stride(a.n_views);
+  const char* planes = static_cast<const char*>(a.planes);
+  const size_t plane_bytes = (size_t)a.hp * a.wp * kTB;
+
+  // plane windows, 64 at a time (lane i: plane kb + i); the planes sampled are the set bits
+  int my_f0 = 0, my_len = 0, my_iy = 0;
+  float my_wy = 0.0f;
+  auto batch = [&](int kb) -> uint64_t {
+    const int k = kb + lane;
+    int f0 = 0, len = 0, iy = 0;
+    float wy = 0.0f;
+    if (k < a.K) {
+      const float4 p = pt[k];
+      const float2 cr = pm[k];
+      const float Y = p.y * yr + p.z;
+      const float fy0 = floorf(Y);
+      wy = BIL ? Y - fy0 : 0.0f;
+      iy = (int)fy0;
+      bool ok = p.w != 0.0f && iy >= (BIL ? -1 : 0) && iy < a.hp;
+      const float lo = floorf(p.x * xr_lo + cr.x);
+      const float hi = floorf(p.x * xr_hi + cr.y) + (BIL ? 1.0f : 0.0f);
+      ok = ok && hi >= 0.0f && lo <= (float)(a.wp - 1);   // else transparent texels only
+      f0 = ok ? (int)lo : 0;
+      len = ok ? (int)(hi - lo) + 1 : 0;                   // <= E: wave_fits
+    }
+    my_f0 = f0;
+    my_len = len;
+    my_iy = iy;
+    my_wy = wy;
+    return __builtin_amdgcn_ballot_w64(len > 0);
+  };
+  int kb = 0;
+  uint64_t mask = batch(0);
+  auto next = [&](int& k, int& f0, int& len, int& iy, float& wy) {
+    while (mask == 0) {
+      kb += 64;
+      if (kb >= a.K) return false;
+      mask = batch(kb);
+    }
+    const int i = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    k = kb + i;
+    f0 = __builtin_amdgcn_readlane(my_f0, i);
+    len = __builtin_amdgcn_readlane(my_len, i);
+    iy = __builtin_amdgcn_readlane(my_iy, i);
+    wy = BIL ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_wy), i)) : 0.0f;
+    return true;
+  };
+  // buffer resource over row iy of plane k (a row outside the plane: no records, zeros)
+  auto row = [&](int k, int iy) {
+    const bool in = iy >= 0 && iy < a.hp;
+    const char* base = planes + (size_t)k * plane_bytes + (size_t)(in ? iy : 0) * a.wp * kTB;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, in ? a.wp * kTB : 0, 0x00020000);
+  };
+  // window fetch into registers (nearest: raw texels; bilinear: the four corners)
+  RT rn[BIL ? 1 : PF];
+  float4 rc[BIL ? PF : 1][4];
+  auto fetch = [&](int k, int f0, int len, int iy) {
+    const auto r0 = row(k, iy);
+    const auto r1 = row(k, iy + 1);
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      if (q * 64 >= len) break;                            // wave uniform
+      const int ix = f0 + lane + q * 64;
+      if constexpr (!BIL) {
+        if constexpr (U8) rn[q] = (RT)__builtin_amdgcn_raw_buffer_load_b32(r0, (uint32_t)ix * 4u, 0, 0);
+        else if constexpr (RAW) rn[q] = __builtin_bit_cast(RT, __builtin_amdgcn_raw_buffer_load_b64(r0, (uint32_t)ix * 8u, 0, 0));
+        else if constexpr (std::is_same<PT, float>::value)
+          rn[q] = __builtin_bit_cast(RT, __builtin_amdgcn_raw_buffer_load_b128(r0, (uint32_t)ix * 16u, 0, 0));
+        else rn[q] = __builtin_bit_cast(RT, wave_texel<PT>(r0, ix));
+      } else {
+        // (texel ix + 1 through an offset the compiler cannot relate to ix's: it would merge
+        // the two loads into one wider load, which the range check zeroes as a whole at the
+        // row's start)
+        int ix1 = ix + 1;
+        asm volatile("" : "+v"(ix1));
+        rc[q][0] = wave_texel<PT>(r0, ix);
+        rc[q][1] = wave_texel<PT>(r1, ix);
+        rc[q][2] = wave_texel<PT>(r0, ix1);
+        rc[q][3] = wave_texel<PT>(r1, ix1);
+      }
+    }
+  };
+  auto store = [&](LT* w, int len, float wy) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      if (q * 64 >= len) break;
+      const int i0 = lane + q * 64;
+      const int i = i0 < len ? i0 : E;                     // past the window: the trash slot
+      if constexpr (!BIL) {
+        if constexpr (U8) w[i] = codes_to_half4(rn[q]);
+        else w[i] = rn[q];
+      } else {
+        const float4 t0 = lerp4(rc[q][0], rc[q][1], wy);
+        const float4 t1 = lerp4(rc[q][2], rc[q][3], wy);
+        w[2 * i] = t0;
+        w[2 * i + 1] = make_float4(t1.x - t0.x, t1.y - t0.y, t1.z - t0.z, t1.w - t0.w);
+      }
+    }
+  };
+
+  float Qr[G], Qg[G], Qb[G], Tr[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    Qr[j] = Qg[j] = Qb[j] = 0.0f;
+    Tr[j] = 1.0f;
+  }
+  int k, f0, len, iy;
+  float wy;
+  bool have = next(k, f0, len, iy, wy);
+  if (have) fetch(k, f0, len, iy);
+  int buf = 0;
+  while (have) {
+    store(win[buf], len, wy);                              // this plane's window (fetched before)
+    const int kc = k, f0c = f0;
+    const float bxr = pt[kc].x * xr;
+    const float* crow = ct + (size_t)kc * S + v0;
+    float Cv[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) Cv[j] = crow[j];
+    have = next(k, f0, len, iy, wy);
+    if (have) fetch(k, f0, len, iy);                       // the next one, in flight meanwhile
+    const char* wb = reinterpret_cast<const char*>(win[buf]) - (ptrdiff_t)f0c * (ptrdiff_t)(BIL ? 32 : (int)sizeof(LT));
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const float X = bxr + Cv[j];
+      const int ix = cvt_flr(X);
+      float4 s;
+      if (!BIL) {
+        s = lds_texel<LT>(wb + (ptrdiff_t)ix * (ptrdiff_t)sizeof(LT));
+      } else {
+        const float w = __builtin_amdgcn_fractf(X);
+        const char* e = wb + (ptrdiff_t)ix * 32;
+        const float4 t = *reinterpret_cast<const float4*>(e);
+        const float4 dd = *reinterpret_cast<const float4*>(e + 16);
+        s = make_float4(fmaf(w, dd.x, t.x), fmaf(w, dd.y, t.y), fmaf(w, dd.z, t.z), fmaf(w, dd.w, t.w));
+      }
+      const float w = U8 ? Tr[j] * (1.0f / 255.0f) : Tr[j];
+      Qr[j] = fmaf(w, s.x, Qr[j]);
+      Qg[j] = fmaf(w, s.y, Qg[j]);
+      Qb[j] = fmaf(w, s.z, Qb[j]);
+      Tr[j] = fmaf(-w, s.w, Tr[j]);
+    }
+    buf ^= 1;
+  }
+  if (x < a.nx) {
     OT* out = static_cast<OT*>(a.out);
 #pragma unroll
     for (int j = 0; j < G; ++j)
@@ -1093,8 +1367,8 @@ __global__ void zero_f32(float* p, int64_t n) {
 // (up to kRowThreads) for the fetch of the whole-row fallback, wp + 4 entries at kPrefetch
 // per thread (half for bilinear); the threads past the segment only fetch.
 int row_threads(const CompositeArgs& a, int* seg_out) {
-  const int nseg = (a.nx + kRowThreads - 1) / kRowThreads;
-  const int seg = (a.nx + nseg - 1) / nseg;
+  // segments of kRowThreads pixels (a multiple of 64: the one-wave kernel's segments nest)
+  const int seg = std::min(kRowThreads, (a.nx + 63) / 64 * 64);
   const int per_thread = a.interp == LF_BILINEAR ? kPrefetch / 2 : kPrefetch;
   const int need = std::min((a.wp + 4 + per_thread - 1) / per_thread, kRowThreads);
   if (seg_out) *seg_out = seg;
@@ -1160,29 +1434,39 @@ void launch_table(const CompositeArgs& a, float4* pt, float* ct, float2* pm, hip
 }
 
 template <typename PT, typename OT, bool BIL>
-hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const float* ct, hipStream_t s) {
+hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const float* ct, const float2* pm,
+                       hipStream_t s) {
   int seg;
   const int threads = row_threads(a, &seg);
   const int nseg = (a.nx + seg - 1) / seg;
   const size_t lds = (size_t)2 * kWinStride * 16;
   const int total = a.n_groups * nseg * a.ny;
   const dim3 grid((unsigned)(((total + 7) / 8) * 8)), block(threads);
+  const int nseg64 = (a.nx + 63) / 64;
+  const int total64 = a.n_groups * nseg64 * a.ny;
+  const dim3 grid64((unsigned)(((total64 + 7) / 8) * 8)), block64(64);
+  // the one-wave kernel over every 64-pixel segment, then the row kernel over every
+  // segment of seg pixels: each takes the 64-pixel segments that are its own
+  auto both = [&](auto wave, auto rows) {
+    hipLaunchKernelGGL(wave, grid64, block64, 0, s, a, nseg64, total64, pt, ct, pm);
+    hipLaunchKernelGGL(rows, grid, block, lds, s, a, seg, nseg, total, pt, ct, pm);
+  };
   switch (G) {
-    case 4: hipLaunchKernelGGL((composite_rows<PT, OT, 4, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
-    case 8: hipLaunchKernelGGL((composite_rows<PT, OT, 8, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
-    case 12: hipLaunchKernelGGL((composite_rows<PT, OT, 12, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
-    case 24: hipLaunchKernelGGL((composite_rows<PT, OT, 24, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
-    default: hipLaunchKernelGGL((composite_rows<PT, OT, 16, BIL>), grid, block, lds, s, a, seg, nseg, total, pt, ct); break;
+    case 4: both(composite_wave<PT, OT, 4, BIL>, composite_rows<PT, OT, 4, BIL>); break;
+    case 8: both(composite_wave<PT, OT, 8, BIL>, composite_rows<PT, OT, 8, BIL>); break;
+    case 12: both(composite_wave<PT, OT, 12, BIL>, composite_rows<PT, OT, 12, BIL>); break;
+    case 24: both(composite_wave<PT, OT, 24, BIL>, composite_rows<PT, OT, 24, BIL>); break;
+    default: both(composite_wave<PT, OT, 16, BIL>, composite_rows<PT, OT, 16, BIL>); break;
   }
   return hipGetLastError();
 }
 
 template <typename PT, typename OT>
 hipError_t dispatch_interp(const CompositeArgs& a, bool rows, int G, const float4* pt, const float* ct,
-                           hipStream_t s) {
+                           const float2* pm, hipStream_t s) {
   if (rows)
-    return a.interp == LF_BILINEAR ? launch_rows<PT, OT, true>(a, G, pt, ct, s)
-                                   : launch_rows<PT, OT, false>(a, G, pt, ct, s);
+    return a.interp == LF_BILINEAR ? launch_rows<PT, OT, true>(a, G, pt, ct, pm, s)
+                                   : launch_rows<PT, OT, false>(a, G, pt, ct, pm, s);
   const int64_t n = (int64_t)a.n_views * a.ny * a.nx;
   const dim3 grid((unsigned)((n + 255) / 256));
   if (a.interp == LF_BILINEAR)
@@ -1193,9 +1477,10 @@ hipError_t dispatch_interp(const CompositeArgs& a, bool rows, int G, const float
 }
 
 template <typename PT>
-hipError_t dispatch_out(const CompositeArgs& a, bool rows, int G, const float4* pt, const float* ct, hipStream_t s) {
-  return a.out_dtype == LF_F16 ? dispatch_interp<PT, __half>(a, rows, G, pt, ct, s)
-                               : dispatch_interp<PT, float>(a, rows, G, pt, ct, s);
+hipError_t dispatch_out(const CompositeArgs& a, bool rows, int G, const float4* pt, const float* ct,
+                        const float2* pm, hipStream_t s) {
+  return a.out_dtype == LF_F16 ? dispatch_interp<PT, __half>(a, rows, G, pt, ct, pm, s)
+                               : dispatch_interp<PT, float>(a, rows, G, pt, ct, pm, s);
 }
 
 template <typename PT, int G>
@@ -1273,14 +1558,14 @@ hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profil
   fill_groups(a, cls_end, nc, G);
   if (rows) {
     PhaseScope ps(prof, LF_PHASE_COEFF, s);
-    launch_table(a, pt, ct, pm, s);
+    launch_table(a, pt, ct, pm, s, G);                     // every view slot is sampled
   }
   PhaseScope ps(prof, LF_PHASE_COMPOSITE, s);
   switch (a.plane_dtype) {
-    case LF_F16: return dispatch_out<__half>(a, rows, G, pt, ct, s);
-    case LF_BF16: return dispatch_out<__hip_bfloat16>(a, rows, G, pt, ct, s);
-    case LF_U8: return dispatch_out<uint8_t>(a, rows, G, pt, ct, s);
-    default: return dispatch_out<float>(a, rows, G, pt, ct, s);
+    case LF_F16: return dispatch_out<__half>(a, rows, G, pt, ct, pm, s);
+    case LF_BF16: return dispatch_out<__hip_bfloat16>(a, rows, G, pt, ct, pm, s);
+    case LF_U8: return dispatch_out<uint8_t>(a, rows, G, pt, ct, pm, s);
+    default: return dispatch_out<float>(a, rows, G, pt, ct, pm, s);
   }
 }
 

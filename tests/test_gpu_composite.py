@@ -254,3 +254,27 @@ def test_composite_captured_after_larger_call():
         torch.cuda.synchronize()
         assert torch.equal(captured, eager), r
         assert np.abs(host(captured) - ref).max() <= 1e-4
+
+
+@pytest.mark.parametrize("group", ["8", "24"])
+@pytest.mark.parametrize("interp", ["nearest", "bilinear"])
+@pytest.mark.parametrize("pdt", ["f32", "f16", "bf16", "u8"])
+def test_composite_every_plane_form_at_row_edges(pdt, interp, group, monkeypatch):
+    """Every plane storage form through both row kernels, where the extreme views sample
+    the texels just outside the plane (columns -1 and wp: zero) and the first and last
+    columns: 1e-4 against the oracle's composite of the planes as stored (FP16 / BF16 values,
+    UNORM8 codes / 255), with view groups of 8 and 24."""
+    announce("composite form", pdt, interp, group)
+    monkeypatch.setenv("LF_COMPOSITE_GROUP", group)
+    cam, g, p, dx, dy = _setup(96, 80, 6, 10, 3, 14, phi_y=12.0)
+    if pdt == "u8":
+        codes = quantize.unorm8(p["rgba"])
+        planes, src = quantize.dequant(codes), dev(codes)
+    else:
+        src = dev(p["rgba"], TDT[pdt])
+        planes = host(src).astype(np.float64)
+    ref, _ = composite.composite(planes, p["depth"], cam, g, dx, dy, interp)
+    out = T.composite(ctx(), src, dev(p["depth"]), cam, T.views_of(dx, dy), interp)
+    err = np.abs(host(out) - ref).max()
+    print(pdt, interp, group, "max-abs", err)
+    assert err <= 1e-4
