@@ -734,25 +734,38 @@ __global__ __launch_bounds__(64) void composite_wave(CompositeArgs a, int nseg, 
     have = next(k, f0, len, iy, wy);
     if (have) fetch(k, f0, len, iy);                       // the next one, in flight meanwhile
     const char* wb = reinterpret_cast<const char*>(win[buf]) - (ptrdiff_t)f0c * (ptrdiff_t)(BIL ? 32 : (int)sizeof(LT));
+    // views in blocks of kSub: the block's LDS reads all in flight, then its blends
 #pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const float X = bxr + Cv[j];
-      const int ix = cvt_flr(X);
-      float4 s;
-      if (!BIL) {
-        s = lds_texel<LT>(wb + (ptrdiff_t)ix * (ptrdiff_t)sizeof(LT));
-      } else {
-        const float w = __builtin_amdgcn_fractf(X);
-        const char* e = wb + (ptrdiff_t)ix * 32;
-        const float4 t = *reinterpret_cast<const float4*>(e);
-        const float4 dd = *reinterpret_cast<const float4*>(e + 16);
-        s = make_float4(fmaf(w, dd.x, t.x), fmaf(w, dd.y, t.y), fmaf(w, dd.z, t.z), fmaf(w, dd.w, t.w));
+    for (int j0 = 0; j0 < G; j0 += kSub) {
+      float4 sv[kSub];
+#pragma unroll
+      for (int jj = 0; jj < kSub; ++jj) {
+        const float X = bxr + Cv[j0 + jj];
+        const int ix = cvt_flr(X);
+        if (!BIL) {
+          sv[jj] = lds_texel<LT>(wb + (ptrdiff_t)ix * (ptrdiff_t)sizeof(LT));
+        } else {
+          const float w = __builtin_amdgcn_fractf(X);
+          const char* e = wb + (ptrdiff_t)ix * 32;
+          const float4 t = *reinterpret_cast<const float4*>(e);
+          const float4 dd = *reinterpret_cast<const float4*>(e + 16);
+          sv[jj] = make_float4(fmaf(w, dd.x, t.x), fmaf(w, dd.y, t.y), fmaf(w, dd.z, t.z), fmaf(w, dd.w, t.w));
+        }
       }
-      const float w = U8 ? Tr[j] * (1.0f / 255.0f) : Tr[j];
-      Qr[j] = fmaf(w, s.x, Qr[j]);
-      Qg[j] = fmaf(w, s.y, Qg[j]);
-      Qb[j] = fmaf(w, s.z, Qb[j]);
-      Tr[j] = fmaf(-w, s.w, Tr[j]);
+#pragma unroll
+      for (int jj = 0; jj < kSub; ++jj) {
+        const int j = j0 + jj;
+        const float w = U8 ? Tr[j] * (1.0f / 255.0f) : Tr[j];
+        Qr[j] = fmaf(w, sv[jj].x, Qr[j]);
+        Qg[j] = fmaf(w, sv[jj].y, Qg[j]);
+        Qb[j] = fmaf(w, sv[jj].z, Qb[j]);
+        Tr[j] = fmaf(-w, sv[jj].w, Tr[j]);
+      }
+      // (the block's blends before the next block's reads: bounds the live sample registers)
+#pragma unroll
+      for (int jj = 0; jj < kSub; ++jj)
+        asm volatile("" ::"v"(Qr[j0 + jj]), "v"(Qg[j0 + jj]), "v"(Qb[j0 + jj]), "v"(Tr[j0 + jj]) : "memory");
+      __builtin_amdgcn_sched_barrier(0);
     }
     buf ^= 1;
   }
