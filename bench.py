@@ -41,8 +41,8 @@ COPY_WRITE_SCALE = 262144.0 / 262144.0
 MEASURED_TRAFFIC = {
     "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133397, write_kib=286992,
                      digest="11e3fa5c8720dcd9"),
-    "composite_rows": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=89674, write_kib=184320,
-                           digest="d974ba25813192f3"),
+    "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=88110, write_kib=184320,
+                           digest="6f2c8f98fa87961a"),
 }
 
 
@@ -65,6 +65,24 @@ def measured_traffic(name):
     if t is None or kernel_digest(t["src"], name) != t["digest"]:
         return None
     return int(round((t["fetch_kib"] * COPY_FETCH_SCALE + t["write_kib"] * COPY_WRITE_SCALE) * 1024))
+# VALU wave-instructions per wave-sample from rocprofv3 --pmc SQ_INSTS_VALU (per dispatch, divided
+# by samples / 64) of `bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-bilinear --forms f32
+# --extra ""`, digest-gated like the traffic
+MEASURED_VALU = {
+    "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", valu_per_wave_sample=8.45,
+                           digest="6f2c8f98fa87961a"),
+}
+
+
+def measured_valu(name):
+    t = MEASURED_VALU.get(name)
+    if t is None or kernel_digest(t["src"], name) != t["digest"]:
+        return None
+    return t["valu_per_wave_sample"]
+
+
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: float32 lane-ops/s (no packed math)
 FP32_PEAK_TFLOPS = 2 * VALU_LANE_OPS / 1e12   # one FMA = 2 flops per lane-op -> 78.6
 
@@ -425,8 +443,8 @@ def main():
         comp_roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
                          unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), copy_peak=round(copy_gbs, 1),
                          frac_of_copy=round(gbs / copy_gbs, 4),
-                         traffic=measured_traffic("composite_rows") if form == "f32" and interp == "nearest" else None,
-                         kernel="composite_rows", bytes_per_launch=comp_bytes,
+                         traffic=measured_traffic("composite_wave") if form == "f32" and interp == "nearest" else None,
+                         kernel="composite_wave", bytes_per_launch=comp_bytes,
                          avg_ms=round(comp_ms, 4))
         # splat: algorithmic work = (entry, texel) evaluations of the tile lists; one evaluation is
         # about 8 FMA-equivalent lane-ops on the included texels (quadratic form, exp2, blend)
@@ -437,13 +455,16 @@ def main():
                           frac=round(evals * 16 / (splat_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
                           traffic=measured_traffic("splat_gs") if form == "f32" else None, kernel="splat_gs",
                           flops_per_launch=evals * 16, avg_ms=round(splat_ms, 4))
-        # the composite's instruction-issue view: its nearest-sampling loop issues 8 VALU per
-        # sample (coordinate add, clamp, floor, LDS address, 4 blend FMA) in the compiled kernel
+        # the composite's instruction-issue view: VALU wave-instructions per wave-sample (64
+        # samples) from the rocprofv3 SQ_INSTS_VALU counter of the nearest FP32 composite kernel
+        # (null once that kernel has changed), and the share of the SIMDs' VALU issue slots they
+        # take (a wave64 VALU instruction occupies a SIMD for 4 cycles)
         samples = V * cam.ny * cam.nx * K
-        comp_valu = dict(bound="alu", achieved=round(samples * 8 / (comp_ms * 1e-3) / 1e12, 3),
-                         peak=round(VALU_LANE_OPS / 1e12, 1), unit="T VALU lane-instructions/s",
-                         frac=round(samples * 8 / (comp_ms * 1e-3) / VALU_LANE_OPS, 4), kernel="composite_rows",
-                         samples_per_launch=samples, valu_per_sample=8)
+        vpw = measured_valu("composite_wave") if form == "f32" and interp == "nearest" else None
+        comp_valu = dict(bound="alu", kernel="composite_wave", samples_per_launch=samples,
+                         valu_per_wave_sample=vpw,
+                         issue_frac=(round(samples / 64 * vpw * 4 / (comp_ms * 1e-3 * SIMDS * CLOCK_HZ), 4)
+                                     if vpw else None))
         return dict(form=form, views="f32" if form == "f32" else "f16", interp=interp, ms_per_step=ms,
                     views_per_s=V / (ms * 1e-3), phases_ms=phases,
                     composite_roofline=comp_roof, splat_roofline=splat_roof, composite_valu=comp_valu,
