@@ -40,29 +40,35 @@ COPY_FETCH_SCALE = 262144.0 / 131084.0
 COPY_WRITE_SCALE = 262144.0 / 262144.0
 MEASURED_TRAFFIC = {
     "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133397, write_kib=286992,
-                     digest="11e3fa5c8720dcd9"),
+                     helpers=("splat_stage", "splat_item", "xcd_item"), digest="11e3fa5c8720dcd9"),
     "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=88110, write_kib=184320,
-                           digest="6f2c8f98fa87961a"),
+                           helpers=("composite_wave_tile",), digest="6f2c8f98fa87961a"),
 }
 
 
-def kernel_digest(path, name):
-    """sha1 of a kernel's definition: from its signature to the closing brace in column 0."""
+def kernel_digest(path, name, helpers=()):
+    """sha1 of a kernel's definition (from its signature to the closing brace in column 0),
+    preceded by the definitions of the device functions it is built from."""
     import hashlib
     import re
 
     text = open(os.path.join(ROOT, path)).read()
-    m = re.search(r"^(template <[^\n]*>\n)?__global__[^\n]*\b" + re.escape(name) + r"\(", text, re.M)
-    if not m:
-        return None
-    end = text.find("\n}\n", m.start())
-    return hashlib.sha1(text[m.start():end].encode()).hexdigest()[:16] if end > 0 else None
+    parts = []
+    for fn, kind in [(h, "__device__") for h in helpers] + [(name, "__global__")]:
+        m = re.search(r"^(template <[^\n]*>\n)?" + kind + r"[^\n]*\b" + re.escape(fn) + r"\(", text, re.M)
+        if not m:
+            return None
+        end = text.find("\n}\n", m.start())
+        if end < 0:
+            return None
+        parts.append(text[m.start():end])
+    return hashlib.sha1("".join(parts).encode()).hexdigest()[:16]
 
 
 def measured_traffic(name):
     """Counter-measured HBM bytes per launch of `name`, or None if the kernel changed since."""
     t = MEASURED_TRAFFIC.get(name)
-    if t is None or kernel_digest(t["src"], name) != t["digest"]:
+    if t is None or kernel_digest(t["src"], name, t.get("helpers", ())) != t["digest"]:
         return None
     return int(round((t["fetch_kib"] * COPY_FETCH_SCALE + t["write_kib"] * COPY_WRITE_SCALE) * 1024))
 # VALU wave-instructions per wave-sample from rocprofv3 --pmc SQ_INSTS_VALU (per dispatch, divided
@@ -70,13 +76,13 @@ def measured_traffic(name):
 # --extra ""`, digest-gated like the traffic
 MEASURED_VALU = {
     "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", valu_per_wave_sample=8.45,
-                           digest="6f2c8f98fa87961a"),
+                           helpers=("composite_wave_tile",), digest="6f2c8f98fa87961a"),
 }
 
 
 def measured_valu(name):
     t = MEASURED_VALU.get(name)
-    if t is None or kernel_digest(t["src"], name) != t["digest"]:
+    if t is None or kernel_digest(t["src"], name, t.get("helpers", ())) != t["digest"]:
         return None
     return t["valu_per_wave_sample"]
 
@@ -331,8 +337,10 @@ def extra_sh500k(ctx, steps, warmup):
 def extra_batch8(ctx, steps, warmup):
     """Eight clustered-Gaussian scenes of uneven size in one batch (seeds 30+i): (N, res,
     N_chunk, views) from 50k / 256^2 / 64 / 9 up to 2M / 768^2 / 128 / 45, FP16 planes and
-    views, autotuned view groups, one HIP graph replay per step; beside it the same scenes
-    rendered one after another with the single-scene entry points."""
+    views, autotuned view groups and row tiles, one HIP graph replay per step, in the
+    work-list form (one splat, merge and composite launch over every scene's work items;
+    `ms_per_step`) and the per-scene stream form; beside them the same scenes rendered one
+    after another with the single-scene entry points."""
     import math
 
     import numpy as np
@@ -348,12 +356,16 @@ def extra_batch8(ctx, steps, warmup):
         vl = L.lf_quilt_views(L.make_camera(cam), V, 1)
         scenes.append(dict(scene=T.to_device(scenegen.cluster_scene(n, seed=30 + i)), cam=cam, n_chunk=K, views=vl,
                            plane_dtype=torch.float16, out_dtype=torch.float16))
-    b = T.Batch(ctx, scenes, graph=True, autotune=True)
-    groups = b.groups()
+    b = T.Batch(ctx, scenes, graph=True, autotune=True, worklist=True)
+    groups, tiles = b.groups(), b.tiles()
     ms, _ = _timed(b.run, warmup, steps, ctx, L)
-    for o in b.outs:
-        T.build_stats(ctx, o["workspace"], check=True)
+    b.stats(check=True)
     total_views = sum(len(sc["views"]) for sc in scenes)
+    # the stream form over the same scenes and buffers (the tuned choices come from the cache)
+    bs = T.Batch(ctx, scenes, graph=True, autotune=True, worklist=False)
+    ms_streams, _ = _timed(bs.run, warmup, steps, ctx, L)
+    bs.stats(check=True)
+    bs.close()
 
     def sequential():
         for sc, o in zip(scenes, b.outs):
@@ -365,7 +377,8 @@ def extra_batch8(ctx, steps, warmup):
     return dict(workload="batch8: 8 scenes, 50k-2M Gaussians, 256^2-768^2, N_chunk 64/128/512, 9-100 views, "
                          "FP16 planes and views",
                 views_per_s=round(total_views / (ms * 1e-3), 1), ms_per_step=round(ms, 4), total_views=total_views,
-                sequential_ms=round(ms_seq, 4), autotuned_view_groups=groups)
+                streams_ms=round(ms_streams, 4), sequential_ms=round(ms_seq, 4), autotuned_view_groups=groups,
+                autotuned_row_tiles=tiles)
 
 
 def main():
@@ -446,15 +459,22 @@ def main():
                          traffic=measured_traffic("composite_wave") if form == "f32" and interp == "nearest" else None,
                          kernel="composite_wave", bytes_per_launch=comp_bytes,
                          avg_ms=round(comp_ms, 4))
-        # splat: algorithmic work = (entry, texel) evaluations of the tile lists; one evaluation is
-        # about 8 FMA-equivalent lane-ops on the included texels (quadratic form, exp2, blend)
+        # splat: algorithmic work = the support pairs, (Gaussian, texel) pairs with o G >= 1/255,
+        # counted on the device over the frame's tile lists (outside the timed region), at 16
+        # flop-equivalent slots each (Taylor-form quadratic 5 FMA, exp2, min, select, blend 4
+        # FMA + T update); beside them the (entry, texel) evaluations the kernel performs and
+        # the texels of the whole listed tiles, per support pair
         splat_ms = phases["splat"]
-        evals = info.entries_needed * 256
-        splat_roof = dict(bound="alu", achieved=round(evals * 16 / (splat_ms * 1e-3) / 1e12, 3),
+        work = T.splat_work(ctx, ds, cam, K, ws)
+        pairs = work["support_pairs"]
+        splat_roof = dict(bound="alu", achieved=round(pairs * 16 / (splat_ms * 1e-3) / 1e12, 3),
                           peak=round(FP32_PEAK_TFLOPS, 1), unit="TFLOP/s",
-                          frac=round(evals * 16 / (splat_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+                          frac=round(pairs * 16 / (splat_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
                           traffic=measured_traffic("splat_gs") if form == "f32" else None, kernel="splat_gs",
-                          flops_per_launch=evals * 16, avg_ms=round(splat_ms, 4))
+                          support_pairs=pairs, flops_per_launch=pairs * 16,
+                          evaluations_per_pair=round(work["evaluations"] / max(pairs, 1), 3),
+                          list_texels_per_pair=round(work["list_texels"] / max(pairs, 1), 3),
+                          avg_ms=round(splat_ms, 4))
         # the composite's instruction-issue view: VALU wave-instructions per wave-sample (64
         # samples) from the rocprofv3 SQ_INSTS_VALU counter of the nearest FP32 composite kernel
         # (null once that kernel has changed), and the share of the SIMDs' VALU issue slots they

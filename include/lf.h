@@ -201,6 +201,20 @@ lf_status lf_build_tile_lists(lf_ctx* ctx, const lf_field* field, const lf_camer
                               const void* workspace, size_t workspace_bytes, int32_t* tile, int32_t* tiles_x,
                               int32_t* tiles_y, int64_t* bucket_start, int32_t* entries, void* stream);
 
+/* The splat's work in the last lf_build_mpi of a Gaussian field on `workspace` (Sec. 4.4,
+ * Alg. 1 "Rasterize"; the blend of Eq. 7 within a chunk), counted with the splat's own
+ * work items and float32 decisions.  Diagnostic entry point for measurement.  field, cam,
+ * n_chunk: those of that build.  counts: device int64 [3], overwritten:
+ *   counts[0] = support pairs: (Gaussian, plane texel) pairs with o G >= 1/255;
+ *   counts[1] = (list entry, texel) evaluations the splat performs: every entry of a
+ *               tile's list against the 64 texels of each 8x8 quadrant its 1/255 ellipse
+ *               reaches;
+ *   counts[2] = list entries x 256 texels (the whole tiles the lists name).
+ * A build that overflowed its capacity counts zero.  Voxel fields: LF_ERR_UNSUPPORTED.
+ * Enqueued on `stream`; needs the tile lists the build left in the workspace.            */
+lf_status lf_build_splat_work(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                              const void* workspace, size_t workspace_bytes, int64_t* counts, void* stream);
+
 /* The conventional per-view render that the light field approximates (the baseline of
  * Sec. 5.1, Table 1): every Gaussian of `field` in one depth-sorted chunk, splatted from
  * the camera of view `view` (Eq. 5: at (dx, dy, 0) in base-camera coordinates, looking
@@ -322,13 +336,23 @@ lf_status lf_sh_colours(lf_ctx* ctx, const float* means, const float* sh, int32_
 
 /* ---------------------------------------------------------------------------------------
  * Batches.  Several scenes (fields, cameras, plane counts, view lists) rendered by one
- * call.  Each scene's build and composite go to a stream of their own, forked from and
- * joined back into the caller's stream, so small scenes run side by side on the GPU.
+ * call.  By default each scene's build and composite go to a stream of their own, forked
+ * from and joined back into the caller's stream, so small scenes run side by side on the
+ * GPU.  With LF_BATCH_WORKLIST the batch runs phase by phase instead: each scene's cull,
+ * depth sort, chunks and tile lists (Alg. 1 steps 1-4) on its own stream, then one splat
+ * launch and one merge launch over the work items (tile, chunk segments) of every scene
+ * with planes of one dtype, then one composite launch over the row tiles of every scene
+ * with one kernel key (plane and view dtypes, sampling, view-group size); each phase's
+ * kernel walks the (scene, item) list.  Voxel and empty fields build on their own streams,
+ * and scenes that need the per-pixel composite or 256-pixel row tiles composite alone.
  * With LF_BATCH_GRAPH the first lf_batch_run captures the whole batch into a HIP graph and
  * every run (the first included) replays it with one launch.  With LF_BATCH_AUTOTUNE,
  * lf_batch_create times the composite of every scene with each view-group size (4, 8,
- * 12, 16 views per work-group) and keeps the fastest (it builds each scene once and
- * synchronises the device).
+ * 12, 16 views per work-group) and row-tile width (64-pixel one-wave tiles, or 256-pixel
+ * row-kernel tiles) and keeps the fastest (it builds each scene once and synchronises the
+ * device); the choice is cached per process for the scene's camera, plane count and
+ * dtype, views, sampling and output dtype, so a later batch of the same shapes is not
+ * timed again.
  * ------------------------------------------------------------------------------------- */
 typedef struct {
   lf_field field;           /* device field, as for lf_build_mpi                          */
@@ -346,7 +370,7 @@ typedef struct {
   size_t workspace_bytes;
 } lf_batch_item;
 
-enum { LF_BATCH_GRAPH = 1, LF_BATCH_AUTOTUNE = 2 };
+enum { LF_BATCH_GRAPH = 1, LF_BATCH_AUTOTUNE = 2, LF_BATCH_WORKLIST = 4 };
 
 typedef struct lf_batch lf_batch;
 
@@ -371,6 +395,10 @@ lf_status lf_batch_stats(lf_batch* batch, lf_build_info* out, int32_t* n_failed,
 
 /* The view-group size the composite of scene `item` uses (autotuned, or 0 for default). */
 lf_status lf_batch_group(const lf_batch* batch, int32_t item, int32_t* group);
+
+/* The row-tile width the composite of scene `item` uses (64 or 256 autotuned, or 0 for
+ * default: 64-pixel one-wave tiles where the windows fit).                               */
+lf_status lf_batch_tile(const lf_batch* batch, int32_t item, int32_t* tile);
 
 void lf_batch_destroy(lf_batch* batch);
 

@@ -115,3 +115,33 @@ def blend_texels(proj: Projected, px: np.ndarray, py: np.ndarray, eps=None):
         out[s:s + step, nc] = 1.0 - Tin[-1] * (1.0 - alpha[-1])
         amb[s:s + step] = np.any(np.abs(ln_a - LN_ALPHA_MIN) <= eps[:, None], axis=0)
     return out, amb
+
+
+def support_pairs(proj: Projected, height: int, width: int, eps=None):
+    """The support pairs of one chunk: the number of (Gaussian, texel) pairs of the
+    height x width plane with o G >= 1/255 (the texels the blend above gives a non-zero
+    alpha), and the number of those pairs within eps_g of the threshold, where a float32
+    decision may go either way (both returned as ints)."""
+    n = proj.mean2d.shape[0]
+    if n == 0:
+        return 0, 0
+    if eps is None:
+        eps = ambiguity_eps(proj.cov2d)
+    hx, hy, ok = support_halfwidth(proj, eps)
+    inside, near = 0, 0
+    for i in range(n):
+        if not ok[i]:
+            continue
+        mx, my = proj.mean2d[i]
+        x0, x1 = max(0, math.ceil(mx - hx[i])), min(width - 1, math.floor(mx + hx[i]))
+        y0, y1 = max(0, math.ceil(my - hy[i])), min(height - 1, math.floor(my + hy[i]))
+        if x0 > x1 or y0 > y1:
+            continue
+        dx = (np.arange(x0, x1 + 1, dtype=np.float64) - mx)[None, :]
+        dy = (np.arange(y0, y1 + 1, dtype=np.float64) - my)[:, None]
+        Q = proj.conic[i]
+        quad = Q[0, 0] * dx * dx + (Q[0, 1] + Q[1, 0]) * dx * dy + Q[1, 1] * dy * dy
+        ln_a = math.log(proj.opacity[i]) - 0.5 * quad
+        inside += int((ln_a >= LN_ALPHA_MIN).sum())
+        near += int((np.abs(ln_a - LN_ALPHA_MIN) <= eps[i]).sum())
+    return inside, near

@@ -28,13 +28,14 @@ EXPORTS = [
     "lf_version", "lf_last_error", "lf_create", "lf_destroy", "lf_geometry", "lf_quilt_views",
     "lf_build_mpi_workspace", "lf_build_mpi", "lf_build_stats", "lf_composite", "lf_composite_backward",
     "lf_build_mpi_backward", "lf_plane_coeffs", "lf_batch_create", "lf_batch_run", "lf_batch_stats", "lf_batch_group",
+    "lf_batch_tile",
     "lf_batch_destroy", "lf_profile_enable", "lf_profile_read", "lf_render_view_workspace", "lf_render_view",
     "lf_sh_texel_floats", "lf_build_mpi_sh", "lf_composite_sh", "lf_sh_colours", "lf_build_tile_lists",
-    "lf_composite_noalloc",
+    "lf_build_splat_work", "lf_composite_noalloc",
 ]
 LF_COMPOSITE_SCRATCH_BYTES = 4 << 20
 LF_MAX_SH_DEGREE = 3
-LF_BATCH_GRAPH, LF_BATCH_AUTOTUNE = 1, 2
+LF_BATCH_GRAPH, LF_BATCH_AUTOTUNE, LF_BATCH_WORKLIST = 1, 2, 4
 PHASES = ["preprocess", "sort", "bin", "splat", "merge", "filter", "coeff", "composite", "composite_bwd",
           "build_bwd"]
 
@@ -129,6 +130,8 @@ def load():
         "lf_build_stats": ([P, P, C.c_size_t, C.POINTER(lf_build_info), P], C.c_int),
         "lf_build_tile_lists": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.c_int32, P, C.c_size_t,
                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), P, P, P], C.c_int),
+        "lf_build_splat_work": ([P, C.POINTER(lf_field), C.POINTER(lf_camera), C.c_int32, P, C.c_size_t, P, P],
+                                C.c_int),
         "lf_composite": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32, C.c_int32,
                           C.c_int32, P, P], C.c_int),
         "lf_composite_noalloc": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
@@ -141,6 +144,7 @@ def load():
         "lf_batch_run": ([P, P], C.c_int),
         "lf_batch_stats": ([P, C.POINTER(lf_build_info), C.POINTER(C.c_int32), P], C.c_int),
         "lf_batch_group": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+        "lf_batch_tile": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
         "lf_batch_destroy": ([P], None),
         "lf_plane_coeffs": ([P, C.POINTER(lf_mpi), C.POINTER(lf_camera), C.POINTER(lf_view), C.c_int32,
                              P, P, P, P, P, P, P], C.c_int),
@@ -311,6 +315,13 @@ def lf_build_tile_lists(ctx: int, field: lf_field, cam: lf_camera, n_chunk: int,
     return t.value, tx.value, ty.value
 
 
+def lf_build_splat_work(ctx: int, field: lf_field, cam: lf_camera, n_chunk: int, workspace: int,
+                        workspace_bytes: int, counts: int, stream: int = 0) -> None:
+    """Fills the device int64[3] counts (support pairs, evaluations, list entries x 256)."""
+    _check(load().lf_build_splat_work(ctx, C.byref(field), C.byref(cam), n_chunk, workspace, workspace_bytes,
+                                      counts, stream), "lf_build_splat_work")
+
+
 def lf_composite(ctx: int, mpi: lf_mpi, cam: lf_camera, views, interp: int, out_dtype: int, out: int,
                  stream: int = 0) -> None:
     _check(load().lf_composite(ctx, C.byref(mpi), C.byref(cam), views, len(views), interp, out_dtype, out, stream),
@@ -366,6 +377,12 @@ def lf_batch_group(batch: int, item: int) -> int:
     g = C.c_int32()
     _check(load().lf_batch_group(batch, item, C.byref(g)), "lf_batch_group")
     return g.value
+
+
+def lf_batch_tile(batch: int, item: int) -> int:
+    t = C.c_int32()
+    _check(load().lf_batch_tile(batch, item, C.byref(t)), "lf_batch_tile")
+    return t.value
 
 
 def lf_batch_destroy(batch: int) -> None:

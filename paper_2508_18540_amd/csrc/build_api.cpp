@@ -1,5 +1,6 @@
 // MPI build entry points (Alg. 1 steps 1-5): validation, workspace layout, launches.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -9,6 +10,14 @@
 namespace lf {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int splat_item_shift() {
+  if (const char* e = getenv("LF_SPLAT_ITEM_SHIFT")) {
+    const int v = atoi(e);
+    if (v >= 0 && v <= 24) return v;
+  }
+  return 6;
+}
 
 BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t cap) {
   BuildLayout L;
@@ -193,6 +202,7 @@ void build_args(BuildArgs& a, const BuildLayout& L, const lf_field* field, const
   a.items = reinterpret_cast<uint2*>(w + L.o_items);
   a.partial = reinterpret_cast<float4*>(w + L.o_partial);
   a.max_items = L.max_items;
+  a.item_shift = splat_item_shift();
   a.stage = reinterpret_cast<float4*>(w + L.o_stage);
   if (field->kind == LF_VOXELS) {
     a.ijk = field->ijk;
@@ -236,11 +246,11 @@ extern "C" lf_status lf_build_mpi_workspace(const lf_field* field, const lf_came
 namespace lf {
 namespace {
 
-// lf_build_mpi, and with sh / sh_coef > 0 the SH planes of lf_build_mpi_sh (mpi then
-// describes float32 planes of sh_texel_floats(sh_coef) floats per texel).
-lf_status build_mpi_impl(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk, int32_t binning,
-                         const float* inv_depth_range, lf_mpi* mpi, const float* sh, int32_t sh_coef, void* workspace,
-                         size_t workspace_bytes, void* stream) {
+}  // namespace
+
+lf_status build_prepare(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk, int32_t binning,
+                        const float* inv_depth_range, const lf_mpi* mpi, const float* sh, int32_t sh_coef,
+                        void* workspace, size_t workspace_bytes, hipStream_t st, BuildArgs* out_a, BuildLayout* out_L) {
   Geom g;
   lf_status s = check_common(field, cam, n_chunk, &g);
   if (s != LF_OK) return s;
@@ -273,7 +283,6 @@ lf_status build_mpi_impl(lf_ctx* ctx, const lf_field* field, const lf_camera* ca
   if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  hipStream_t st = (hipStream_t)stream;
 
   const BuildLayout L = build_layout(field->kind, n, n_chunk, g.wp, g.hp, cap);
   if (L.tile_bits + L.chunk_bits > 32)
@@ -291,7 +300,26 @@ lf_status build_mpi_impl(lf_ctx* ctx, const lf_field* field, const lf_camera* ca
     if ((e = upload_table(a.edges, edges.data(), n_chunk, st)) != hipSuccess) return hip_fail(e, "table upload");
     if ((e = upload_table(a.dtab, dtab.data(), n_chunk, st)) != hipSuccess) return hip_fail(e, "table upload");
   }
-  if ((e = build_planes(a, L, st, &ctx->prof)) != hipSuccess) return hip_fail(e, "build launch");
+  *out_a = a;
+  *out_L = L;
+  return LF_OK;
+}
+
+namespace {
+
+// lf_build_mpi, and with sh / sh_coef > 0 the SH planes of lf_build_mpi_sh (mpi then
+// describes float32 planes of sh_texel_floats(sh_coef) floats per texel).
+lf_status build_mpi_impl(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk, int32_t binning,
+                         const float* inv_depth_range, lf_mpi* mpi, const float* sh, int32_t sh_coef, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+  BuildArgs a;
+  BuildLayout L;
+  hipStream_t st = (hipStream_t)stream;
+  lf_status s = build_prepare(ctx, field, cam, n_chunk, binning, inv_depth_range, mpi, sh, sh_coef, workspace,
+                              workspace_bytes, st, &a, &L);
+  if (s != LF_OK) return s;
+  const hipError_t e = build_planes(a, L, st, &ctx->prof);
+  if (e != hipSuccess) return hip_fail(e, "build launch");
   return LF_OK;
 }
 
@@ -437,6 +465,30 @@ extern "C" lf_status lf_build_tile_lists(lf_ctx* ctx, const lf_field* field, con
   if (radix_passes(L.tile_bits, tile_digit_bits()) & 1) a.evals = a.evals_alt;
   if ((e = tile_lists_launch(a, L, bucket_start, entries, (hipStream_t)stream)) != hipSuccess)
     return hip_fail(e, "tile list copy");
+  return LF_OK;
+}
+
+extern "C" lf_status lf_build_splat_work(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
+                                        const void* workspace, size_t workspace_bytes, int64_t* counts, void* stream) {
+  Geom g;
+  lf_status s = check_common(field, cam, n_chunk, &g);
+  if (s != LF_OK) return s;
+  if (field->kind != LF_GAUSSIANS) return fail(LF_ERR_UNSUPPORTED, "the splat work count covers Gaussian fields only");
+  if (!counts) return fail(LF_ERR_INVALID_ARG, "counts is NULL");
+  if (!workspace) return fail(LF_ERR_INVALID_ARG, "workspace is NULL");
+  const int64_t cap = capacity_of(field->kind, field->n, n_chunk, g.wp, g.hp, workspace_bytes);
+  if (cap < 1) return fail(LF_ERR_CAPACITY, "workspace of %zu bytes is too small for this field", workspace_bytes);
+  const BuildLayout L = build_layout(field->kind, field->n, n_chunk, g.wp, g.hp, cap);
+  if (L.tile_bits + L.chunk_bits > 32)
+    return fail(LF_ERR_INVALID_ARG, "%d tiles x %d chunks do not fit a 32-bit (tile, chunk) key", L.n_tiles, n_chunk);
+  if (!ctx) return fail(LF_ERR_INVALID_ARG, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  BuildArgs a;
+  lf_mpi none{LF_F32, n_chunk, g.hp, g.wp, nullptr, nullptr, nullptr, nullptr};
+  build_args(a, L, field, cam, g, n_chunk, LF_BIN_QUANTILE, &none, const_cast<void*>(workspace), cap);
+  if (radix_passes(L.tile_bits, tile_digit_bits()) & 1) a.evals = a.evals_alt;
+  if ((e = splat_work_launch(a, L, counts, (hipStream_t)stream)) != hipSuccess) return hip_fail(e, "splat work count");
   return LF_OK;
 }
 

@@ -420,46 +420,58 @@ __device__ __forceinline__ uint32_t reached_quadrants(const GRec& g, uint32_t bo
   return qm;
 }
 
-template <typename PT>
-__global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) {
-  // entry e: (ca, cb, cc, A), (B, C, r, g), (b, -, -, -) with A, B, C the value and gradient
-  // of log2(o G) at the tile centre; per quadrant, the byte offsets 16 e of the entries
-  // reaching it, in order
-  __shared__ float4 s_p[kSegment], s_q[kSegment], s_c[kSegment];
-  __shared__ uint32_t s_list[4][kSegment];
-  __shared__ int s_cnt[4][4];                              // [quadrant][loading wave]
-  const uint32_t item = blockIdx.x;
-  if (item >= a.item_start[n_buckets]) return;             // beyond this frame's work list
+// LDS of one splat work item: entry e's (ca, cb, cc, A), (B, C, r, g), (b, -, -, -) with A,
+// B, C the value and gradient of log2(o G) at the tile centre; per quadrant, the byte
+// offsets 16 e of the entries reaching it, in order.
+struct SplatLds {
+  float4 p[kSegment], q[kSegment], c[kSegment];
+  uint32_t list[4][kSegment];
+  int cnt[4][4];                                           // [quadrant][loading wave]
+};
+
+// Where a work item's texels are: its bucket, segment, tile origin and this thread's texel.
+struct SplatItem {
+  int64_t bidx;
+  uint32_t seg, nseg;
+  int k, ox, oy, px, py;
+  float du, dv;                                            // texel offset from the tile centre
+};
+
+// Stage work item `item` of a build: every thread holds one entry of the segment (its mean
+// relative to the tile origin as a double-float difference, so a texel offset is one
+// exact-enough add), and the work-group compacts, per 8x8 quadrant, the entries whose 1/255
+// ellipse reaches it (with a margin far above the float32 error of q, so no texel is
+// dropped), in order.  Returns the length of this wave's quadrant list.
+__device__ __forceinline__ int splat_stage(const BuildArgs& a, uint32_t item, SplatLds& sm, SplatItem& si) {
   const uint2 it = a.items[item];
   const int64_t bidx = it.x;
-  const int tile = (int)(bidx / a.K), k = (int)(bidx % a.K);
+  const int tile = (int)(bidx / a.K);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int ox = (tile % a.ntx) << kTileShift, oy = (tile / a.ntx) << kTileShift;
+  si.bidx = bidx;
+  si.seg = it.y;
+  si.k = (int)(bidx % a.K);
+  si.ox = (tile % a.ntx) << kTileShift;
+  si.oy = (tile / a.ntx) << kTileShift;
   const int lxi = ((wave & 1) << 3) + (lane & 7), lyi = ((wave >> 1) << 3) + (lane >> 3);
-  const int px = ox + lxi, py = oy + lyi;
-  // texel offset from the tile centre, and its quadratic monomials
-  const float du = (float)lxi - 7.5f, dv = (float)lyi - 7.5f;
-  const float duu = du * du, duv = du * dv, dvv = dv * dv;
+  si.px = si.ox + lxi;
+  si.py = si.oy + lyi;
+  si.du = (float)lxi - 7.5f;
+  si.dv = (float)lyi - 7.5f;
   const bool ok = a.hdr->overflow == 0;
   const uint32_t bb0 = a.bucket[bidx], bb1 = a.bucket[bidx + 1];
-  const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
+  si.nseg = a.item_start[bidx + 1] - a.item_start[bidx];
   const uint32_t b0 = bb0 + it.y * kSegment;
   const int n = ok ? (int)(min(bb1, b0 + kSegment) - b0) : 0;
-  // stage: thread t holds entry t of the segment.  Its mean is kept relative to the tile
-  // origin (double-float difference, so a texel offset is one exact-enough add), and the
-  // 8x8 blocks its support box touches are kept only if the ellipse o G >= 1/255 reaches
-  // them (with a margin far above the float32 error of q, so no texel is dropped).
   uint32_t qm = 0;
   if (tid < n) {
     const uint32_t ent = a.evals[b0 + tid];
     const GRec& g = a.rec[min(ent & 0x0fffffffu, (uint32_t)a.n - 1u)];
-    const TileTaylor tt = tile_taylor(g, ox, oy);
-    const float sx = tt.sx, sy = tt.sy;
-    s_p[tid] = make_float4(g.ca, g.cb, g.cc, tt.A);
-    s_q[tid] = make_float4(tt.B, tt.C, g.rgb[0], g.rgb[1]);
-    s_c[tid] = make_float4(g.rgb[2], 0.0f, 0.0f, 0.0f);
-    qm = reached_quadrants(g, ent >> 28, sx, sy);
+    const TileTaylor tt = tile_taylor(g, si.ox, si.oy);
+    sm.p[tid] = make_float4(g.ca, g.cb, g.cc, tt.A);
+    sm.q[tid] = make_float4(tt.B, tt.C, g.rgb[0], g.rgb[1]);
+    sm.c[tid] = make_float4(g.rgb[2], 0.0f, 0.0f, 0.0f);
+    qm = reached_quadrants(g, ent >> 28, tt.sx, tt.sy);
   }
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   uint32_t rank[4];
@@ -467,25 +479,37 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
   for (int q = 0; q < 4; ++q) {
     const uint64_t m = __ballot((qm >> q) & 1u);
     rank[q] = __popcll(m & below);
-    if (lane == 0) s_cnt[q][wave] = __popcll(m);
+    if (lane == 0) sm.cnt[q][wave] = __popcll(m);
   }
   __syncthreads();
   int my_count = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     int off = 0;
-    for (int w = 0; w < 4; ++w) off += w < wave ? s_cnt[q][w] : 0;
-    if ((qm >> q) & 1u) s_list[q][off + rank[q]] = (uint32_t)tid * 16u;   // byte offset: no index math below
-    if (q == wave) my_count = s_cnt[q][0] + s_cnt[q][1] + s_cnt[q][2] + s_cnt[q][3];
+    for (int w = 0; w < 4; ++w) off += w < wave ? sm.cnt[q][w] : 0;
+    if ((qm >> q) & 1u) sm.list[q][off + rank[q]] = (uint32_t)tid * 16u;   // byte offset: no index math below
+    if (q == wave) my_count = sm.cnt[q][0] + sm.cnt[q][1] + sm.cnt[q][2] + sm.cnt[q][3];
   }
   __syncthreads();
+  return __builtin_amdgcn_readfirstlane(my_count);
+}
+
+// Wave w of the 256 threads owns the 8x8 texel block at ((w & 1) * 8, (w >> 1) * 8) of the
+// 16x16 tile and walks its own quadrant list, reading records from LDS (broadcast reads):
+// no scalar memory traffic and no per-entry test on the critical path.
+template <typename PT>
+__device__ __forceinline__ void splat_item(const BuildArgs& a, uint32_t item, SplatLds& sm) {
+  SplatItem si;
+  const int cnt = splat_stage(a, item, sm, si);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const float du = si.du, dv = si.dv;
+  const float duu = du * du, duv = du * dv, dvv = dv * dv;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
-  const int cnt = __builtin_amdgcn_readfirstlane(my_count);
   for (int i = 0; i < cnt; ++i) {
-    const uint32_t e16 = s_list[wave][i];
-    const float4 P = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_p) + e16);
-    const float4 Q = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_q) + e16);
-    const float cb = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_c) + e16)->x;
+    const uint32_t e16 = sm.list[wave][i];
+    const float4 P = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sm.p) + e16);
+    const float4 Q = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sm.q) + e16);
+    const float cb = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sm.c) + e16)->x;
     const float4 col = make_float4(Q.z, Q.w, cb, 0.0f);
     const float q = taylor_q(P.x, P.y, P.z, P.w, Q.x, Q.y, du, dv, duu, duv, dvv);
     // excluded texels get alpha 0 (a select, not a branch)
@@ -496,12 +520,84 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
     C2 = fmaf(w, col.z, C2);
     T = T - w;
   }
-  if (nseg > 1) {
+  const int px = si.px, py = si.py;
+  if (si.nseg > 1) {
     // partial (C, T) of this segment; the combine pass composes the segments in order
-    const size_t slot = (size_t)a.pslot[bidx] + it.y;
-    a.partial[slot * (kTile * kTile) + ((py - oy) << kTileShift) + (px - ox)] = make_float4(C0, C1, C2, T);
+    const size_t slot = (size_t)a.pslot[si.bidx] + si.seg;
+    a.partial[slot * (kTile * kTile) + ((py - si.oy) << kTileShift) + (px - si.ox)] = make_float4(C0, C1, C2, T);
   } else if (px < a.c.wp && py < a.c.hp) {
-    store_rgba(static_cast<PT*>(a.planes), ((size_t)k * a.c.hp + py) * a.c.wp + px, C0, C1, C2, 1.0f - T);
+    store_rgba(static_cast<PT*>(a.planes), ((size_t)si.k * a.c.hp + py) * a.c.wp + px, C0, C1, C2, 1.0f - T);
+  }
+}
+
+// Work item of work-group wg when `total` items are dealt to the 8 XCDs (work-group wg runs
+// on XCD wg mod 8) in 2^shift blocks of consecutive items, block B on XCD B mod 8: the items
+// of neighbouring tiles, whose lists share Gaussians, run on one XCD and read the shared
+// records from its L2, while the dense and sparse parts of the frame are spread over all
+// XCDs.  Within an XCD its work-groups take its blocks' items in order.  The grid must hold
+// xcd_grid(max_items, shift) work-groups (total <= max_items); work-groups past the items
+// return.
+__device__ __forceinline__ bool xcd_item(uint32_t wg, uint32_t total, int shift, uint32_t* item) {
+  const uint32_t C = max(1u, total >> shift);              // items per block
+  const uint32_t j = wg >> 3, x = wg & 7u;
+  const uint32_t q = j / C, r = j - q * C;
+  *item = (q * 8u + x) * C + r;
+  return *item < total;
+}
+
+// Work-groups of a launch over at most max_items items dealt by xcd_item: with C <=
+// max(1, max_items >> shift) items per block, XCD x holds ceil(blocks / 8) blocks of C, so
+// the largest index used is below total + 8 C.
+inline int64_t xcd_grid(int64_t max_items, int shift) {
+  const int64_t C = std::max<int64_t>(1, max_items >> shift);
+  return ((max_items + 8 * C + 7) / 8) * 8;
+}
+
+// One work-group per (tile, chunk) segment of at most kSegment entries.
+template <typename PT>
+__global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) {
+  __shared__ SplatLds sm;
+  uint32_t item;
+  if (!xcd_item(blockIdx.x, a.item_start[n_buckets], a.item_shift, &item)) return;
+  splat_item<PT>(a, item, sm);
+}
+
+// The splat's work, counted over the same work items and decisions: out[0] += (Gaussian,
+// texel) pairs inside the plane with o G >= 1/255 (the support pairs), out[1] += (entry,
+// texel) evaluations of the quadrant lists (what the splat computes), out[2] += list
+// entries x 256 texels (the tile lists' superset).
+__global__ __launch_bounds__(256) void count_splat_work(BuildArgs a, int64_t n_buckets,
+                                                        unsigned long long* __restrict__ out) {
+  __shared__ SplatLds sm;
+  __shared__ unsigned long long part[4][2];
+  uint32_t item;
+  if (!xcd_item(blockIdx.x, a.item_start[n_buckets], a.item_shift, &item)) return;
+  SplatItem si;
+  const int cnt = splat_stage(a, item, sm, si);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const float du = si.du, dv = si.dv;
+  const float duu = du * du, duv = du * dv, dvv = dv * dv;
+  const bool inside = si.px < a.c.wp && si.py < a.c.hp;
+  unsigned long long support = 0;
+  for (int i = 0; i < cnt; ++i) {
+    const uint32_t e16 = sm.list[wave][i];
+    const float4 P = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sm.p) + e16);
+    const float4 Q = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sm.q) + e16);
+    const float q = taylor_q(P.x, P.y, P.z, P.w, Q.x, Q.y, du, dv, duu, duv, dvv);
+    support += __popcll(__ballot(inside && q >= kLog2AlphaMin));
+  }
+  if (lane == 0) {
+    part[wave][0] = support;
+    part[wave][1] = (unsigned long long)cnt * 64u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t bb0 = a.bucket[si.bidx], bb1 = a.bucket[si.bidx + 1];
+    const uint32_t b0 = bb0 + si.seg * kSegment;
+    const unsigned long long n = a.hdr->overflow == 0 ? min(bb1, b0 + kSegment) - b0 : 0u;
+    atomicAdd(&out[0], part[0][0] + part[1][0] + part[2][0] + part[3][0]);
+    atomicAdd(&out[1], part[0][1] + part[1][1] + part[2][1] + part[3][1]);
+    atomicAdd(&out[2], n * (unsigned long long)(kTile * kTile));
   }
 }
 
@@ -647,6 +743,50 @@ __global__ __launch_bounds__(256) void combine_segments(BuildArgs a, int64_t n_b
   }
 }
 
+// The splat and merge of several builds in one launch each: the work items of builds
+// [0 .. n) form one list, build after build (each build's count read on the device), and
+// each work-group finds its build by a scan of the per-build counts.  Items are dealt to
+// the XCDs as in splat_gs.
+__device__ __forceinline__ int job_of(const BuildArgs* __restrict__ args, const SplatJobs& jobs, bool partial,
+                                      uint32_t w, uint32_t* local) {
+  int j = 0;
+  for (; j + 1 < jobs.n; ++j) {
+    const BuildArgs& a = args[j];
+    const uint32_t c = partial ? a.pslot[jobs.n_buckets[j]] : a.item_start[jobs.n_buckets[j]];
+    if (w < c) break;
+    w -= c;
+  }
+  *local = w;
+  return j;
+}
+
+__device__ __forceinline__ uint32_t jobs_total(const BuildArgs* __restrict__ args, const SplatJobs& jobs, bool partial) {
+  uint32_t t = 0;
+  for (int j = 0; j < jobs.n; ++j)
+    t += partial ? args[j].pslot[jobs.n_buckets[j]] : args[j].item_start[jobs.n_buckets[j]];
+  return t;
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void splat_gs_jobs(const BuildArgs* __restrict__ args, SplatJobs jobs) {
+  __shared__ SplatLds sm;
+  uint32_t w, item;
+  if (!xcd_item(blockIdx.x, jobs_total(args, jobs, false), jobs.item_shift, &w)) return;
+  const int j = job_of(args, jobs, false, w, &item);
+  splat_item<PT>(args[j], item, sm);
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void combine_jobs(const BuildArgs* __restrict__ args, SplatJobs jobs) {
+  const uint32_t nslots = jobs_total(args, jobs, true);
+  for (uint32_t i = blockIdx.x; i < nslots; i += gridDim.x) {
+    uint32_t slot;
+    const int j = job_of(args, jobs, true, i, &slot);
+    const uint32_t b = args[j].split[slot];
+    if (b != 0xffffffffu) combine_bucket<PT>(args[j], b);
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Backward of the splat.  Per texel of a bucket with cotangents gC = dL/dC, gA = dL/dA of
 // its plane texel, over the bucket's Gaussians i (front to back, alpha_i, colour c_i):
@@ -677,8 +817,8 @@ __global__ __launch_bounds__(256) void splat_bwd_gs(BuildArgs a, int64_t n_bucke
   // entry e of the segment, staged once: (ca, cb, cc, A), (B, C, r, g), (b, sx, sy, entry
   // bits: Gaussian index and quadrant mask); the same Taylor form the forward evaluated
   __shared__ float4 s_p[kSegment], s_q[kSegment], s_c[kSegment];
-  const uint32_t item = blockIdx.x;
-  if (item >= a.item_start[n_buckets]) return;
+  uint32_t item;
+  if (!xcd_item(blockIdx.x, a.item_start[n_buckets], a.item_shift, &item)) return;
   if (a.hdr->overflow) return;
   const uint2 it = a.items[item];
   const int64_t bidx = it.x;
@@ -960,8 +1100,9 @@ int key_digit_bits() {
   return kKeyDigitBits;
 }
 
-hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
+hipError_t build_lists(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof, bool* done) {
   hipError_t e;
+  *done = false;
   const unsigned gN = (unsigned)((a.n + 255) / 256);
   {
     PhaseScope ps(prof, LF_PHASE_PREPROCESS, s);
@@ -974,6 +1115,7 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
       const size_t words = (size_t)a.K * a.c.hp * a.c.wp * texel_words;
       if ((e = fill(reinterpret_cast<uint32_t*>(a.planes), (int64_t)words, 0u, s)) != hipSuccess) return e;
       hipLaunchKernelGGL(chunk_table, dim3(1), dim3(1024), 0, s, a, a.keys);
+      *done = true;
       return hipGetLastError();
     }
     if (a.kind == LF_VOXELS) {
@@ -1019,6 +1161,11 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
       return e;
     hipLaunchKernelGGL(emit_items, dim3(gB), dim3(256), 0, s, a, L.n_buckets);
   }
+  return hipGetLastError();
+}
+
+hipError_t build_splat(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
+  hipError_t e;
   if (a.sh_coef) {
     // SH planes: one work-group per bucket, no partial tiles to merge
     PhaseScope ps(prof, LF_PHASE_SPLAT, s);
@@ -1041,7 +1188,7 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
   }
   {
     PhaseScope ps(prof, LF_PHASE_SPLAT, s);
-    const dim3 grid((unsigned)L.max_items);
+    const dim3 grid((unsigned)xcd_grid(L.max_items, a.item_shift));
     if (a.kind == LF_VOXELS) {
       if ((e = launch_splat_vox(a, L, s)) != hipSuccess) return e;
     } else switch (a.plane_dtype) {
@@ -1070,12 +1217,53 @@ hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profi
   return hipGetLastError();
 }
 
+hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
+  bool done = false;
+  const hipError_t e = build_lists(a, L, s, prof, &done);
+  if (e != hipSuccess || done) return e;
+  return build_splat(a, L, s, prof);
+}
+
+hipError_t splat_batch_launch(const BuildArgs* args, const SplatJobs& jobs, int plane_dtype, hipStream_t s) {
+  if (jobs.n < 1 || jobs.n > kMaxSplatJobs) return hipErrorInvalidValue;
+  int64_t items = 0;
+  for (int i = 0; i < jobs.n; ++i) items += jobs.max_items[i];
+  const dim3 g((unsigned)xcd_grid(items, jobs.item_shift)), c((unsigned)kCombineGroups);
+  switch (plane_dtype) {
+    case LF_F16:
+      hipLaunchKernelGGL((splat_gs_jobs<__half>), g, dim3(256), 0, s, args, jobs);
+      hipLaunchKernelGGL((combine_jobs<__half>), c, dim3(256), 0, s, args, jobs);
+      break;
+    case LF_BF16:
+      hipLaunchKernelGGL((splat_gs_jobs<__hip_bfloat16>), g, dim3(256), 0, s, args, jobs);
+      hipLaunchKernelGGL((combine_jobs<__hip_bfloat16>), c, dim3(256), 0, s, args, jobs);
+      break;
+    case LF_U8:
+      hipLaunchKernelGGL((splat_gs_jobs<uint8_t>), g, dim3(256), 0, s, args, jobs);
+      hipLaunchKernelGGL((combine_jobs<uint8_t>), c, dim3(256), 0, s, args, jobs);
+      break;
+    default:
+      hipLaunchKernelGGL((splat_gs_jobs<float>), g, dim3(256), 0, s, args, jobs);
+      hipLaunchKernelGGL((combine_jobs<float>), c, dim3(256), 0, s, args, jobs);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t splat_work_launch(const BuildArgs& a, const BuildLayout& L, int64_t* counts, hipStream_t s) {
+  hipError_t e = fill(reinterpret_cast<uint32_t*>(counts), 6, 0u, s);
+  if (e != hipSuccess || a.n == 0) return e;
+  hipLaunchKernelGGL(count_splat_work, dim3((unsigned)xcd_grid(L.max_items, a.item_shift)), dim3(256), 0, s, a, L.n_buckets,
+                     reinterpret_cast<unsigned long long*>(counts));
+  return hipGetLastError();
+}
+
 hipError_t build_backward(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof) {
   PhaseScope ps(prof, LF_PHASE_BUILD_BWD, s);
   hipError_t e;
   if (a.n == 0) return hipSuccess;
   if ((e = fill(reinterpret_cast<uint32_t*>(a.ggrad), a.n * kGradSlots, 0u, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(splat_bwd_gs, dim3((unsigned)L.max_items), dim3(256), 0, s, a, L.n_buckets);
+  hipLaunchKernelGGL(splat_bwd_gs, dim3((unsigned)xcd_grid(L.max_items, a.item_shift)), dim3(256), 0, s, a, L.n_buckets);
   hipLaunchKernelGGL(preprocess_bwd_gs, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }

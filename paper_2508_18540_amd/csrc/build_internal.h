@@ -59,6 +59,10 @@ struct BuildLayout {
   size_t total;
 };
 
+// log2 of the number of blocks the splat's work items are dealt to the XCDs in
+// (LF_SPLAT_ITEM_SHIFT overrides it, 0..24)
+int splat_item_shift();
+
 // Fixed part of the layout for n primitives of `kind`, K planes and a wp x hp plane; cap
 // entries.
 BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t cap);
@@ -108,6 +112,7 @@ struct BuildArgs {
   uint2* items;
   float4* partial;
   int64_t max_items;
+  int32_t item_shift;                 // the splat's items go to the XCDs in 2^item_shift blocks
   // voxel planes: float32 stage [K][hp][wp] of the splat, filtered into the planes
   float4* stage;
   int32_t filt_bands, filt_segs;
@@ -129,6 +134,28 @@ struct TableChunk {
 hipError_t upload_table(float* dst, const float* host, int n, hipStream_t s);
 // The whole build of one field (either kind) on stream s.
 hipError_t build_planes(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof);
+// Validates a build, derives its layout and kernel arguments and uploads its inverse-depth
+// tables on st: what lf_build_mpi does before it launches (mpi: RGB planes, or with sh_coef
+// > 0 float32 SH planes).
+lf_status build_prepare(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk, int32_t binning,
+                        const float* inv_depth_range, const lf_mpi* mpi, const float* sh, int32_t sh_coef,
+                        void* workspace, size_t workspace_bytes, hipStream_t st, BuildArgs* a, BuildLayout* L);
+// build_planes in two parts: the cull, sort, chunks, tile lists and work items (*done: the
+// planes are complete already, an empty field), then the splat and merge.  build_lists
+// leaves a.evals on the entries' final array.
+hipError_t build_lists(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof, bool* done);
+hipError_t build_splat(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof);
+// The splat and merge of several Gaussian builds (RGB planes of one dtype) in one launch
+// each, over the work items of all of them: args [0 .. n) in device memory, each build's
+// lists complete.
+constexpr int kMaxSplatJobs = LF_MAX_BATCH;
+struct SplatJobs {
+  int32_t n;
+  int32_t item_shift;                 // as BuildArgs::item_shift, over the joined item list
+  int64_t n_buckets[kMaxSplatJobs];
+  int64_t max_items[kMaxSplatJobs];
+};
+hipError_t splat_batch_launch(const BuildArgs* args, const SplatJobs& jobs, int plane_dtype, hipStream_t s);
 // Copies the (tile, chunk) bucket starts and the entries' primitive indices of the last build
 // (a.evals must name the array the tile sort ended in); either output may be null.
 hipError_t tile_lists_launch(const BuildArgs& a, const BuildLayout& L, int64_t* bucket_start, int32_t* entries,
@@ -145,5 +172,7 @@ hipError_t launch_lowpass(const BuildArgs& a, hipStream_t s);
 // Backward of the Gaussian build (build_gs.hip): splat VJP into the per-Gaussian
 // accumulators, then the projection's chain rule into the parameter gradients.
 hipError_t build_backward(BuildArgs& a, const BuildLayout& L, hipStream_t s, Profiler* prof);
+// counts[3] (int64) of the splat's work over the tile lists of the last build
+hipError_t splat_work_launch(const BuildArgs& a, const BuildLayout& L, int64_t* counts, hipStream_t s);
 
 }  // namespace lf

@@ -343,10 +343,10 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
   // a window fits a buffer of `cap` entries (and the fetch of PF entries per thread)
   auto fits = [&](float lo, float hi, int cap) { return lo >= -1.0e9f && hi <= 1.0e9f && hi - lo + 1.0f <= (float)cap; };
   // this wave's 64-pixel segment is the one-wave kernel's when its windows fit that
-  // kernel's buffer (segments start at multiples of 64: seg_len is); the work-group
-  // returns when all its waves' are
+  // kernel's buffer (segments start at multiples of 64: seg_len is) and 64-pixel tiles are
+  // in use; the work-group returns when all its waves' are
   const int wx0 = xs0 + (tid & ~63);
-  const bool wave_done = wx0 >= a.nx || wave_fits<BIL>(a, pt, pm, wx0, y);
+  const bool wave_done = wx0 >= a.nx || (a.tile != 256 && wave_fits<BIL>(a, pt, pm, wx0, y));
   if (__syncthreads_and(wave_done)) return;
   float Qr[G], Qg[G], Qb[G], Tr[G];
 #pragma unroll
@@ -582,9 +582,9 @@ __device__ __forceinline__ float4 wave_texel<uint8_t>(__amdgpu_buffer_rsrc_t r, 
 }
 
 template <typename PT, typename OT, int G, bool BIL>
-__global__ __launch_bounds__(64) void composite_wave(CompositeArgs a, int nseg, int total,
-                                                     const float4* __restrict__ pt, const float* __restrict__ ct,
-                                                     const float2* __restrict__ pm) {
+__device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int nseg, int lg,
+                                                   const float4* __restrict__ pt, const float* __restrict__ ct,
+                                                   const float2* __restrict__ pm) {
   // LDS texels: FP16 for FP16 / UNORM8 nearest windows (UNORM8 as codes 0..255), else float32
   using LT = typename std::conditional<BIL, float4, typename LdsTexel<PT>::type>::type;
   constexpr bool RAW = !std::is_same<LT, float4>::value;
@@ -594,10 +594,6 @@ __global__ __launch_bounds__(64) void composite_wave(CompositeArgs a, int nseg, 
   constexpr int PF = E / 64;                                 // entries each lane fetches
   constexpr int kTB = std::is_same<PT, float>::value ? 16 : (std::is_same<PT, uint8_t>::value ? 4 : 8);
   __shared__ LT win[2][(BIL ? 2 : 1) * E + 2];              // plus a trash slot (entries past the window)
-  const int wg = blockIdx.x;
-  const int per = (total + 7) / 8;
-  const int lg = (wg % 8) * per + wg / 8;
-  if (lg >= total) return;                                 // whole work-group: grid padded to 8 per
   const int gi = lg % a.n_groups, rest = lg / a.n_groups;
   const int y = rest / nseg, xs0 = (rest % nseg) * 64;
   const uint32_t gd = a.vgroup[gi];
@@ -775,6 +771,41 @@ __global__ __launch_bounds__(64) void composite_wave(CompositeArgs a, int nseg, 
     for (int j = 0; j < G; ++j)
       if (j < nv) store_pixel(out, ((size_t)a.perm[v0 + j] * a.ny + y) * a.nx + x, Qr[j], Qg[j], Qb[j], Tr[j]);
   }
+}
+
+// One wave per 64-pixel segment of one scene; tile lg of `total` is dealt to the XCDs in
+// contiguous runs (work-group w runs on XCD w mod 8), so the view groups and segments of
+// one output row, which stage the same plane rows, share an L2.
+template <typename PT, typename OT, int G, bool BIL>
+__global__ __launch_bounds__(64) void composite_wave(CompositeArgs a, int nseg, int total,
+                                                     const float4* __restrict__ pt, const float* __restrict__ ct,
+                                                     const float2* __restrict__ pm) {
+  const int wg = blockIdx.x;
+  const int per = (total + 7) / 8;
+  const int lg = (wg % 8) * per + wg / 8;
+  if (lg >= total) return;                                 // whole work-group: grid padded to 8 per
+  composite_wave_tile<PT, OT, G, BIL>(a, nseg, lg, pt, ct, pm);
+}
+
+// The tiles of several scenes' composites in one launch: jobs [0 .. n) in a device array,
+// start[j] = the first tile of job j in the launch's tile list (start[n] tiles in all).  A
+// tile's job is found by a scan of the starts; tiles are dealt to the XCDs as above.
+struct JobStarts {
+  int32_t n;
+  int32_t start[kMaxJobs + 1];
+};
+
+template <typename PT, typename OT, int G, bool BIL>
+__global__ __launch_bounds__(64) void composite_wave_jobs(const CompositeJob* __restrict__ jobs, JobStarts js) {
+  const int total = js.start[js.n];
+  const int wg = blockIdx.x;
+  const int per = (total + 7) / 8;
+  const int lg = (wg % 8) * per + wg / 8;
+  if (lg >= total) return;
+  int j = 0;
+  while (j + 1 < js.n && lg >= js.start[j + 1]) ++j;
+  const CompositeJob& jb = jobs[j];
+  composite_wave_tile<PT, OT, G, BIL>(jb.a, jb.nseg, lg - js.start[j], jb.pt, jb.ct, jb.pm);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1461,7 +1492,7 @@ hipError_t launch_rows(const CompositeArgs& a, int G, const float4* pt, const fl
   // the one-wave kernel over every 64-pixel segment, then the row kernel over every
   // segment of seg pixels: each takes the 64-pixel segments that are its own
   auto both = [&](auto wave, auto rows) {
-    hipLaunchKernelGGL(wave, grid64, block64, 0, s, a, nseg64, total64, pt, ct, pm);
+    if (a.tile != 256) hipLaunchKernelGGL(wave, grid64, block64, 0, s, a, nseg64, total64, pt, ct, pm);
     hipLaunchKernelGGL(rows, grid, block, lds, s, a, seg, nseg, total, pt, ct, pm);
   };
   switch (G) {
@@ -1537,11 +1568,11 @@ size_t composite_table_bytes(int K, int n_views) {
          align_256((size_t)K * n_views * 8);
 }
 
-hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profiler* prof) {
-  float4* pt;
-  float* ct;
-  float2* pm;
-  table_parts(table, a.K, a.n_views, &pt, &ct, &pm);
+namespace {
+
+// The view-group size G and kernel form of a composite (the row kernels, or the per-pixel
+// kernel when rows is false); fills a's view groups for G.
+void composite_plan(CompositeArgs& a, int* G_out, bool* rows_out) {
   int cls_end[LF_MAX_VIEWS];
   const int nc = dy_classes(a, cls_end);
   int G = 16, best = group_cost(cls_end, nc, 16);
@@ -1568,7 +1599,90 @@ hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profil
     const int g = atoi(e);
     if (g == 4 || g == 8 || g == 12 || g == 16 || g == 24) G = g;
   }
+  // an explicit tile (autotuned) wins; else LF_COMPOSITE_TILE=256 sends every segment to the
+  // row kernel
+  if (a.tile != 64 && a.tile != 256) {
+    const char* t = getenv("LF_COMPOSITE_TILE");
+    a.tile = t && atoi(t) == 256 ? 256 : 64;
+  }
   fill_groups(a, cls_end, nc, G);
+  *G_out = G;
+  *rows_out = rows;
+}
+
+template <typename PT, typename OT, int G, bool BIL>
+void launch_jobs_wave(const CompositeJob* jobs, const JobStarts& js, hipStream_t s) {
+  const int total = js.start[js.n];
+  const dim3 grid((unsigned)(((total + 7) / 8) * 8));
+  hipLaunchKernelGGL((composite_wave_jobs<PT, OT, G, BIL>), grid, dim3(64), 0, s, jobs, js);
+}
+
+template <typename PT, typename OT, bool BIL>
+void launch_jobs_g(const CompositeJob* jobs, const JobStarts& js, int G, hipStream_t s) {
+  switch (G) {
+    case 4: launch_jobs_wave<PT, OT, 4, BIL>(jobs, js, s); break;
+    case 8: launch_jobs_wave<PT, OT, 8, BIL>(jobs, js, s); break;
+    case 12: launch_jobs_wave<PT, OT, 12, BIL>(jobs, js, s); break;
+    case 24: launch_jobs_wave<PT, OT, 24, BIL>(jobs, js, s); break;
+    default: launch_jobs_wave<PT, OT, 16, BIL>(jobs, js, s); break;
+  }
+}
+
+template <typename PT, typename OT>
+void launch_jobs_interp(const CompositeJob* jobs, const JobStarts& js, const CompositeKey& k, hipStream_t s) {
+  if (k.interp == LF_BILINEAR) launch_jobs_g<PT, OT, true>(jobs, js, k.group, s);
+  else launch_jobs_g<PT, OT, false>(jobs, js, k.group, s);
+}
+
+template <typename PT>
+void launch_jobs_out(const CompositeJob* jobs, const JobStarts& js, const CompositeKey& k, hipStream_t s) {
+  if (k.out_dtype == LF_F16) launch_jobs_interp<PT, __half>(jobs, js, k, s);
+  else launch_jobs_interp<PT, float>(jobs, js, k, s);
+}
+
+// The row kernel alone over one job's segments (those that do not fit a wave).
+template <typename PT, typename OT, bool BIL>
+hipError_t launch_rows_only(const CompositeArgs& a, int G, const float4* pt, const float* ct, const float2* pm,
+                            hipStream_t s) {
+  CompositeArgs b = a;
+  b.tile = 64;
+  int seg;
+  const int threads = row_threads(b, &seg);
+  const int nseg = (b.nx + seg - 1) / seg;
+  const size_t lds = (size_t)2 * kWinStride * 16;
+  const int total = b.n_groups * nseg * b.ny;
+  const dim3 grid((unsigned)(((total + 7) / 8) * 8)), block(threads);
+  switch (G) {
+    case 4: hipLaunchKernelGGL((composite_rows<PT, OT, 4, BIL>), grid, block, lds, s, b, seg, nseg, total, pt, ct, pm); break;
+    case 8: hipLaunchKernelGGL((composite_rows<PT, OT, 8, BIL>), grid, block, lds, s, b, seg, nseg, total, pt, ct, pm); break;
+    case 12: hipLaunchKernelGGL((composite_rows<PT, OT, 12, BIL>), grid, block, lds, s, b, seg, nseg, total, pt, ct, pm); break;
+    case 24: hipLaunchKernelGGL((composite_rows<PT, OT, 24, BIL>), grid, block, lds, s, b, seg, nseg, total, pt, ct, pm); break;
+    default: hipLaunchKernelGGL((composite_rows<PT, OT, 16, BIL>), grid, block, lds, s, b, seg, nseg, total, pt, ct, pm); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename PT, typename OT>
+hipError_t rows_only_interp(const CompositeJob& j, int G, hipStream_t s) {
+  return j.a.interp == LF_BILINEAR ? launch_rows_only<PT, OT, true>(j.a, G, j.pt, j.ct, j.pm, s)
+                                   : launch_rows_only<PT, OT, false>(j.a, G, j.pt, j.ct, j.pm, s);
+}
+
+template <typename PT>
+hipError_t rows_only_out(const CompositeJob& j, int G, hipStream_t s) {
+  return j.a.out_dtype == LF_F16 ? rows_only_interp<PT, __half>(j, G, s) : rows_only_interp<PT, float>(j, G, s);
+}
+
+}  // namespace
+
+hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profiler* prof) {
+  float4* pt;
+  float* ct;
+  float2* pm;
+  table_parts(table, a.K, a.n_views, &pt, &ct, &pm);
+  int G;
+  bool rows;
+  composite_plan(a, &G, &rows);
   if (rows) {
     PhaseScope ps(prof, LF_PHASE_COEFF, s);
     launch_table(a, pt, ct, pm, s, G);                     // every view slot is sampled
@@ -1580,6 +1694,58 @@ hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profil
     case LF_U8: return dispatch_out<uint8_t>(a, rows, G, pt, ct, pm, s);
     default: return dispatch_out<float>(a, rows, G, pt, ct, pm, s);
   }
+}
+
+bool composite_job(CompositeArgs& a, void* table, CompositeJob* j, CompositeKey* key) {
+  float4* pt;
+  float* ct;
+  float2* pm;
+  table_parts(table, a.K, a.n_views, &pt, &ct, &pm);
+  int G;
+  bool rows;
+  composite_plan(a, &G, &rows);
+  if (!rows || a.tile == 256) return false;
+  a.group = G;                                             // the table's slots and the kernel's
+  j->a = a;
+  j->pt = pt;
+  j->ct = ct;
+  j->pm = pm;
+  j->nseg = (a.nx + 63) / 64;
+  j->tiles = a.n_groups * j->nseg * a.ny;
+  *key = CompositeKey{a.plane_dtype, a.out_dtype, a.interp, G};
+  return true;
+}
+
+hipError_t composite_job_table(const CompositeJob& j, hipStream_t s) {
+  launch_table(j.a, const_cast<float4*>(j.pt), const_cast<float*>(j.ct), const_cast<float2*>(j.pm), s, j.a.group);
+  return hipGetLastError();
+}
+
+hipError_t composite_jobs_launch(const CompositeJob* jobs, const CompositeJob* jobs_host, int n, const CompositeKey& k,
+                                 hipStream_t s) {
+  if (n < 1 || n > kMaxJobs) return hipErrorInvalidValue;
+  JobStarts js;
+  js.n = n;
+  js.start[0] = 0;
+  for (int i = 0; i < n; ++i) js.start[i + 1] = js.start[i] + jobs_host[i].tiles;
+  if (js.start[n] > 0) {
+    switch (k.plane_dtype) {
+      case LF_F16: launch_jobs_out<__half>(jobs, js, k, s); break;
+      case LF_BF16: launch_jobs_out<__hip_bfloat16>(jobs, js, k, s); break;
+      case LF_U8: launch_jobs_out<uint8_t>(jobs, js, k, s); break;
+      default: launch_jobs_out<float>(jobs, js, k, s); break;
+    }
+  }
+  hipError_t e = hipGetLastError();
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    switch (k.plane_dtype) {
+      case LF_F16: e = rows_only_out<__half>(jobs_host[i], k.group, s); break;
+      case LF_BF16: e = rows_only_out<__hip_bfloat16>(jobs_host[i], k.group, s); break;
+      case LF_U8: e = rows_only_out<uint8_t>(jobs_host[i], k.group, s); break;
+      default: e = rows_only_out<float>(jobs_host[i], k.group, s); break;
+    }
+  }
+  return e;
 }
 
 hipError_t composite_backward_launch(CompositeArgs& a, void* table, const float* d_out, float* d_planes,

@@ -105,6 +105,8 @@ struct CompositeArgs {
   int32_t K, hp, wp, nx, ny, n_views;
   int32_t plane_dtype, out_dtype, interp;
   int32_t group;            // views per row work-group (4, 8, 12, 16); 0 picks by view count
+  int32_t tile;             // pixels per row tile: 64 (one wave, where the window fits; also 0)
+                            // or 256 (every segment to the 256-thread row kernel)
   Consts c;
   float dx[LF_MAX_VIEWS];
   float dy[LF_MAX_VIEWS];
@@ -115,6 +117,36 @@ struct CompositeArgs {
   uint8_t perm[LF_MAX_VIEWS];
 };
 static_assert(LF_MAX_VIEWS <= 256, "view positions and group starts are 8-bit");
+
+// One scene's composite inside a batch launch: its arguments (view groups filled), its
+// coefficient table (filled on the scene's stream beforehand), its 64-pixel segments per
+// row and its tile count n_groups * nseg * ny.
+struct CompositeJob {
+  CompositeArgs a;
+  const float4* pt;
+  const float* ct;
+  const float2* pm;
+  int32_t nseg, tiles;
+};
+constexpr int kMaxJobs = LF_MAX_BATCH;
+// Kernel key of a batch launch: scenes that share it composite in one launch.
+struct CompositeKey {
+  int32_t plane_dtype, out_dtype, interp, group;
+  bool operator==(const CompositeKey& o) const {
+    return plane_dtype == o.plane_dtype && out_dtype == o.out_dtype && interp == o.interp && group == o.group;
+  }
+};
+// Prepares scene job j of a batch: picks the view-group size (a.group, else by view count),
+// fills the view groups and the table's pointers; returns false if the scene needs the
+// per-pixel kernel (then composite_launch serves it alone).
+bool composite_job(CompositeArgs& a, void* table, CompositeJob* j, CompositeKey* key);
+// Enqueues the coefficient table of a prepared job on s.
+hipError_t composite_job_table(const CompositeJob& j, hipStream_t s);
+// One launch of the one-wave kernel over the 64-pixel tiles of jobs[0 .. n) (device array,
+// every job of one key), then each job's row kernel over its segments that do not fit a
+// wave (jobs_host: the same jobs on the host).
+hipError_t composite_jobs_launch(const CompositeJob* jobs, const CompositeJob* jobs_host, int n, const CompositeKey& key,
+                                 hipStream_t s);
 
 // Bytes of the coefficient table lf_composite keeps in its context for K planes, V views.
 size_t composite_table_bytes(int K, int n_views);

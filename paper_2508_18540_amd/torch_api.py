@@ -278,6 +278,16 @@ def tile_lists(ctx: Context, scene: dict, cam, n_chunk: int, workspace: Workspac
     return tile, tx, ty, starts, entries[:int(info.entries_needed)]
 
 
+def splat_work(ctx: Context, scene: dict, cam, n_chunk: int, workspace: Workspace) -> dict:
+    """lf_build_splat_work after a build_mpi on ``workspace``: the splat's support pairs,
+    its (entry, texel) evaluations and the list entries x 256 texels."""
+    counts = torch.empty(3, dtype=torch.int64, device=ctx.device)
+    L.lf_build_splat_work(ctx.handle, field_of(scene), L.make_camera(cam), n_chunk, workspace.ptr, workspace.nbytes,
+                          counts.data_ptr(), torch.cuda.current_stream(ctx.device).cuda_stream)
+    c = counts.cpu().tolist()
+    return {"support_pairs": c[0], "evaluations": c[1], "list_texels": c[2]}
+
+
 def composite_backward(ctx: Context, rgba: torch.Tensor, depth: torch.Tensor, cam, views, d_out: torch.Tensor,
                        interp: str = "nearest", d_planes: torch.Tensor | None = None) -> torch.Tensor:
     """lf_composite_backward: dL/d(planes) [K, H, W, 4] float32 from dL/d(views) [V, ny, nx, 4]."""
@@ -349,9 +359,12 @@ class Batch:
     and workspace; ``run()`` renders them all (``outs[i]`` = dict(rgba, depth, chunk_of,
     chunk_count, views, workspace)), ``stats()`` reports every scene's build.  A scene's
     tile-list capacity is sized by one probe build unless ``probe`` (or the scene's own
-    "probe" key) is false."""
+    "probe" key) is false.  ``worklist`` runs the batch phase by phase (one splat, merge
+    and composite launch over the work items of every scene) instead of one stream per
+    scene."""
 
-    def __init__(self, ctx: Context, scenes: list, graph: bool = True, autotune: bool = False, probe: bool = True):
+    def __init__(self, ctx: Context, scenes: list, graph: bool = True, autotune: bool = False, probe: bool = True,
+                 worklist: bool = False):
         self.ctx = ctx
         self.outs, self._keep, items = [], [], []
         for sc in scenes:
@@ -371,7 +384,7 @@ class Batch:
             o = dict(rgba=torch.empty((K, info.plane_height, info.plane_width, 4), dtype=sc.get("plane_dtype", torch.float16),
                                       device=dev),
                      depth=torch.empty(K, dtype=torch.float32, device=dev),
-                     chunk_of=torch.empty(max(int(sc["scene"]["means"].shape[0]), 1), dtype=torch.int32, device=dev),
+                     chunk_of=torch.empty(max(int(field_of(sc["scene"]).n), 1), dtype=torch.int32, device=dev),
                      chunk_count=torch.empty(K, dtype=torch.int32, device=dev),
                      views=torch.empty((len(views), cam.ny, cam.nx, 4), dtype=sc.get("out_dtype", torch.float32), device=dev),
                      workspace=ws)
@@ -393,7 +406,8 @@ class Batch:
             items.append(it)
             self.outs.append(o)
             self._keep.append((sc, views))
-        flags = (L.LF_BATCH_GRAPH if graph else 0) | (L.LF_BATCH_AUTOTUNE if autotune else 0)
+        flags = ((L.LF_BATCH_GRAPH if graph else 0) | (L.LF_BATCH_AUTOTUNE if autotune else 0)
+                 | (L.LF_BATCH_WORKLIST if worklist else 0))
         self.handle = L.lf_batch_create(ctx.handle, items, flags)
 
     def run(self):
@@ -408,6 +422,9 @@ class Batch:
 
     def groups(self):
         return [L.lf_batch_group(self.handle, i) for i in range(len(self.outs))]
+
+    def tiles(self):
+        return [L.lf_batch_tile(self.handle, i) for i in range(len(self.outs))]
 
     def close(self):
         if getattr(self, "handle", 0):

@@ -1,8 +1,9 @@
 """Batched rendering (lf_batch_*): several scenes of different sizes, plane counts, view
-counts and dtypes rendered by one call on per-scene streams, optionally captured into one
-HIP graph and autotuned.  Every output must equal, bit for bit, the same scene rendered
-alone with lf_build_mpi + lf_composite (whose parity with the oracle the other GPU tests
-establish), on every graph replay."""
+counts, dtypes and field kinds rendered by one call, on per-scene streams or phase by phase
+over the (scene, item) work list, optionally captured into one HIP graph and autotuned.
+Every output must equal, bit for bit, the same scene rendered alone with lf_build_mpi +
+lf_composite (whose parity with the oracle the other GPU tests establish), on every graph
+replay."""
 import math
 
 import numpy as np
@@ -24,6 +25,7 @@ SCENES = [
     (60_000, 256, 64, (16, 1), "quantile", torch.bfloat16, "nearest"),
     (30_000, 160, 8, (24, 1), "quantile", torch.float16, "nearest"),
     (25_000, 144, 12, (4, 3), "quantile", torch.uint8, "nearest"),
+    (35_000, 160, 16, (5, 1), "quantile", torch.float32, "nearest"),
 ]
 
 
@@ -36,6 +38,13 @@ def _scenes():
                         views=T.views_of(dx.astype(np.float32), dy.astype(np.float32)), binning=binning,
                         inv_depth_range=(1.0, 20.0) if binning == "inv_depth" else None, plane_dtype=pdt,
                         interp=interp))
+    # a voxel field (its splat is not one of the work list's)
+    cam = scenegen.camera(96, 96, 50.0, 4.0, math.radians(40.0))
+    vox = scenegen.voxel_scene(res=32, n_occupied=2000, seed=6)
+    vox["density"] = (vox["density"] * np.float32(0.1)).astype(np.float32)
+    dx, dy, _, _ = geometry.quilt_views(cam, 7, 1)
+    out.append(dict(scene=T.to_device(vox), cam=cam, n_chunk=8, views=T.views_of(dx.astype(np.float32), dy.astype(np.float32)),
+                    binning="quantile", inv_depth_range=None, plane_dtype=torch.float16, interp="nearest"))
     return out
 
 
@@ -55,12 +64,12 @@ def _same(b, refs):
         assert torch.equal(o["views"], img), i
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_matches_single_scene_calls(graph):
-    announce("batch", "graph" if graph else "streams")
+@pytest.mark.parametrize("graph,worklist", [(False, False), (True, False), (False, True), (True, True)])
+def test_batch_matches_single_scene_calls(graph, worklist):
+    announce("batch", "graph" if graph else "eager", "work list" if worklist else "streams")
     scs = _scenes()
     refs = [_eager(sc) for sc in scs]
-    b = T.Batch(ctx(), scs, graph=graph)
+    b = T.Batch(ctx(), scs, graph=graph, worklist=worklist)
     for rep in range(3):
         for o in b.outs:                                   # eager work between runs / replays
             o["views"].zero_()
@@ -73,17 +82,37 @@ def test_batch_matches_single_scene_calls(graph):
     b.close()
 
 
-def test_batch_autotuned_groups():
-    announce("batch autotune")
+@pytest.mark.parametrize("worklist", [False, True])
+def test_batch_autotuned_groups(worklist):
+    """The autotuned view groups and row tiles (64-pixel waves or 256-pixel row tiles) give
+    the same results as the defaults; a second batch of the same shapes takes the cached
+    choices."""
+    announce("batch autotune", "work list" if worklist else "streams")
     scs = _scenes()
     refs = [_eager(sc) for sc in scs]
-    b = T.Batch(ctx(), scs, graph=True, autotune=True)
-    gs = b.groups()
-    print("autotuned view groups", gs)
-    assert all(g in (4, 8, 12, 16) for g in gs)
+    b = T.Batch(ctx(), scs, graph=True, autotune=True, worklist=worklist)
+    gs, ts = b.groups(), b.tiles()
+    print("autotuned view groups", gs, "row tiles", ts)
+    assert all(g in (4, 8, 12, 16) for g in gs) and all(t in (64, 256) for t in ts)
     b.run()
     _same(b, refs)
     b.close()
+    again = T.Batch(ctx(), scs, graph=True, autotune=True, worklist=worklist)
+    assert again.groups() == gs and again.tiles() == ts
+    again.close()
+
+
+def test_composite_row_tiles_match_wave_tiles(monkeypatch):
+    """The 256-pixel row-tile form of the composite (LF_COMPOSITE_TILE=256, the row kernel
+    over every segment) equals the default one-wave form bit for bit."""
+    announce("composite row tiles")
+    for sc in _scenes()[:3]:
+        rgba, depth, img = _eager(sc)
+        monkeypatch.setenv("LF_COMPOSITE_TILE", "256")
+        alt = T.composite(ctx(), rgba, depth, sc["cam"], sc["views"], sc["interp"])
+        torch.cuda.synchronize()
+        monkeypatch.delenv("LF_COMPOSITE_TILE")
+        assert torch.equal(alt, img)
 
 
 @pytest.mark.parametrize("graph", [False, True])

@@ -274,3 +274,30 @@ def test_tile_lists_against_oracle(case):
     torch.cuda.synchronize()
     stats = bins.check_lists(starts.cpu().numpy(), entries.cpu().numpy(), must, may, part, tx * ty * K, K)
     print(name, stats)
+
+
+@pytest.mark.parametrize("case", BIN_CASES, ids=[c[0] for c in BIN_CASES])
+def test_splat_work_counts(case):
+    """lf_build_splat_work: the support pairs equal the oracle's count of (Gaussian, texel)
+    pairs with o G >= 1/255 (Sec. 4.4) up to the pairs within rounding of the threshold; the
+    splat's evaluations cover every support pair and lie within the list texels, which are
+    the entries x 256."""
+    name, make = case
+    scene, cam, K, binning, rng = make()
+    announce("splat work counts", name)
+    ds = T.to_device(scene)
+    ws = T.workspace_for(ds, cam, K)
+    T.build_mpi(ctx(), ds, cam, K, binning, rng, workspace=ws)
+    w = T.splat_work(ctx(), ds, cam, K, ws)
+    info, _ = T.build_stats(ctx(), ws, check=True)
+    g = geometry.derive(cam)
+    part = partition.partition(scene["means"], cam, g, K, binning, rng)
+    want, near = 0, 0
+    for k in range(K):
+        got_k = splat.support_pairs(render.chunk_projection(scene, cam, g, part, k), g.hp, g.wp)
+        want += got_k[0]
+        near += got_k[1]
+    print(name, w, "oracle support pairs", want, "near the threshold", near, flush=True)
+    assert abs(w["support_pairs"] - want) <= near
+    assert w["list_texels"] == int(info.entries_needed) * 256
+    assert w["support_pairs"] <= w["evaluations"] <= w["list_texels"]

@@ -170,3 +170,24 @@ def test_ambiguity_flags_threshold_texels():
     pr.mean2d[0] = [10.0 - r_edge, 20.0]
     rgba, amb = splat.render_plane(pr, g.hp, g.wp)
     assert amb[20, 10] and amb.sum() <= 3
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_support_pairs_brute_force(seed):
+    """support_pairs against plain loops over every texel of the plane and every Gaussian
+    (o G >= 1/255, no bounding boxes)."""
+    cam = scenegen.camera(40, 32, 50.0, 2.0, math.radians(35.0))
+    g = geometry.derive(cam)
+    sc = scenegen.small_scene(30, seed)
+    K = 3
+    part = partition.partition(sc["means"], cam, g, K, "quantile", None)
+    for k in range(K):
+        pr = render.chunk_projection(sc, cam, g, part, k)
+        got, near = splat.support_pairs(pr, g.hp, g.wp)
+        want = 0
+        for n in range(pr.mean2d.shape[0]):
+            for j in range(g.hp):
+                for i in range(g.wp):
+                    d = np.array([i, j], float) - pr.mean2d[n]
+                    want += pr.opacity[n] * math.exp(-0.5 * d @ pr.conic[n] @ d) >= 1.0 / 255.0
+        assert got == want and near <= got + 10
