@@ -272,10 +272,14 @@ lf_status plan_worklist(lf_batch* b) {
     nj += v.size();
   }
   const size_t bytes_a = ((na * sizeof(BuildArgs) + 255) / 256) * 256;
-  hipError_t e = hipMalloc(&b->dev, bytes_a + nj * sizeof(CompositeJob) + 256);
+  const size_t bytes_j = ((nj * sizeof(CompositeJob) + 255) / 256) * 256;
+  const size_t bytes_p = b->splat_jobs.size() * (2 * (size_t)kMaxSplatJobs + 2) * 4;
+  hipError_t e = hipMalloc(&b->dev, bytes_a + bytes_j + bytes_p + 256);
   if (e != hipSuccess) return hip_fail(e, "batch work list allocation");
   b->dargs = static_cast<BuildArgs*>(b->dev);
   b->djobs = reinterpret_cast<CompositeJob*>(static_cast<char*>(b->dev) + bytes_a);
+  uint32_t* pre = reinterpret_cast<uint32_t*>(static_cast<char*>(b->dev) + bytes_a + bytes_j);
+  for (size_t g = 0; g < b->splat_jobs.size(); ++g) b->splat_jobs[g].prefix = pre + g * (2 * (size_t)kMaxSplatJobs + 2);
   for (size_t g = 0; g < b->dargs_host.size() && e == hipSuccess; ++g)
     e = hipMemcpy(b->dargs + b->splat_off[g], b->dargs_host[g].data(), b->dargs_host[g].size() * sizeof(BuildArgs),
                   hipMemcpyHostToDevice);

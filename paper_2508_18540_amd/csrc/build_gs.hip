@@ -744,44 +744,47 @@ __global__ __launch_bounds__(256) void combine_segments(BuildArgs a, int64_t n_b
 }
 
 // The splat and merge of several builds in one launch each: the work items of builds
-// [0 .. n) form one list, build after build (each build's count read on the device), and
-// each work-group finds its build by a scan of the per-build counts.  Items are dealt to
+// [0 .. n) form one list, build after build, and so do their partial slots.  A one-thread
+// kernel first writes the prefix sums of the builds' counts (read on the device, after the
+// builds' lists): prefix[0 .. n] of the items, prefix[n + 1 .. 2n + 1] of the partial
+// slots.  A work-group finds its build by a scan of that short array.  Items are dealt to
 // the XCDs as in splat_gs.
-__device__ __forceinline__ int job_of(const BuildArgs* __restrict__ args, const SplatJobs& jobs, bool partial,
-                                      uint32_t w, uint32_t* local) {
-  int j = 0;
-  for (; j + 1 < jobs.n; ++j) {
-    const BuildArgs& a = args[j];
-    const uint32_t c = partial ? a.pslot[jobs.n_buckets[j]] : a.item_start[jobs.n_buckets[j]];
-    if (w < c) break;
-    w -= c;
+__global__ void jobs_prefix(const BuildArgs* __restrict__ args, SplatJobs jobs) {
+  uint32_t* p = jobs.prefix;
+  uint32_t t = 0, u = 0;
+  p[0] = 0;
+  p[jobs.n + 1] = 0;
+  for (int j = 0; j < jobs.n; ++j) {
+    t += args[j].item_start[jobs.n_buckets[j]];
+    u += args[j].pslot[jobs.n_buckets[j]];
+    p[j + 1] = t;
+    p[jobs.n + 2 + j] = u;
   }
-  *local = w;
-  return j;
 }
 
-__device__ __forceinline__ uint32_t jobs_total(const BuildArgs* __restrict__ args, const SplatJobs& jobs, bool partial) {
-  uint32_t t = 0;
-  for (int j = 0; j < jobs.n; ++j)
-    t += partial ? args[j].pslot[jobs.n_buckets[j]] : args[j].item_start[jobs.n_buckets[j]];
-  return t;
+__device__ __forceinline__ int job_of(const uint32_t* __restrict__ prefix, int n, uint32_t w, uint32_t* local) {
+  int j = 0;
+  while (j + 1 < n && w >= prefix[j + 1]) ++j;
+  *local = w - prefix[j];
+  return j;
 }
 
 template <typename PT>
 __global__ __launch_bounds__(256) void splat_gs_jobs(const BuildArgs* __restrict__ args, SplatJobs jobs) {
   __shared__ SplatLds sm;
   uint32_t w, item;
-  if (!xcd_item(blockIdx.x, jobs_total(args, jobs, false), jobs.item_shift, &w)) return;
-  const int j = job_of(args, jobs, false, w, &item);
+  if (!xcd_item(blockIdx.x, jobs.prefix[jobs.n], jobs.item_shift, &w)) return;
+  const int j = job_of(jobs.prefix, jobs.n, w, &item);
   splat_item<PT>(args[j], item, sm);
 }
 
 template <typename PT>
 __global__ __launch_bounds__(256) void combine_jobs(const BuildArgs* __restrict__ args, SplatJobs jobs) {
-  const uint32_t nslots = jobs_total(args, jobs, true);
+  const uint32_t* pp = jobs.prefix + jobs.n + 1;
+  const uint32_t nslots = pp[jobs.n];
   for (uint32_t i = blockIdx.x; i < nslots; i += gridDim.x) {
     uint32_t slot;
-    const int j = job_of(args, jobs, true, i, &slot);
+    const int j = job_of(pp, jobs.n, i, &slot);
     const uint32_t b = args[j].split[slot];
     if (b != 0xffffffffu) combine_bucket<PT>(args[j], b);
   }
@@ -1229,6 +1232,7 @@ hipError_t splat_batch_launch(const BuildArgs* args, const SplatJobs& jobs, int 
   int64_t items = 0;
   for (int i = 0; i < jobs.n; ++i) items += jobs.max_items[i];
   const dim3 g((unsigned)xcd_grid(items, jobs.item_shift)), c((unsigned)kCombineGroups);
+  hipLaunchKernelGGL(jobs_prefix, dim3(1), dim3(1), 0, s, args, jobs);
   switch (plane_dtype) {
     case LF_F16:
       hipLaunchKernelGGL((splat_gs_jobs<__half>), g, dim3(256), 0, s, args, jobs);

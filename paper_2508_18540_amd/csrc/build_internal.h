@@ -152,6 +152,7 @@ constexpr int kMaxSplatJobs = LF_MAX_BATCH;
 struct SplatJobs {
   int32_t n;
   int32_t item_shift;                 // as BuildArgs::item_shift, over the joined item list
+  uint32_t* prefix;                   // device scratch of 2 n + 2 words (the launch fills it)
   int64_t n_buckets[kMaxSplatJobs];
   int64_t max_items[kMaxSplatJobs];
 };

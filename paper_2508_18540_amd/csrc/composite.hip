@@ -192,14 +192,31 @@ constexpr int kWinStride = kWin + 2;          // plus a trash slot for inactive 
 constexpr int kPrefetch = kWin / kRowThreads; // window entries prefetched per thread (nearest)
 constexpr int kWaveWin = 256;                 // window entries of the one-wave kernel's buffers
 
+// Table pointers in the global address space: a kernel that reads them from device memory
+// (the batch's jobs) then still loads through them with global, not flat, instructions.
+typedef const float4 __attribute__((address_space(1)))* GF4;
+typedef const float __attribute__((address_space(1)))* GF1;
+typedef const float2 __attribute__((address_space(1)))* GF2;
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 ld4(GF4 p) {
+  const v4f v = *(const v4f __attribute__((address_space(1)))*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ld2(GF2 p) {
+  const v2f v = *(const v2f __attribute__((address_space(1)))*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld4(const float4* p) { return *p; }
+__device__ __forceinline__ float2 ld2(const float2* p) { return *p; }
+
 // Whether every plane that view group `pt`/`pm` (the group's table rows) samples has, for
 // the 64 pixels [xs0, xs0 + 64) of row y, a window of at most kWaveWin entries (the
 // one-wave kernel's); wave uniform.  A plane is sampled unless it is invalid, its row lies
 // outside the plane, or its window lies wholly outside the row (transparent texels only).
 // The one-wave kernel and the row kernel decide each segment with this same function.
-template <bool BIL>
-__device__ bool wave_fits(const CompositeArgs& a, const float4* __restrict__ pt, const float2* __restrict__ pm,
-                          int xs0, int y) {
+template <bool BIL, typename P4, typename P2>
+__device__ bool wave_fits(const CompositeArgs& a, P4 pt, P2 pm, int xs0, int y) {
   const int lane = threadIdx.x & 63;
   const float yr = (float)y - a.c.cy;
   const float xr_lo = (float)xs0 - a.c.cx, xr_hi = (float)(xs0 + 63) - a.c.cx;
@@ -209,8 +226,8 @@ __device__ bool wave_fits(const CompositeArgs& a, const float4* __restrict__ pt,
     const int k = kb + lane;
     bool s = false;
     if (k < a.K) {
-      const float4 p = pt[k];
-      const float2 cr = pm[k];
+      const float4 p = ld4(pt + k);
+      const float2 cr = ld2(pm + k);
       const float Y = p.y * yr + p.z;
       const int iy = (int)floorf(Y);
       const bool ok = p.w != 0.0f && iy >= (BIL ? -1 : 0) && iy < a.hp;
@@ -582,9 +599,8 @@ __device__ __forceinline__ float4 wave_texel<uint8_t>(__amdgpu_buffer_rsrc_t r, 
 }
 
 template <typename PT, typename OT, int G, bool BIL>
-__device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int nseg, int lg,
-                                                   const float4* __restrict__ pt, const float* __restrict__ ct,
-                                                   const float2* __restrict__ pm) {
+__device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int nseg, int lg, GF4 __restrict__ pt,
+                                                   GF1 __restrict__ ct, GF2 __restrict__ pm) {
   // LDS texels: FP16 for FP16 / UNORM8 nearest windows (UNORM8 as codes 0..255), else float32
   using LT = typename std::conditional<BIL, float4, typename LdsTexel<PT>::type>::type;
   constexpr bool RAW = !std::is_same<LT, float4>::value;
@@ -594,22 +610,26 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   constexpr int PF = E / 64;                                 // entries each lane fetches
   constexpr int kTB = std::is_same<PT, float>::value ? 16 : (std::is_same<PT, uint8_t>::value ? 4 : 8);
   __shared__ LT win[2][(BIL ? 2 : 1) * E + 2];              // plus a trash slot (entries past the window)
+  // the scalars of the arguments in registers: the asm memory barriers of the sample
+  // loop would otherwise reload them when the arguments live in global memory
+  const int aK = a.K, ahp = a.hp, awp = a.wp, anx = a.nx;
+  const float acx = a.c.cx, acy = a.c.cy;
   const int gi = lg % a.n_groups, rest = lg / a.n_groups;
   const int y = rest / nseg, xs0 = (rest % nseg) * 64;
   const uint32_t gd = a.vgroup[gi];
   const int v0 = gd & 0xffu;
   const int nv = gd >> 8;
-  pt += (size_t)gi * a.K;
-  pm += (size_t)gi * a.K;
+  pt += (size_t)gi * aK;
+  pm += (size_t)gi * aK;
   if (!wave_fits<BIL>(a, pt, pm, xs0, y)) return;          // the row kernel's segment
   const int lane = threadIdx.x;
   const int x = xs0 + lane;
   // lanes past the row's end sample at their own x (results dropped)
-  const float xr = (float)x - a.c.cx, yr = (float)y - a.c.cy;
-  const float xr_lo = (float)xs0 - a.c.cx, xr_hi = (float)(xs0 + 63) - a.c.cx;
+  const float xr = (float)x - acx, yr = (float)y - acy;
+  const float xr_lo = (float)xs0 - acx, xr_hi = (float)(xs0 + 63) - acx;
   const int S = ct_stride(a.n_views);
   const char* planes = static_cast<const char*>(a.planes);
-  const size_t plane_bytes = (size_t)a.hp * a.wp * kTB;
+  const size_t plane_bytes = (size_t)ahp * awp * kTB;
 
   // plane windows, 64 at a time (lane i: plane kb + i); the planes sampled are the set bits
   int my_f0 = 0, my_len = 0, my_iy = 0;
@@ -618,17 +638,17 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
     const int k = kb + lane;
     int f0 = 0, len = 0, iy = 0;
     float wy = 0.0f;
-    if (k < a.K) {
-      const float4 p = pt[k];
-      const float2 cr = pm[k];
+    if (k < aK) {
+      const float4 p = ld4(pt + k);
+      const float2 cr = ld2(pm + k);
       const float Y = p.y * yr + p.z;
       const float fy0 = floorf(Y);
       wy = BIL ? Y - fy0 : 0.0f;
       iy = (int)fy0;
-      bool ok = p.w != 0.0f && iy >= (BIL ? -1 : 0) && iy < a.hp;
+      bool ok = p.w != 0.0f && iy >= (BIL ? -1 : 0) && iy < ahp;
       const float lo = floorf(p.x * xr_lo + cr.x);
       const float hi = floorf(p.x * xr_hi + cr.y) + (BIL ? 1.0f : 0.0f);
-      ok = ok && hi >= 0.0f && lo <= (float)(a.wp - 1);   // else transparent texels only
+      ok = ok && hi >= 0.0f && lo <= (float)(awp - 1);   // else transparent texels only
       f0 = ok ? (int)lo : 0;
       len = ok ? (int)(hi - lo) + 1 : 0;                   // <= E: wave_fits
     }
@@ -643,7 +663,7 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   auto next = [&](int& k, int& f0, int& len, int& iy, float& wy) {
     while (mask == 0) {
       kb += 64;
-      if (kb >= a.K) return false;
+      if (kb >= aK) return false;
       mask = batch(kb);
     }
     const int i = __builtin_ctzll(mask);
@@ -657,9 +677,9 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   };
   // buffer resource over row iy of plane k (a row outside the plane: no records, zeros)
   auto row = [&](int k, int iy) {
-    const bool in = iy >= 0 && iy < a.hp;
-    const char* base = planes + (size_t)k * plane_bytes + (size_t)(in ? iy : 0) * a.wp * kTB;
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, in ? a.wp * kTB : 0, 0x00020000);
+    const bool in = iy >= 0 && iy < ahp;
+    const char* base = planes + (size_t)k * plane_bytes + (size_t)(in ? iy : 0) * awp * kTB;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, in ? awp * kTB : 0, 0x00020000);
   };
   // window fetch into registers (nearest: raw texels; bilinear: the four corners)
   RT rn[BIL ? 1 : PF];
@@ -722,8 +742,8 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   while (have) {
     store(win[buf], len, wy);                              // this plane's window (fetched before)
     const int kc = k, f0c = f0;
-    const float bxr = pt[kc].x * xr;
-    const float* crow = ct + (size_t)kc * S + v0;
+    const float bxr = ld4(pt + kc).x * xr;
+    const GF1 crow = ct + (size_t)kc * S + v0;
     float Cv[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) Cv[j] = crow[j];
@@ -765,7 +785,7 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
     }
     buf ^= 1;
   }
-  if (x < a.nx) {
+  if (x < anx) {
     OT* out = static_cast<OT*>(a.out);
 #pragma unroll
     for (int j = 0; j < G; ++j)
@@ -784,7 +804,7 @@ __global__ __launch_bounds__(64) void composite_wave(CompositeArgs a, int nseg, 
   const int per = (total + 7) / 8;
   const int lg = (wg % 8) * per + wg / 8;
   if (lg >= total) return;                                 // whole work-group: grid padded to 8 per
-  composite_wave_tile<PT, OT, G, BIL>(a, nseg, lg, pt, ct, pm);
+  composite_wave_tile<PT, OT, G, BIL>(a, nseg, lg, (GF4)pt, (GF1)ct, (GF2)pm);
 }
 
 // The tiles of several scenes' composites in one launch: jobs [0 .. n) in a device array,
@@ -795,17 +815,28 @@ struct JobStarts {
   int32_t start[kMaxJobs + 1];
 };
 
+// Jobs differ in cost per tile (their plane counts), so the tiles go to the XCDs in
+// 2^kJobShift blocks of consecutive tiles, block B on XCD B mod 8 (a block still holds the
+// view groups and segments of about one output row): every XCD gets a share of every job.
+constexpr int kJobShift = 9;
+
+inline int64_t job_grid(int64_t total) {
+  const int64_t C = std::max<int64_t>(1, total >> kJobShift);
+  return ((total + 8 * C + 7) / 8) * 8;
+}
+
 template <typename PT, typename OT, int G, bool BIL>
 __global__ __launch_bounds__(64) void composite_wave_jobs(const CompositeJob* __restrict__ jobs, JobStarts js) {
   const int total = js.start[js.n];
-  const int wg = blockIdx.x;
-  const int per = (total + 7) / 8;
-  const int lg = (wg % 8) * per + wg / 8;
+  const int C = max(1, total >> kJobShift);
+  const int wg = blockIdx.x, jw = wg >> 3, xw = wg & 7;
+  const int q = jw / C;
+  const int lg = (q * 8 + xw) * C + (jw - q * C);
   if (lg >= total) return;
   int j = 0;
   while (j + 1 < js.n && lg >= js.start[j + 1]) ++j;
   const CompositeJob& jb = jobs[j];
-  composite_wave_tile<PT, OT, G, BIL>(jb.a, jb.nseg, lg - js.start[j], jb.pt, jb.ct, jb.pm);
+  composite_wave_tile<PT, OT, G, BIL>(jb.a, jb.nseg, lg - js.start[j], (GF4)jb.pt, (GF1)jb.ct, (GF2)jb.pm);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1612,8 +1643,7 @@ void composite_plan(CompositeArgs& a, int* G_out, bool* rows_out) {
 
 template <typename PT, typename OT, int G, bool BIL>
 void launch_jobs_wave(const CompositeJob* jobs, const JobStarts& js, hipStream_t s) {
-  const int total = js.start[js.n];
-  const dim3 grid((unsigned)(((total + 7) / 8) * 8));
+  const dim3 grid((unsigned)job_grid(js.start[js.n]));
   hipLaunchKernelGGL((composite_wave_jobs<PT, OT, G, BIL>), grid, dim3(64), 0, s, jobs, js);
 }
 
