@@ -197,6 +197,8 @@ constexpr int kWaveWin = 256;                 // window entries of the one-wave 
 typedef const float4 __attribute__((address_space(1)))* GF4;
 typedef const float __attribute__((address_space(1)))* GF1;
 typedef const float2 __attribute__((address_space(1)))* GF2;
+// wave-uniform table reads through the constant address space: scalar loads into SGPRs
+typedef const float __attribute__((address_space(4)))* CF1;
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float4 ld4(GF4 p) {
@@ -610,6 +612,12 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   constexpr int PF = E / 64;                                 // entries each lane fetches
   constexpr int kTB = std::is_same<PT, float>::value ? 16 : (std::is_same<PT, uint8_t>::value ? 4 : 8);
   __shared__ LT win[2][(BIL ? 2 : 1) * E + 2];              // plus a trash slot (entries past the window)
+  // FP32 nearest windows are held as two arrays of 8-byte halves, (r, g) at entries
+  // [0, E) and (b, a) kHalf entries on: a sample is two ds_read_b64 at one address (the
+  // second through the instruction's offset), which meet far fewer bank conflicts than one
+  // ds_read_b128 of neighbouring texels.
+  constexpr bool SPLIT = std::is_same<PT, float>::value && !BIL;
+  constexpr int kHalf = E + 2;                               // float2 entries to the (b, a) half
   // the scalars of the arguments in registers: the asm memory barriers of the sample
   // loop would otherwise reload them when the arguments live in global memory
   const int aK = a.K, ahp = a.hp, awp = a.wp, anx = a.nx;
@@ -716,7 +724,12 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
       if (q * 64 >= len) break;
       const int i0 = lane + q * 64;
       const int i = i0 < len ? i0 : E;                     // past the window: the trash slot
-      if constexpr (!BIL) {
+      if constexpr (SPLIT) {
+        float2* w2 = reinterpret_cast<float2*>(w);
+        const float4 t = __builtin_bit_cast(float4, rn[q]);
+        w2[i] = make_float2(t.x, t.y);
+        w2[kHalf + i] = make_float2(t.z, t.w);
+      } else if constexpr (!BIL) {
         if constexpr (U8) w[i] = codes_to_half4(rn[q]);
         else w[i] = rn[q];
       } else {
@@ -742,14 +755,14 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   while (have) {
     store(win[buf], len, wy);                              // this plane's window (fetched before)
     const int kc = k, f0c = f0;
-    const float bxr = ld4(pt + kc).x * xr;
-    const GF1 crow = ct + (size_t)kc * S + v0;
+    const float bxr = *(CF1)(pt + kc) * xr;
+    const CF1 crow = (CF1)(ct + (size_t)kc * S + v0);
     float Cv[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) Cv[j] = crow[j];
     have = next(k, f0, len, iy, wy);
     if (have) fetch(k, f0, len, iy);                       // the next one, in flight meanwhile
-    const char* wb = reinterpret_cast<const char*>(win[buf]) - (ptrdiff_t)f0c * (ptrdiff_t)(BIL ? 32 : (int)sizeof(LT));
+    const char* wb = reinterpret_cast<const char*>(win[buf]) - (ptrdiff_t)f0c * (ptrdiff_t)(BIL ? 32 : SPLIT ? 8 : (int)sizeof(LT));
     // views in blocks of kSub: the block's LDS reads all in flight, then its blends
 #pragma unroll
     for (int j0 = 0; j0 < G; j0 += kSub) {
@@ -758,7 +771,12 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
       for (int jj = 0; jj < kSub; ++jj) {
         const float X = bxr + Cv[j0 + jj];
         const int ix = cvt_flr(X);
-        if (!BIL) {
+        if constexpr (SPLIT) {
+          const char* e = wb + (ptrdiff_t)ix * 8;
+          const float2 rg = *reinterpret_cast<const float2*>(e);
+          const float2 ba = *reinterpret_cast<const float2*>(e + kHalf * 8);
+          sv[jj] = make_float4(rg.x, rg.y, ba.x, ba.y);
+        } else if constexpr (!BIL) {
           sv[jj] = lds_texel<LT>(wb + (ptrdiff_t)ix * (ptrdiff_t)sizeof(LT));
         } else {
           const float w = __builtin_amdgcn_fractf(X);
