@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 COPY_FETCH_SCALE = 262144.0 / 131084.0
 COPY_WRITE_SCALE = 262144.0 / 262144.0
 MEASURED_TRAFFIC = {
-    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133397, write_kib=286992,
-                     helpers=("splat_stage", "splat_item", "xcd_item"), digest="11e3fa5c8720dcd9"),
-    "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=88110, write_kib=184320,
-                           helpers=("composite_wave_tile",), digest="6f2c8f98fa87961a"),
+    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133400, write_kib=286992,
+                     helpers=("splat_stage", "splat_item", "xcd_item"), digest="0dc42ae47ac34e6a"),
+    "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=88133, write_kib=184320,
+                           helpers=("composite_wave_tile",), digest="5555f5722bd3a626"),
 }
 
 
@@ -76,7 +76,7 @@ def measured_traffic(name):
 # --extra ""`, digest-gated like the traffic
 MEASURED_VALU = {
     "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", valu_per_wave_sample=8.45,
-                           helpers=("composite_wave_tile",), digest="6f2c8f98fa87961a"),
+                           helpers=("composite_wave_tile",), digest="5555f5722bd3a626"),
 }
 
 

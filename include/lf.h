@@ -211,7 +211,9 @@ lf_status lf_build_tile_lists(lf_ctx* ctx, const lf_field* field, const lf_camer
  *               reaches;
  *   counts[2] = list entries x 256 texels (the whole tiles the lists name).
  * A build that overflowed its capacity counts zero.  Voxel fields: LF_ERR_UNSUPPORTED.
- * Enqueued on `stream`; needs the tile lists the build left in the workspace.            */
+ * Enqueued on `stream`; needs the tile lists the build left in the workspace, and uses the
+ * workspace's sort scratch (which nothing after the build reads, lf_build_mpi_backward
+ * included) for partial counts.                                                         */
 lf_status lf_build_splat_work(lf_ctx* ctx, const lf_field* field, const lf_camera* cam, int32_t n_chunk,
                               const void* workspace, size_t workspace_bytes, int64_t* counts, void* stream);
 

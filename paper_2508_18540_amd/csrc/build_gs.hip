@@ -565,7 +565,9 @@ __global__ __launch_bounds__(256) void splat_gs(BuildArgs a, int64_t n_buckets) 
 // The splat's work, counted over the same work items and decisions: out[0] += (Gaussian,
 // texel) pairs inside the plane with o G >= 1/255 (the support pairs), out[1] += (entry,
 // texel) evaluations of the quadrant lists (what the splat computes), out[2] += list
-// entries x 256 texels (the tile lists' superset).
+// entries x 256 texels (the tile lists' superset).  out is 64 such triples, work-group b
+// adding to triple b mod 64 (so the atomics do not all meet on three words); sum_slots
+// adds them up.
 __global__ __launch_bounds__(256) void count_splat_work(BuildArgs a, int64_t n_buckets,
                                                         unsigned long long* __restrict__ out) {
   __shared__ SplatLds sm;
@@ -595,10 +597,19 @@ __global__ __launch_bounds__(256) void count_splat_work(BuildArgs a, int64_t n_b
     const uint32_t bb0 = a.bucket[si.bidx], bb1 = a.bucket[si.bidx + 1];
     const uint32_t b0 = bb0 + si.seg * kSegment;
     const unsigned long long n = a.hdr->overflow == 0 ? min(bb1, b0 + kSegment) - b0 : 0u;
-    atomicAdd(&out[0], part[0][0] + part[1][0] + part[2][0] + part[3][0]);
-    atomicAdd(&out[1], part[0][1] + part[1][1] + part[2][1] + part[3][1]);
-    atomicAdd(&out[2], n * (unsigned long long)(kTile * kTile));
+    unsigned long long* o = out + 3 * (blockIdx.x & 63u);
+    atomicAdd(&o[0], part[0][0] + part[1][0] + part[2][0] + part[3][0]);
+    atomicAdd(&o[1], part[0][1] + part[1][1] + part[2][1] + part[3][1]);
+    atomicAdd(&o[2], n * (unsigned long long)(kTile * kTile));
   }
+}
+
+__global__ void sum_slots(const unsigned long long* __restrict__ slots, unsigned long long* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= 3) return;
+  unsigned long long t = 0;
+  for (int i = 0; i < 64; ++i) t += slots[3 * i + c];
+  out[c] = t;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1257,8 +1268,12 @@ hipError_t splat_batch_launch(const BuildArgs* args, const SplatJobs& jobs, int 
 hipError_t splat_work_launch(const BuildArgs& a, const BuildLayout& L, int64_t* counts, hipStream_t s) {
   hipError_t e = fill(reinterpret_cast<uint32_t*>(counts), 6, 0u, s);
   if (e != hipSuccess || a.n == 0) return e;
+  // 64 partial triples in the radix sorts' scratch, which the build no longer needs
+  unsigned long long* slots = reinterpret_cast<unsigned long long*>(a.radix_tmp);
+  if ((e = fill(a.radix_tmp, 2 * 3 * 64, 0u, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(count_splat_work, dim3((unsigned)xcd_grid(L.max_items, a.item_shift)), dim3(256), 0, s, a, L.n_buckets,
-                     reinterpret_cast<unsigned long long*>(counts));
+                     slots);
+  hipLaunchKernelGGL(sum_slots, dim3(1), dim3(64), 0, s, slots, reinterpret_cast<unsigned long long*>(counts));
   return hipGetLastError();
 }
 
