@@ -40,7 +40,8 @@ COPY_FETCH_SCALE = 262144.0 / 131084.0
 COPY_WRITE_SCALE = 262144.0 / 262144.0
 MEASURED_TRAFFIC = {
     "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133400, write_kib=286992,
-                     helpers=("splat_stage", "splat_item", "xcd_item"), digest="0dc42ae47ac34e6a"),
+                     helpers=("block_max_q", "reached_quadrants", "splat_stage", "splat_item", "xcd_item"),
+                     digest="0dc42ae47ac34e6a"),
     "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=88133, write_kib=184320,
                            helpers=("composite_wave_tile",), digest="5555f5722bd3a626"),
 }

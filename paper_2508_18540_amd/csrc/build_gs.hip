@@ -384,8 +384,12 @@ __device__ __forceinline__ float taylor_q(float ca, float cb, float cc, float A,
 // centre value if the centre lies inside, else the best point of the four edges (each a 1-D
 // concave quadratic), each raised by 1e-5 of the magnitude of its terms, far above the
 // float32 rounding of q at that point, so a rectangle whose texels pass the 1/255 test is
-// never reported below it.
-__device__ __forceinline__ float block_max_q(float ca, float cb, float cc, float l2o, float u0, float v0) {
+// never reported below it.  On an edge u = const the 1-D maximum lies at v = kv u, on an
+// edge v = const at u = ku v (kv = -cb / (2 cc), ku = -cb / (2 ca), per Gaussian); a point
+// off the exact maximum by the rounding of kv, ku lowers q by a second-order amount far
+// inside the margin.
+__device__ __forceinline__ float block_max_q(float ca, float cb, float cc, float l2o, float ku, float kv, float u0,
+                                             float v0) {
   const float u1 = u0 + 7.0f, v1 = v0 + 7.0f;
   if (u0 <= 0.0f && 0.0f <= u1 && v0 <= 0.0f && 0.0f <= v1) return l2o;
   float best = -INFINITY;
@@ -395,10 +399,10 @@ __device__ __forceinline__ float block_max_q(float ca, float cb, float cc, float
     float u, v;
     if (e < 2) {
       u = e ? u1 : u0;
-      v = fminf(fmaxf(-cb * u / (2.0f * cc), v0), v1);
+      v = fminf(fmaxf(kv * u, v0), v1);
     } else {
       v = e == 3 ? v1 : v0;
-      u = fminf(fmaxf(-cb * v / (2.0f * ca), u0), u1);
+      u = fminf(fmaxf(ku * v, u0), u1);
     }
     const float tu = ca * u * u, tv = cc * v * v, tx = cb * u * v;
     const float mag = fabsf(tu) + fabsf(tv) + fabsf(tx);
@@ -410,12 +414,14 @@ __device__ __forceinline__ float block_max_q(float ca, float cb, float cc, float
 // The 8x8 quadrants of the tile (bit q = 2 qy + qx, among those of `box`) that the 1/255
 // ellipse of the Gaussian reaches; (sx, sy) = tile origin minus the mean.
 __device__ __forceinline__ uint32_t reached_quadrants(const GRec& g, uint32_t box, float sx, float sy) {
+  // (ca, cc < 0 for every projected Gaussian: its conic is negative definite)
+  const float kv = -g.cb * __builtin_amdgcn_rcpf(2.0f * g.cc), ku = -g.cb * __builtin_amdgcn_rcpf(2.0f * g.ca);
   uint32_t qm = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (!((box >> q) & 1u)) continue;
     const float u0 = (float)((q & 1) << 3) + sx, v0 = (float)((q >> 1) << 3) + sy;
-    if (block_max_q(g.ca, g.cb, g.cc, g.l2o, u0, v0) >= kLog2AlphaMin - 1e-2f) qm |= 1u << q;
+    if (block_max_q(g.ca, g.cb, g.cc, g.l2o, ku, kv, u0, v0) >= kLog2AlphaMin - 1e-2f) qm |= 1u << q;
   }
   return qm;
 }
