@@ -826,9 +826,22 @@ __global__ __launch_bounds__(256) void combine_jobs(const BuildArgs* __restrict_
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr int kBwdBlock = 16;
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// Sum of v over the wave, complete in lane 63 (the other lanes hold partial sums): inclusive
+// sums within each row of 16 lanes (data-parallel-primitive shifts by 1, 2, 4, 8; lanes
+// shifted in from outside the row add zero), then row 0's total added to row 1 and row 2's
+// to row 3 (broadcast of lane 15), then lane 31's to rows 2 and 3 (broadcast of lane 31).
+// VALU only, where a butterfly of lane shuffles goes through the LDS crossbar.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, kRowMask, 0xf, true));
+}
+__device__ __forceinline__ float wave_sum_last(float v) {
+  v = dpp_add<0x111, 0xf>(v);                              // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);                              // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);                              // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);                              // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);                              // row_bcast:15 into rows 1, 3
+  v = dpp_add<0x143, 0xc>(v);                              // row_bcast:31 into rows 2, 3
   return v;
 }
 
@@ -946,13 +959,16 @@ __global__ __launch_bounds__(256) void splat_bwd_gs(BuildArgs a, int64_t n_bucke
       v[6] = wa * gp.x;
       v[7] = wa * gp.y;
       v[8] = wa * gp.z;
+      // the wave's sums, read out of lane 63 as wave-uniform values, added by lane 0
+      float t[kGradSlots];
 #pragma unroll
-      for (int s = 0; s < kGradSlots; ++s) v[s] = wave_sum(v[s]);
+      for (int s = 0; s < kGradSlots; ++s)
+        t[s] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_last(v[s])), 63));
       if (lane == 0) {
         float* dst = a.ggrad + (size_t)idx * kGradSlots;
 #pragma unroll
         for (int s = 0; s < kGradSlots; ++s)
-          if (v[s] != 0.0f) atomicAdd(dst + s, v[s]);
+          if (t[s] != 0.0f) atomicAdd(dst + s, t[s]);
       }
     }
   }
