@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 COPY_FETCH_SCALE = 262144.0 / 131084.0
 COPY_WRITE_SCALE = 262144.0 / 262144.0
 MEASURED_TRAFFIC = {
-    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133400, write_kib=286992,
+    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133359, write_kib=286992,
                      helpers=("block_max_q", "reached_quadrants", "splat_stage", "splat_item", "xcd_item"),
-                     digest="0dc42ae47ac34e6a"),
+                     digest="bee5fa49fd8a334f"),
     "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=88133, write_kib=184320,
                            helpers=("composite_wave_tile",), digest="5555f5722bd3a626"),
 }
