@@ -479,23 +479,31 @@ __device__ __forceinline__ int splat_stage(const BuildArgs& a, uint32_t item, Sp
     sm.c[tid] = make_float4(g.rgb[2], 0.0f, 0.0f, 0.0f);
     qm = reached_quadrants(g, ent >> 28, tt.sx, tt.sy);
   }
+  // waves that hold no entry (most segments are shorter than 256 entries) count zero and
+  // write nothing: they skip the ranking (wave-uniform branch)
+  const bool staged = wave * 64 < n;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-  uint32_t rank[4];
+  uint32_t rank[4] = {0u, 0u, 0u, 0u};
+  if (staged) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint64_t m = __ballot((qm >> q) & 1u);
-    rank[q] = __popcll(m & below);
-    if (lane == 0) sm.cnt[q][wave] = __popcll(m);
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t m = __ballot((qm >> q) & 1u);
+      rank[q] = __popcll(m & below);
+      if (lane == 0) sm.cnt[q][wave] = __popcll(m);
+    }
+  } else if (lane < 4) {
+    sm.cnt[lane][wave] = 0;
   }
   __syncthreads();
-  int my_count = 0;
+  if (staged) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int off = 0;
-    for (int w = 0; w < 4; ++w) off += w < wave ? sm.cnt[q][w] : 0;
-    if ((qm >> q) & 1u) sm.list[q][off + rank[q]] = (uint32_t)tid * 16u;   // byte offset: no index math below
-    if (q == wave) my_count = sm.cnt[q][0] + sm.cnt[q][1] + sm.cnt[q][2] + sm.cnt[q][3];
+    for (int q = 0; q < 4; ++q) {
+      int off = 0;
+      for (int w = 0; w < 4; ++w) off += w < wave ? sm.cnt[q][w] : 0;
+      if ((qm >> q) & 1u) sm.list[q][off + rank[q]] = (uint32_t)tid * 16u;   // byte offset: no index math below
+    }
   }
+  const int my_count = sm.cnt[wave][0] + sm.cnt[wave][1] + sm.cnt[wave][2] + sm.cnt[wave][3];
   __syncthreads();
   return __builtin_amdgcn_readfirstlane(my_count);
 }
