@@ -611,7 +611,7 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   constexpr int E = BIL ? kWaveWin / 2 : kWaveWin;          // window entries
   constexpr int PF = E / 64;                                 // entries each lane fetches
   constexpr int kTB = std::is_same<PT, float>::value ? 16 : (std::is_same<PT, uint8_t>::value ? 4 : 8);
-  __shared__ LT win[2][(BIL ? 2 : 1) * E + 2];              // plus a trash slot (entries past the window)
+  __shared__ LT win[2][(BIL ? 2 : 1) * E + 2];              // (+2: the split halves' spacing)
   // FP32 nearest windows are held as two arrays of 8-byte halves, (r, g) at entries
   // [0, E) and (b, a) kHalf entries on: a sample is two ds_read_b64 at one address (the
   // second through the instruction's offset), which meet far fewer bank conflicts than one
@@ -695,15 +695,19 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   auto fetch = [&](int k, int f0, int len, int iy) {
     const auto r0 = row(k, iy);
     const auto r1 = row(k, iy + 1);
+    // (texel f0 + lane + 64 q at byte (f0 + lane) kTB + 64 q kTB: one offset, the q steps
+    // in the loads' immediate offsets; unsigned wrap-around keeps it exact)
+    const uint32_t vo = (uint32_t)(f0 + lane) * (uint32_t)kTB;
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       if (q * 64 >= len) break;                            // wave uniform
       const int ix = f0 + lane + q * 64;
+      const uint32_t o = vo + (uint32_t)(q * 64 * kTB);
       if constexpr (!BIL) {
-        if constexpr (U8) rn[q] = (RT)__builtin_amdgcn_raw_buffer_load_b32(r0, (uint32_t)ix * 4u, 0, 0);
-        else if constexpr (RAW) rn[q] = __builtin_bit_cast(RT, __builtin_amdgcn_raw_buffer_load_b64(r0, (uint32_t)ix * 8u, 0, 0));
+        if constexpr (U8) rn[q] = (RT)__builtin_amdgcn_raw_buffer_load_b32(r0, o, 0, 0);
+        else if constexpr (RAW) rn[q] = __builtin_bit_cast(RT, __builtin_amdgcn_raw_buffer_load_b64(r0, o, 0, 0));
         else if constexpr (std::is_same<PT, float>::value)
-          rn[q] = __builtin_bit_cast(RT, __builtin_amdgcn_raw_buffer_load_b128(r0, (uint32_t)ix * 16u, 0, 0));
+          rn[q] = __builtin_bit_cast(RT, __builtin_amdgcn_raw_buffer_load_b128(r0, o, 0, 0));
         else rn[q] = __builtin_bit_cast(RT, wave_texel<PT>(r0, ix));
       } else {
         // (texel ix + 1 through an offset the compiler cannot relate to ix's: it would merge
@@ -722,8 +726,8 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       if (q * 64 >= len) break;
-      const int i0 = lane + q * 64;
-      const int i = i0 < len ? i0 : E;                     // past the window: the trash slot
+      // entries past the window's end (i >= len) land in the buffer's unread tail
+      const int i = lane + q * 64;
       if constexpr (SPLIT) {
         float2* w2 = reinterpret_cast<float2*>(w);
         const float4 t = __builtin_bit_cast(float4, rn[q]);
