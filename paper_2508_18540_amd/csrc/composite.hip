@@ -1343,13 +1343,14 @@ __global__ __launch_bounds__(64) void composite_rows_bwd(CompositeArgs a, int ns
     // Lanes update texels other lanes read and write next, which the compiler cannot see:
     // an empty asm with a memory clobber after every update keeps the LDS operations in
     // program order (one wave executes them in order, so no wait is needed).
-    auto scatter = [&](int i, const float4& e, bool own) {
+    // adds s e to accumulator entry i (one rounding per channel)
+    auto scatter = [&](int i, float sc, const float4& e, bool own) {
       auto rmw = [&]() {
         float4 v = ac[i];
-        v.x += e.x;
-        v.y += e.y;
-        v.z += e.z;
-        v.w += e.w;
+        v.x = fmaf(sc, e.x, v.x);
+        v.y = fmaf(sc, e.y, v.y);
+        v.z = fmaf(sc, e.z, v.z);
+        v.w = fmaf(sc, e.w, v.w);
         ac[i] = v;
       };
       if (FAST) {
@@ -1399,7 +1400,8 @@ __global__ __launch_bounds__(64) void composite_rows_bwd(CompositeArgs a, int ns
         const float tm = tmL[j * 64 + lane];
         Tk = at_m ? tm : Tk;
       }
-      const float4 d = make_float4(Tk * g[j].x, Tk * g[j].y, Tk * g[j].z, -Tk * U[j]);
+      // the sample's cotangent: Tk (g_r, g_g, g_b, -U)
+      const float4 d = make_float4(g[j].x, g[j].y, g[j].z, -U[j]);
       float Un = fmaf(om, U[j], gc);
       // (an empty asm pins the update here: sunk below the scatters, it would keep every
       // view's texel live across them)
@@ -1407,11 +1409,10 @@ __global__ __launch_bounds__(64) void composite_rows_bwd(CompositeArgs a, int ns
       Tc[j] = own ? Tk : Tc[j];
       U[j] = own ? Un : U[j];
       if (!BIL) {
-        scatter(ix, d, own);
+        scatter(ix, Tk, d, own);
       } else {
-        const float w0 = 1.0f - wx;
-        scatter(ix, make_float4(w0 * d.x, w0 * d.y, w0 * d.z, w0 * d.w), own);
-        scatter(ix + 1, make_float4(wx * d.x, wx * d.y, wx * d.z, wx * d.w), own);
+        scatter(ix, (1.0f - wx) * Tk, d, own);
+        scatter(ix + 1, wx * Tk, d, own);
       }
     }
   };
