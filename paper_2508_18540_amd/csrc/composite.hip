@@ -612,11 +612,12 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   constexpr int PF = E / 64;                                 // entries each lane fetches
   constexpr int kTB = std::is_same<PT, float>::value ? 16 : (std::is_same<PT, uint8_t>::value ? 4 : 8);
   __shared__ LT win[2][(BIL ? 2 : 1) * E + 2];              // (+2: the split halves' spacing)
-  // FP32 nearest windows are held as two arrays of 8-byte halves, (r, g) at entries
-  // [0, E) and (b, a) kHalf entries on: a sample is two ds_read_b64 at one address (the
-  // second through the instruction's offset), which meet far fewer bank conflicts than one
-  // ds_read_b128 of neighbouring texels.
-  constexpr bool SPLIT = std::is_same<PT, float>::value && !BIL;
+  // Float32 nearest windows (FP32 planes, and BF16 planes widened to float32) are held as
+  // two arrays of 8-byte halves, (r, g) at entries [0, E) and (b, a) kHalf entries on: a
+  // sample is two ds_read_b64 at one address (the second through the instruction's
+  // offset), which meet far fewer bank conflicts than one ds_read_b128 of neighbouring
+  // texels.
+  constexpr bool SPLIT = !RAW && !BIL;
   constexpr int kHalf = E + 2;                               // float2 entries to the (b, a) half
   // the scalars of the arguments in registers: the asm memory barriers of the sample
   // loop would otherwise reload them when the arguments live in global memory
