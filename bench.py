@@ -39,11 +39,11 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 COPY_FETCH_SCALE = 262144.0 / 131084.0
 COPY_WRITE_SCALE = 262144.0 / 262144.0
 MEASURED_TRAFFIC = {
-    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133318, write_kib=286992,
+    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133312, write_kib=286992,
                      helpers=("block_max_q", "reached_quadrants", "splat_stage", "splat_item", "xcd_item"),
                      digest="23854328a6c1fc45"),
-    "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=88117, write_kib=184320,
-                           helpers=("composite_wave_tile",), digest="30b985defccdef23"),
+    "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=88157, write_kib=184320,
+                           helpers=("composite_wave_tile",), digest="d2e09e4a30bb0dee"),
 }
 
 
@@ -77,7 +77,7 @@ def measured_traffic(name):
 # --extra ""`, digest-gated like the traffic
 MEASURED_VALU = {
     "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", valu_per_wave_sample=8.05,
-                           helpers=("composite_wave_tile",), digest="30b985defccdef23"),
+                           helpers=("composite_wave_tile",), digest="d2e09e4a30bb0dee"),
 }
 
 
