@@ -38,10 +38,13 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 # null.
 COPY_FETCH_SCALE = 262144.0 / 131084.0
 COPY_WRITE_SCALE = 262144.0 / 262144.0
+_DEV = "paper_2508_18540_amd/csrc/build_device.h::"
 MEASURED_TRAFFIC = {
-    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=133312, write_kib=286992,
-                     helpers=("block_max_q", "reached_quadrants", "splat_stage", "splat_item", "xcd_item"),
-                     digest="23854328a6c1fc45"),
+    "splat_gs": dict(src="paper_2508_18540_amd/csrc/build_gs.hip", fetch_kib=50944, write_kib=286992,
+                     helpers=("block_max_q", "reached_quadrants", "splat_stage", "splat_item", "bucket_segments",
+                              "emit_items", _DEV + "seg_count", _DEV + "item_order", _DEV + "item_bucket",
+                              _DEV + "xcd_item", "paper_2508_18540_amd/csrc/build_api.cpp::splat_item_shift"),
+                     digest="b08401825c5240c4"),
     "composite_wave": dict(src="paper_2508_18540_amd/csrc/composite.hip", fetch_kib=88157, write_kib=184320,
                            helpers=("composite_wave_tile",), digest="d2e09e4a30bb0dee"),
 }
@@ -49,13 +52,17 @@ MEASURED_TRAFFIC = {
 
 def kernel_digest(path, name, helpers=()):
     """sha1 of a kernel's definition (from its signature to the closing brace in column 0),
-    preceded by the definitions of the device functions it is built from."""
+    preceded by the definitions of the device functions and kernels it is built from or whose
+    output decides its traffic (a helper "file::name" is looked up in that file)."""
     import hashlib
     import re
 
-    text = open(os.path.join(ROOT, path)).read()
     parts = []
-    for fn, kind in [(h, "__device__") for h in helpers] + [(name, "__global__")]:
+    for h in tuple(helpers) + (name,):
+        src, fn = h.split("::") if "::" in h else (path, h)
+        text = open(os.path.join(ROOT, src)).read()
+        # (a helper from another file may be a host function: any definition in column 0)
+        kind = "__global__" if h == name else ("[A-Za-z_]" if "::" in h else "__(?:device|global)__")
         m = re.search(r"^(template <[^\n]*>\n)?" + kind + r"[^\n]*\b" + re.escape(fn) + r"\(", text, re.M)
         if not m:
             return None

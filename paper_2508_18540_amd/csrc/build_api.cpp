@@ -16,11 +16,12 @@ int splat_item_shift() {
     const int v = atoi(e);
     if (v >= 0 && v <= 24) return v;
   }
-  // one item per block: item i on XCD i mod 8.  Measured on the 500k-Gaussian frame, the
-  // splat (bound by VALU issue) ran fastest so: 0.308 ms, against 0.310 / 0.316 / 0.337 ms
-  // with 4096 / 512 / 64 blocks and 0.41 ms with one contiguous run per XCD, which read 42 %
-  // fewer bytes (the Gaussian records from one L2) but left the XCDs unevenly loaded.
-  return 24;
+  // 256 blocks: with the items chunk-major, a block is about a quarter of one plane.
+  // Measured on the 500k-Gaussian frame (splat work-group reads, FETCH_SIZE, and splat
+  // time): 256 blocks read 105 MB at 0.285-0.30 ms; 1024 blocks 138 MB at 0.276-0.29 ms; one item
+  // per block (item i on XCD i mod 8) 203 MB at 0.32 ms; 128 blocks 98 MB at 0.31 ms.
+  // (The splat backward deals the same items in blocks of its own.)
+  return 8;
 }
 
 BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t hp, int64_t cap) {
@@ -154,6 +155,7 @@ void build_args(BuildArgs& a, const BuildLayout& L, const lf_field* field, const
   a.capacity = cap;
   a.K = n_chunk;
   a.ntx = L.ntx;
+  a.n_tiles = L.n_tiles;
   a.chunk_bits = L.chunk_bits;
   a.kind = field->kind;
   a.rec_bytes = L.rec_bytes;

@@ -1,6 +1,8 @@
 // Device helpers shared by the Gaussian and voxel MPI builds.
 #pragma once
 
+#include <algorithm>
+
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -42,6 +44,46 @@ __device__ __forceinline__ KeyCull key_and_cull(const Consts& c, float mx, float
 __device__ __forceinline__ uint32_t box_tiles(int x0, int y0, int x1, int y1) {
   if (x1 < x0 || y1 < y0) return 0u;
   return (uint32_t)(((x1 >> kTileShift) - (x0 >> kTileShift) + 1) * ((y1 >> kTileShift) - (y0 >> kTileShift) + 1));
+}
+
+// Segments of a (tile, chunk) bucket of len entries: runs of kSegment entries, and one
+// (empty) segment for an empty bucket, whose texels are still written.
+__device__ __forceinline__ uint32_t seg_count(uint32_t len) { return len ? (len + kSegment - 1) / kSegment : 1u; }
+
+// Chunk-major work-item order, (chunk, tile): a run of consecutive items is a band of tile
+// rows of one plane.  A run of items dealt to one XCD then reads the records of the
+// plane's Gaussians in that band (which several of its tiles share) once into that XCD's
+// L2.  item_order(bidx) is the position of (tile, chunk) bucket bidx = tile K + chunk in
+// this order, item_bucket its inverse.  (The tile-major order is bidx itself.)
+__device__ __forceinline__ int64_t item_order(const BuildArgs& a, int64_t bidx) {
+  return (bidx % a.K) * a.n_tiles + bidx / a.K;
+}
+
+__device__ __forceinline__ int64_t item_bucket(const BuildArgs& a, int64_t c) {
+  return (c % a.n_tiles) * a.K + c / a.n_tiles;
+}
+
+// Work item of work-group wg when `total` items are dealt to the 8 XCDs (work-group wg runs
+// on XCD wg mod 8) in 2^shift blocks of consecutive items, block B on XCD B mod 8: as the
+// items run in item_order, a block is a band of neighbouring tiles of one plane, whose
+// lists share Gaussians, so it reads the shared records from one L2, while the dense and
+// sparse parts of the frame are spread over all XCDs.  Within an XCD its work-groups take
+// its blocks' items in order.  The grid must hold xcd_grid(max_items, shift) work-groups
+// (total <= max_items); work-groups past the items return.
+__device__ __forceinline__ bool xcd_item(uint32_t wg, uint32_t total, int shift, uint32_t* item) {
+  const uint32_t C = max(1u, total >> shift);              // items per block
+  const uint32_t j = wg >> 3, x = wg & 7u;
+  const uint32_t q = j / C, r = j - q * C;
+  *item = (q * 8u + x) * C + r;
+  return *item < total;
+}
+
+// Work-groups of a launch over at most max_items items dealt by xcd_item: with C <=
+// max(1, max_items >> shift) items per block, XCD x holds ceil(blocks / 8) blocks of C, so
+// the largest index used is below total + 8 C.
+inline int64_t xcd_grid(int64_t max_items, int shift) {
+  const int64_t C = std::max<int64_t>(1, max_items >> shift);
+  return ((max_items + 8 * C + 7) / 8) * 8;
 }
 
 // Premultiplied RGBA texel store in the plane's storage type (round to nearest even).

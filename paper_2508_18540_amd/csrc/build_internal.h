@@ -69,7 +69,7 @@ BuildLayout build_layout(int32_t kind, int64_t n, int32_t K, int32_t wp, int32_t
 
 struct BuildArgs {
   int64_t n, capacity;
-  int32_t K, ntx, binning, plane_dtype, chunk_bits, kind, rec_bytes;
+  int32_t K, ntx, n_tiles, binning, plane_dtype, chunk_bits, kind, rec_bytes;
   float d_focal32;
   Consts c;
   // field (Gaussians)

@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void splat_vox(BuildArgs a, int64_t n_buckets)
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
   const bool ok = a.hdr->overflow == 0;
   const uint32_t bb0 = a.bucket[bidx], bb1 = a.bucket[bidx + 1];
-  const uint32_t nseg = a.item_start[bidx + 1] - a.item_start[bidx];
+  const uint32_t nseg = seg_count(bb1 - bb0);
   if (ok) {
     const uint32_t b0 = bb0 + it.y * kSegment;
     const uint32_t b1 = min(bb1, b0 + kSegment);
