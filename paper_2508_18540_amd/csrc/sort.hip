@@ -287,12 +287,16 @@ __global__ __launch_bounds__(kRadixThreads) void radix_onesweep(const uint32_t* 
                                                                 uint64_t* status, uint32_t* err) {
   constexpr int R = 1 << BITS;
   constexpr int PER = R >= kRadixThreads ? R / kRadixThreads : 1;
+  // elements per thread and per chunk: wide digits get longer chunks, so that each digit's
+  // run of a chunk (about CH / R elements) still fills part of a cache line
+  constexpr int IT = BITS >= 10 ? 2 * kItems : kItems;
+  constexpr int CH = IT * kRadixThreads;
   __shared__ uint32_t hist[R];            // this span's digit counts
   __shared__ uint32_t running[R];         // output position of the next element of each digit
   __shared__ uint32_t wcount[kWaves][R];  // per-wave digit counts of a chunk, then offsets
   __shared__ uint32_t lstart[R + 1];      // digit starts inside the chunk's LDS copy
-  __shared__ uint32_t s_key[kChunk];
-  __shared__ uint32_t s_val[kChunk];
+  __shared__ uint32_t s_key[CH];
+  __shared__ uint32_t s_val[CH];
   __shared__ uint32_t wt[kWaves];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -310,15 +314,15 @@ __global__ __launch_bounds__(kRadixThreads) void radix_onesweep(const uint32_t* 
   // Spans are filled in order, so an empty span has only empty successors, and no
   // one waits on it.
   if (b0 >= b1) return;
-  for (int64_t c0 = b0; c0 < b1; c0 += kChunk) {
-    uint32_t kk[kItems];
+  for (int64_t c0 = b0; c0 < b1; c0 += CH) {
+    uint32_t kk[IT];
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
       const int64_t e = c0 + i * kRadixThreads + tid;
       kk[i] = e < b1 ? keys_in[e] : 0u;
     }
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
       if (c0 + i * kRadixThreads + tid >= b1) break;
       count_digit(hist, (kk[i] >> shift) & mask);
     }
@@ -360,24 +364,24 @@ __global__ __launch_bounds__(kRadixThreads) void radix_onesweep(const uint32_t* 
     }
   }
   lds_barrier();
-  // Scatter, a chunk of kChunk elements at a time.  Wave w takes the chunk's w-th quarter
+  // Scatter, a chunk of CH elements at a time.  Wave w takes the chunk's w-th quarter
   // (contiguous, so waves in order and items in order within a wave is element order:
   // stable) and ranks its items one after another against its own digit counters (one
   // wave's LDS operations complete in order: no barrier between items).  The chunk is then
   // reordered by digit in LDS, so the global writes of each digit's run are contiguous.
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  for (int64_t c0 = b0; c0 < b1; c0 += kChunk) {
-    const int clen = (int)min((int64_t)kChunk, b1 - c0);
-    const int64_t wb = c0 + (int64_t)wave * (kItems * 64) + lane;
-    uint32_t kk[kItems], vv[kItems], rk[kItems];
+  for (int64_t c0 = b0; c0 < b1; c0 += CH) {
+    const int clen = (int)min((int64_t)CH, b1 - c0);
+    const int64_t wb = c0 + (int64_t)wave * (IT * 64) + lane;
+    uint32_t kk[IT], vv[IT], rk[IT];
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
       const int64_t e = wb + i * 64;
       kk[i] = e < b1 ? keys_in[e] : 0u;
       vv[i] = e < b1 ? vals_in[e] : 0u;
     }
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
       const bool valid = wb + i * 64 < b1;
       const uint32_t d = valid ? (kk[i] >> shift) & mask : 0u;
       // lanes of this wave holding the same digit
@@ -425,7 +429,7 @@ __global__ __launch_bounds__(kRadixThreads) void radix_onesweep(const uint32_t* 
     }
     lds_barrier();
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
       if (wb + i * 64 < b1) {
         const uint32_t d = (kk[i] >> shift) & mask;
         const uint32_t lp = lstart[d] + wcount[wave][d] + rk[i];
