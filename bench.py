@@ -191,7 +191,7 @@ def copy_rate(dev, nbytes=1 << 30, reps=5):
 def _passes(fn, steps, ctx, L):
     """The timed region, then the instrumented one: `steps` calls of fn with the library's
     per-phase HIP events off (the step time reported), then `steps` more with them on (the
-    per-phase times, from events recorded on the launch stream; the events add about 0.05
+    per-phase times, from events recorded on the launch stream; the events add about 0.03
     ms to a cluster500k frame, so they stay out of the step time).  Returns (ms per step,
     ms per step instrumented, {phase: (total ms, launches)})."""
     import torch

@@ -148,7 +148,10 @@ hipEvent_t Profiler::take() {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // timing only: no system-scope fence (cache write-back and invalidation) when an event is
+  // recorded; with it, each phase boundary cost about 4 us and cooled the caches of the
+  // phase after it
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
