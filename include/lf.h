@@ -245,7 +245,7 @@ lf_status lf_composite(lf_ctx* ctx, const lf_mpi* mpi, const lf_camera* cam, con
  * the coefficient table in a static device array of LF_COMPOSITE_SCRATCH_BYTES that each
  * GPU holds until the process ends (its address is resolved by lf_create).  The call
  * allocates nothing, host or device.  The table needs
- * 16 K V + 4 K (V + 24) + 8 K V bytes, each term rounded up to 256, for K = mpi->n_chunk
+ * 16 K V + 4 K (V + 24) + 8 K V bytes, each term rounded up to 256, plus 256, for K = mpi->n_chunk
  * planes and V = n_views views; a call beyond LF_COMPOSITE_SCRATCH_BYTES returns LF_ERR_CAPACITY
  * before anything is enqueued.  Every call on one GPU shares that one array (each call
  * rewrites it before compositing): calls that overlap on one GPU, on any streams or

@@ -135,6 +135,7 @@ __global__ void coeff_table(CompositeArgs a, float4* __restrict__ pt, float* __r
                             int slots) {
   const int S = ct_stride(a.n_views);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && a.spill) *a.spill = 0u;
   if (i >= a.K * S) return;
   const int k = i / S, p = i % S;
   const int v = a.perm[min(p, a.n_views - 1)];
@@ -318,6 +319,8 @@ __global__ __launch_bounds__(kRowThreads) void composite_rows(CompositeArgs a, i
   const int per = (total + 7) / 8;
   const int lg = (wg % 8) * per + wg / 8;
   if (lg >= total) return;                                 // whole work-group: grid padded to 8 per
+  // the one-wave kernel ran before (64-pixel tiles) and took every segment: nothing to do
+  if (a.tile != 256 && a.spill && *a.spill == 0u) return;
   const int gi = lg % a.n_groups, rest = lg / a.n_groups;
   const int y = rest / nseg;
   const uint32_t gd = a.vgroup[gi];
@@ -630,7 +633,10 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   const int nv = gd >> 8;
   pt += (size_t)gi * aK;
   pm += (size_t)gi * aK;
-  if (!wave_fits<BIL>(a, pt, pm, xs0, y)) return;          // the row kernel's segment
+  if (!wave_fits<BIL>(a, pt, pm, xs0, y)) {                // the row kernel's segment
+    if (threadIdx.x == 0 && a.spill) *a.spill = 1u;
+    return;
+  }
   const int lane = threadIdx.x;
   const int x = xs0 + lane;
   // lanes past the row's end sample at their own x (results dropped)
@@ -1618,9 +1624,13 @@ int view_groups(CompositeArgs& a, int G) {
 }
 
 size_t composite_table_bytes(int K, int n_views) {
-  // at most one view group per view
+  // at most one view group per view; the last 256 bytes hold the spill flag
   return align_256((size_t)K * n_views * 16) + align_256((size_t)K * ct_stride(n_views) * 4) +
-         align_256((size_t)K * n_views * 8);
+         align_256((size_t)K * n_views * 8) + 256;
+}
+
+uint32_t* table_spill(void* table, int K, int n_views) {
+  return reinterpret_cast<uint32_t*>(static_cast<char*>(table) + composite_table_bytes(K, n_views) - 256);
 }
 
 namespace {
@@ -1734,6 +1744,7 @@ hipError_t composite_launch(CompositeArgs& a, void* table, hipStream_t s, Profil
   float* ct;
   float2* pm;
   table_parts(table, a.K, a.n_views, &pt, &ct, &pm);
+  a.spill = table_spill(table, a.K, a.n_views);
   int G;
   bool rows;
   composite_plan(a, &G, &rows);
@@ -1755,6 +1766,7 @@ bool composite_job(CompositeArgs& a, void* table, CompositeJob* j, CompositeKey*
   float* ct;
   float2* pm;
   table_parts(table, a.K, a.n_views, &pt, &ct, &pm);
+  a.spill = table_spill(table, a.K, a.n_views);
   int G;
   bool rows;
   composite_plan(a, &G, &rows);

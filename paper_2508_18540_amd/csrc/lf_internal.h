@@ -107,6 +107,10 @@ struct CompositeArgs {
   int32_t group;            // views per row work-group (4, 8, 12, 16); 0 picks by view count
   int32_t tile;             // pixels per row tile: 64 (one wave, where the window fits; also 0)
                             // or 256 (every segment to the 256-thread row kernel)
+  uint32_t* spill;          // set by the launch, in the coefficient table: the table kernel
+                            // clears it, a one-wave work-group that leaves its segment to the
+                            // row kernel sets it, and the row kernel returns at once while it
+                            // is clear
   Consts c;
   float dx[LF_MAX_VIEWS];
   float dy[LF_MAX_VIEWS];

@@ -57,7 +57,7 @@ def test_noalloc_rejects_tables_beyond_scratch():
     announce("composite_noalloc capacity")
     cam = scenegen.camera(16, 8, 50.0, 2.0, math.radians(40.0))
     g = geometry.derive(cam)
-    K, V = 1024, 256                                  # 16 K V + 4 K (V + 24) + 8 K V > 4 MiB
+    K, V = 1024, 256                                  # 16 K V + 4 K (V + 24) + 8 K V + 256 > 4 MiB
     planes = torch.zeros((K, g.hp, g.wp, 4), device="cuda")
     depth = torch.linspace(g.d_forward + 0.5, 10.0, K, device="cuda")
     dx = np.linspace(-0.1, 0.1, V).astype(np.float32)
