@@ -621,6 +621,7 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   // offset), which meet far fewer bank conflicts than one ds_read_b128 of neighbouring
   // texels.
   constexpr bool SPLIT = !RAW && !BIL;
+  constexpr int kSubW = SPLIT && std::is_same<PT, float>::value && G % 8 == 0 ? 8 : kSub;
   constexpr int kHalf = E + 2;                               // float2 entries to the (b, a) half
   // the scalars of the arguments in registers: the asm memory barriers of the sample
   // loop would otherwise reload them when the arguments live in global memory
@@ -774,12 +775,12 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
     have = next(k, f0, len, iy, wy);
     if (have) fetch(k, f0, len, iy);                       // the next one, in flight meanwhile
     const char* wb = reinterpret_cast<const char*>(win[buf]) - (ptrdiff_t)f0c * (ptrdiff_t)(BIL ? 32 : SPLIT ? 8 : (int)sizeof(LT));
-    // views in blocks of kSub: the block's LDS reads all in flight, then its blends
+    // views in blocks of kSubW: the block's LDS reads all in flight, then its blends
 #pragma unroll
-    for (int j0 = 0; j0 < G; j0 += kSub) {
-      float4 sv[kSub];
+    for (int j0 = 0; j0 < G; j0 += kSubW) {
+      float4 sv[kSubW];
 #pragma unroll
-      for (int jj = 0; jj < kSub; ++jj) {
+      for (int jj = 0; jj < kSubW; ++jj) {
         const float X = bxr + Cv[j0 + jj];
         const int ix = cvt_flr(X);
         if constexpr (SPLIT) {
@@ -798,7 +799,7 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
         }
       }
 #pragma unroll
-      for (int jj = 0; jj < kSub; ++jj) {
+      for (int jj = 0; jj < kSubW; ++jj) {
         const int j = j0 + jj;
         const float w = U8 ? Tr[j] * (1.0f / 255.0f) : Tr[j];
         Qr[j] = fmaf(w, sv[jj].x, Qr[j]);
@@ -808,7 +809,7 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
       }
       // (the block's blends before the next block's reads: bounds the live sample registers)
 #pragma unroll
-      for (int jj = 0; jj < kSub; ++jj)
+      for (int jj = 0; jj < kSubW; ++jj)
         asm volatile("" ::"v"(Qr[j0 + jj]), "v"(Qg[j0 + jj]), "v"(Qb[j0 + jj]), "v"(Tr[j0 + jj]) : "memory");
       __builtin_amdgcn_sched_barrier(0);
     }
