@@ -357,8 +357,8 @@ extern "C" lf_status lf_build_mpi_sh(lf_ctx* ctx, const lf_field* field, const f
                         workspace, workspace_bytes, stream);
 }
 
-// The view camera of lf_render_view as a light-field camera with no baseline// The view camera of lf_render_view as a light-field camera with no baseline: D_forward = 0,
-// theta' = theta, one plane at the view resolution, f' = 0.3 texel^2.
+// The view camera of lf_render_view as a light-field camera with no baseline: D_forward = 0,
+// theta' = theta, one plane at the view resolution, and the 0.3 texel^2 dilation of 3DGS.
 static lf_camera view_camera(const lf_camera* cam) {
   lf_camera v = *cam;
   v.phi_x = v.phi_y = 0.0f;
