@@ -199,6 +199,24 @@ def test_sort_digit_widths_agree(key_bits, tile_bits, monkeypatch):
     assert torch.equal(ref["rgba"], got["rgba"])
 
 
+@pytest.mark.parametrize("shift", [0, 5, 12, 24])
+def test_splat_item_blocks_agree(shift, monkeypatch):
+    """The splat's work items (chunk-major) are dealt to the XCDs in 2^shift blocks of
+    consecutive items (LF_SPLAT_ITEM_SHIFT; the default is 8).  Which work-group takes which
+    item changes no item's arithmetic, so every block count gives the default's planes bit
+    for bit: 0 is one contiguous run per XCD, 24 one item per block."""
+    announce("splat item blocks", shift)
+    scene = scenegen.cluster_scene(100_000, seed=8)
+    cam = scenegen.camera(384, 384, 50.0, 2.0, math.radians(40))
+    ref, info0, st0 = _gpu_build(scene, cam, 32)
+    assert st0 == L.LF_OK
+    monkeypatch.setenv("LF_SPLAT_ITEM_SHIFT", str(shift))
+    got, info, st = _gpu_build(scene, cam, 32)
+    assert st == L.LF_OK, L.lf_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(ref["rgba"], got["rgba"]) and torch.equal(ref["depth"], got["depth"])
+
+
 def test_constant_filter_planes():
     """The camera's constant dilation (adaptive-filter ablation) reaches the splat: planes at
     P_s = 2 against the oracle's with the same constant, and a constant equal to the Eq. 8
