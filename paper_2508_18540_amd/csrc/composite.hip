@@ -648,7 +648,9 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
   const size_t plane_bytes = (size_t)ahp * awp * kTB;
 
   // plane windows, 64 at a time (lane i: plane kb + i); the planes sampled are the set bits
-  int my_f0 = 0, my_len = 0, my_iy = 0;
+  // per lane: its plane's window start f0 (22-bit signed) and length (at most E) in one
+  // word, so a plane's window takes one readlane less
+  int my_fl = 0, my_iy = 0;
   float my_wy = 0.0f;
   auto batch = [&](int kb) -> uint64_t {
     const int k = kb + lane;
@@ -668,8 +670,7 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
       f0 = ok ? (int)lo : 0;
       len = ok ? (int)(hi - lo) + 1 : 0;                   // <= E: wave_fits
     }
-    my_f0 = f0;
-    my_len = len;
+    my_fl = (f0 & 0x3fffff) | (len << 22);
     my_iy = iy;
     my_wy = wy;
     return __builtin_amdgcn_ballot_w64(len > 0);
@@ -685,8 +686,9 @@ __device__ __forceinline__ void composite_wave_tile(const CompositeArgs& a, int 
     const int i = __builtin_ctzll(mask);
     mask &= mask - 1;
     k = kb + i;
-    f0 = __builtin_amdgcn_readlane(my_f0, i);
-    len = __builtin_amdgcn_readlane(my_len, i);
+    const int fl = __builtin_amdgcn_readlane(my_fl, i);
+    f0 = (fl << 10) >> 10;
+    len = (int)((uint32_t)fl >> 22);
     iy = __builtin_amdgcn_readlane(my_iy, i);
     wy = BIL ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_wy), i)) : 0.0f;
     return true;
